@@ -1,0 +1,557 @@
+/*
+ * stride_oracle.c -- plain FP64 CPU oracle for the acoustic FWI hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY: used by the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark; never by the product path.  It shares no
+ * source with the HIP library.  Every loop below is the textbook form of the
+ * scheme: no tiling, no fusion beyond what the update formula states.
+ *
+ * Scheme (paper Sec. 2.4, acoustic equation with constant density and no
+ * attenuation; Sec. 2.2 adjoint-state gradient):
+ *   u^{n+1} = a (2 u^n + k (L u^n + S^n)) - b u^{n-1},   n = 0 .. nt-2,
+ *   u^0 = u^{-1} = 0,  k = dt^2 vp^2,  a = 1/(1 + eta dt/2),  b = (1 - eta dt/2) a,
+ *   L u = sum_axes (c0 u + sum_j cj (u_{+j} + u_{-j})) / dx_axis^2,
+ *   S^n = sum_s W_s^T s_s^n / (cell volume),   traces[r][n] = W_r u^n.
+ * Adjoint (exact transpose of the above, with w = a k lambda):
+ *   w^m = a (2 w^{m+1} + k L w^{m+1}) - b w^{m+2} + a k R^T g^m,  w^{nt} = w^{nt+1} = 0,
+ *   dJ/dk  = sum_{n=0}^{nt-2} (w^{n+1}/k) (L u^n + S^n),
+ *   dJ/dvp = P^T [ (2/vp) sum_n w^{n+1} (L u^n + S^n) ],  P = edge-replicating pad,
+ *   dJ/ds_s^n = W_s w^{n+1} / (cell volume).
+ */
+#include "stride_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define R0_SPONGE 1e-3
+
+typedef struct {
+    int nd;
+    long n[3];      /* physical */
+    long np[3];     /* padded (axis 2 = 1 in 2D) */
+    long st[3];     /* strides of the padded array */
+    long N;         /* padded points */
+    int r;          /* stencil radius */
+    double c[6];
+    double inv_dx2[3];
+    double cellvol;
+} geo_t;
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* Central second-derivative weights: the unique weights of the (2r+1)-point
+ * symmetric stencil exact on polynomials of degree <= 2r+1 (Taylor moment
+ * conditions); written as the exact rationals. */
+int oracle_fd_weights(int space_order, double *c)
+{
+    switch (space_order) {
+    case 2:  c[0] = -2.0;             c[1] = 1.0; break;
+    case 4:  c[0] = -5.0 / 2.0;       c[1] = 4.0 / 3.0; c[2] = -1.0 / 12.0; break;
+    case 6:  c[0] = -49.0 / 18.0;     c[1] = 3.0 / 2.0; c[2] = -3.0 / 20.0; c[3] = 1.0 / 90.0; break;
+    case 8:  c[0] = -205.0 / 72.0;    c[1] = 8.0 / 5.0; c[2] = -1.0 / 5.0; c[3] = 8.0 / 315.0;
+             c[4] = -1.0 / 560.0; break;
+    case 10: c[0] = -5269.0 / 1800.0; c[1] = 5.0 / 3.0; c[2] = -5.0 / 21.0; c[3] = 5.0 / 126.0;
+             c[4] = -5.0 / 1008.0; c[5] = 1.0 / 3150.0; break;
+    default: return -1;
+    }
+    return 0;
+}
+
+static int make_geo(const oracle_grid_t *g, geo_t *G)
+{
+    if (!g || (g->ndim != 2 && g->ndim != 3) || g->nb < 0 || g->nt < 1 || !(g->dt > 0))
+        return -1;
+    memset(G, 0, sizeof(*G));
+    G->nd = g->ndim;
+    if (oracle_fd_weights(g->space_order, G->c) != 0)
+        return -1;
+    G->r = g->space_order / 2;
+    G->cellvol = 1.0;
+    for (int a = 0; a < 3; a++) {
+        if (a < g->ndim) {
+            if (g->shape[a] < 2 || !(g->spacing[a] > 0))
+                return -1;
+            G->n[a] = g->shape[a];
+            G->np[a] = g->shape[a] + 2L * g->nb;
+            G->inv_dx2[a] = 1.0 / (g->spacing[a] * g->spacing[a]);
+            G->cellvol *= g->spacing[a];
+        } else {
+            G->n[a] = 1;
+            G->np[a] = 1;
+        }
+    }
+    G->st[2] = 1;
+    G->st[1] = G->np[2];
+    G->st[0] = G->np[1] * G->np[2];
+    if (g->ndim == 2) {
+        G->st[1] = 1;
+        G->st[0] = G->np[1];
+    }
+    G->N = G->np[0] * G->np[1] * G->np[2];
+    return 0;
+}
+
+long oracle_padded_points(const oracle_grid_t *g, long *npad3)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0)
+        return -1;
+    if (npad3)
+        for (int a = 0; a < 3; a++)
+            npad3[a] = G.np[a];
+    return G.N;
+}
+
+static long pidx(const geo_t *G, long i0, long i1, long i2)
+{
+    return i0 * G->st[0] + i1 * G->st[1] + (G->nd == 3 ? i2 : 0);
+}
+
+static long clampl(long v, long lo, long hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+int oracle_pad(const oracle_grid_t *g, const double *phys, double *pad)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0)
+        return -1;
+    long nb = g->nb;
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G.np[0]; i0++)
+        for (long i1 = 0; i1 < G.np[1]; i1++)
+            for (long i2 = 0; i2 < G.np[2]; i2++) {
+                long j0 = clampl(i0 - nb, 0, G.n[0] - 1);
+                long j1 = clampl(i1 - nb, 0, G.n[1] - 1);
+                long j2 = G.nd == 3 ? clampl(i2 - nb, 0, G.n[2] - 1) : 0;
+                long src = G.nd == 3 ? (j0 * G.n[1] + j1) * G.n[2] + j2 : j0 * G.n[1] + j1;
+                pad[pidx(&G, i0, i1, i2)] = phys[src];
+            }
+    return 0;
+}
+
+int oracle_pad_transpose(const oracle_grid_t *g, const double *pad, double *phys)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0)
+        return -1;
+    long nb = g->nb;
+    long nphys = G.n[0] * G.n[1] * G.n[2];
+    memset(phys, 0, sizeof(double) * nphys);
+    /* serial: several padded cells add into one edge cell */
+    for (long i0 = 0; i0 < G.np[0]; i0++)
+        for (long i1 = 0; i1 < G.np[1]; i1++)
+            for (long i2 = 0; i2 < G.np[2]; i2++) {
+                long j0 = clampl(i0 - nb, 0, G.n[0] - 1);
+                long j1 = clampl(i1 - nb, 0, G.n[1] - 1);
+                long j2 = G.nd == 3 ? clampl(i2 - nb, 0, G.n[2] - 1) : 0;
+                long dst = G.nd == 3 ? (j0 * G.n[1] + j1) * G.n[2] + j2 : j0 * G.n[1] + j1;
+                phys[dst] += pad[pidx(&G, i0, i1, i2)];
+            }
+    return 0;
+}
+
+/* Cells into the layer along one axis: nb - i before the physical grid,
+ * i - (nb + n - 1) after it, 0 inside. */
+static long layer_depth(long i, long n, long nb)
+{
+    if (i < nb)
+        return nb - i;
+    if (i > nb + n - 1)
+        return i - (nb + n - 1);
+    return 0;
+}
+
+int oracle_eta(const oracle_grid_t *g, double *eta)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0)
+        return -1;
+    double emax[3] = {0, 0, 0};
+    if (g->nb > 0 && g->vref > 0)
+        for (int a = 0; a < G.nd; a++)
+            emax[a] = 3.0 * g->vref * log(1.0 / R0_SPONGE) / ((double)g->nb * g->spacing[a]);
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G.np[0]; i0++)
+        for (long i1 = 0; i1 < G.np[1]; i1++)
+            for (long i2 = 0; i2 < G.np[2]; i2++) {
+                long ii[3] = {i0, i1, i2};
+                double e = 0.0;
+                for (int a = 0; a < G.nd; a++) {
+                    double d = (double)layer_depth(ii[a], G.n[a], g->nb) / (double)(g->nb > 0 ? g->nb : 1);
+                    e += emax[a] * d * d;
+                }
+                eta[pidx(&G, i0, i1, i2)] = e;
+            }
+    return 0;
+}
+
+int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, double *w)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0 || npts < 0)
+        return -1;
+    for (int p = 0; p < npts; p++) {
+        long lo[3] = {0, 0, 0};
+        double fr[3] = {0, 0, 0};
+        for (int a = 0; a < G.nd; a++) {
+            double x = xyz[(long)p * G.nd + a];
+            double xmax = (double)(G.n[a] - 1) * g->spacing[a];
+            double tol = 1e-9 * g->spacing[a];
+            if (!(x >= -tol && x <= xmax + tol))
+                return -3;
+            double gx = x / g->spacing[a] + (double)g->nb;
+            long i = (long)floor(gx);
+            i = clampl(i, 0, G.np[a] - 2);
+            double f = gx - (double)i;
+            if (fabs(f) < 1e-9)
+                f = 0.0;
+            if (fabs(1.0 - f) < 1e-9)
+                f = 1.0;
+            lo[a] = i;
+            fr[a] = f;
+        }
+        for (int t = 0; t < 8; t++) {
+            idx[(long)p * 8 + t] = 0;
+            w[(long)p * 8 + t] = 0.0;
+        }
+        int ntap = 1 << G.nd;
+        for (int t = 0; t < ntap; t++) {
+            long lin = 0;
+            double wt = 1.0;
+            for (int a = 0; a < G.nd; a++) {
+                int bit = (t >> a) & 1;
+                lin += (lo[a] + bit) * G.st[a];
+                wt *= bit ? fr[a] : 1.0 - fr[a];
+            }
+            idx[(long)p * 8 + t] = lin;
+            w[(long)p * 8 + t] = wt;
+        }
+    }
+    return 0;
+}
+
+static double lap_at(const geo_t *G, const double *u, long i0, long i1, long i2)
+{
+    long ii[3] = {i0, i1, i2};
+    long p = pidx(G, i0, i1, i2);
+    double total = 0.0;
+    for (int a = 0; a < G->nd; a++) {
+        double s = G->c[0] * u[p];
+        for (int j = 1; j <= G->r; j++) {
+            double up = (ii[a] + j < G->np[a]) ? u[p + j * G->st[a]] : 0.0;
+            double um = (ii[a] - j >= 0) ? u[p - j * G->st[a]] : 0.0;
+            s += G->c[j] * (up + um);
+        }
+        total += s * G->inv_dx2[a];
+    }
+    return total;
+}
+
+int oracle_laplacian(const oracle_grid_t *g, const double *u, double *lu)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0)
+        return -1;
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G.np[0]; i0++)
+        for (long i1 = 0; i1 < G.np[1]; i1++)
+            for (long i2 = 0; i2 < G.np[2]; i2++)
+                lu[pidx(&G, i0, i1, i2)] = lap_at(&G, u, i0, i1, i2);
+    return 0;
+}
+
+/* Per-solve coefficient fields on the padded grid. */
+typedef struct {
+    geo_t G;
+    double *k, *a, *b, *vpp;
+    long *sidx, *ridx;
+    double *sw, *rw;
+    int nsrc, nrec, ntap;
+} solve_t;
+
+static void solve_free(solve_t *S)
+{
+    free(S->k);
+    free(S->a);
+    free(S->b);
+    free(S->vpp);
+    free(S->sidx);
+    free(S->ridx);
+    free(S->sw);
+    free(S->rw);
+}
+
+static int solve_init(solve_t *S, const oracle_grid_t *g, const double *vp,
+                      int nsrc, const double *src_xyz, int nrec, const double *rec_xyz)
+{
+    memset(S, 0, sizeof(*S));
+    int rc = make_geo(g, &S->G);
+    if (rc != 0)
+        return rc;
+    if (nsrc < 0 || nrec < 0)
+        return -1;
+    long N = S->G.N;
+    S->nsrc = nsrc;
+    S->nrec = nrec;
+    S->ntap = 1 << S->G.nd;
+    S->k = malloc(sizeof(double) * N);
+    S->a = malloc(sizeof(double) * N);
+    S->b = malloc(sizeof(double) * N);
+    S->vpp = malloc(sizeof(double) * N);
+    S->sidx = malloc(sizeof(long) * 8 * (nsrc + 1));
+    S->ridx = malloc(sizeof(long) * 8 * (nrec + 1));
+    S->sw = malloc(sizeof(double) * 8 * (nsrc + 1));
+    S->rw = malloc(sizeof(double) * 8 * (nrec + 1));
+    if (!S->k || !S->a || !S->b || !S->vpp || !S->sidx || !S->ridx || !S->sw || !S->rw) {
+        solve_free(S);
+        return -7;
+    }
+    if ((rc = oracle_taps(g, nsrc, src_xyz, S->sidx, S->sw)) != 0 ||
+        (rc = oracle_taps(g, nrec, rec_xyz, S->ridx, S->rw)) != 0) {
+        solve_free(S);
+        return rc;
+    }
+    oracle_pad(g, vp, S->vpp);
+    oracle_eta(g, S->a); /* eta into a, then converted */
+    double dt = g->dt;
+    for (long p = 0; p < N; p++) {
+        double eta = S->a[p];
+        S->k[p] = dt * dt * S->vpp[p] * S->vpp[p];
+        S->a[p] = 1.0 / (1.0 + eta * dt / 2.0);
+        S->b[p] = (1.0 - eta * dt / 2.0) * S->a[p];
+    }
+    return 0;
+}
+
+/* Dense source term S^n = sum_s W_s^T wavelet[s][n] / cell volume. */
+static void source_term(const solve_t *S, const double *wavelet, int nt, int n, double *dense)
+{
+    memset(dense, 0, sizeof(double) * S->G.N);
+    for (int s = 0; s < S->nsrc; s++)
+        for (int t = 0; t < S->ntap; t++)
+            dense[S->sidx[s * 8 + t]] += S->sw[s * 8 + t] * wavelet[(long)s * nt + n] / S->G.cellvol;
+}
+
+/* Dense adjoint source R^T g^m (no volume factor: sampling has none). */
+static void receiver_transpose(const solve_t *S, const double *gtr, int nt, int m, double *dense)
+{
+    memset(dense, 0, sizeof(double) * S->G.N);
+    for (int r = 0; r < S->nrec; r++)
+        for (int t = 0; t < S->ntap; t++)
+            dense[S->ridx[r * 8 + t]] += S->rw[r * 8 + t] * gtr[(long)r * nt + m];
+}
+
+static double sample(const solve_t *S, const long *idx, const double *w, int p, const double *u)
+{
+    double acc = 0.0;
+    for (int t = 0; t < S->ntap; t++)
+        acc += w[p * 8 + t] * u[idx[p * 8 + t]];
+    return acc;
+}
+
+/* One forward leapfrog step: unext = a (2 ucur + k (L ucur + src)) - b uprev. */
+static void forward_step(const solve_t *S, const double *ucur, const double *uprev,
+                         const double *src, double *unext)
+{
+    const geo_t *G = &S->G;
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G->np[0]; i0++)
+        for (long i1 = 0; i1 < G->np[1]; i1++)
+            for (long i2 = 0; i2 < G->np[2]; i2++) {
+                long p = pidx(G, i0, i1, i2);
+                double lap = lap_at(G, ucur, i0, i1, i2);
+                unext[p] = S->a[p] * (2.0 * ucur[p] + S->k[p] * (lap + src[p])) - S->b[p] * uprev[p];
+            }
+}
+
+int oracle_forward(const oracle_grid_t *g, const double *vp,
+                   int nsrc, const double *src_xyz, const double *wavelet,
+                   int nrec, const double *rec_xyz, double *traces,
+                   int nsnap, const int *snap_steps, double *snaps)
+{
+    solve_t S;
+    int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
+    if (rc != 0)
+        return rc;
+    long N = S.G.N;
+    int nt = g->nt;
+    double *up = calloc(N, sizeof(double));
+    double *uc = calloc(N, sizeof(double));
+    double *un = calloc(N, sizeof(double));
+    double *src = calloc(N, sizeof(double));
+    if (!up || !uc || !un || !src) {
+        free(up); free(uc); free(un); free(src);
+        solve_free(&S);
+        return -7;
+    }
+    for (int n = 0; n < nt; n++) {
+        for (int r = 0; r < nrec; r++)
+            traces[(long)r * nt + n] = sample(&S, S.ridx, S.rw, r, uc);
+        for (int q = 0; q < nsnap; q++)
+            if (snap_steps[q] == n)
+                memcpy(snaps + (long)q * N, uc, sizeof(double) * N);
+        if (n == nt - 1)
+            break;
+        source_term(&S, wavelet, nt, n, src);
+        forward_step(&S, uc, up, src, un);
+        double *tmp = up;
+        up = uc;
+        uc = un;
+        un = tmp;
+    }
+    free(up); free(uc); free(un); free(src);
+    solve_free(&S);
+    return 0;
+}
+
+int oracle_adjoint(const oracle_grid_t *g, const double *vp,
+                   int nsrc, const double *src_xyz, const double *wavelet,
+                   int nrec, const double *rec_xyz, const double *grad_traces,
+                   double *dvp, double *dwavelet, int seg)
+{
+    solve_t S;
+    int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
+    if (rc != 0)
+        return rc;
+    const geo_t *G = &S.G;
+    long N = G->N;
+    int nt = g->nt;
+    if (seg <= 0)
+        seg = (int)ceil(sqrt((double)nt));
+    if (seg > nt)
+        seg = nt;
+    int nseg = (nt + seg - 1) / seg;
+
+    /* checkpoints: state (u^i, u^{i-1}) at i = j*seg */
+    double *ck = malloc(sizeof(double) * 2 * N * (size_t)nseg);
+    double *useg = malloc(sizeof(double) * N * (size_t)seg);
+    double *up = calloc(N, sizeof(double)), *uc = calloc(N, sizeof(double)), *un = calloc(N, sizeof(double));
+    double *src = calloc(N, sizeof(double)), *q = calloc(N, sizeof(double));
+    double *w1 = calloc(N, sizeof(double)), *w2 = calloc(N, sizeof(double)), *w0 = calloc(N, sizeof(double));
+    double *G_acc = calloc(N, sizeof(double)), *lu = calloc(N, sizeof(double));
+    if (!ck || !useg || !up || !uc || !un || !src || !q || !w1 || !w2 || !w0 || !G_acc || !lu) {
+        free(ck); free(useg); free(up); free(uc); free(un); free(src); free(q);
+        free(w1); free(w2); free(w0); free(G_acc); free(lu);
+        solve_free(&S);
+        return -7;
+    }
+
+    /* forward sweep, keeping the segment-start states */
+    for (int n = 0; n < nt; n++) {
+        if (n % seg == 0) {
+            memcpy(ck + (size_t)(n / seg) * 2 * N, uc, sizeof(double) * N);
+            memcpy(ck + (size_t)(n / seg) * 2 * N + N, up, sizeof(double) * N);
+        }
+        if (n == nt - 1)
+            break;
+        source_term(&S, wavelet, nt, n, src);
+        forward_step(&S, uc, up, src, un);
+        double *tmp = up;
+        up = uc;
+        uc = un;
+        un = tmp;
+    }
+
+    if (dwavelet)
+        memset(dwavelet, 0, sizeof(double) * (size_t)nsrc * nt);
+
+    /* reverse sweep: w1 = w^{m+1}, w2 = w^{m+2} */
+    for (int j = nseg - 1; j >= 0; j--) {
+        int start = j * seg;
+        int end = start + seg < nt ? start + seg : nt;
+        memcpy(uc, ck + (size_t)j * 2 * N, sizeof(double) * N);
+        memcpy(up, ck + (size_t)j * 2 * N + N, sizeof(double) * N);
+        for (int n = start; n < end; n++) {
+            memcpy(useg + (size_t)(n - start) * N, uc, sizeof(double) * N);
+            if (n == end - 1)
+                break;
+            source_term(&S, wavelet, nt, n, src);
+            forward_step(&S, uc, up, src, un);
+            double *tmp = up;
+            up = uc;
+            uc = un;
+            un = tmp;
+        }
+        for (int m = end - 1; m >= start; m--) {
+            const double *um = useg + (size_t)(m - start) * N;
+            /* imaging: G += w^{m+1} (L u^m + S^m) */
+            oracle_laplacian(g, um, lu);
+            source_term(&S, wavelet, nt, m, src);
+#pragma omp parallel for
+            for (long p = 0; p < N; p++)
+                G_acc[p] += w1[p] * (lu[p] + src[p]);
+            /* source cotangent: W_s w^{m+1} / cell volume */
+            if (dwavelet)
+                for (int s = 0; s < nsrc; s++)
+                    dwavelet[(long)s * nt + m] = sample(&S, S.sidx, S.sw, s, w1) / G->cellvol;
+            if (m == 0)
+                break;
+            /* adjoint step: w^m = a (2 w^{m+1} + k L w^{m+1}) - b w^{m+2} + a k R^T g^m */
+            oracle_laplacian(g, w1, lu);
+            receiver_transpose(&S, grad_traces, nt, m, q);
+#pragma omp parallel for
+            for (long p = 0; p < N; p++)
+                w0[p] = S.a[p] * (2.0 * w1[p] + S.k[p] * lu[p]) - S.b[p] * w2[p] + S.a[p] * S.k[p] * q[p];
+            double *tmp = w2;
+            w2 = w1;
+            w1 = w0;
+            w0 = tmp;
+        }
+    }
+
+    if (dvp) {
+        /* dJ/dvp_pad = 2 G / vp_pad, then the transpose of the padding */
+        for (long p = 0; p < N; p++)
+            lu[p] = 2.0 * G_acc[p] / S.vpp[p];
+        oracle_pad_transpose(g, lu, dvp);
+    }
+    free(ck); free(useg); free(up); free(uc); free(un); free(src); free(q);
+    free(w1); free(w2); free(w0); free(G_acc); free(lu);
+    solve_free(&S);
+    return 0;
+}
+
+int oracle_gradient(const oracle_grid_t *g, const double *vp,
+                    int nsrc, const double *src_xyz, const double *wavelet,
+                    int nrec, const double *rec_xyz, const double *observed,
+                    double *traces_out, double *misfit, double *dvp, int seg)
+{
+    if (!g || g->nt < 1 || nrec < 0)
+        return -1;
+    size_t ntr = (size_t)nrec * g->nt;
+    double *tr = malloc(sizeof(double) * (ntr + 1));
+    double *res = malloc(sizeof(double) * (ntr + 1));
+    if (!tr || !res) {
+        free(tr); free(res);
+        return -7;
+    }
+    int rc = oracle_forward(g, vp, nsrc, src_xyz, wavelet, nrec, rec_xyz, tr, 0, NULL, NULL);
+    if (rc == 0) {
+        double J = 0.0;
+        for (size_t i = 0; i < ntr; i++) {
+            res[i] = tr[i] - observed[i];
+            J += 0.5 * res[i] * res[i];
+        }
+        if (misfit)
+            *misfit = J;
+        if (traces_out)
+            memcpy(traces_out, tr, sizeof(double) * ntr);
+        rc = oracle_adjoint(g, vp, nsrc, src_xyz, wavelet, nrec, rec_xyz, res, dvp, NULL, seg);
+    }
+    free(tr);
+    free(res);
+    return rc;
+}

@@ -1,0 +1,111 @@
+/*
+ * stride_oracle.h -- plain FP64 CPU oracle for the acoustic FWI hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this code; only the test suite, the smoke check and the CPU-baseline leg
+ * of the benchmark load it.  It shares no source with the HIP path.
+ *
+ * What it computes (all in double precision, plain loops, OpenMP over the
+ * outermost grid axis only):
+ *   - the constant-density, lossless acoustic wave equation
+ *         (1/vp^2) d2p/dt2 = lap(p) + s                          (Sec. 2.4, acoustic
+ *     equation with rho constant and alpha0 = 0)
+ *     stepped by second-order leapfrog in time and a 2r-order central Laplacian,
+ *     r in 1..5 (Sec. 2.4 gives 10th order in space);
+ *   - a sponge absorbing layer padded outside the physical grid (Sec. 2.4 cites a
+ *     sponge; profile and placement are readings, see below);
+ *   - bi/tri-linear point sources and receivers (Sec. 2.4, off-grid sources and
+ *     receivers by linear interpolation); injection is the transpose of sampling
+ *     divided by the cell volume;
+ *   - the exact discrete adjoint of that scheme, and the gradient of the L2 trace
+ *     misfit with respect to vp by the adjoint-state method (Sec. 2.2, reduced
+ *     objective and adjoint PDE; Sec. 3.2 describes one shot gradient as one
+ *     forward and one adjoint propagation).
+ *
+ * Readings where the paper is silent (each is restated in the design notes):
+ *   time order 2 (leapfrog); sponge outside the stated grid: a damping term
+ *   eta dp/dt / vp^2 with eta = sum_axes eta_max_axis (d/nb)^2, d the depth in
+ *   cells, and eta_max_axis = 3 vref ln(1/R0) / (nb dx_axis), so that the
+ *   round-trip amplitude decay exp(-int eta/vref dx) through the layer is
+ *   R0 = 1e-3; vref fixed per solve, so eta does not depend on vp
+ *   (vref = 0 switches damping off but keeps the padding); vp edge-replicated
+ *   into the layer; zero field beyond the padded array; traces[r][n] = R u^n with
+ *   t_n = n dt; s^n drives u^{n+1}; misfit J = 1/2 sum (traces - observed)^2.
+ *
+ * Layout: C order, last axis contiguous.  Physical arrays have shape `shape`;
+ * coordinates are metres with the origin at physical node 0, xyz[p*ndim + axis].
+ * Traces and wavelets are [count][nt].
+ *
+ * Return codes: 0 ok, -1 bad argument, -3 a point lies outside the physical grid,
+ * -7 out of host memory.
+ */
+#ifndef STRIDE_ORACLE_H
+#define STRIDE_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    int ndim;            /* 2 or 3 */
+    long shape[3];       /* physical grid */
+    double spacing[3];   /* metres */
+    int space_order;     /* 2, 4, 6, 8 or 10 */
+    int nb;              /* sponge cells added on every side */
+    double vref;         /* sponge reference speed (m/s); 0 = no damping */
+    double dt;           /* seconds */
+    int nt;              /* number of time samples */
+} oracle_grid_t;
+
+/* Central second-derivative weights c[0..order/2]. */
+int oracle_fd_weights(int space_order, double *c);
+
+/* Padded size per axis and total. */
+long oracle_padded_points(const oracle_grid_t *g, long *npad3);
+
+/* Edge-replicating pad of a physical field, and its transpose (sum of the
+ * padded strips into the edge cells). */
+int oracle_pad(const oracle_grid_t *g, const double *phys, double *pad);
+int oracle_pad_transpose(const oracle_grid_t *g, const double *pad, double *phys);
+
+/* Damping rate eta on the padded grid (1/s). */
+int oracle_eta(const oracle_grid_t *g, double *eta);
+
+/* Linear-interpolation taps of npts points: idx[p*8+t] padded linear index,
+ * w[p*8+t] weight; 2^ndim taps used, the rest are set to (0, 0.0). */
+int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, double *w);
+
+/* Apply the 2r-order Laplacian on the padded grid (zero outside). */
+int oracle_laplacian(const oracle_grid_t *g, const double *u, double *lu);
+
+/* Forward solve.  vp: physical [shape]; wavelet [nsrc][nt]; traces [nrec][nt].
+ * nsnap > 0 stores u^n for n = snap_steps[i] into snaps[i][padded]. */
+int oracle_forward(const oracle_grid_t *g, const double *vp,
+                   int nsrc, const double *src_xyz, const double *wavelet,
+                   int nrec, const double *rec_xyz, double *traces,
+                   int nsnap, const int *snap_steps, double *snaps);
+
+/* Vector-Jacobian product of the forward map (vp, wavelet) -> traces, evaluated
+ * at (vp, wavelet) with trace cotangent grad_traces [nrec][nt].  Outputs:
+ * dvp (physical shape, may be NULL) and dwavelet [nsrc][nt] (may be NULL).
+ * The forward states are kept by two-level checkpointing every `seg` steps
+ * (seg <= 0 picks ceil(sqrt(nt))); the result does not depend on seg. */
+int oracle_adjoint(const oracle_grid_t *g, const double *vp,
+                   int nsrc, const double *src_xyz, const double *wavelet,
+                   int nrec, const double *rec_xyz, const double *grad_traces,
+                   double *dvp, double *dwavelet, int seg);
+
+/* Shot gradient: traces (optional out), misfit J = 1/2 sum (traces-observed)^2
+ * and dJ/dvp. */
+int oracle_gradient(const oracle_grid_t *g, const double *vp,
+                    int nsrc, const double *src_xyz, const double *wavelet,
+                    int nrec, const double *rec_xyz, const double *observed,
+                    double *traces_out, double *misfit, double *dvp, int seg);
+
+/* Number of OpenMP threads the oracle will use. */
+int oracle_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
