@@ -1,0 +1,158 @@
+/*
+ * stride_hip.h -- C ABI of the MI355X (gfx950) acoustic full-waveform-inversion
+ * hot path: finite-difference time stepping of the acoustic wave equation with
+ * point sources and receivers, its exact discrete adjoint, and the gradient of
+ * the L2 trace misfit with respect to the speed of sound.
+ *
+ * What is computed (Cueto et al., "Stride", arXiv 2110.03345):
+ *   - Sec. 2.4, acoustic equation with constant density and no attenuation,
+ *         (1/vp^2) d2p/dt2 = lap p + s,
+ *     stepped by second-order leapfrog in time with an 8th- or 10th-order
+ *     central Laplacian (the paper's solver is 10th order in space), a sponge
+ *     absorbing layer, and off-grid sources/receivers by bi/tri-linear
+ *     interpolation;
+ *   - Sec. 2.2, reduced gradient of a PDE-constrained objective by the
+ *     adjoint-state method: one forward and one adjoint propagation per shot
+ *     (Sec. 3.2, 3.3), with the objective the L2 trace misfit
+ *     J = 1/2 sum_{r,n} (traces[r][n] - observed[r][n])^2.
+ *
+ * Discrete scheme (the adjoint is its exact transpose, sponge included):
+ *   u^{n+1} = a (2 u^n + k (L u^n + S^n)) - b u^{n-1},  u^0 = u^{-1} = 0,
+ *   k = dt^2 vp^2, a = 1/(1 + eta dt/2), b = (1 - eta dt/2) a,
+ *   S^n = sum_s W_s^T wavelet[s][n] / (cell volume),  traces[r][n] = W_r u^n,
+ *   eta = sum_axes eta_max (d/nb)^2 in the nb-cell layer padded outside the
+ *   physical grid, eta_max = 3 vref ln(1000) / (nb dx), zero inside.
+ *   vp is replicated from the edge cells into the layer; the field is zero
+ *   beyond the padded array.
+ *
+ * Conventions:
+ *   - Arrays are C order (last axis contiguous).  vp and dvp have the physical
+ *     shape; wavelets are [nsrc][nt]; traces, observed and grad_traces are
+ *     [nrec][nt].  All of these are FP32 DEVICE pointers owned by the caller.
+ *   - Coordinates (src_xyz, rec_xyz) are FP64 HOST arrays [count][ndim] in
+ *     metres, origin at physical node 0, axis order of the arrays.
+ *   - ws is a caller-owned DEVICE workspace of ws_bytes bytes, 256-byte aligned,
+ *     sized with stride_workspace_bytes().  Calls that run solves allocate
+ *     nothing; stride_plan_create allocates the plan's small tap tables.
+ *   - stream is a hipStream_t passed as void*; NULL is the default stream.
+ *     Solve calls only enqueue work (no host synchronisation) except the
+ *     one-shot stride_forward / stride_gradient, which create and destroy a
+ *     plan and therefore return after the work has finished.
+ *   - Every entry point returns STRIDE_OK or a negative error code; nothing is
+ *     enqueued when validation fails.  stride_last_error() returns a message
+ *     for the calling thread's last error.
+ *   - Plans are immutable after creation and may be shared between threads;
+ *     concurrent solves need distinct workspaces.
+ */
+#ifndef STRIDE_HIP_H
+#define STRIDE_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    STRIDE_OK = 0,
+    STRIDE_E_INVALID_ARG = -1, /* bad pointer, size, order, shape or mode */
+    STRIDE_E_CFL = -2,         /* dt * vp_max violates the leapfrog stability limit */
+    STRIDE_E_GEOMETRY = -3,    /* a source or receiver lies outside the physical grid */
+    STRIDE_E_WORKSPACE = -4,   /* ws_bytes below what the call needs */
+    STRIDE_E_HIP = -5,         /* a HIP runtime call failed */
+    STRIDE_E_NONFINITE = -6    /* non-finite values detected */
+};
+
+enum { STRIDE_MODE_FORWARD = 0, STRIDE_MODE_GRADIENT = 1 };
+
+/* Physical grid, stencil, sponge and time axis of a solve. */
+typedef struct stride_grid {
+    int32_t ndim;         /* 2 or 3 */
+    int32_t space_order;  /* 8 or 10 */
+    int32_t sponge_cells; /* nb >= 0 cells padded on every side */
+    int32_t nt;           /* time samples, >= 2 */
+    int64_t shape[3];     /* physical points per axis (>= 2; unused axes ignored) */
+    double spacing[3];    /* metres */
+    double sponge_vref;   /* reference speed of the sponge (m/s); 0 disables damping */
+    double dt;            /* seconds */
+} stride_grid_t;
+
+/* A plan: the validated grid plus the source/receiver tap tables of one shot
+ * geometry on the current HIP device. */
+typedef struct stride_plan stride_plan_t;
+
+/* Validates the grid and geometry (CFL is checked per solve, against vp) and
+ * builds the tap tables.  Errors: INVALID_ARG, GEOMETRY (Sec. 2.4 off-grid
+ * points must lie in the physical grid), HIP. */
+int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* src_xyz,
+                       int32_t nrec, const double* rec_xyz, stride_plan_t** out);
+
+/* Releases the plan (synchronises the device). */
+int stride_plan_destroy(stride_plan_t* plan);
+
+/* Padded extent per axis (shape + 2 nb; unused axes 1). */
+int stride_plan_padded_shape(const stride_plan_t* plan, int64_t out[3]);
+
+/* Workspace bytes for mode FORWARD or GRADIENT.  For GRADIENT, budget_bytes
+ * caps the size: the forward wavefields are kept by binomial checkpointing
+ * (Griewank-Walther revolve) with as many snapshots as fit, and 0 asks for the
+ * size that keeps every state (no recomputation).  The snapshot count a solve
+ * uses is derived from the ws_bytes it is given.  Errors: INVALID_ARG,
+ * WORKSPACE (budget below the minimum of 6 wavefields plus traces). */
+int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budget_bytes,
+                           size_t* out_bytes);
+
+/* Forward solve: traces[r][n] = W_r u^n, n = 0..nt-1.  vp must satisfy the
+ * CFL limit (dt vp_max sqrt(lambda sum_a 1/dx_a^2) <= 2, lambda = 6.5016 for
+ * order 8, 6.8267 for order 10); the check reads vp on the device and
+ * synchronises the stream once.  Errors: INVALID_ARG, CFL, WORKSPACE, HIP. */
+int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                        float* traces, void* ws, size_t ws_bytes, void* stream);
+
+/* Forward solve that also keeps the checkpoints of the forward wavefield in
+ * ws (GRADIENT-sized) for a later stride_backward with the same ws, vp and
+ * wavelet. */
+int stride_forward_save(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                        float* traces, void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of (vp, wavelet) -> traces at the point of the
+ * preceding stride_forward_save on ws: dvp = (d traces / d vp)^T grad_traces
+ * (physical shape) and, if dwavelet is not NULL, dwavelet = (d traces /
+ * d wavelet)^T grad_traces ([nsrc][nt]).  Recomputes forward states from the
+ * checkpoints as the revolve schedule dictates.  Sec. 2.2 adjoint method. */
+int stride_backward(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                    const float* grad_traces, float* dvp, float* dwavelet, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* Shot gradient: forward (traces optional, may be NULL), residual, misfit
+ * (FP64 device scalar) and dvp = dJ/dvp. */
+int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                         const float* observed, float* traces, double* misfit, float* dvp,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* One-shot forms (plan created and destroyed inside; blocking). */
+int stride_forward(const stride_grid_t* grid, const float* vp, const float* wavelet, int32_t nsrc,
+                   const double* src_xyz, int32_t nrec, const double* rec_xyz, float* traces,
+                   void* ws, size_t ws_bytes, void* stream);
+int stride_gradient(const stride_grid_t* grid, const float* vp, const float* wavelet,
+                    int32_t nsrc, const double* src_xyz, int32_t nrec, const double* rec_xyz,
+                    const float* observed, double* misfit, float* dvp, void* ws, size_t ws_bytes,
+                    void* stream);
+int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec, int32_t mode,
+                           size_t budget_bytes, size_t* out_bytes);
+
+/* Checkpointing schedule summary for nt steps within `fields` wavefields
+ * (host only): snapshots used, total forward steps (nt - 1 means no
+ * recomputation) and peak wavefields alive. */
+int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* forward_steps,
+                         int32_t* peak_fields);
+
+/* Message of the calling thread's last error ("" if none). */
+const char* stride_last_error(void);
+const char* stride_error_string(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

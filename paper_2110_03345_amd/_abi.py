@@ -1,0 +1,328 @@
+"""ctypes binding of libstride_hip.so (include/stride_hip.h).
+
+Argument marshalling only: every step of the solves runs in the HIP library.
+torch supplies device memory and the current stream.  When the library is
+missing this module raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstride_hip.so")
+
+STRIDE_OK = 0
+STRIDE_E_INVALID_ARG = -1
+STRIDE_E_CFL = -2
+STRIDE_E_GEOMETRY = -3
+STRIDE_E_WORKSPACE = -4
+STRIDE_E_HIP = -5
+STRIDE_E_NONFINITE = -6
+STRIDE_MODE_FORWARD = 0
+STRIDE_MODE_GRADIENT = 1
+
+EXPORTS = (
+    "stride_plan_create", "stride_plan_destroy", "stride_plan_padded_shape",
+    "stride_workspace_bytes", "stride_plan_forward", "stride_forward_save", "stride_backward",
+    "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
+    "stride_schedule_info", "stride_last_error", "stride_error_string",
+)
+
+
+class StrideError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class stride_grid_t(ctypes.Structure):
+    _fields_ = [
+        ("ndim", ctypes.c_int32),
+        ("space_order", ctypes.c_int32),
+        ("sponge_cells", ctypes.c_int32),
+        ("nt", ctypes.c_int32),
+        ("shape", ctypes.c_int64 * 3),
+        ("spacing", ctypes.c_double * 3),
+        ("sponge_vref", ctypes.c_double),
+        ("dt", ctypes.c_double),
+    ]
+
+
+_LIB = None
+
+
+def lib():
+    """Load the library (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp_ = ctypes.c_void_p
+        i32 = ctypes.c_int32
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp = ctypes.POINTER(stride_grid_t)
+        sz = ctypes.c_size_t
+        L.stride_plan_create.argtypes = [gp, i32, dp, i32, dp, ctypes.POINTER(vp_)]
+        L.stride_plan_destroy.argtypes = [vp_]
+        L.stride_plan_padded_shape.argtypes = [vp_, ctypes.POINTER(ctypes.c_int64)]
+        L.stride_workspace_bytes.argtypes = [vp_, i32, sz, ctypes.POINTER(sz)]
+        L.stride_plan_forward.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_forward_save.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_backward.argtypes = [vp_, vp_, vp_, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_plan_gradient.argtypes = [vp_, vp_, vp_, vp_, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_forward.argtypes = [gp, vp_, vp_, i32, dp, i32, dp, vp_, vp_, sz, vp_]
+        L.stride_gradient.argtypes = [gp, vp_, vp_, i32, dp, i32, dp, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_workspace_query.argtypes = [gp, i32, i32, i32, sz, ctypes.POINTER(sz)]
+        L.stride_schedule_info.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(i32),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+        L.stride_last_error.restype = ctypes.c_char_p
+        L.stride_error_string.restype = ctypes.c_char_p
+        L.stride_error_string.argtypes = [ctypes.c_int]
+        _LIB = L
+    return _LIB
+
+
+def _check(rc: int):
+    if rc != STRIDE_OK:
+        msg = lib().stride_last_error().decode() or lib().stride_error_string(rc).decode()
+        raise StrideError(rc, msg)
+
+
+def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: float, dt: float,
+              nt: int) -> stride_grid_t:
+    g = stride_grid_t()
+    nd = len(shape)
+    sp = (float(spacing),) * nd if np.isscalar(spacing) else tuple(float(s) for s in spacing)
+    g.ndim = nd
+    g.space_order = int(space_order)
+    g.sponge_cells = int(nb)
+    g.nt = int(nt)
+    for a in range(3):
+        g.shape[a] = int(shape[a]) if a < nd else 1
+        g.spacing[a] = sp[a] if a < nd else 1.0
+    g.sponge_vref = float(vref)
+    g.dt = float(dt)
+    return g
+
+
+def _coords(xyz, ndim) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, ndim))
+    return a
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream(stream) -> ctypes.c_void_p:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, shape=None, dtype=None, name="tensor"):
+    """Device pointer of a contiguous CUDA tensor after checking it."""
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise StrideError(STRIDE_E_INVALID_ARG, f"{name} must be a CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise StrideError(STRIDE_E_INVALID_ARG, f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise StrideError(STRIDE_E_INVALID_ARG, f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise StrideError(STRIDE_E_INVALID_ARG, f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------- C-ABI mirrors
+
+def stride_plan_create(grid: stride_grid_t, src_xyz, rec_xyz) -> ctypes.c_void_p:
+    src = _coords(src_xyz, grid.ndim)
+    rec = _coords(rec_xyz, grid.ndim)
+    out = ctypes.c_void_p()
+    _check(lib().stride_plan_create(ctypes.byref(grid), src.shape[0], _dp(src), rec.shape[0],
+                                    _dp(rec), ctypes.byref(out)))
+    return out
+
+
+def stride_plan_destroy(plan) -> None:
+    _check(lib().stride_plan_destroy(plan))
+
+
+def stride_plan_padded_shape(plan):
+    out = (ctypes.c_int64 * 3)()
+    _check(lib().stride_plan_padded_shape(plan, out))
+    return tuple(out)
+
+
+def stride_workspace_bytes(plan, mode: int, budget_bytes: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().stride_workspace_bytes(plan, mode, budget_bytes, ctypes.byref(out)))
+    return int(out.value)
+
+
+def stride_workspace_query(grid: stride_grid_t, nsrc: int, nrec: int, mode: int,
+                           budget_bytes: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().stride_workspace_query(ctypes.byref(grid), nsrc, nrec, mode, budget_bytes,
+                                        ctypes.byref(out)))
+    return int(out.value)
+
+
+def stride_schedule_info(nt: int, fields: int):
+    s = ctypes.c_int32()
+    f = ctypes.c_int64()
+    p = ctypes.c_int32()
+    _check(lib().stride_schedule_info(nt, fields, ctypes.byref(s), ctypes.byref(f), ctypes.byref(p)))
+    return int(s.value), int(f.value), int(p.value)
+
+
+def stride_plan_forward(plan, vp, wavelet, traces, ws, stream=None):
+    _check(lib().stride_plan_forward(plan, _dev(vp), _dev(wavelet), _dev(traces), _dev(ws),
+                                     ws.numel(), _stream(stream)))
+
+
+def stride_forward_save(plan, vp, wavelet, traces, ws, stream=None):
+    _check(lib().stride_forward_save(plan, _dev(vp), _dev(wavelet), _dev(traces), _dev(ws),
+                                     ws.numel(), _stream(stream)))
+
+
+def stride_backward(plan, vp, wavelet, grad_traces, dvp, dwavelet, ws, stream=None):
+    _check(lib().stride_backward(plan, _dev(vp), _dev(wavelet), _dev(grad_traces), _dev(dvp),
+                                 _dev(dwavelet), _dev(ws), ws.numel(), _stream(stream)))
+
+
+def stride_plan_gradient(plan, vp, wavelet, observed, traces, misfit, dvp, ws, stream=None):
+    _check(lib().stride_plan_gradient(plan, _dev(vp), _dev(wavelet), _dev(observed), _dev(traces),
+                                      _dev(misfit), _dev(dvp), _dev(ws), ws.numel(), _stream(stream)))
+
+
+def stride_forward(grid: stride_grid_t, vp, wavelet, src_xyz, rec_xyz, traces, ws, stream=None):
+    src = _coords(src_xyz, grid.ndim)
+    rec = _coords(rec_xyz, grid.ndim)
+    _check(lib().stride_forward(ctypes.byref(grid), _dev(vp), _dev(wavelet), src.shape[0], _dp(src),
+                                rec.shape[0], _dp(rec), _dev(traces), _dev(ws), ws.numel(),
+                                _stream(stream)))
+
+
+def stride_gradient(grid: stride_grid_t, vp, wavelet, src_xyz, rec_xyz, observed, misfit, dvp, ws,
+                    stream=None):
+    src = _coords(src_xyz, grid.ndim)
+    rec = _coords(rec_xyz, grid.ndim)
+    _check(lib().stride_gradient(ctypes.byref(grid), _dev(vp), _dev(wavelet), src.shape[0], _dp(src),
+                                 rec.shape[0], _dp(rec), _dev(observed), _dev(misfit), _dev(dvp),
+                                 _dev(ws), ws.numel(), _stream(stream)))
+
+
+# ------------------------------------------------------------- Plan object
+
+class Plan:
+    """A validated grid + shot geometry with its tap tables on the current device."""
+
+    def __init__(self, shape, spacing, space_order, nb, vref, dt, nt, src_xyz, rec_xyz):
+        self.grid = make_grid(shape, spacing, space_order, nb, vref, dt, nt)
+        self.shape = tuple(int(s) for s in shape)
+        self.ndim = len(self.shape)
+        self.nt = int(nt)
+        self.src_xyz = _coords(src_xyz, self.ndim)
+        self.rec_xyz = _coords(rec_xyz, self.ndim)
+        self.nsrc = self.src_xyz.shape[0]
+        self.nrec = self.rec_xyz.shape[0]
+        self.handle = stride_plan_create(self.grid, self.src_xyz, self.rec_xyz)
+
+    @classmethod
+    def from_workload(cls, w, src_xyz=None, rec_xyz=None, nt=None):
+        return cls(w.shape, w.spacing, w.space_order, w.nb, w.vref, w.dt,
+                   w.nt if nt is None else nt,
+                   w.src_xyz if src_xyz is None else src_xyz,
+                   w.rec_xyz if rec_xyz is None else rec_xyz)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            try:
+                lib().stride_plan_destroy(h)
+            except Exception:
+                pass
+            self.handle = None
+
+    @property
+    def padded_shape(self):
+        return stride_plan_padded_shape(self.handle)[: self.ndim]
+
+    def workspace_bytes(self, mode: int, budget_bytes: int = 0) -> int:
+        return stride_workspace_bytes(self.handle, mode, budget_bytes)
+
+    def workspace(self, mode: int, budget_bytes: int = 0, device=None):
+        import torch
+        n = self.workspace_bytes(mode, budget_bytes)
+        return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+    # tensor checks ------------------------------------------------------
+    def _vp(self, vp):
+        import torch
+        _dev(vp, self.shape, torch.float32, "vp")
+
+    def _traces_like(self, t, name):
+        import torch
+        _dev(t, (self.nrec, self.nt), torch.float32, name)
+
+    def _wavelet(self, w):
+        import torch
+        _dev(w, (self.nsrc, self.nt), torch.float32, "wavelet")
+
+    # solves --------------------------------------------------------------
+    def forward(self, vp, wavelet, traces=None, ws=None, stream=None):
+        import torch
+        self._vp(vp)
+        self._wavelet(wavelet)
+        if traces is None:
+            traces = torch.empty((self.nrec, self.nt), dtype=torch.float32, device=vp.device)
+        self._traces_like(traces, "traces")
+        if ws is None:
+            ws = self.workspace(STRIDE_MODE_FORWARD, device=vp.device)
+        stride_plan_forward(self.handle, vp, wavelet, traces, ws, stream)
+        return traces
+
+    def gradient(self, vp, wavelet, observed, ws=None, budget_bytes: int = 0, traces=None,
+                 stream=None):
+        """(misfit [1] float64, dvp) for J = 1/2 sum (traces - observed)^2."""
+        import torch
+        self._vp(vp)
+        self._wavelet(wavelet)
+        self._traces_like(observed, "observed")
+        if traces is not None:
+            self._traces_like(traces, "traces")
+        if ws is None:
+            ws = self.workspace(STRIDE_MODE_GRADIENT, budget_bytes, device=vp.device)
+        misfit = torch.zeros(1, dtype=torch.float64, device=vp.device)
+        dvp = torch.empty_like(vp)
+        stride_plan_gradient(self.handle, vp, wavelet, observed, traces, misfit, dvp, ws, stream)
+        return misfit, dvp
+
+    def forward_save(self, vp, wavelet, ws, traces=None, stream=None):
+        import torch
+        self._vp(vp)
+        self._wavelet(wavelet)
+        if traces is None:
+            traces = torch.empty((self.nrec, self.nt), dtype=torch.float32, device=vp.device)
+        stride_forward_save(self.handle, vp, wavelet, traces, ws, stream)
+        return traces
+
+    def backward(self, vp, wavelet, grad_traces, ws, want_dwavelet=False, stream=None):
+        import torch
+        self._vp(vp)
+        self._wavelet(wavelet)
+        self._traces_like(grad_traces, "grad_traces")
+        dvp = torch.empty_like(vp)
+        dwav = torch.empty_like(wavelet) if want_dwavelet else None
+        stride_backward(self.handle, vp, wavelet, grad_traces, dvp, dwav, ws, stream)
+        return dvp, dwav

@@ -1,0 +1,98 @@
+// Internal definitions shared by the host code and the HIP kernels of the
+// acoustic FWI library (not part of the public C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace stride {
+
+constexpr int kMaxR = 5;        // stencil radius (10th order)
+constexpr int kThreads = 256;   // 4 wave64 per block
+constexpr int kTileX = 64;      // contiguous axis: one wave64 spans a tile row
+constexpr int kTileY = 16;      // rows per tile: 4 waves x 4 rows per thread
+constexpr int kRowsPerThread = 4;
+constexpr int kMaxTaps = 8;
+
+// Padded grid as laid out in the workspace.  Axis nd-1 is contiguous.
+// 2D: axis 0 = rows, axis 1 = columns.  3D: axis 0 is the marching axis.
+struct Dims {
+    int nd;
+    int n[3];          // padded extent per axis (unused axes = 1)
+    int phys[3];       // physical extent
+    int nb;            // sponge cells per side
+    long long st[3];   // element strides; st[nd-1] = 1
+    long long total;   // elements in one field (with row pitch)
+};
+
+// Laplacian weights already divided by dx_axis^2 (rounded once from FP64);
+// c0 is the summed centre weight over all axes.
+struct StencilCoef {
+    float c0;
+    float c[3][kMaxR + 1];
+};
+
+// Sponge: eta = sum_axes e[a] * depth_a^2, e[a] = eta_max_a / nb^2.
+struct SpongeCoef {
+    float e[3];
+    float half_dt;
+};
+
+// Per-tile list of grid points that receive an injected signal: entries of
+// tile t are [tile_ptr[t], tile_ptr[t+1]); entry e adds w[e] * sig[id[e]][step]
+// at linear index pidx[e].
+struct TileTable {
+    const int* tile_ptr;
+    const long long* pidx;
+    const int* id;
+    const float* w;
+};
+
+// Point sampling: out[r * out_stride + step] = sum_t w[r*8+t] * field[idx[r*8+t]].
+struct SampleSet {
+    int count;
+    const long long* idx;
+    const float* w;
+    float* out;
+    int out_stride;
+};
+
+struct StepParams {
+    const float* A;   // stencil field: u^n (forward) or w^{m+1} (adjoint)
+    const float* B;   // u^{n-1} or w^{m+2}
+    float* C;         // result; may alias B
+    const float* K;   // dt^2 vp^2
+    const float* U;   // adjoint only: forward field u^m (second stencil)
+    float* G;         // adjoint only: imaging accumulator
+    int step;         // time index of the injected / sampled signals
+    TileTable inj;    // injection into C: sources (forward), receivers (adjoint)
+    const float* inj_sig;
+    int inj_stride;
+    TileTable img;    // adjoint only: source term S^m of the imaging condition
+    const float* img_sig;
+    int img_stride;
+    SampleSet smp;    // sampling of A at `step`
+};
+
+struct LaunchShape {
+    int tiles_x, tiles_y, tiles_xy;
+    int zc, nzc;          // 3D: planes per block and number of z chunks
+    int tile_blocks;      // logical tile blocks (before XCD padding)
+    int tile_blocks_pad;  // rounded up to a multiple of 8 XCDs
+};
+
+// Kernel launchers (stride_kernels.hip).
+void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
+                 const LaunchShape& ls, const StepParams& p, hipStream_t s);
+void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
+void launch_fill(float* p, long long n, float v, hipStream_t s);
+void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s);
+void launch_residual_misfit(const float* traces, const float* observed, float* residual,
+                            long long n, double* misfit, hipStream_t s);
+void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, hipStream_t s);
+void launch_copy(float* dst, const float* src, long long n, hipStream_t s);
+// flags[0] = bits of max(vp) (vp > 0), flags[1] = 1 if any vp <= 0 or non-finite.
+void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s);
+
+}  // namespace stride

@@ -1,0 +1,966 @@
+// Host side of the acoustic FWI library: plan construction (validation,
+// bi/tri-linear taps, per-tile injection tables), workspace layout, the
+// forward and adjoint time loops, binomial checkpointing over a pool of
+// wavefields, and the exported C ABI (include/stride_hip.h).
+#include "../../include/stride_hip.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+#include "revolve.h"
+
+using namespace stride;
+
+struct stride_plan {
+    stride_grid_t g;
+    int nd, R, nb, nt;
+    Dims dims;
+    StencilCoef cf;
+    SpongeCoef sp;
+    LaunchShape ls_fwd, ls_adj;
+    double nyquist;      // -(c0 + 2 sum_j cj (-1)^j): largest eigenvalue of -L per axis
+    double cellvol;
+    int nsrc, nrec;
+    int device;
+    void* blob;          // device memory of the tables below
+    TileTable src_inj;   // sources, weights / cell volume
+    TileTable rec_inj;   // receivers (adjoint injection), weights
+    const long long* rec_idx;
+    const float* rec_w;  // receiver sampling
+    const long long* src_idx;
+    const float* src_w;  // source sampling (adjoint w.r.t. the wavelet), weights / cell volume
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(STRIDE_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
+
+int env_int(const char* name, int dflt)
+{
+    const char* s = getenv(name);
+    return s && *s ? atoi(s) : dflt;
+}
+
+// Central second-derivative weights of the (2r+1)-point stencil, as exact
+// rationals (unique solution of the Taylor moment conditions).
+bool fd_weights(int order, double* c)
+{
+    if (order == 8) {
+        const double w[] = {-205.0 / 72.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
+        std::memcpy(c, w, sizeof(w));
+        return true;
+    }
+    if (order == 10) {
+        const double w[] = {-5269.0 / 1800.0, 5.0 / 3.0, -5.0 / 21.0, 5.0 / 126.0, -5.0 / 1008.0,
+                            1.0 / 3150.0};
+        std::memcpy(c, w, sizeof(w));
+        return true;
+    }
+    return false;
+}
+
+LaunchShape make_shape(const Dims& d, int zc)
+{
+    LaunchShape ls{};
+    int nx = d.n[d.nd - 1], ny = d.n[d.nd - 2];
+    ls.tiles_x = (nx + kTileX - 1) / kTileX;
+    ls.tiles_y = (ny + kTileY - 1) / kTileY;
+    ls.tiles_xy = ls.tiles_x * ls.tiles_y;
+    if (d.nd == 3) {
+        ls.zc = std::max(1, std::min(zc, d.n[0]));
+        ls.nzc = (d.n[0] + ls.zc - 1) / ls.zc;
+    } else {
+        ls.zc = 1;
+        ls.nzc = 1;
+    }
+    ls.tile_blocks = ls.tiles_xy * ls.nzc;
+    ls.tile_blocks_pad = (int)round_up(ls.tile_blocks, 8);
+    return ls;
+}
+
+// Planes per 3D block: enough blocks to fill 256 CUs several times over, but
+// long enough marches that the 2R lead-in planes stay a small overhead.
+int default_zc(const Dims& d, int R)
+{
+    if (d.nd != 3)
+        return 1;
+    int want = env_int("STRIDE_ZC", 0);
+    if (want > 0)
+        return want;
+    int tiles = ((d.n[2] + kTileX - 1) / kTileX) * ((d.n[1] + kTileY - 1) / kTileY);
+    int target_blocks = 1024;
+    int nzc = std::max(1, (target_blocks + tiles - 1) / tiles);
+    int zc = (d.n[0] + nzc - 1) / nzc;
+    return std::max(zc, 4 * R);
+}
+
+struct Tap {
+    long long idx[kMaxTaps];
+    double w[kMaxTaps];
+    int coord[kMaxTaps][3];
+};
+
+// Bi/tri-linear taps of a physical coordinate (metres from physical node 0).
+int make_taps(const stride_plan& P, const double* xyz, int count, std::vector<Tap>& out,
+              const char* what)
+{
+    out.resize(count);
+    for (int p = 0; p < count; ++p) {
+        int lo[3] = {0, 0, 0};
+        double fr[3] = {0, 0, 0};
+        for (int a = 0; a < P.nd; ++a) {
+            double x = xyz[(size_t)p * P.nd + a];
+            double dx = P.g.spacing[a];
+            double xmax = (double)(P.g.shape[a] - 1) * dx;
+            double tol = 1e-9 * dx;
+            if (!(x >= -tol && x <= xmax + tol))
+                return fail(STRIDE_E_GEOMETRY,
+                            "%s %d: coordinate %g on axis %d is outside the physical grid [0, %g]",
+                            what, p, x, a, xmax);
+            double gx = x / dx + (double)P.nb;
+            long long i = (long long)std::floor(gx);
+            i = std::min<long long>(std::max<long long>(i, 0), P.dims.n[a] - 2);
+            double f = gx - (double)i;
+            if (std::fabs(f) < 1e-9)
+                f = 0.0;
+            if (std::fabs(1.0 - f) < 1e-9)
+                f = 1.0;
+            lo[a] = (int)i;
+            fr[a] = f;
+        }
+        Tap& T = out[p];
+        for (int t = 0; t < kMaxTaps; ++t) {
+            T.idx[t] = 0;
+            T.w[t] = 0.0;
+            T.coord[t][0] = T.coord[t][1] = T.coord[t][2] = 0;
+        }
+        int ntap = 1 << P.nd;
+        for (int t = 0; t < ntap; ++t) {
+            long long lin = 0;
+            double w = 1.0;
+            for (int a = 0; a < P.nd; ++a) {
+                int bit = (t >> a) & 1;
+                int c = lo[a] + bit;
+                T.coord[t][a] = c;
+                lin += (long long)c * P.dims.st[a];
+                w *= bit ? fr[a] : 1.0 - fr[a];
+            }
+            T.idx[t] = lin;
+            T.w[t] = w;
+        }
+    }
+    return STRIDE_OK;
+}
+
+int tile_of(const stride_plan& P, const int* c)
+{
+    int x = c[P.nd - 1], y = c[P.nd - 2];
+    return (y / kTileY) * P.ls_fwd.tiles_x + x / kTileX;
+}
+
+struct HostTable {
+    std::vector<int> ptr;
+    std::vector<long long> pidx;
+    std::vector<int> id;
+    std::vector<float> w;
+};
+
+// Per-tile injection entries, grouped by tile in (point, tap) order so that the
+// summation order inside the kernel is fixed.
+HostTable build_table(const stride_plan& P, const std::vector<Tap>& taps, double scale)
+{
+    HostTable T;
+    int ntiles = P.ls_fwd.tiles_xy;
+    std::vector<std::vector<std::pair<long long, std::pair<int, float>>>> per(ntiles);
+    int ntap = 1 << P.nd;
+    for (size_t p = 0; p < taps.size(); ++p)
+        for (int t = 0; t < ntap; ++t) {
+            if (taps[p].w[t] == 0.0)
+                continue;
+            int tile = tile_of(P, taps[p].coord[t]);
+            per[tile].push_back({taps[p].idx[t], {(int)p, (float)(taps[p].w[t] * scale)}});
+        }
+    T.ptr.resize(ntiles + 1, 0);
+    for (int t = 0; t < ntiles; ++t) {
+        T.ptr[t + 1] = T.ptr[t] + (int)per[t].size();
+        for (auto& e : per[t]) {
+            T.pidx.push_back(e.first);
+            T.id.push_back(e.second.first);
+            T.w.push_back(e.second.second);
+        }
+    }
+    return T;
+}
+
+void flatten_sample(const std::vector<Tap>& taps, double scale, std::vector<long long>& idx,
+                    std::vector<float>& w)
+{
+    idx.assign(taps.size() * kMaxTaps, 0);
+    w.assign(taps.size() * kMaxTaps, 0.f);
+    for (size_t p = 0; p < taps.size(); ++p)
+        for (int t = 0; t < kMaxTaps; ++t) {
+            idx[p * kMaxTaps + t] = taps[p].idx[t];
+            w[p * kMaxTaps + t] = (float)(taps[p].w[t] * scale);
+        }
+}
+
+int validate_grid(const stride_grid_t* g)
+{
+    if (!g)
+        return fail(STRIDE_E_INVALID_ARG, "grid is NULL");
+    if (g->ndim != 2 && g->ndim != 3)
+        return fail(STRIDE_E_INVALID_ARG, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->space_order != 8 && g->space_order != 10)
+        return fail(STRIDE_E_INVALID_ARG, "space_order must be 8 or 10 (got %d)", g->space_order);
+    if (g->sponge_cells < 0)
+        return fail(STRIDE_E_INVALID_ARG, "sponge_cells must be >= 0");
+    if (g->nt < 2)
+        return fail(STRIDE_E_INVALID_ARG, "nt must be >= 2 (got %d)", g->nt);
+    if (!(g->dt > 0) || !std::isfinite(g->dt))
+        return fail(STRIDE_E_INVALID_ARG, "dt must be positive");
+    if (!(g->sponge_vref >= 0) || !std::isfinite(g->sponge_vref))
+        return fail(STRIDE_E_INVALID_ARG, "sponge_vref must be >= 0");
+    long long total = 1;
+    for (int a = 0; a < g->ndim; ++a) {
+        if (g->shape[a] < 2)
+            return fail(STRIDE_E_INVALID_ARG, "shape[%d] must be >= 2", a);
+        if (!(g->spacing[a] > 0) || !std::isfinite(g->spacing[a]))
+            return fail(STRIDE_E_INVALID_ARG, "spacing[%d] must be positive", a);
+        long long np = g->shape[a] + 2LL * g->sponge_cells;
+        if (np > (1 << 30))
+            return fail(STRIDE_E_INVALID_ARG, "padded axis %d too large", a);
+        total *= np;
+    }
+    if (total > (1LL << 40))
+        return fail(STRIDE_E_INVALID_ARG, "grid too large");
+    return STRIDE_OK;
+}
+
+// ------------------------------------------------------------ workspace
+
+struct Layout {
+    size_t field;      // bytes per wavefield
+    size_t scratch;    // small scalars
+    size_t traces;     // nrec * nt floats
+    size_t fixed_fwd;  // scratch + k + 2 fields
+    size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual
+};
+
+Layout layout_of(const stride_plan& P)
+{
+    Layout L;
+    L.field = (size_t)round_up(P.dims.total * 4, 256);
+    L.scratch = 256;
+    L.traces = (size_t)round_up((long long)P.nrec * P.nt * 4, 256);
+    L.fixed_fwd = L.scratch + 3 * L.field;
+    L.fixed_grad = L.scratch + 4 * L.field + 2 * L.traces;
+    return L;
+}
+
+struct GradWs {
+    unsigned* flags;   // [0] = max vp bits, [1] = bad-value flag
+    float* k;
+    float* G;
+    float* w[2];
+    float* traces;
+    float* residual;
+    std::vector<float*> pool;
+    int snaps;
+};
+
+int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
+{
+    Layout L = layout_of(P);
+    if (!ws)
+        return fail(STRIDE_E_INVALID_ARG, "workspace is NULL");
+    if ((uintptr_t)ws % 256)
+        return fail(STRIDE_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (bytes < L.fixed_grad + 4 * L.field)
+        return fail(STRIDE_E_WORKSPACE, "gradient workspace needs at least %zu bytes (got %zu)",
+                    L.fixed_grad + 4 * L.field, bytes);
+    long long nfields = (long long)((bytes - L.fixed_grad) / L.field);
+    int s = snaps_for_fields(P.nt, nfields);
+    if (s < 0)
+        return fail(STRIDE_E_WORKSPACE, "workspace too small for checkpointing");
+    ScheduleStats st = cached_schedule(P.nt, s)->stats;
+    char* b = (char*)ws;
+    W.flags = (unsigned*)b;
+    b += L.scratch;
+    W.k = (float*)b;
+    b += L.field;
+    W.G = (float*)b;
+    b += L.field;
+    W.w[0] = (float*)b;
+    b += L.field;
+    W.w[1] = (float*)b;
+    b += L.field;
+    W.traces = (float*)b;
+    b += L.traces;
+    W.residual = (float*)b;
+    b += L.traces;
+    W.pool.clear();
+    for (int f = 0; f < st.peak_fields; ++f) {
+        W.pool.push_back((float*)b);
+        b += L.field;
+    }
+    W.snaps = s;
+    return STRIDE_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Reads max(vp) and a bad-value flag back from the device (one stream sync)
+// and applies the leapfrog stability bound.
+int check_vp(const stride_plan& P, const float* vp, unsigned* flags, hipStream_t s)
+{
+    long long n = 1;
+    for (int a = 0; a < P.nd; ++a)
+        n *= P.g.shape[a];
+    launch_vp_check(vp, n, flags, s);
+    unsigned host[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(host, flags, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (host[1])
+        return fail(STRIDE_E_INVALID_ARG, "vp contains non-positive or non-finite values");
+    float vmax;
+    std::memcpy(&vmax, &host[0], sizeof(float));
+    double inv2 = 0;
+    for (int a = 0; a < P.nd; ++a)
+        inv2 += 1.0 / (P.g.spacing[a] * P.g.spacing[a]);
+    double courant = P.g.dt * vmax * std::sqrt(P.nyquist * inv2);
+    if (courant > 2.0)
+        return fail(STRIDE_E_CFL,
+                    "dt %g with vp_max %g violates the leapfrog stability limit "
+                    "(dt vp sqrt(lambda sum 1/dx^2) = %.4f > 2)",
+                    P.g.dt, (double)vmax, courant);
+    return STRIDE_OK;
+}
+
+StepParams base_params(const stride_plan& P)
+{
+    StepParams p{};
+    p.inj = P.src_inj;
+    p.inj_stride = P.nt;
+    p.img = P.src_inj;
+    p.img_stride = P.nt;
+    return p;
+}
+
+// ------------------------------------------------------------ executors
+
+// Replays a checkpointing schedule over the wavefield pool.  forward_phase
+// runs the forward sweep up to the first reverse operation (sampling traces on
+// every step, since the first descent visits each index once); called with
+// run = false it only replays the bookkeeping, which stride_backward uses to
+// find the pool state the forward sweep left behind.  backward_phase then
+// runs the recomputation and adjoint steps.
+struct Runner {
+    const stride_plan& P;
+    GradWs& W;
+    hipStream_t s;
+    const float* wavelet;
+    std::vector<int> ref;
+    std::vector<int> freelist;
+    std::unordered_map<int, std::pair<int, int>> snaps;
+    int cur = 0, prev = 1, idx = 0;
+    std::shared_ptr<const CachedSchedule> cs;
+    const std::vector<Action>& sched;
+    size_t pc = 0;
+
+    Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
+        : P(p), W(w), s(st), wavelet(wav), cs(cached_schedule(p.nt, w.snaps)), sched(cs->actions)
+    {
+        ref.assign(W.pool.size(), 0);
+        for (int f = (int)W.pool.size() - 1; f >= 2; --f)
+            freelist.push_back(f);
+        ref[0] = ref[1] = 1;
+    }
+
+    bool overflow = false;   // the schedule needed more fields than the pool holds
+
+    int alloc()
+    {
+        if (freelist.empty()) {
+            overflow = true;
+            return -1;
+        }
+        int f = freelist.back();
+        freelist.pop_back();
+        ref[f] = 1;
+        return f;
+    }
+    void release(int f)
+    {
+        if (--ref[f] == 0)
+            freelist.push_back(f);
+    }
+
+    void fwd_step(bool run, float* traces)
+    {
+        int old_prev = prev;
+        int out;
+        if (ref[prev] == 1) {
+            out = prev;
+        } else {
+            out = alloc();
+            if (out < 0)
+                return;
+        }
+        if (run) {
+            StepParams p = base_params(P);
+            p.A = W.pool[cur];
+            p.B = W.pool[old_prev];
+            p.C = W.pool[out];
+            p.K = W.k;
+            p.step = idx;
+            p.inj_sig = wavelet;
+            if (traces)
+                p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+            launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
+        }
+        if (out != old_prev)
+            release(old_prev);
+        prev = cur;
+        cur = out;
+        ++idx;
+    }
+
+    // Executes actions until the first Reverse (phase 0) or to the end
+    // (phase 1).  `run` false replays bookkeeping only.
+    void forward_phase(bool run, float* traces)
+    {
+        for (; pc < sched.size() && !overflow; ++pc) {
+            const Action& a = sched[pc];
+            if (a.type == Act::Reverse)
+                return;
+            apply_bookkeeping(a, run, traces);
+        }
+    }
+
+    void apply_bookkeeping(const Action& a, bool run, float* traces)
+    {
+        switch (a.type) {
+        case Act::Advance:
+            while (idx < a.step && !overflow)
+                fwd_step(run, traces);
+            break;
+        case Act::Store:
+            snaps[a.step] = {cur, prev};
+            ++ref[cur];
+            ++ref[prev];
+            break;
+        case Act::Free: {
+            auto it = snaps.find(a.step);
+            release(it->second.first);
+            release(it->second.second);
+            snaps.erase(it);
+            break;
+        }
+        case Act::Restore: {
+            auto it = snaps.find(a.step);
+            release(cur);
+            release(prev);
+            cur = it->second.first;
+            prev = it->second.second;
+            ++ref[cur];
+            ++ref[prev];
+            idx = a.step;
+            break;
+        }
+        case Act::Reverse:
+            break;
+        }
+    }
+
+    // Phase 1: recomputation and adjoint steps.
+    void backward_phase(const float* grad_traces, float* dwavelet)
+    {
+        int wa = 0;   // W.w[wa] = w^{m+1}, W.w[1-wa] = w^{m+2}
+        for (; pc < sched.size() && !overflow; ++pc) {
+            const Action& a = sched[pc];
+            if (a.type != Act::Reverse) {
+                apply_bookkeeping(a, true, nullptr);
+                continue;
+            }
+            int m = a.step;
+            StepParams p = base_params(P);
+            p.A = W.w[wa];
+            p.B = W.w[1 - wa];
+            p.C = W.w[1 - wa];
+            p.K = W.k;
+            p.U = W.pool[cur];
+            p.G = W.G;
+            p.step = m;
+            p.inj = P.rec_inj;
+            p.inj_sig = grad_traces;
+            p.inj_stride = P.nt;
+            p.img = P.src_inj;
+            p.img_sig = wavelet;
+            p.img_stride = P.nt;
+            if (dwavelet)
+                p.smp = SampleSet{P.nsrc, P.src_idx, P.src_w, dwavelet, P.nt};
+            launch_step(P.dims, P.R, true, P.cf, P.sp, P.ls_adj, p, s);
+            wa = 1 - wa;
+        }
+    }
+};
+
+int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
+                  void* ws, size_t bytes, hipStream_t s)
+{
+    Layout L = layout_of(P);
+    if (!vp || !wavelet || !traces)
+        return fail(STRIDE_E_INVALID_ARG, "vp, wavelet and traces must be device pointers");
+    if (!ws || (uintptr_t)ws % 256)
+        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.fixed_fwd)
+        return fail(STRIDE_E_WORKSPACE, "forward workspace needs %zu bytes (got %zu)", L.fixed_fwd,
+                    bytes);
+    char* b = (char*)ws;
+    unsigned* flags = (unsigned*)b;
+    float* k = (float*)(b + L.scratch);
+    float* u[2] = {(float*)(b + L.scratch + L.field), (float*)(b + L.scratch + 2 * L.field)};
+    int rc = check_vp(P, vp, flags, s);
+    if (rc)
+        return rc;
+    launch_prep_k(P.dims, vp, P.g.dt, k, s);
+    launch_fill(u[0], P.dims.total, 0.f, s);
+    launch_fill(u[1], P.dims.total, 0.f, s);
+    int cur = 0;
+    for (int n = 0; n < P.nt - 1; ++n) {
+        StepParams p = base_params(P);
+        p.A = u[cur];
+        p.B = u[1 - cur];
+        p.C = u[1 - cur];
+        p.K = k;
+        p.step = n;
+        p.inj_sig = wavelet;
+        p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+        launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
+        cur = 1 - cur;
+    }
+    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
+    HIP_TRY(hipGetLastError());
+    return STRIDE_OK;
+}
+
+int forward_save(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
+                 void* ws, size_t bytes, hipStream_t s, GradWs& W)
+{
+    if (!vp || !wavelet)
+        return fail(STRIDE_E_INVALID_ARG, "vp and wavelet must be device pointers");
+    int rc = grad_ws(P, ws, bytes, W);
+    if (rc)
+        return rc;
+    rc = check_vp(P, vp, W.flags, s);
+    if (rc)
+        return rc;
+    float* tr = traces ? traces : W.traces;
+    launch_prep_k(P.dims, vp, P.g.dt, W.k, s);
+    launch_fill(W.pool[0], P.dims.total, 0.f, s);
+    launch_fill(W.pool[1], P.dims.total, 0.f, s);
+    Runner run(P, W, s, wavelet);
+    run.forward_phase(true, tr);
+    if (run.overflow)
+        return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
+    // last sample from the final state x_{nt-1}
+    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, tr, P.nt}, W.pool[run.cur], P.nt - 1, s);
+    if (traces && traces != W.traces)
+        launch_copy(W.traces, traces, (long long)P.nrec * P.nt, s);
+    HIP_TRY(hipGetLastError());
+    return STRIDE_OK;
+}
+
+int backward(const stride_plan& P, const float* vp, const float* wavelet, const float* grad_traces,
+             float* dvp, float* dwavelet, void* ws, size_t bytes, hipStream_t s)
+{
+    if (!vp || !wavelet || !grad_traces || !dvp)
+        return fail(STRIDE_E_INVALID_ARG, "vp, wavelet, grad_traces and dvp must be device pointers");
+    GradWs W;
+    int rc = grad_ws(P, ws, bytes, W);
+    if (rc)
+        return rc;
+    Runner run(P, W, s, wavelet);
+    run.forward_phase(false, nullptr);
+    launch_fill(W.G, P.dims.total, 0.f, s);
+    launch_fill(W.w[0], P.dims.total, 0.f, s);
+    launch_fill(W.w[1], P.dims.total, 0.f, s);
+    run.backward_phase(grad_traces, dwavelet);
+    if (run.overflow)
+        return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
+    launch_finalize_dvp(P.dims, W.G, vp, dvp, s);
+    HIP_TRY(hipGetLastError());
+    return STRIDE_OK;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+}  // namespace
+
+// ============================================================== C ABI
+
+extern "C" {
+
+const char* stride_last_error(void) { return g_err.c_str(); }
+
+const char* stride_error_string(int code)
+{
+    switch (code) {
+    case STRIDE_OK: return "ok";
+    case STRIDE_E_INVALID_ARG: return "invalid argument";
+    case STRIDE_E_CFL: return "CFL stability limit violated";
+    case STRIDE_E_GEOMETRY: return "source or receiver outside the physical grid";
+    case STRIDE_E_WORKSPACE: return "workspace too small";
+    case STRIDE_E_HIP: return "HIP runtime error";
+    case STRIDE_E_NONFINITE: return "non-finite values";
+    default: return "unknown error";
+    }
+}
+
+int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* src_xyz,
+                       int32_t nrec, const double* rec_xyz, stride_plan_t** out)
+{
+    g_err.clear();
+    if (!out)
+        return fail(STRIDE_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = validate_grid(grid);
+    if (rc)
+        return rc;
+    if (nsrc < 0 || nrec < 0 || (nsrc > 0 && !src_xyz) || (nrec > 0 && !rec_xyz))
+        return fail(STRIDE_E_INVALID_ARG, "bad source/receiver arrays");
+    stride_plan* P = new stride_plan();
+    P->g = *grid;
+    P->nd = grid->ndim;
+    P->R = grid->space_order / 2;
+    P->nb = grid->sponge_cells;
+    P->nt = grid->nt;
+    P->nsrc = nsrc;
+    P->nrec = nrec;
+    P->blob = nullptr;
+
+    Dims& d = P->dims;
+    d.nd = P->nd;
+    for (int a = 0; a < 3; ++a) {
+        d.n[a] = a < P->nd ? (int)(grid->shape[a] + 2LL * P->nb) : 1;
+        d.phys[a] = a < P->nd ? (int)grid->shape[a] : 1;
+    }
+    d.nb = P->nb;
+    int align = std::max(1, env_int("STRIDE_PITCH_ALIGN", 16));
+    long long pitch = round_up(d.n[P->nd - 1], align);
+    if (P->nd == 2) {
+        d.st[1] = 1;
+        d.st[0] = pitch;
+        d.st[2] = 0;
+        d.total = (long long)d.n[0] * pitch;
+    } else {
+        d.st[2] = 1;
+        d.st[1] = pitch;
+        d.st[0] = (long long)d.n[1] * pitch;
+        d.total = (long long)d.n[0] * d.st[0];
+    }
+
+    double c[kMaxR + 1] = {0};
+    fd_weights(grid->space_order, c);
+    P->nyquist = c[0];
+    for (int j = 1; j <= P->R; ++j)
+        P->nyquist += 2.0 * c[j] * ((j % 2) ? -1.0 : 1.0);
+    P->nyquist = -P->nyquist;
+    double c0 = 0;
+    P->cellvol = 1.0;
+    std::memset(&P->cf, 0, sizeof(P->cf));
+    for (int a = 0; a < P->nd; ++a) {
+        double inv = 1.0 / (grid->spacing[a] * grid->spacing[a]);
+        c0 += c[0] * inv;
+        for (int j = 1; j <= P->R; ++j)
+            P->cf.c[a][j] = (float)(c[j] * inv);
+        P->cellvol *= grid->spacing[a];
+    }
+    P->cf.c0 = (float)c0;
+    std::memset(&P->sp, 0, sizeof(P->sp));
+    if (P->nb > 0 && grid->sponge_vref > 0)
+        for (int a = 0; a < P->nd; ++a) {
+            double emax = 3.0 * grid->sponge_vref * std::log(1000.0) / ((double)P->nb * grid->spacing[a]);
+            P->sp.e[a] = (float)(emax / ((double)P->nb * P->nb));
+        }
+    P->sp.half_dt = (float)(0.5 * grid->dt);
+
+    P->ls_fwd = make_shape(d, default_zc(d, P->R));
+    P->ls_adj = make_shape(d, default_zc(d, P->R));
+
+    std::vector<Tap> st, rt;
+    if ((rc = make_taps(*P, src_xyz, nsrc, st, "source")) ||
+        (rc = make_taps(*P, rec_xyz, nrec, rt, "receiver"))) {
+        delete P;
+        return rc;
+    }
+    HostTable ts = build_table(*P, st, 1.0 / P->cellvol);
+    HostTable tr = build_table(*P, rt, 1.0);
+    std::vector<long long> ridx, sidx;
+    std::vector<float> rw, sw;
+    flatten_sample(rt, 1.0, ridx, rw);
+    flatten_sample(st, 1.0 / P->cellvol, sidx, sw);
+
+    // one device blob: [ts.ptr | tr.ptr | ts.id | tr.id] ints, [pidx..] longs, floats
+    auto bytes_of = [](size_t n, size_t sz) { return (size_t)round_up((long long)(n * sz), 256); };
+    size_t off = 0;
+    std::vector<std::pair<size_t, std::pair<const void*, size_t>>> parts;
+    auto add = [&](const void* src, size_t n, size_t sz) {
+        size_t o = off;
+        parts.push_back({o, {src, n * sz}});
+        off += bytes_of(std::max<size_t>(n, 1), sz);
+        return o;
+    };
+    size_t o_ts_ptr = add(ts.ptr.data(), ts.ptr.size(), 4);
+    size_t o_ts_pidx = add(ts.pidx.data(), ts.pidx.size(), 8);
+    size_t o_ts_id = add(ts.id.data(), ts.id.size(), 4);
+    size_t o_ts_w = add(ts.w.data(), ts.w.size(), 4);
+    size_t o_tr_ptr = add(tr.ptr.data(), tr.ptr.size(), 4);
+    size_t o_tr_pidx = add(tr.pidx.data(), tr.pidx.size(), 8);
+    size_t o_tr_id = add(tr.id.data(), tr.id.size(), 4);
+    size_t o_tr_w = add(tr.w.data(), tr.w.size(), 4);
+    size_t o_ridx = add(ridx.data(), ridx.size(), 8);
+    size_t o_rw = add(rw.data(), rw.size(), 4);
+    size_t o_sidx = add(sidx.data(), sidx.size(), 8);
+    size_t o_sw = add(sw.data(), sw.size(), 4);
+    std::vector<char> host(off, 0);
+    for (auto& pt : parts)
+        if (pt.second.second)
+            std::memcpy(host.data() + pt.first, pt.second.first, pt.second.second);
+    hipError_t e = hipGetDevice(&P->device);
+    if (e == hipSuccess)
+        e = hipMalloc(&P->blob, off);
+    if (e == hipSuccess)
+        e = hipMemcpy(P->blob, host.data(), off, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        if (P->blob)
+            (void)hipFree(P->blob);
+        delete P;
+        return fail(STRIDE_E_HIP, "plan tables: %s", hipGetErrorString(e));
+    }
+    char* B = (char*)P->blob;
+    P->src_inj = TileTable{(const int*)(B + o_ts_ptr), (const long long*)(B + o_ts_pidx),
+                           (const int*)(B + o_ts_id), (const float*)(B + o_ts_w)};
+    P->rec_inj = TileTable{(const int*)(B + o_tr_ptr), (const long long*)(B + o_tr_pidx),
+                           (const int*)(B + o_tr_id), (const float*)(B + o_tr_w)};
+    P->rec_idx = (const long long*)(B + o_ridx);
+    P->rec_w = (const float*)(B + o_rw);
+    P->src_idx = (const long long*)(B + o_sidx);
+    P->src_w = (const float*)(B + o_sw);
+    *out = P;
+    return STRIDE_OK;
+}
+
+int stride_plan_destroy(stride_plan_t* plan)
+{
+    if (!plan)
+        return STRIDE_OK;
+    if (plan->blob) {
+        hipError_t e = hipFree(plan->blob);
+        delete plan;
+        if (e != hipSuccess)
+            return fail(STRIDE_E_HIP, "hipFree: %s", hipGetErrorString(e));
+        return STRIDE_OK;
+    }
+    delete plan;
+    return STRIDE_OK;
+}
+
+int stride_plan_padded_shape(const stride_plan_t* plan, int64_t out[3])
+{
+    if (!plan || !out)
+        return fail(STRIDE_E_INVALID_ARG, "NULL argument");
+    for (int a = 0; a < 3; ++a)
+        out[a] = plan->dims.n[a];
+    return STRIDE_OK;
+}
+
+int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budget_bytes,
+                           size_t* out_bytes)
+{
+    if (!plan || !out_bytes)
+        return fail(STRIDE_E_INVALID_ARG, "NULL argument");
+    Layout L = layout_of(*plan);
+    if (mode == STRIDE_MODE_FORWARD) {
+        *out_bytes = L.fixed_fwd;
+        return STRIDE_OK;
+    }
+    if (mode != STRIDE_MODE_GRADIENT)
+        return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD or GRADIENT");
+    long long nfields;
+    if (budget_bytes == 0) {
+        nfields = cached_schedule(plan->nt, plan->nt)->stats.peak_fields;
+    } else {
+        if (budget_bytes < L.fixed_grad + 4 * L.field)
+            return fail(STRIDE_E_WORKSPACE, "budget %zu below the gradient minimum %zu", budget_bytes,
+                        L.fixed_grad + 4 * L.field);
+        long long cap = (long long)((budget_bytes - L.fixed_grad) / L.field);
+        int s = snaps_for_fields(plan->nt, cap);
+        if (s < 0)
+            return fail(STRIDE_E_WORKSPACE, "budget too small for checkpointing");
+        nfields = cached_schedule(plan->nt, s)->stats.peak_fields;
+    }
+    *out_bytes = L.fixed_grad + (size_t)nfields * L.field;
+    return STRIDE_OK;
+}
+
+int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                        float* traces, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    return forward_solve(*plan, vp, wavelet, traces, ws, ws_bytes, as_stream(stream));
+}
+
+int stride_forward_save(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                        float* traces, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    GradWs W;
+    return forward_save(*plan, vp, wavelet, traces, ws, ws_bytes, as_stream(stream), W);
+}
+
+int stride_backward(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                    const float* grad_traces, float* dvp, float* dwavelet, void* ws,
+                    size_t ws_bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    return backward(*plan, vp, wavelet, grad_traces, dvp, dwavelet, ws, ws_bytes, as_stream(stream));
+}
+
+int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                         const float* observed, float* traces, double* misfit, float* dvp,
+                         void* ws, size_t ws_bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    if (!observed || !misfit || !dvp)
+        return fail(STRIDE_E_INVALID_ARG, "observed, misfit and dvp must be device pointers");
+    hipStream_t s = as_stream(stream);
+    GradWs W;
+    int rc = forward_save(*plan, vp, wavelet, traces, ws, ws_bytes, s, W);
+    if (rc)
+        return rc;
+    launch_residual_misfit(W.traces, observed, W.residual, (long long)plan->nrec * plan->nt, misfit, s);
+    return backward(*plan, vp, wavelet, W.residual, dvp, nullptr, ws, ws_bytes, s);
+}
+
+int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec, int32_t mode,
+                           size_t budget_bytes, size_t* out_bytes)
+{
+    g_err.clear();
+    int rc = validate_grid(grid);
+    if (rc)
+        return rc;
+    if (!out_bytes || nsrc < 0 || nrec < 0)
+        return fail(STRIDE_E_INVALID_ARG, "bad arguments");
+    // the tables do not change the workspace: a geometry-free plan suffices
+    stride_plan P{};
+    P.g = *grid;
+    P.nd = grid->ndim;
+    P.nt = grid->nt;
+    P.nrec = nrec;
+    P.nb = grid->sponge_cells;
+    Dims& d = P.dims;
+    d.nd = P.nd;
+    for (int a = 0; a < 3; ++a)
+        d.n[a] = a < P.nd ? (int)(grid->shape[a] + 2LL * P.nb) : 1;
+    int align = std::max(1, env_int("STRIDE_PITCH_ALIGN", 16));
+    long long pitch = round_up(d.n[P.nd - 1], align);
+    d.total = P.nd == 2 ? (long long)d.n[0] * pitch : (long long)d.n[0] * d.n[1] * pitch;
+    return stride_workspace_bytes(&P, mode, budget_bytes, out_bytes);
+}
+
+int stride_forward(const stride_grid_t* grid, const float* vp, const float* wavelet, int32_t nsrc,
+                   const double* src_xyz, int32_t nrec, const double* rec_xyz, float* traces,
+                   void* ws, size_t ws_bytes, void* stream)
+{
+    stride_plan_t* plan = nullptr;
+    int rc = stride_plan_create(grid, nsrc, src_xyz, nrec, rec_xyz, &plan);
+    if (rc)
+        return rc;
+    rc = stride_plan_forward(plan, vp, wavelet, traces, ws, ws_bytes, stream);
+    std::string err = g_err;
+    hipError_t e = hipStreamSynchronize(as_stream(stream));
+    stride_plan_destroy(plan);
+    g_err = err;
+    if (!rc && e != hipSuccess)
+        rc = fail(STRIDE_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return rc;
+}
+
+int stride_gradient(const stride_grid_t* grid, const float* vp, const float* wavelet,
+                    int32_t nsrc, const double* src_xyz, int32_t nrec, const double* rec_xyz,
+                    const float* observed, double* misfit, float* dvp, void* ws, size_t ws_bytes,
+                    void* stream)
+{
+    stride_plan_t* plan = nullptr;
+    int rc = stride_plan_create(grid, nsrc, src_xyz, nrec, rec_xyz, &plan);
+    if (rc)
+        return rc;
+    rc = stride_plan_gradient(plan, vp, wavelet, observed, nullptr, misfit, dvp, ws, ws_bytes, stream);
+    std::string err = g_err;
+    hipError_t e = hipStreamSynchronize(as_stream(stream));
+    stride_plan_destroy(plan);
+    g_err = err;
+    if (!rc && e != hipSuccess)
+        rc = fail(STRIDE_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+    return rc;
+}
+
+int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* forward_steps,
+                         int32_t* peak_fields)
+{
+    if (nt < 1)
+        return fail(STRIDE_E_INVALID_ARG, "nt must be >= 1");
+    int s = snaps_for_fields(nt, fields);
+    if (s < 0)
+        return fail(STRIDE_E_WORKSPACE, "%lld wavefields cannot hold the checkpointing schedule",
+                    (long long)fields);
+    ScheduleStats st = cached_schedule(nt, s)->stats;
+    if (snaps)
+        *snaps = s;
+    if (forward_steps)
+        *forward_steps = st.forward_steps;
+    if (peak_fields)
+        *peak_fields = st.peak_fields;
+    return STRIDE_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports
+every function the public header declares, validates arguments before any
+launch, sizes workspaces, and builds optimal checkpointing schedules."""
+import os
+import re
+from functools import lru_cache
+
+import numpy as np
+import pytest
+
+import paper_2110_03345_amd as S
+import workloads as W
+from paper_2110_03345_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    txt = open(os.path.join(ROOT, "include", "stride_hip.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(stride_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_function():
+    L = S.lib()
+    names = _header_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_abi.EXPORTS)
+
+
+def _grid(**kw):
+    base = dict(shape=(40, 50), spacing=0.2e-3, space_order=8, nb=6, vref=1500.0,
+                dt=0.4 * 0.2e-3 / 1500, nt=20)
+    base.update(kw)
+    return S.make_grid(**base)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(space_order=6), _abi.STRIDE_E_INVALID_ARG),
+    (dict(nt=1), _abi.STRIDE_E_INVALID_ARG),
+    (dict(dt=0.0), _abi.STRIDE_E_INVALID_ARG),
+    (dict(nb=-1), _abi.STRIDE_E_INVALID_ARG),
+    (dict(shape=(1, 50)), _abi.STRIDE_E_INVALID_ARG),
+])
+def test_plan_rejects_bad_grid(kw, code):
+    with pytest.raises(S.StrideError) as e:
+        S.stride_plan_create(_grid(**kw), np.array([[1e-3, 1e-3]]), np.array([[2e-3, 2e-3]]))
+    assert e.value.code == code
+
+
+def test_plan_rejects_points_outside_the_grid():
+    g = _grid()
+    inside = np.array([[1e-3, 1e-3]])
+    for bad in ([[-1e-4, 1e-3]], [[1e-3, 49 * 0.2e-3 + 1e-6]], [[39 * 0.2e-3 + 1e-6, 0.0]]):
+        with pytest.raises(S.StrideError) as e:
+            S.stride_plan_create(g, inside, np.array(bad))
+        assert e.value.code == _abi.STRIDE_E_GEOMETRY
+        assert "outside the physical grid" in str(e.value)
+        with pytest.raises(S.StrideError) as e:
+            S.stride_plan_create(g, np.array(bad), inside)
+        assert e.value.code == _abi.STRIDE_E_GEOMETRY
+
+
+def test_workspace_sizes():
+    g = _grid(nt=50)
+    f = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_FORWARD)
+    field = -(-(52 * 64 * 4) // 256) * 256          # 52 x 62 padded, pitch 64
+    assert f == 256 + 3 * field
+    full = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT)
+    traces = -(-(3 * 50 * 4) // 256) * 256
+    fixed = 256 + 4 * field + 2 * traces
+    assert (full - fixed) % field == 0
+    assert (full - fixed) // field == 51              # every state kept: u^-1 .. u^49
+    small = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT, fixed + 10 * field)
+    assert small <= fixed + 10 * field and small < full
+    with pytest.raises(S.StrideError) as e:
+        S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT, fixed + 3 * field)
+    assert e.value.code == _abi.STRIDE_E_WORKSPACE
+
+
+@lru_cache(None)
+def _dp(l, s):
+    """Brute-force minimal forward steps to reverse l steps with s free slots."""
+    if l <= 1:
+        return 0
+    if s == 0:
+        return l * (l - 1) // 2
+    return min(m + _dp(l - m, s - 1) + _dp(m, s) for m in range(1, l))
+
+
+@pytest.mark.parametrize("nt", [2, 3, 7, 20, 41, 90])
+def test_schedule_is_optimal_for_its_snapshot_count(nt):
+    for fields in range(4, nt + 6):
+        snaps, steps, peak = S.stride_schedule_info(nt, fields)
+        assert peak <= fields
+        assert steps == _dp(nt, snaps), (nt, fields, snaps)
+        if fields >= nt + 2:
+            assert steps == nt - 1
+
+
+def test_schedule_large_and_monotone():
+    prev = None
+    for fields in (6, 10, 30, 100, 400):
+        snaps, steps, peak = S.stride_schedule_info(3000, fields)
+        assert peak <= fields
+        if prev is not None:
+            assert steps <= prev
+        prev = steps
+    # fewer than two forward sweeps once a few hundred wavefields fit
+    snaps, steps, _ = S.stride_schedule_info(3000, 200)
+    assert steps < 2.0 * 3000
+    with pytest.raises(S.StrideError):
+        S.stride_schedule_info(3000, 3)

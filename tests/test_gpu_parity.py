@@ -1,0 +1,156 @@
+"""HIP path vs the FP64 oracle, through the C ABI.
+
+Tolerances (relative L2 over the whole output): 1e-4 for solves of at most
+1000 steps and 1e-3 for at most 3000 steps; the FP32 kernel and the FP64
+oracle differ only by rounding, which grows with the number of steps.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2110_03345_amd as S
+
+
+def tol_for(nt):
+    return 1e-4 if nt <= 1000 else 1e-3
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _case(maker, order, **kw):
+    w = maker(space_order=order, **kw)
+    return w, oracle.Grid(**w.grid_kwargs()), S.Plan.from_workload(w)
+
+
+CASES = [
+    ("2d_o8", W.tiny_2d, 8, {}),
+    ("2d_o10", W.tiny_2d, 10, {}),
+    ("2d_o8_ragged", W.tiny_2d, 8, dict(n=(83, 141), nb=7, nt=150)),
+    ("3d_o10", W.tiny_3d, 10, {}),
+    ("3d_o8", W.tiny_3d, 8, {}),
+    ("3d_o10_ragged", W.tiny_3d, 10, dict(n=(37, 21, 70), nb=4, nt=70)),
+]
+
+
+@pytest.mark.parametrize("name,maker,order,kw", CASES, ids=[c[0] for c in CASES])
+def test_forward_matches_oracle(name, maker, order, kw):
+    w, g, plan = _case(maker, order, **kw)
+    print(f"case {name} shape={w.shape} nt={w.nt}", flush=True)
+    ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    tr = plan.forward(dev(w.vp), dev(w.wavelet)).cpu().numpy()
+    assert np.all(tr[:, 0] == 0.0)
+    assert rel(tr, ref) < tol_for(w.nt), rel(tr, ref)
+
+
+@pytest.mark.parametrize("name,maker,order,kw", CASES, ids=[c[0] for c in CASES])
+def test_gradient_matches_oracle(name, maker, order, kw):
+    w, g, plan = _case(maker, order, **kw)
+    print(f"case {name} shape={w.shape} nt={w.nt}", flush=True)
+    rng = np.random.default_rng(7)
+    obs = oracle.forward(g, w.vp * (1 + 0.02 * rng.standard_normal(w.shape).clip(-2, 2)),
+                         w.src_xyz, w.wavelet, w.rec_xyz).astype(np.float32)
+    _, J, dvp_ref = oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, obs)
+    misfit, dvp = plan.gradient(dev(w.vp), dev(w.wavelet), dev(obs))
+    assert abs(misfit.item() - J) <= tol_for(w.nt) * abs(J)
+    assert rel(dvp.cpu().numpy(), dvp_ref) < tol_for(w.nt), rel(dvp.cpu().numpy(), dvp_ref)
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_backward_vjp_matches_oracle(maker):
+    w = maker()
+    g = oracle.Grid(**w.grid_kwargs())
+    plan = S.Plan.from_workload(w)
+    rng = np.random.default_rng(3)
+    gt = rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32)
+    dvp_ref, dwav_ref = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, gt)
+    ws = plan.workspace(S.STRIDE_MODE_GRADIENT)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    plan.forward_save(vp, wav, ws)
+    dvp, dwav = plan.backward(vp, wav, dev(gt), ws, want_dwavelet=True)
+    assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4
+    assert rel(dwav.cpu().numpy(), dwav_ref) < 1e-4
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_dot_product_fp32(maker):
+    """<F s, d> = <s, F^T d> for the wavelet -> traces map on the GPU."""
+    w = maker()
+    plan = S.Plan.from_workload(w)
+    rng = np.random.default_rng(12)
+    s = rng.standard_normal(w.wavelet.shape).astype(np.float32)
+    d = rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32)
+    vp, sd = dev(w.vp), dev(s)
+    ws = plan.workspace(S.STRIDE_MODE_GRADIENT)
+    Fs = plan.forward_save(vp, sd, ws).cpu().numpy().astype(np.float64)
+    _, FTd = plan.backward(vp, sd, dev(d), ws, want_dwavelet=True)
+    lhs = np.sum(Fs * d)
+    rhs = np.sum(s.astype(np.float64) * FTd.cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs)), (lhs, rhs)
+
+
+@pytest.mark.parametrize("maker,kw", [(W.tiny_2d, dict(nt=90)), (W.tiny_3d, dict(nt=50))])
+def test_checkpointing_is_bitwise_invisible(maker, kw):
+    """The gradient is the same bits with every state kept and with binomial
+    checkpointing at several budgets; repeated runs are bitwise identical."""
+    w = maker(**kw)
+    plan = S.Plan.from_workload(w)
+    rng = np.random.default_rng(5)
+    obs = dev(rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32) * 1e-3)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    m0, g0 = plan.gradient(vp, wav, obs)
+    m1, g1 = plan.gradient(vp, wav, obs)
+    assert torch.equal(g0, g1) and torch.equal(m0, m1)
+    full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+    fixed = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT, 1 << 62) - 0  # == full
+    assert fixed == full
+    field_est = (full - plan.workspace_bytes(S.STRIDE_MODE_GRADIENT, full // 2)) > 0
+    assert field_est
+    for frac in (0.5, 0.2, 0.08):
+        budget = int(full * frac)
+        try:
+            ws = plan.workspace(S.STRIDE_MODE_GRADIENT, budget)
+        except S.StrideError:
+            continue
+        m2, g2 = plan.gradient(vp, wav, obs, ws=ws)
+        assert torch.equal(g0, g2), frac
+        assert torch.equal(m0, m2)
+
+
+def test_config1_forward_matches_oracle():
+    w = W.config1()
+    g = oracle.Grid(**w.grid_kwargs())
+    ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    tr = S.Plan.from_workload(w).forward(dev(w.vp), dev(w.wavelet)).cpu().numpy()
+    assert rel(tr, ref) < tol_for(w.nt), rel(tr, ref)
+
+
+def test_errors_are_reported_before_launch():
+    w = W.tiny_2d()
+    plan = S.Plan.from_workload(w)
+    vp = dev(w.vp * 3.0)       # violates the CFL limit at this dt
+    with pytest.raises(S.StrideError) as e:
+        plan.forward(vp, dev(w.wavelet))
+    assert e.value.code == -2
+    bad = w.vp.copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(S.StrideError) as e:
+        plan.forward(dev(bad), dev(w.wavelet))
+    assert e.value.code == -1
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(S.StrideError) as e:
+        plan.forward(dev(w.vp), dev(w.wavelet), ws=small)
+    assert e.value.code == -4
