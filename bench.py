@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Throughput of the acoustic FWI hot path on one MI355X.
+
+A step is one shot gradient: forward solve with source injection and receiver
+sampling, every forward state kept (or checkpointed), residual and misfit,
+adjoint solve fused with the imaging condition, and the gradient finalise:
+the whole hot path once over one shot of the workload.
+
+value = grid-point updates per second of forward + adjoint propagation,
+2 * N_padded * (nt - 1) per step (recomputation by checkpointing is not
+counted as work).  A forward-only solve of the same workload is timed too.
+
+roofline: the dominant kernel is the fused adjoint + imaging step (28
+algorithmic bytes per grid point: reads u^m, w^{m+1}, w^{m+2}, k, G; writes
+w^m, G).  Its per-launch time comes from HIP events the library records on
+the solve stream around the adjoint time loop during the timed steps.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FWD_BYTES = 16   # read u^n, u^{n-1}, k; write u^{n+1}
+ADJ_BYTES = 28   # read u^m, w^{m+1}, w^{m+2}, k, G; write w^m, G
+
+WORKLOADS = {
+    "config2": "2D breast-like phantom, 1024^2 at 0.2 mm + 40-cell sponge (1104^2 padded), "
+               "8th order, 2500 steps, 1 shot, 256 ring receivers; gradient at the 1500 m/s "
+               "starting model against data from the phantom",
+    "config4": "3D head-like phantom, 256^3 at 0.5 mm + 30-cell sponge (316^3 padded), 10th order, "
+               "3000 steps, 1 shot, 1024 hemisphere receivers; gradient at the skull-only starting "
+               "model, binomial checkpointing within the HBM budget",
+    "config3": "2D breast-like phantom, 512^2 at 0.2 mm + 40-cell sponge (592^2 padded), 8th order, "
+               "1500 steps, shot 0 of the 64-shot ring survey; gradient at 1500 m/s",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--budget-gb", type=float, default=200.0,
+                    help="HBM budget of the gradient workspace (checkpointing beyond it)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-forward", action="store_true")
+    return ap.parse_args()
+
+
+def build_workload(name):
+    import numpy as np
+    import workloads as W
+    if name == "config2":
+        w = W.config2()
+        vp_model = np.full(w.shape, 1500.0, dtype=np.float32)
+        return w, w.vp, vp_model
+    if name == "config3":
+        w = W.config3()
+        return w, w.vp_true, w.vp_start
+    if name == "config4":
+        w = W.config4()
+        return w, w.vp_true, w.vp_start
+    raise ValueError(name)
+
+
+def cpu_baseline(w, vp_model, obs_np, seconds):
+    """The FP64 oracle's shot gradient on the same grid, for a bounded number
+    of time steps chosen to take about `seconds` on the host cores."""
+    import numpy as np
+    import oracle
+    npad = w.padded_points
+    nt_probe = 4
+    g = oracle.Grid(**{**w.grid_kwargs(), "nt": nt_probe})
+    wav = w.wavelet[:, :nt_probe]
+    t0 = time.perf_counter()
+    oracle.gradient(g, vp_model, w.src_xyz, wav, w.rec_xyz, obs_np[:, :nt_probe])
+    per_step = (time.perf_counter() - t0) / (nt_probe - 1)
+    nt_s = int(max(8, min(w.nt, seconds / max(per_step, 1e-9))))
+    g = oracle.Grid(**{**w.grid_kwargs(), "nt": nt_s})
+    t0 = time.perf_counter()
+    oracle.gradient(g, vp_model, w.src_xyz, w.wavelet[:, :nt_s], w.rec_xyz, obs_np[:, :nt_s])
+    el = time.perf_counter() - t0
+    return {
+        "value": 2.0 * npad * (nt_s - 1) / el,
+        "unit": "grid-point updates/s (fwd+adj)",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"{w.name} grid, first {nt_s} of {w.nt} steps, one shot gradient "
+                  f"(FP64 C, OpenMP), {el:.1f} s",
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the shot-parallel multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2110_03345_amd as S
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w, vp_true, vp_model = build_workload(args.workload)
+    npad = w.padded_points
+    print(f"[bench] {args.workload}: padded {w.padded_shape} = {npad} points, nt={w.nt}",
+          file=sys.stderr, flush=True)
+
+    plan = S.Plan.from_workload(w)
+    vp_t = torch.from_numpy(vp_true).to(dev)
+    vp_m = torch.from_numpy(vp_model).to(dev)
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    obs = plan.forward(vp_t, wav)        # observed data: forward on the phantom
+    torch.cuda.synchronize()
+
+    budget = int(args.budget_gb * 2**30)
+    full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+    ws_bytes = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full, budget))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    traces = torch.empty((plan.nrec, plan.nt), dtype=torch.float32, device=dev)
+    misfit = torch.zeros(1, dtype=torch.float64, device=dev)
+    dvp = torch.empty_like(vp_m)
+
+    def grad_step():
+        S.stride_plan_gradient(plan.handle, vp_m, wav, obs, traces, misfit, dvp, ws)
+
+    for _ in range(args.warmup):
+        grad_step()
+    torch.cuda.synchronize()
+    S.stride_timing_read()
+    S.stride_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        grad_step()
+        print(f"[bench] gradient step {i + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.stride_timing_enable(False)
+    f_ms, f_n, a_ms, a_n = S.stride_timing_read()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = 2.0 * npad * (w.nt - 1) * args.steps / elapsed
+    adj_launch_s = a_ms * 1e-3 / max(a_n, 1)
+    fwd_launch_s = f_ms * 1e-3 / max(f_n, 1)
+    adj_gbs = ADJ_BYTES * npad / adj_launch_s / 1e9
+    fwd_in_grad_gbs = FWD_BYTES * npad / fwd_launch_s / 1e9
+    recompute = f_n / max(1, args.steps * (w.nt - 1))
+    print(f"[bench] gradient: {ms_per_step:.2f} ms/step, adjoint kernel {adj_launch_s * 1e6:.2f} us/launch "
+          f"({adj_gbs:.0f} GB/s), forward kernel {fwd_launch_s * 1e6:.2f} us/launch, "
+          f"forward steps per step {f_n / args.steps:.0f}", file=sys.stderr, flush=True)
+
+    fwd = {}
+    if not args.no_forward:
+        fws = plan.workspace(S.STRIDE_MODE_FORWARD, device=dev)
+        plan.forward(vp_m, wav, traces=traces, ws=fws)
+        torch.cuda.synchronize()
+        S.stride_timing_enable(True)
+        tf0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.forward(vp_m, wav, traces=traces, ws=fws)
+        torch.cuda.synchronize()
+        tf1 = time.perf_counter()
+        S.stride_timing_enable(False)
+        ff_ms, ff_n, _, _ = S.stride_timing_read()
+        f_launch = ff_ms * 1e-3 / max(ff_n, 1)
+        fwd = {
+            "fwd_updates_per_s": npad * (w.nt - 1) * args.steps / (tf1 - tf0),
+            "fwd_ms_per_solve": 1e3 * (tf1 - tf0) / args.steps,
+            "fwd_kernel_us": f_launch * 1e6,
+            "fwd_kernel_gbs": FWD_BYTES * npad / f_launch / 1e9,
+        }
+        print(f"[bench] forward: {fwd['fwd_ms_per_solve']:.2f} ms/solve, kernel "
+              f"{fwd['fwd_kernel_us']:.2f} us ({fwd['fwd_kernel_gbs']:.0f} GB/s)",
+              file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        obs_np = obs.cpu().numpy()
+        cpu = cpu_baseline(w, vp_model, obs_np, args.cpu_seconds)
+        print(f"[bench] cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} threads",
+              file=sys.stderr, flush=True)
+
+    line = {
+        "metric": "grid-point updates/s (fwd, fwd+adj), % HBM peak; served solves/s + p50/p99",
+        "value": value,
+        "unit": "grid-point updates/s (fwd+adj)",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded phantom and ring geometry; observed data from a forward solve "
+                "on the phantom)",
+        "config": {
+            "workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+            "padded_points": npad,
+            "nt": w.nt,
+            "nrec": plan.nrec,
+            "step": "one shot gradient (forward + residual/misfit + adjoint/imaging + finalise)",
+            "workspace_gb": ws_bytes / 2**30,
+            "forward_steps_per_gradient": f_n / args.steps,
+            "recompute_factor": recompute,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "adjoint + imaging step (step%dd_kernel<R,true>)" % w.ndim,
+            "achieved": adj_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": adj_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "bytes_per_point": ADJ_BYTES,
+            "us_per_launch": adj_launch_s * 1e6,
+            "forward_kernel_in_gradient_gbs": fwd_in_grad_gbs,
+        },
+        **fwd,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -148,6 +148,15 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
 int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* forward_steps,
                          int32_t* peak_fields);
 
+/* Tracing of the time loops.  While enabled on the calling thread, every solve
+ * records a HIP event pair on its stream around its forward time loop and its
+ * adjoint time loop.  stride_timing_read waits for the recorded events, returns
+ * the summed loop times (ms) and step-kernel launch counts since the last read,
+ * and clears them. */
+int stride_timing_enable(int32_t on);
+int stride_timing_read(double* fwd_ms, int64_t* fwd_launches, double* adj_ms,
+                       int64_t* adj_launches);
+
 /* Message of the calling thread's last error ("" if none). */
 const char* stride_last_error(void);
 const char* stride_error_string(int code);

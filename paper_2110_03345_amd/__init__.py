@@ -27,6 +27,8 @@ from ._abi import (  # noqa: F401
     stride_plan_gradient,
     stride_plan_padded_shape,
     stride_schedule_info,
+    stride_timing_enable,
+    stride_timing_read,
     stride_workspace_bytes,
     stride_workspace_query,
 )

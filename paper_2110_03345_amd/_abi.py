@@ -30,6 +30,7 @@ EXPORTS = (
     "stride_workspace_bytes", "stride_plan_forward", "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
     "stride_schedule_info", "stride_last_error", "stride_error_string",
+    "stride_timing_enable", "stride_timing_read",
 )
 
 
@@ -80,6 +81,9 @@ def lib():
         L.stride_workspace_query.argtypes = [gp, i32, i32, i32, sz, ctypes.POINTER(sz)]
         L.stride_schedule_info.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(i32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+        L.stride_timing_enable.argtypes = [i32]
+        L.stride_timing_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp,
+                                         ctypes.POINTER(ctypes.c_int64)]
         L.stride_last_error.restype = ctypes.c_char_p
         L.stride_error_string.restype = ctypes.c_char_p
         L.stride_error_string.argtypes = [ctypes.c_int]
@@ -183,6 +187,19 @@ def stride_schedule_info(nt: int, fields: int):
     p = ctypes.c_int32()
     _check(lib().stride_schedule_info(nt, fields, ctypes.byref(s), ctypes.byref(f), ctypes.byref(p)))
     return int(s.value), int(f.value), int(p.value)
+
+
+def stride_timing_enable(on: bool) -> None:
+    _check(lib().stride_timing_enable(1 if on else 0))
+
+
+def stride_timing_read():
+    """(fwd_ms, fwd_launches, adj_ms, adj_launches) since the last read."""
+    f, a = ctypes.c_double(), ctypes.c_double()
+    nf, na = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().stride_timing_read(ctypes.byref(f), ctypes.byref(nf), ctypes.byref(a),
+                                    ctypes.byref(na)))
+    return f.value, int(nf.value), a.value, int(na.value)
 
 
 def stride_plan_forward(plan, vp, wavelet, traces, ws, stream=None):

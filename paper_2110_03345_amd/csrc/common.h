@@ -11,8 +11,7 @@ namespace stride {
 constexpr int kMaxR = 5;        // stencil radius (10th order)
 constexpr int kThreads = 256;   // 4 wave64 per block
 constexpr int kTileX = 64;      // contiguous axis: one wave64 spans a tile row
-constexpr int kTileY = 16;      // rows per tile: 4 waves x 4 rows per thread
-constexpr int kRowsPerThread = 4;
+constexpr int kWaves = 4;       // waves per block, stacked along the row axis
 constexpr int kMaxTaps = 8;
 
 // Padded grid as laid out in the workspace.  Axis nd-1 is contiguous.
@@ -39,12 +38,13 @@ struct SpongeCoef {
     float half_dt;
 };
 
-// Per-tile list of grid points that receive an injected signal: entries of
-// tile t are [tile_ptr[t], tile_ptr[t+1]); entry e adds w[e] * sig[id[e]][step]
-// at linear index pidx[e].
-struct TileTable {
-    const int* tile_ptr;
-    const long long* pidx;
+// Grid points that receive an injected signal, grouped by grid row (every
+// axis but the contiguous one: row = i0 in 2D, i0 * n1 + i1 in 3D).  Entries
+// of row r are [row_ptr[r], row_ptr[r+1]); entry e adds w[e] * sig[id[e]][step]
+// at column x[e] of that row, in entry order.
+struct RowTable {
+    const int* row_ptr;
+    const int* x;
     const int* id;
     const float* w;
 };
@@ -66,21 +66,25 @@ struct StepParams {
     const float* U;   // adjoint only: forward field u^m (second stencil)
     float* G;         // adjoint only: imaging accumulator
     int step;         // time index of the injected / sampled signals
-    TileTable inj;    // injection into C: sources (forward), receivers (adjoint)
+    RowTable inj;     // injection into C: sources (forward), receivers (adjoint)
     const float* inj_sig;
     int inj_stride;
-    TileTable img;    // adjoint only: source term S^m of the imaging condition
+    RowTable img;     // adjoint only: source term S^m of the imaging condition
     const float* img_sig;
     int img_stride;
     SampleSet smp;    // sampling of A at `step`
 };
 
 struct LaunchShape {
+    int ty;               // tile rows (kWaves x rows per thread)
     int tiles_x, tiles_y, tiles_xy;
     int zc, nzc;          // 3D: planes per block and number of z chunks
     int tile_blocks;      // logical tile blocks (before XCD padding)
     int tile_blocks_pad;  // rounded up to a multiple of 8 XCDs
 };
+
+// Tile rows of the step kernels for a dimension and direction.
+int tile_rows(int nd, bool adjoint);
 
 // Kernel launchers (stride_kernels.hip).
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,

@@ -31,8 +31,8 @@ struct stride_plan {
     int nsrc, nrec;
     int device;
     void* blob;          // device memory of the tables below
-    TileTable src_inj;   // sources, weights / cell volume
-    TileTable rec_inj;   // receivers (adjoint injection), weights
+    RowTable src_inj;    // sources, weights / cell volume
+    RowTable rec_inj;    // receivers (adjoint injection), weights
     const long long* rec_idx;
     const float* rec_w;  // receiver sampling
     const long long* src_idx;
@@ -87,12 +87,13 @@ bool fd_weights(int order, double* c)
     return false;
 }
 
-LaunchShape make_shape(const Dims& d, int zc)
+LaunchShape make_shape(const Dims& d, int zc, int ty)
 {
     LaunchShape ls{};
     int nx = d.n[d.nd - 1], ny = d.n[d.nd - 2];
+    ls.ty = ty;
     ls.tiles_x = (nx + kTileX - 1) / kTileX;
-    ls.tiles_y = (ny + kTileY - 1) / kTileY;
+    ls.tiles_y = (ny + ty - 1) / ty;
     ls.tiles_xy = ls.tiles_x * ls.tiles_y;
     if (d.nd == 3) {
         ls.zc = std::max(1, std::min(zc, d.n[0]));
@@ -106,20 +107,17 @@ LaunchShape make_shape(const Dims& d, int zc)
     return ls;
 }
 
-// Planes per 3D block: enough blocks to fill 256 CUs several times over, but
-// long enough marches that the 2R lead-in planes stay a small overhead.
-int default_zc(const Dims& d, int R)
+// Planes per 3D block.  Short chunks give many independent blocks (the march
+// is latency-bound, so parallelism wins over the 2R lead-in planes each chunk
+// re-reads, which mostly hit L2); 16 was fastest on 316^3 for both kernels.
+int default_zc(const Dims& d, int R, int ty)
 {
+    (void)R;
+    (void)ty;
     if (d.nd != 3)
         return 1;
     int want = env_int("STRIDE_ZC", 0);
-    if (want > 0)
-        return want;
-    int tiles = ((d.n[2] + kTileX - 1) / kTileX) * ((d.n[1] + kTileY - 1) / kTileY);
-    int target_blocks = 1024;
-    int nzc = std::max(1, (target_blocks + tiles - 1) / tiles);
-    int zc = (d.n[0] + nzc - 1) / nzc;
-    return std::max(zc, 4 * R);
+    return want > 0 ? want : 16;
 }
 
 struct Tap {
@@ -180,39 +178,35 @@ int make_taps(const stride_plan& P, const double* xyz, int count, std::vector<Ta
     return STRIDE_OK;
 }
 
-int tile_of(const stride_plan& P, const int* c)
-{
-    int x = c[P.nd - 1], y = c[P.nd - 2];
-    return (y / kTileY) * P.ls_fwd.tiles_x + x / kTileX;
-}
-
 struct HostTable {
     std::vector<int> ptr;
-    std::vector<long long> pidx;
+    std::vector<int> x;
     std::vector<int> id;
     std::vector<float> w;
 };
 
-// Per-tile injection entries, grouped by tile in (point, tap) order so that the
-// summation order inside the kernel is fixed.
-HostTable build_table(const stride_plan& P, const std::vector<Tap>& taps, double scale)
+// Injection entries grouped by grid row (every axis but the contiguous one),
+// in (point, tap) order within a row so that the kernel sums in a fixed order.
+HostTable build_rows(const stride_plan& P, const std::vector<Tap>& taps, double scale)
 {
     HostTable T;
-    int ntiles = P.ls_fwd.tiles_xy;
-    std::vector<std::vector<std::pair<long long, std::pair<int, float>>>> per(ntiles);
+    const Dims& d = P.dims;
+    long long nrows = d.nd == 2 ? d.n[0] : (long long)d.n[0] * d.n[1];
+    std::vector<std::vector<std::pair<int, std::pair<int, float>>>> per(nrows);
     int ntap = 1 << P.nd;
     for (size_t p = 0; p < taps.size(); ++p)
         for (int t = 0; t < ntap; ++t) {
             if (taps[p].w[t] == 0.0)
                 continue;
-            int tile = tile_of(P, taps[p].coord[t]);
-            per[tile].push_back({taps[p].idx[t], {(int)p, (float)(taps[p].w[t] * scale)}});
+            const int* c = taps[p].coord[t];
+            long long row = d.nd == 2 ? c[0] : (long long)c[0] * d.n[1] + c[1];
+            per[row].push_back({c[d.nd - 1], {(int)p, (float)(taps[p].w[t] * scale)}});
         }
-    T.ptr.resize(ntiles + 1, 0);
-    for (int t = 0; t < ntiles; ++t) {
-        T.ptr[t + 1] = T.ptr[t] + (int)per[t].size();
-        for (auto& e : per[t]) {
-            T.pidx.push_back(e.first);
+    T.ptr.assign(nrows + 1, 0);
+    for (long long r = 0; r < nrows; ++r) {
+        T.ptr[r + 1] = T.ptr[r] + (int)per[r].size();
+        for (auto& e : per[r]) {
+            T.x.push_back(e.first);
             T.id.push_back(e.second.first);
             T.w.push_back(e.second.second);
         }
@@ -376,6 +370,56 @@ StepParams base_params(const stride_plan& P)
     return p;
 }
 
+// ------------------------------------------------------------ phase timing
+
+// Tracing of the time loops: when enabled on a thread, every solve records a
+// HIP event pair around its forward time loop and its adjoint time loop on the
+// solve's stream and counts the step launches in between.
+struct PhaseTimer {
+    bool on = false;
+    struct Rec {
+        hipEvent_t a, b;
+        int kind;   // 0 forward loop, 1 adjoint loop
+        long long launches;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> spare;
+
+    hipEvent_t ev()
+    {
+        if (!spare.empty()) {
+            hipEvent_t e = spare.back();
+            spare.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess)
+            return nullptr;
+        return e;
+    }
+    int begin(hipStream_t s)
+    {
+        if (!on)
+            return -1;
+        Rec r{ev(), ev(), 0, 0};
+        if (!r.a || !r.b)
+            return -1;
+        (void)hipEventRecord(r.a, s);
+        recs.push_back(r);
+        return (int)recs.size() - 1;
+    }
+    void end(int id, hipStream_t s, int kind, long long launches)
+    {
+        if (id < 0)
+            return;
+        recs[id].kind = kind;
+        recs[id].launches = launches;
+        (void)hipEventRecord(recs[id].b, s);
+    }
+};
+
+thread_local PhaseTimer g_timer;
+
 // ------------------------------------------------------------ executors
 
 // Replays a checkpointing schedule over the wavefield pool.  forward_phase
@@ -407,6 +451,8 @@ struct Runner {
     }
 
     bool overflow = false;   // the schedule needed more fields than the pool holds
+    long long launches = 0;      // forward step launches
+    long long adj_launches = 0;  // adjoint step launches
 
     int alloc()
     {
@@ -447,6 +493,7 @@ struct Runner {
             if (traces)
                 p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
             launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
+            ++launches;
         }
         if (out != old_prev)
             release(old_prev);
@@ -530,6 +577,7 @@ struct Runner {
             if (dwavelet)
                 p.smp = SampleSet{P.nsrc, P.src_idx, P.src_w, dwavelet, P.nt};
             launch_step(P.dims, P.R, true, P.cf, P.sp, P.ls_adj, p, s);
+            ++adj_launches;
             wa = 1 - wa;
         }
     }
@@ -556,6 +604,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
     launch_prep_k(P.dims, vp, P.g.dt, k, s);
     launch_fill(u[0], P.dims.total, 0.f, s);
     launch_fill(u[1], P.dims.total, 0.f, s);
+    int tid = g_timer.begin(s);
     int cur = 0;
     for (int n = 0; n < P.nt - 1; ++n) {
         StepParams p = base_params(P);
@@ -569,6 +618,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
         launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
         cur = 1 - cur;
     }
+    g_timer.end(tid, s, 0, P.nt - 1);
     launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
     return STRIDE_OK;
@@ -590,7 +640,9 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     launch_fill(W.pool[0], P.dims.total, 0.f, s);
     launch_fill(W.pool[1], P.dims.total, 0.f, s);
     Runner run(P, W, s, wavelet);
+    int tid = g_timer.begin(s);
     run.forward_phase(true, tr);
+    g_timer.end(tid, s, 0, run.launches);
     if (run.overflow)
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     // last sample from the final state x_{nt-1}
@@ -615,7 +667,9 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     launch_fill(W.G, P.dims.total, 0.f, s);
     launch_fill(W.w[0], P.dims.total, 0.f, s);
     launch_fill(W.w[1], P.dims.total, 0.f, s);
+    int tid = g_timer.begin(s);
     run.backward_phase(grad_traces, dwavelet);
+    g_timer.end(tid, s, 1, run.adj_launches);
     if (run.overflow)
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     launch_finalize_dvp(P.dims, W.G, vp, dvp, s);
@@ -715,8 +769,9 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         }
     P->sp.half_dt = (float)(0.5 * grid->dt);
 
-    P->ls_fwd = make_shape(d, default_zc(d, P->R));
-    P->ls_adj = make_shape(d, default_zc(d, P->R));
+    int tyf = tile_rows(P->nd, false), tya = tile_rows(P->nd, true);
+    P->ls_fwd = make_shape(d, default_zc(d, P->R, tyf), tyf);
+    P->ls_adj = make_shape(d, default_zc(d, P->R, tya), tya);
 
     std::vector<Tap> st, rt;
     if ((rc = make_taps(*P, src_xyz, nsrc, st, "source")) ||
@@ -724,8 +779,8 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         delete P;
         return rc;
     }
-    HostTable ts = build_table(*P, st, 1.0 / P->cellvol);
-    HostTable tr = build_table(*P, rt, 1.0);
+    HostTable ts = build_rows(*P, st, 1.0 / P->cellvol);
+    HostTable tr = build_rows(*P, rt, 1.0);
     std::vector<long long> ridx, sidx;
     std::vector<float> rw, sw;
     flatten_sample(rt, 1.0, ridx, rw);
@@ -742,11 +797,11 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         return o;
     };
     size_t o_ts_ptr = add(ts.ptr.data(), ts.ptr.size(), 4);
-    size_t o_ts_pidx = add(ts.pidx.data(), ts.pidx.size(), 8);
+    size_t o_ts_x = add(ts.x.data(), ts.x.size(), 4);
     size_t o_ts_id = add(ts.id.data(), ts.id.size(), 4);
     size_t o_ts_w = add(ts.w.data(), ts.w.size(), 4);
     size_t o_tr_ptr = add(tr.ptr.data(), tr.ptr.size(), 4);
-    size_t o_tr_pidx = add(tr.pidx.data(), tr.pidx.size(), 8);
+    size_t o_tr_x = add(tr.x.data(), tr.x.size(), 4);
     size_t o_tr_id = add(tr.id.data(), tr.id.size(), 4);
     size_t o_tr_w = add(tr.w.data(), tr.w.size(), 4);
     size_t o_ridx = add(ridx.data(), ridx.size(), 8);
@@ -769,10 +824,10 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         return fail(STRIDE_E_HIP, "plan tables: %s", hipGetErrorString(e));
     }
     char* B = (char*)P->blob;
-    P->src_inj = TileTable{(const int*)(B + o_ts_ptr), (const long long*)(B + o_ts_pidx),
-                           (const int*)(B + o_ts_id), (const float*)(B + o_ts_w)};
-    P->rec_inj = TileTable{(const int*)(B + o_tr_ptr), (const long long*)(B + o_tr_pidx),
-                           (const int*)(B + o_tr_id), (const float*)(B + o_tr_w)};
+    P->src_inj = RowTable{(const int*)(B + o_ts_ptr), (const int*)(B + o_ts_x),
+                          (const int*)(B + o_ts_id), (const float*)(B + o_ts_w)};
+    P->rec_inj = RowTable{(const int*)(B + o_tr_ptr), (const int*)(B + o_tr_x),
+                          (const int*)(B + o_tr_id), (const float*)(B + o_tr_w)};
     P->rec_idx = (const long long*)(B + o_ridx);
     P->rec_w = (const float*)(B + o_rw);
     P->src_idx = (const long long*)(B + o_sidx);
@@ -942,6 +997,37 @@ int stride_gradient(const stride_grid_t* grid, const float* vp, const float* wav
     if (!rc && e != hipSuccess)
         rc = fail(STRIDE_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return rc;
+}
+
+int stride_timing_enable(int32_t on)
+{
+    g_timer.on = on != 0;
+    return STRIDE_OK;
+}
+
+int stride_timing_read(double* fwd_ms, int64_t* fwd_launches, double* adj_ms, int64_t* adj_launches)
+{
+    double t[2] = {0, 0};
+    long long n[2] = {0, 0};
+    for (auto& r : g_timer.recs) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        t[r.kind] += ms;
+        n[r.kind] += r.launches;
+        g_timer.spare.push_back(r.a);
+        g_timer.spare.push_back(r.b);
+    }
+    g_timer.recs.clear();
+    if (fwd_ms)
+        *fwd_ms = t[0];
+    if (fwd_launches)
+        *fwd_launches = n[0];
+    if (adj_ms)
+        *adj_ms = t[1];
+    if (adj_launches)
+        *adj_launches = n[1];
+    return STRIDE_OK;
 }
 
 int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* forward_steps,

@@ -18,7 +18,21 @@
 
 #include "common.h"
 
+#include <cstdlib>
+#include <type_traits>
+
 namespace stride {
+
+// Tile rows the kernels use (the host sizes launch shapes with these).
+int tile_rows(int nd, bool adjoint)
+{
+    if (nd == 2)
+        return 16;
+    const char* e = getenv(adjoint ? "STRIDE_RY3D_ADJ" : "STRIDE_RY3D");
+    int ry = e && *e ? atoi(e) : (adjoint ? 2 : 4);
+    return (ry == 2 ? 2 : 4) * kWaves;
+}
+
 
 namespace {
 
@@ -33,19 +47,55 @@ __device__ __forceinline__ int xcd_logical(int b, int nblk_pad)
     return (b % kXcds) * per + b / kXcds;
 }
 
+// Calls fn(integral_constant<I>) for I = 0..N-1 while it returns true; every
+// I is a compile-time constant in the body (used to index register queues).
+template <int N, int I = 0, class Fn>
+__device__ __forceinline__ void unrolled_while(Fn&& fn)
+{
+    if constexpr (I < N) {
+        if (fn(std::integral_constant<int, I>{}))
+            unrolled_while<N, I + 1>(fn);
+    }
+}
+
+// Raw buffer access (CDNA): a descriptor over [base, base + bytes) returns 0
+// for any byte offset at or beyond `bytes`, so loads of points outside the
+// grid need no branch: their offset is set to 0xffffffff, and a plane outside
+// the grid gets bytes = 0.  Third descriptor word of the gfx9 family.
+constexpr int kBufWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, int bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, bytes, kBufWord3);
+}
+
+__device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int byte_off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, 0, 0);
+}
+
+// The builtin returns the raw 32 bits; reinterpret them (no numeric conversion).
+__device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
 __device__ __forceinline__ int layer_depth(int i, int n, int nb)
 {
     int hi = n - 1 - nb;
     return i < nb ? nb - i : (i > hi ? i - hi : 0);
 }
 
-__device__ __forceinline__ float tile_signal(const TileTable& t, int b0, int b1, long long gi,
-                                             const float* sig, int stride, int step)
+// Signal injected at column gx of grid row `row`: sum over the row's entries
+// at that column, in table order.
+__device__ __forceinline__ float row_signal(const RowTable& t, long long row, int gx,
+                                            const float* sig, int stride, int step)
 {
     float s = 0.f;
-    for (int e = b0; e < b1; ++e)
-        if (t.pidx[e] == gi)
-            s += t.w[e] * sig[(long long)t.id[e] * stride + step];
+    const int b = t.row_ptr[row], e = t.row_ptr[row + 1];
+    for (int i = b; i < e; ++i)
+        if (t.x[i] == gx)
+            s += t.w[i] * sig[(long long)t.id[i] * stride + step];
     return s;
 }
 
@@ -74,13 +124,19 @@ __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float
 }
 
 // ----------------------------------------------------------------------- 2D
+//
+// One block = one 64 x 16 tile (4 waves x 4 rows per thread).  The point
+// loads of B, K (and G) are issued first so that their latency overlaps the
+// LDS tile load.
 
 template <int R, bool ADJ>
 __global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
                                                           StepParams p, LaunchShape ls)
 {
+    constexpr int RY = 4;
+    constexpr int TY = kWaves * RY;
     constexpr int LW = kTileX + 2 * R;
-    constexpr int LH = kTileY + 2 * R;
+    constexpr int LH = TY + 2 * R;
     __shared__ float sA[LH][LW];
     __shared__ float sU[ADJ ? LH : 1][ADJ ? LW : 1];
 
@@ -92,60 +148,69 @@ __global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf
     const int tile = xcd_logical(b, ls.tile_blocks_pad);
     if (tile >= ls.tile_blocks)
         return;
-    const int y0 = (tile / ls.tiles_x) * kTileY;
+    const int y0 = (tile / ls.tiles_x) * TY;
     const int x0 = (tile % ls.tiles_x) * kTileX;
     const int tid = threadIdx.x;
     const int lx = tid & 63;
     const int wy = tid >> 6;
     const int n0 = d.n[0], n1 = d.n[1];
     const long long s0 = d.st[0];
+    const int gx = x0 + lx;
+
+    float bb[RY], kk[RY], gg[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        const int gy = y0 + wy * RY + j;
+        const bool ok = gx < n1 && gy < n0;
+        const long long gi = (long long)gy * s0 + gx;
+        bb[j] = ok ? p.B[gi] : 0.f;
+        kk[j] = ok ? p.K[gi] : 0.f;
+        if constexpr (ADJ)
+            gg[j] = ok ? p.G[gi] : 0.f;
+    }
 
     for (int i = tid; i < LH * LW; i += kThreads) {
         int r = i / LW;
         int c = i - r * LW;
         int gy = y0 - R + r;
-        int gx = x0 - R + c;
-        bool in = gy >= 0 && gy < n0 && gx >= 0 && gx < n1;
-        long long gi = (long long)gy * s0 + gx;
+        int gxx = x0 - R + c;
+        bool in = gy >= 0 && gy < n0 && gxx >= 0 && gxx < n1;
+        long long gi = (long long)gy * s0 + gxx;
         sA[r][c] = in ? p.A[gi] : 0.f;
         if constexpr (ADJ)
             sU[r][c] = in ? p.U[gi] : 0.f;
     }
     __syncthreads();
 
-    const int gx = x0 + lx;
     if (gx >= n1)
         return;
-    const int ib = p.inj.tile_ptr[tile], ie = p.inj.tile_ptr[tile + 1];
-    int mb = 0, me = 0;
-    if constexpr (ADJ) {
-        mb = p.img.tile_ptr[tile];
-        me = p.img.tile_ptr[tile + 1];
-    }
+    const int ylast = min(y0 + TY, n0);
+    const bool inj_any = p.inj.row_ptr[y0] < p.inj.row_ptr[ylast];
+    bool img_any = false;
+    if constexpr (ADJ)
+        img_any = p.img.row_ptr[y0] < p.img.row_ptr[ylast];
     const int dxd = layer_depth(gx, n1, d.nb);
 
 #pragma unroll
-    for (int j = 0; j < kRowsPerThread; ++j) {
-        const int ly = wy * kRowsPerThread + j;
+    for (int j = 0; j < RY; ++j) {
+        const int ly = wy * RY + j;
         const int gy = y0 + ly;
         if (gy >= n0)
             break;
         const long long gi = (long long)gy * s0 + gx;
         const float ctr = sA[ly + R][lx + R];
-        float ly_sum = 0.f, lx_sum = 0.f;
+        float ay = 0.f, ax = 0.f;
 #pragma unroll
         for (int q = R; q >= 1; --q) {
-            ly_sum = fmaf(cf.c[0][q], sA[ly + R + q][lx + R] + sA[ly + R - q][lx + R], ly_sum);
-            lx_sum = fmaf(cf.c[1][q], sA[ly + R][lx + R + q] + sA[ly + R][lx + R - q], lx_sum);
+            ay = fmaf(cf.c[0][q], sA[ly + R + q][lx + R] + sA[ly + R - q][lx + R], ay);
+            ax = fmaf(cf.c[1][q], sA[ly + R][lx + R + q] + sA[ly + R][lx + R - q], ax);
         }
-        float lap = fmaf(cf.c0, ctr, ly_sum + lx_sum);
-        if (ib < ie)
-            lap += tile_signal(p.inj, ib, ie, gi, p.inj_sig, p.inj_stride, p.step);
+        float lap = fmaf(cf.c0, ctr, ay + ax);
+        if (inj_any)
+            lap += row_signal(p.inj, gy, gx, p.inj_sig, p.inj_stride, p.step);
         const int dyd = layer_depth(gy, n0, d.nb);
         const float eta = sp.e[0] * (float)(dyd * dyd) + sp.e[1] * (float)(dxd * dxd);
-        const float prev = p.B[gi];
-        const float kk = p.K[gi];
-        p.C[gi] = leapfrog(ctr, prev, kk, lap, eta, sp.half_dt);
+        p.C[gi] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
         if constexpr (ADJ) {
             const float uc = sU[ly + R][lx + R];
             float uy = 0.f, ux = 0.f;
@@ -155,25 +220,40 @@ __global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf
                 ux = fmaf(cf.c[1][q], sU[ly + R][lx + R + q] + sU[ly + R][lx + R - q], ux);
             }
             float lu = fmaf(cf.c0, uc, uy + ux);
-            if (mb < me)
-                lu += tile_signal(p.img, mb, me, gi, p.img_sig, p.img_stride, p.step);
-            p.G[gi] = fmaf(ctr, lu, p.G[gi]);
+            if (img_any)
+                lu += row_signal(p.img, gy, gx, p.img_sig, p.img_stride, p.step);
+            p.G[gi] = fmaf(ctr, lu, gg[j]);
         }
     }
 }
 
 // ----------------------------------------------------------------------- 3D
+//
+// One block = one 64 x TY column tile marching along axis 0 over a chunk of
+// planes.  Each thread keeps the 2R+1 axis-0 neighbours of its RY points in a
+// rotating register queue (the march is unrolled by 2R+1 so that the queue
+// never shifts).  The plane tile with its halo goes to a double-buffered LDS
+// slot, so one barrier per plane suffices.  The march is software-pipelined:
+// while plane z is computed, the loads of plane z+1 (the queue's lead plane,
+// the halo, and the streamed point values of B, K, G) are in flight.  All
+// global accesses are raw buffer accesses with per-plane descriptors: offsets
+// outside the grid read 0 and drop stores, so no access needs a branch.
 
-template <int R, bool ADJ>
+template <int R, bool ADJ, int RY>
 __global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
                                                           StepParams p, LaunchShape ls)
 {
+    constexpr int TY = kWaves * RY;
     constexpr int LW = kTileX + 2 * R;
-    constexpr int LH = kTileY + 2 * R;
+    constexpr int LH = TY + 2 * R;
     constexpr int Q = 2 * R + 1;
-    constexpr int RY = kRowsPerThread;
-    __shared__ float sA[LH][LW];
-    __shared__ float sU[ADJ ? LH : 1][ADJ ? LW : 1];
+    constexpr int NYH = 2 * R * kTileX;             // halo rows above/below
+    constexpr int NXH = 2 * R * TY;                 // halo columns left/right
+    constexpr int HY = (NYH + kThreads - 1) / kThreads;
+    constexpr int HX = (NXH + kThreads - 1) / kThreads;
+    constexpr int NF = ADJ ? 2 : 1;                 // stencil fields: A (and U)
+    constexpr int PLANE = LH * LW;
+    __shared__ float sF[2][NF][PLANE];
 
     const int b = blockIdx.x;
     if (b >= ls.tile_blocks_pad) {
@@ -185,137 +265,207 @@ __global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf
         return;
     const int zci = lb / ls.tiles_xy;
     const int tile = lb - zci * ls.tiles_xy;
-    const int y0 = (tile / ls.tiles_x) * kTileY;
+    const int y0 = (tile / ls.tiles_x) * TY;
     const int x0 = (tile % ls.tiles_x) * kTileX;
     const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
     const int z0 = zci * ls.zc;
     const int z1 = min(z0 + ls.zc, n0);
-    const long long s0 = d.st[0], s1 = d.st[1];
+    const long long s0 = d.st[0];
+    const int s1 = (int)d.st[1];
     const int tid = threadIdx.x;
     const int lx = tid & 63;
     const int wy = tid >> 6;
     const int gx = x0 + lx;
     const bool xin = gx < n2;
+    const float* F[2] = {p.A, ADJ ? p.U : p.A};
 
-    float qa[RY][Q];
-    float qu[ADJ ? RY : 1][ADJ ? Q : 1];
+    // plane-independent geometry: byte offsets within a plane (-1 = outside)
+    const int plane_bytes = (int)(s0 * 4);
+    int rbo[RY], roff[RY];
     bool rin[RY];
+    float ey[RY];
+    const int dxd = layer_depth(gx, n2, d.nb);
+    const float ex = sp.e[2] * (float)(dxd * dxd);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         const int gy = y0 + wy * RY + j;
         rin[j] = xin && gy < n1;
-        const long long base = (long long)gy * s1 + gx;
-#pragma unroll
-        for (int t = 0; t < 2 * R; ++t) {
-            const int z = z0 - R + t;
-            const bool ok = rin[j] && z >= 0 && z < n0;
-            qa[j][t] = ok ? p.A[base + (long long)z * s0] : 0.f;
-            if constexpr (ADJ)
-                qu[j][t] = ok ? p.U[base + (long long)z * s0] : 0.f;
-        }
+        roff[j] = gy * s1 + gx;
+        rbo[j] = rin[j] ? roff[j] * 4 : -1;
+        const int dyd = layer_depth(gy, n1, d.nb);
+        ey[j] = sp.e[1] * (float)(dyd * dyd) + ex;
     }
-
-    const int ib = p.inj.tile_ptr[tile], ie = p.inj.tile_ptr[tile + 1];
-    int mb = 0, me = 0;
-    if constexpr (ADJ) {
-        mb = p.img.tile_ptr[tile];
-        me = p.img.tile_ptr[tile + 1];
-    }
-    const int dxd = layer_depth(gx, n2, d.nb);
-
-    for (int z = z0; z < z1; ++z) {
-        const long long zoff = (long long)z * s0;
-        // lead plane z + R into the register queues
+    int hy_l[HY], hy_o[HY];
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            const int gy = y0 + wy * RY + j;
-            const bool ok = rin[j] && z + R < n0;
-            const long long gi = (long long)(z + R) * s0 + (long long)gy * s1 + gx;
-            qa[j][2 * R] = ok ? p.A[gi] : 0.f;
-            if constexpr (ADJ)
-                qu[j][2 * R] = ok ? p.U[gi] : 0.f;
-            sA[wy * RY + j + R][lx + R] = qa[j][R];
-            if constexpr (ADJ)
-                sU[wy * RY + j + R][lx + R] = qu[j][R];
-        }
-        // halo rows above and below the tile (R rows each, 64 wide)
-        for (int i = tid; i < 2 * R * kTileX; i += kThreads) {
+    for (int h = 0; h < HY; ++h) {
+        const int i = tid + h * kThreads;
+        hy_l[h] = -1;
+        hy_o[h] = -1;
+        if (i < NYH) {
             const int hr = i / kTileX;
             const int c = i - hr * kTileX;
-            const int ly = hr < R ? hr - R : kTileY + hr - R;
+            const int ly = hr < R ? hr - R : TY + hr - R;
             const int gy = y0 + ly;
             const int g = x0 + c;
-            const bool ok = gy >= 0 && gy < n1 && g < n2;
-            const long long gi = zoff + (long long)gy * s1 + g;
-            sA[ly + R][c + R] = ok ? p.A[gi] : 0.f;
-            if constexpr (ADJ)
-                sU[ly + R][c + R] = ok ? p.U[gi] : 0.f;
+            hy_l[h] = (ly + R) * LW + c + R;
+            if (gy >= 0 && gy < n1 && g < n2)
+                hy_o[h] = (gy * s1 + g) * 4;
         }
-        // halo columns left and right of the tile (R columns each, 16 high)
-        for (int i = tid; i < 2 * R * kTileY; i += kThreads) {
+    }
+    int hx_l[HX], hx_o[HX];
+#pragma unroll
+    for (int h = 0; h < HX; ++h) {
+        const int i = tid + h * kThreads;
+        hx_l[h] = -1;
+        hx_o[h] = -1;
+        if (i < NXH) {
             const int row = i / (2 * R);
             const int cc = i - row * (2 * R);
             const int lxx = cc < R ? cc - R : kTileX + cc - R;
             const int g = x0 + lxx;
             const int gy = y0 + row;
-            const bool ok = g >= 0 && g < n2 && gy < n1;
-            const long long gi = zoff + (long long)gy * s1 + g;
-            sA[row + R][lxx + R] = ok ? p.A[gi] : 0.f;
-            if constexpr (ADJ)
-                sU[row + R][lxx + R] = ok ? p.U[gi] : 0.f;
+            hx_l[h] = (row + R) * LW + lxx + R;
+            if (g >= 0 && g < n2 && gy < n1)
+                hx_o[h] = (gy * s1 + g) * 4;
         }
-        __syncthreads();
+    }
+    auto rsrc = [&](const float* f, int z) {
+        const bool in = z >= 0 && z < n0;
+        return plane_rsrc(f + (long long)(in ? z : 0) * s0, in ? plane_bytes : 0);
+    };
 
-        const int dzd = layer_depth(z, n0, d.nb);
+    // queue slot (i + t) % Q holds plane z0 + i + t - R at march iteration i
+    float q[NF][RY][Q];
+#pragma unroll
+    for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int t = 0; t < 2 * R; ++t) {
+            const auto r = rsrc(F[f], z0 - R + t);
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                q[f][j][t] = bload(r, rbo[j]);
+        }
+
+    float pl[NF][RY], phy[NF][HY], phx[NF][HX];
+    float pb[RY], pk[RY], pg[RY];
+    auto prefetch = [&](int z) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const auto rz = rsrc(F[f], z);
+            const auto rl = rsrc(F[f], z + R);
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                pl[f][j] = bload(rl, rbo[j]);
+#pragma unroll
+            for (int h = 0; h < HY; ++h)
+                phy[f][h] = bload(rz, hy_o[h]);
+#pragma unroll
+            for (int h = 0; h < HX; ++h)
+                phx[f][h] = bload(rz, hx_o[h]);
+        }
+        const auto rb = rsrc(p.B, z);
+        const auto rk = rsrc(p.K, z);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            if (!rin[j])
-                continue;
-            const int ly = wy * RY + j;
-            const int gy = y0 + ly;
-            const long long gi = zoff + (long long)gy * s1 + gx;
-            const float ctr = qa[j][R];
-            float az = 0.f, ay = 0.f, ax = 0.f;
+            pb[j] = bload(rb, rbo[j]);
+            pk[j] = bload(rk, rbo[j]);
+        }
+        if constexpr (ADJ) {
+            const auto rg = rsrc(p.G, z);
 #pragma unroll
-            for (int q = R; q >= 1; --q) {
-                az = fmaf(cf.c[0][q], qa[j][R + q] + qa[j][R - q], az);
-                ay = fmaf(cf.c[1][q], sA[ly + R + q][lx + R] + sA[ly + R - q][lx + R], ay);
-                ax = fmaf(cf.c[2][q], sA[ly + R][lx + R + q] + sA[ly + R][lx + R - q], ax);
-            }
-            float lap = fmaf(cf.c0, ctr, az + ay + ax);
-            if (ib < ie)
-                lap += tile_signal(p.inj, ib, ie, gi, p.inj_sig, p.inj_stride, p.step);
-            const int dyd = layer_depth(gy, n1, d.nb);
-            const float eta = sp.e[0] * (float)(dzd * dzd) + sp.e[1] * (float)(dyd * dyd) +
-                              sp.e[2] * (float)(dxd * dxd);
-            const float prev = p.B[gi];
-            const float kk = p.K[gi];
-            p.C[gi] = leapfrog(ctr, prev, kk, lap, eta, sp.half_dt);
-            if constexpr (ADJ) {
-                const float uc = qu[j][R];
-                float uz = 0.f, uy = 0.f, ux = 0.f;
+            for (int j = 0; j < RY; ++j)
+                pg[j] = bload(rg, rbo[j]);
+        }
+    };
+    prefetch(z0);
+
+    const int ylast = min(y0 + TY, n1);
+    int buf = 0;
+    for (int zb = z0; zb < z1; zb += Q) {
+        unrolled_while<Q>([&](auto uc) {
+            constexpr int u = decltype(uc)::value;
+            constexpr int slot_lead = (u + 2 * R) % Q;
+            constexpr int slot_c = (u + R) % Q;
+            const int z = zb + u;
+            if (z >= z1)
+                return false;
+            float bb[RY], kk[RY], gg[RY];
+            float* S = &sF[buf][0][0];
 #pragma unroll
-                for (int q = R; q >= 1; --q) {
-                    uz = fmaf(cf.c[0][q], qu[j][R + q] + qu[j][R - q], uz);
-                    uy = fmaf(cf.c[1][q], sU[ly + R + q][lx + R] + sU[ly + R - q][lx + R], uy);
-                    ux = fmaf(cf.c[2][q], sU[ly + R][lx + R + q] + sU[ly + R][lx + R - q], ux);
+            for (int f = 0; f < NF; ++f) {
+                float* Sf = S + f * PLANE;
+#pragma unroll
+                for (int j = 0; j < RY; ++j) {
+                    q[f][j][slot_lead] = pl[f][j];
+                    Sf[(wy * RY + j + R) * LW + lx + R] = q[f][j][slot_c];
                 }
-                float lu = fmaf(cf.c0, uc, uz + uy + ux);
-                if (mb < me)
-                    lu += tile_signal(p.img, mb, me, gi, p.img_sig, p.img_stride, p.step);
-                p.G[gi] = fmaf(ctr, lu, p.G[gi]);
-            }
-        }
-        __syncthreads();
 #pragma unroll
-        for (int j = 0; j < RY; ++j) {
+                for (int h = 0; h < HY; ++h)
+                    if (hy_l[h] >= 0)
+                        Sf[hy_l[h]] = phy[f][h];
 #pragma unroll
-            for (int t = 0; t < 2 * R; ++t) {
-                qa[j][t] = qa[j][t + 1];
-                if constexpr (ADJ)
-                    qu[j][t] = qu[j][t + 1];
+                for (int h = 0; h < HX; ++h)
+                    if (hx_l[h] >= 0)
+                        Sf[hx_l[h]] = phx[f][h];
             }
-        }
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                bb[j] = pb[j];
+                kk[j] = pk[j];
+                gg[j] = ADJ ? pg[j] : 0.f;
+            }
+            if (z + 1 < z1)
+                prefetch(z + 1);
+            __syncthreads();
+
+            float* Cz = p.C + (long long)z * s0;
+            float* Gz = ADJ ? p.G + (long long)z * s0 : nullptr;
+            const long long rbase = (long long)z * n1;
+            const bool inj_any = p.inj.row_ptr[rbase + y0] < p.inj.row_ptr[rbase + ylast];
+            bool img_any = false;
+            if constexpr (ADJ)
+                img_any = p.img.row_ptr[rbase + y0] < p.img.row_ptr[rbase + ylast];
+            const int dzd = layer_depth(z, n0, d.nb);
+            const float ez = sp.e[0] * (float)(dzd * dzd);
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                if (!rin[j])
+                    continue;
+                const int ly = wy * RY + j;
+                const float* SA = S;
+                const float ctr = q[0][j][slot_c];
+                float az = 0.f, ay = 0.f, ax = 0.f;
+#pragma unroll
+                for (int qq = R; qq >= 1; --qq) {
+                    az = fmaf(cf.c[0][qq], q[0][j][(u + R + qq) % Q] + q[0][j][(u + R - qq) % Q], az);
+                    ay = fmaf(cf.c[1][qq], SA[(ly + R + qq) * LW + lx + R] + SA[(ly + R - qq) * LW + lx + R], ay);
+                    ax = fmaf(cf.c[2][qq], SA[(ly + R) * LW + lx + R + qq] + SA[(ly + R) * LW + lx + R - qq], ax);
+                }
+                float lap = fmaf(cf.c0, ctr, az + ay + ax);
+                if (inj_any)
+                    lap += row_signal(p.inj, rbase + y0 + ly, gx, p.inj_sig, p.inj_stride, p.step);
+                const float eta = ez + ey[j];
+                __builtin_nontemporal_store(leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt),
+                                            Cz + roff[j]);
+                if constexpr (ADJ) {
+                    const float* SU = S + (NF - 1) * PLANE;
+                    const float uc0 = q[NF - 1][j][slot_c];
+                    float uz = 0.f, uy = 0.f, ux = 0.f;
+#pragma unroll
+                    for (int qq = R; qq >= 1; --qq) {
+                        uz = fmaf(cf.c[0][qq], q[NF - 1][j][(u + R + qq) % Q] + q[NF - 1][j][(u + R - qq) % Q], uz);
+                        uy = fmaf(cf.c[1][qq], SU[(ly + R + qq) * LW + lx + R] + SU[(ly + R - qq) * LW + lx + R], uy);
+                        ux = fmaf(cf.c[2][qq], SU[(ly + R) * LW + lx + R + qq] + SU[(ly + R) * LW + lx + R - qq], ux);
+                    }
+                    float lu = fmaf(cf.c0, uc0, uz + uy + ux);
+                    if (img_any)
+                        lu += row_signal(p.img, rbase + y0 + ly, gx, p.img_sig, p.img_stride, p.step);
+                    __builtin_nontemporal_store(fmaf(ctr, lu, gg[j]), Gz + roff[j]);
+                }
+            }
+            buf ^= 1;
+            return true;
+        });
     }
 }
 
@@ -466,8 +616,10 @@ void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
     dim3 grid(ls.tile_blocks_pad + smp_blocks);
     if (d.nd == 2)
         hipLaunchKernelGGL((step2d_kernel<R, ADJ>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
+    else if (ls.ty == 4 * kWaves)
+        hipLaunchKernelGGL((step3d_kernel<R, ADJ, 4>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
     else
-        hipLaunchKernelGGL((step3d_kernel<R, ADJ>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
+        hipLaunchKernelGGL((step3d_kernel<R, ADJ, 2>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
 }
 
 int grid_for(long long n, int threads)
