@@ -149,10 +149,11 @@ int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* fo
                          int32_t* peak_fields);
 
 /* Tracing of the time loops.  While enabled on the calling thread, every solve
- * records a HIP event pair on its stream around its forward time loop and its
- * adjoint time loop.  stride_timing_read waits for the recorded events, returns
- * the summed loop times (ms) and step-kernel launch counts since the last read,
- * and clears them. */
+ * records HIP event pairs on its stream around its forward time loop, its
+ * adjoint time loop and each recomputation segment inside the adjoint loop.
+ * stride_timing_read waits for the recorded events and returns, since the last
+ * read, the time (ms) and launch count of forward steps (recomputation
+ * included) and of adjoint steps (recomputation excluded), then clears them. */
 int stride_timing_enable(int32_t on);
 int stride_timing_read(double* fwd_ms, int64_t* fwd_launches, double* adj_ms,
                        int64_t* adj_launches);

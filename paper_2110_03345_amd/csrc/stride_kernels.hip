@@ -80,6 +80,16 @@ __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int byte_off)
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
+// Streamed operands (read once per step: u^{n-1}, k, G) are loaded with the
+// non-temporal cache policy so they do not evict the stencil field's halo.
+#ifndef STRIDE_STREAM_AUX
+#define STRIDE_STREAM_AUX 2
+#endif
+__device__ __forceinline__ float bload_stream(__amdgpu_buffer_rsrc_t r, int byte_off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, STRIDE_STREAM_AUX));
+}
+
 __device__ __forceinline__ int layer_depth(int i, int n, int nb)
 {
     int hi = n - 1 - nb;
@@ -367,14 +377,14 @@ __global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf
         const auto rk = rsrc(p.K, z);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            pb[j] = bload(rb, rbo[j]);
-            pk[j] = bload(rk, rbo[j]);
+            pb[j] = bload_stream(rb, rbo[j]);
+            pk[j] = bload_stream(rk, rbo[j]);
         }
         if constexpr (ADJ) {
             const auto rg = rsrc(p.G, z);
 #pragma unroll
             for (int j = 0; j < RY; ++j)
-                pg[j] = bload(rg, rbo[j]);
+                pg[j] = bload_stream(rg, rbo[j]);
         }
     };
     prefetch(z0);
