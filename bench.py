@@ -51,21 +51,26 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forward", action="store_true")
+    ap.add_argument("--nt", type=int, default=0,
+                    help="override the number of time steps (profiling runs only)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run a 1 GiB device-to-device copy first (scale for HBM byte counters)")
     return ap.parse_args()
 
 
-def build_workload(name):
+def build_workload(name, nt=0):
     import numpy as np
     import workloads as W
+    kw = {"nt": nt} if nt else {}
     if name == "config2":
-        w = W.config2()
+        w = W.config2(**kw)
         vp_model = np.full(w.shape, 1500.0, dtype=np.float32)
         return w, w.vp, vp_model
     if name == "config3":
-        w = W.config3()
+        w = W.config3(**kw)
         return w, w.vp_true, w.vp_start
     if name == "config4":
-        w = W.config4()
+        w = W.config4(**kw)
         return w, w.vp_true, w.vp_start
     raise ValueError(name)
 
@@ -110,7 +115,13 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    w, vp_true, vp_model = build_workload(args.workload)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    w, vp_true, vp_model = build_workload(args.workload, args.nt)
     npad = w.padded_points
     print(f"[bench] {args.workload}: padded {w.padded_shape} = {npad} points, nt={w.nt}",
           file=sys.stderr, flush=True)

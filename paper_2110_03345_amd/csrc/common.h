@@ -75,18 +75,31 @@ struct StepParams {
     SampleSet smp;    // sampling of A at `step`
 };
 
+// One slot's step in a batched launch.
+struct SlotStep {
+    StepParams p;
+    SpongeCoef sp;
+    int active;
+};
+
 struct LaunchShape {
-    int ty;               // tile rows (kWaves x rows per thread)
+    int ty;               // tile rows (waves x rows per thread)
+    int ry, waves;        // rows per thread, wave64s per block
     int tiles_x, tiles_y, tiles_xy;
     int zc, nzc;          // 3D: planes per block and number of z chunks
     int tile_blocks;      // logical tile blocks (before XCD padding)
     int tile_blocks_pad;  // rounded up to a multiple of 8 XCDs
 };
 
-// Tile rows of the step kernels for a dimension and direction.
-int tile_rows(int nd, bool adjoint);
+// Rows per thread and waves per block of the step kernels for a dimension
+// and direction (the tile is 64 x ry*waves).
+void tile_shape(int nd, bool adjoint, int* ry, int* waves);
 
 // Kernel launchers (stride_kernels.hip).
+void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
+                         const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
+                         hipStream_t s);
+void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);

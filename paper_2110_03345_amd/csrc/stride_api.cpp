@@ -87,11 +87,14 @@ bool fd_weights(int order, double* c)
     return false;
 }
 
-LaunchShape make_shape(const Dims& d, int zc, int ty)
+LaunchShape make_shape(const Dims& d, int zc, int ry, int waves)
 {
     LaunchShape ls{};
     int nx = d.n[d.nd - 1], ny = d.n[d.nd - 2];
+    const int ty = ry * waves;
     ls.ty = ty;
+    ls.ry = ry;
+    ls.waves = waves;
     ls.tiles_x = (nx + kTileX - 1) / kTileX;
     ls.tiles_y = (ny + ty - 1) / ty;
     ls.tiles_xy = ls.tiles_x * ls.tiles_y;
@@ -776,9 +779,11 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         }
     P->sp.half_dt = (float)(0.5 * grid->dt);
 
-    int tyf = tile_rows(P->nd, false), tya = tile_rows(P->nd, true);
-    P->ls_fwd = make_shape(d, default_zc(d, P->R, tyf), tyf);
-    P->ls_adj = make_shape(d, default_zc(d, P->R, tya), tya);
+    int ryf, wf, rya, wa;
+    tile_shape(P->nd, false, &ryf, &wf);
+    tile_shape(P->nd, true, &rya, &wa);
+    P->ls_fwd = make_shape(d, default_zc(d, P->R, ryf * wf), ryf, wf);
+    P->ls_adj = make_shape(d, default_zc(d, P->R, rya * wa), rya, wa);
 
     std::vector<Tap> st, rt;
     if ((rc = make_taps(*P, src_xyz, nsrc, st, "source")) ||

@@ -23,16 +23,28 @@
 
 namespace stride {
 
-// Tile rows the kernels use (the host sizes launch shapes with these).
-int tile_rows(int nd, bool adjoint)
+// Tile shapes the kernels use (the host sizes launch shapes with these).
+// 3D defaults (fastest on 316^3): forward 4 rows x 4 waves, adjoint 2 rows x 4 waves.
+void tile_shape(int nd, bool adjoint, int* ry, int* waves)
 {
-    if (nd == 2)
-        return 16;
-    const char* e = getenv(adjoint ? "STRIDE_RY3D_ADJ" : "STRIDE_RY3D");
-    int ry = e && *e ? atoi(e) : (adjoint ? 2 : 4);
-    return (ry == 2 ? 2 : 4) * kWaves;
+    if (nd == 2) {
+        *ry = 4;
+        *waves = 4;
+        return;
+    }
+    const char* er = getenv(adjoint ? "STRIDE_RY3D_ADJ" : "STRIDE_RY3D");
+    const char* ew = getenv(adjoint ? "STRIDE_WAVES3D_ADJ" : "STRIDE_WAVES3D");
+    int r = er && *er ? atoi(er) : (adjoint ? 2 : 4);
+    int w = ew && *ew ? atoi(ew) : 4;
+    if (w != 8)
+        w = 4;
+    if (r != 1 && r != 2)
+        r = 4;
+    if (w == 4 && r == 1)
+        r = 2;
+    *ry = r;
+    *waves = w;
 }
-
 
 namespace {
 
@@ -112,7 +124,7 @@ __device__ __forceinline__ float row_signal(const RowTable& t, long long row, in
 __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* field, int step,
                                              int sb)
 {
-    int r = sb * kThreads + (int)threadIdx.x;
+    int r = sb * (int)blockDim.x + (int)threadIdx.x;
     if (r >= smp.count)
         return;
     float acc = 0.f;
@@ -140,8 +152,9 @@ __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float
 // LDS tile load.
 
 template <int R, bool ADJ>
-__global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
-                                                          StepParams p, LaunchShape ls)
+__device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf,
+                                            const SpongeCoef& sp, const StepParams& p,
+                                            const LaunchShape& ls, const int b)
 {
     constexpr int RY = 4;
     constexpr int TY = kWaves * RY;
@@ -150,7 +163,6 @@ __global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf
     __shared__ float sA[LH][LW];
     __shared__ float sU[ADJ ? LH : 1][ADJ ? LW : 1];
 
-    const int b = blockIdx.x;
     if (b >= ls.tile_blocks_pad) {
         sample_block(p.smp, p.A, p.step, b - ls.tile_blocks_pad);
         return;
@@ -249,23 +261,24 @@ __global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf
 // global accesses are raw buffer accesses with per-plane descriptors: offsets
 // outside the grid read 0 and drop stores, so no access needs a branch.
 
-template <int R, bool ADJ, int RY>
-__global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
-                                                          StepParams p, LaunchShape ls)
+template <int R, bool ADJ, int RY, int WAVES>
+__device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf,
+                                            const SpongeCoef& sp, const StepParams& p,
+                                            const LaunchShape& ls, const int b)
 {
-    constexpr int TY = kWaves * RY;
+    constexpr int NT = 64 * WAVES;
+    constexpr int TY = WAVES * RY;
     constexpr int LW = kTileX + 2 * R;
     constexpr int LH = TY + 2 * R;
     constexpr int Q = 2 * R + 1;
     constexpr int NYH = 2 * R * kTileX;             // halo rows above/below
     constexpr int NXH = 2 * R * TY;                 // halo columns left/right
-    constexpr int HY = (NYH + kThreads - 1) / kThreads;
-    constexpr int HX = (NXH + kThreads - 1) / kThreads;
+    constexpr int HY = (NYH + NT - 1) / NT;
+    constexpr int HX = (NXH + NT - 1) / NT;
     constexpr int NF = ADJ ? 2 : 1;                 // stencil fields: A (and U)
     constexpr int PLANE = LH * LW;
     __shared__ float sF[2][NF][PLANE];
 
-    const int b = blockIdx.x;
     if (b >= ls.tile_blocks_pad) {
         sample_block(p.smp, p.A, p.step, b - ls.tile_blocks_pad);
         return;
@@ -308,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf
     int hy_l[HY], hy_o[HY];
 #pragma unroll
     for (int h = 0; h < HY; ++h) {
-        const int i = tid + h * kThreads;
+        const int i = tid + h * NT;
         hy_l[h] = -1;
         hy_o[h] = -1;
         if (i < NYH) {
@@ -325,7 +338,7 @@ __global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf
     int hx_l[HX], hx_o[HX];
 #pragma unroll
     for (int h = 0; h < HX; ++h) {
-        const int i = tid + h * kThreads;
+        const int i = tid + h * NT;
         hx_l[h] = -1;
         hx_o[h] = -1;
         if (i < NXH) {
@@ -479,6 +492,47 @@ __global__ __launch_bounds__(kThreads) void step3d_kernel(Dims d, StencilCoef cf
     }
 }
 
+// ------------------------------------------------------------ kernel entry points
+//
+// Single shot: parameters by value.  Batched: blockIdx.y selects a slot whose
+// parameters (and sponge, which depends on the slot's dt) are read from a
+// device table; inactive slots exit at once.  Both run the same body, so a
+// shot computes the same bits alone and in a batch.
+
+template <int R, bool ADJ>
+__global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
+                                                          StepParams p, LaunchShape ls)
+{
+    step2d_body<R, ADJ>(d, cf, sp, p, ls, blockIdx.x);
+}
+
+template <int R, bool ADJ>
+__global__ __launch_bounds__(kThreads) void step2d_batched(Dims d, StencilCoef cf, LaunchShape ls,
+                                                           const SlotStep* table)
+{
+    const SlotStep st = table[blockIdx.y];
+    if (!st.active)
+        return;
+    step2d_body<R, ADJ>(d, cf, st.sp, st.p, ls, blockIdx.x);
+}
+
+template <int R, bool ADJ, int RY, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
+                                                            StepParams p, LaunchShape ls)
+{
+    step3d_body<R, ADJ, RY, WAVES>(d, cf, sp, p, ls, blockIdx.x);
+}
+
+template <int R, bool ADJ, int RY, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void step3d_batched(Dims d, StencilCoef cf, LaunchShape ls,
+                                                             const SlotStep* table)
+{
+    const SlotStep st = table[blockIdx.y];
+    if (!st.active)
+        return;
+    step3d_body<R, ADJ, RY, WAVES>(d, cf, st.sp, st.p, ls, blockIdx.x);
+}
+
 // ------------------------------------------------------------ small kernels
 
 __global__ void sample_kernel(SampleSet smp, const float* field, int step)
@@ -622,14 +676,58 @@ template <int R, bool ADJ>
 void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                    const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
-    int smp_blocks = (p.smp.count + kThreads - 1) / kThreads;
+    const int nt = d.nd == 2 ? kThreads : 64 * ls.waves;
+    int smp_blocks = (p.smp.count + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks);
-    if (d.nd == 2)
+    if (d.nd == 2) {
         hipLaunchKernelGGL((step2d_kernel<R, ADJ>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
-    else if (ls.ty == 4 * kWaves)
-        hipLaunchKernelGGL((step3d_kernel<R, ADJ, 4>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
-    else
-        hipLaunchKernelGGL((step3d_kernel<R, ADJ, 2>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
+        return;
+    }
+#define STRIDE_LAUNCH3D(RY_, W_)                                                                  \
+    hipLaunchKernelGGL((step3d_kernel<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, p, ls)
+    if (ls.waves == 8) {
+        if (ls.ry == 1)
+            STRIDE_LAUNCH3D(1, 8);
+        else if (ls.ry == 2)
+            STRIDE_LAUNCH3D(2, 8);
+        else
+            STRIDE_LAUNCH3D(4, 8);
+    } else {
+        if (ls.ry == 2)
+            STRIDE_LAUNCH3D(2, 4);
+        else
+            STRIDE_LAUNCH3D(4, 4);
+    }
+#undef STRIDE_LAUNCH3D
+}
+
+template <int R, bool ADJ>
+void launch_batched_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
+                      const SlotStep* table, int nslots, int max_samples, hipStream_t s)
+{
+    const int nt = d.nd == 2 ? kThreads : 64 * ls.waves;
+    int smp_blocks = (max_samples + nt - 1) / nt;
+    dim3 grid(ls.tile_blocks_pad + smp_blocks, nslots);
+    if (d.nd == 2) {
+        hipLaunchKernelGGL((step2d_batched<R, ADJ>), grid, dim3(kThreads), 0, s, d, cf, ls, table);
+        return;
+    }
+#define STRIDE_LAUNCH3DB(RY_, W_)                                                                  \
+    hipLaunchKernelGGL((step3d_batched<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, ls, table)
+    if (ls.waves == 8) {
+        if (ls.ry == 1)
+            STRIDE_LAUNCH3DB(1, 8);
+        else if (ls.ry == 2)
+            STRIDE_LAUNCH3DB(2, 8);
+        else
+            STRIDE_LAUNCH3DB(4, 8);
+    } else {
+        if (ls.ry == 2)
+            STRIDE_LAUNCH3DB(2, 4);
+        else
+            STRIDE_LAUNCH3DB(4, 4);
+    }
+#undef STRIDE_LAUNCH3DB
 }
 
 int grid_for(long long n, int threads)
@@ -651,6 +749,31 @@ void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, cons
         adjoint ? launch_step_t<4, true>(d, cf, sp, ls, p, s) : launch_step_t<4, false>(d, cf, sp, ls, p, s);
     else
         adjoint ? launch_step_t<5, true>(d, cf, sp, ls, p, s) : launch_step_t<5, false>(d, cf, sp, ls, p, s);
+}
+
+void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
+                         const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
+                         hipStream_t s)
+{
+    if (R == 4)
+        adjoint ? launch_batched_t<4, true>(d, cf, ls, table, nslots, max_samples, s)
+                : launch_batched_t<4, false>(d, cf, ls, table, nslots, max_samples, s);
+    else
+        adjoint ? launch_batched_t<5, true>(d, cf, ls, table, nslots, max_samples, s)
+                : launch_batched_t<5, false>(d, cf, ls, table, nslots, max_samples, s);
+}
+
+__global__ void accumulate_kernel(float* dst, const float* src, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        dst[i] += src[i];
+}
+
+void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(accumulate_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
 }
 
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s)
