@@ -37,6 +37,9 @@ WORKLOADS = {
                "model, binomial checkpointing within the HBM budget",
     "config3": "2D breast-like phantom, 512^2 at 0.2 mm + 40-cell sponge (592^2 padded), 8th order, "
                "1500 steps, shot 0 of the 64-shot ring survey; gradient at 1500 m/s",
+    "serving": "seeded Poisson stream of forward (70%) and gradient (30%) requests of 1-16 shots, each "
+               "with its own phantom and ring/hemisphere geometry; served with continuous batching vs "
+               "one request at a time through the plain entry points",
 }
 
 
@@ -53,6 +56,14 @@ def parse():
     ap.add_argument("--no-forward", action="store_true")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
+    ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
+    ap.add_argument("--full-mix", action="store_true",
+                    help="serving: all six grid classes and nt 500-3000 (default: 2D classes and "
+                         "128^3, nt 500-1500)")
+    ap.add_argument("--no-graphs", action="store_true", help="serving: direct launches, no hipGraphs")
+    ap.add_argument("--no-baseline", action="store_true", help="serving: skip the one-at-a-time run")
+    ap.add_argument("--load", type=float, default=1.5,
+                    help="serving: arrival rate in units of the one-at-a-time service rate")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (scale for HBM byte counters)")
     return ap.parse_args()
@@ -102,6 +113,85 @@ def cpu_baseline(w, vp_model, obs_np, seconds):
     }
 
 
+def serving_bench(args):
+    """Served shot solves per second and p50/p99 latency against one request at
+    a time, on the same seeded request stream."""
+    import numpy as np
+    import torch
+
+    from paper_2110_03345_amd.serving import Server, serve_one_at_a_time
+    from workloads.serving_mix import materialise, request_stream
+
+    if args.full_mix:
+        kw = dict(nt_range=(500, 3000), classes_2d=(256, 512, 1024), classes_3d=(128, 192, 256))
+    else:
+        kw = dict(nt_range=(500, 1500), classes_2d=(256, 512, 1024), classes_3d=(128,))
+    # calibration: one-at-a-time service time of a small sample sets the arrival rate
+    probe = [materialise(r) for r in request_stream(6, 99, 1.0, **kw)]
+    serve_one_at_a_time(probe[:1], realtime=False)
+    cal = serve_one_at_a_time(probe, realtime=False)
+    mean_service = cal["makespan_s"] / len(probe)
+    rate = args.load / mean_service
+    specs = [materialise(r) for r in request_stream(args.requests, 2024, rate, **kw)]
+    print(f"[bench] serving: {len(specs)} requests, {sum(r.nshots for r in specs)} shots, "
+          f"mean one-at-a-time service {mean_service * 1e3:.1f} ms, rate {rate:.2f}/s",
+          file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    srv = Server(use_graphs=not args.no_graphs)
+    try:
+        served = srv.run(specs, realtime=True)
+    finally:
+        srv.close()
+    print(f"[bench] served: {served['solves_per_s']:.1f} shot solves/s, p50 {served['p50_s']:.3f} s, "
+          f"p99 {served['p99_s']:.3f} s", file=sys.stderr, flush=True)
+    if args.no_baseline:
+        return
+    base = serve_one_at_a_time(specs, realtime=True)
+    print(f"[bench] one at a time: {base['solves_per_s']:.1f} shot solves/s, p50 {base['p50_s']:.3f} s, "
+          f"p99 {base['p99_s']:.3f} s", file=sys.stderr, flush=True)
+    # equal accuracy: every served request equals its one-at-a-time result
+    same = 0
+    for r, b in zip(sorted(served["requests"], key=lambda q: q.spec.arrival), base["results"]):
+        ok = all(torch.equal(x, y) for x, y in zip(r.result["traces"], b["traces"]))
+        if r.spec.kind == "gradient":
+            ok = ok and torch.equal(r.result["dvp"], b["dvp"])
+        same += int(ok)
+    line = {
+        "metric": "grid-point updates/s (fwd, fwd+adj), % HBM peak; served solves/s + p50/p99",
+        "value": served["solves_per_s"],
+        "unit": "shot solves/s (served)",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": served["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded request stream, phantoms and geometries)",
+        "config": {
+            "workload": f"serving: {WORKLOADS['serving']}",
+            "requests": len(specs),
+            "shots": served["shot_solves"],
+            "grid_classes": {"2d": list(kw["classes_2d"]), "3d": list(kw["classes_3d"])},
+            "nt_range": list(kw["nt_range"]),
+            "arrival_rate_per_s": rate,
+            "load": args.load,
+        },
+        "p50_s": served["p50_s"],
+        "p99_s": served["p99_s"],
+        "requests_per_s": served["requests_per_s"],
+        "peak_hbm_gb": served["peak_hbm_gb"],
+        "one_at_a_time": {k: base[k] for k in ("solves_per_s", "requests_per_s", "p50_s", "p99_s",
+                                               "makespan_s")},
+        "speedup_solves_per_s": served["solves_per_s"] / base["solves_per_s"],
+        "identical_results": f"{same}/{len(specs)}",
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -113,6 +203,9 @@ def main():
 
     import paper_2110_03345_amd as S
 
+    if args.workload == "serving":
+        torch.cuda.set_device(0)
+        return serving_bench(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:

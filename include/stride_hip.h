@@ -148,6 +148,58 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
 int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* forward_steps,
                          int32_t* peak_fields);
 
+/* ---------------------------------------------------------------- batching
+ * An engine advances many shots on one padded grid together (shot
+ * parallelism, Sec. 2.5, on one device): each slot holds one forward solve or
+ * one checkpointed shot gradient with its own model, geometry, nt, dt and
+ * sponge speed; a tick advances every active slot by one forward or adjoint
+ * step in one batched launch per direction.  Slots attach and detach between
+ * stride_engine_run calls (continuous batching).  A slot computes exactly the
+ * bits the one-shot entry points compute.  All calls on one engine must use
+ * the same stream and come from one thread. */
+typedef struct stride_engine stride_engine_t;
+
+/* grid fixes shape, spacing, space_order and sponge_cells (nt, dt and
+ * sponge_vref are per slot, taken from each plan).  max_receivers bounds the
+ * receivers of an attached plan; max_chunk bounds the ticks per run call
+ * (rounded down to a power of two); use_graphs replays each chunk as a
+ * captured hipGraph (needs a non-NULL stream).  Allocates the engine's slot
+ * tables (device and pinned host). */
+int stride_engine_create(const stride_grid_t* grid, int32_t max_slots, int32_t max_receivers,
+                         int32_t max_chunk, int32_t use_graphs, stride_engine_t** out);
+int stride_engine_destroy(stride_engine_t* engine);
+
+/* Attaches one shot to a free slot and enqueues its setup on stream.  mode
+ * FORWARD needs traces; mode GRADIENT needs observed, misfit (device FP64
+ * scalar) and dvp, traces optional.  ws / ws_bytes: a workspace sized with
+ * stride_workspace_bytes for the mode (gradient snapshots follow ws_bytes).
+ * vp_max > 0 is the caller's maximum of vp for the CFL check; vp_max <= 0
+ * reads it from the device (one stream sync).  Buffers must stay valid until
+ * the slot finishes.  Errors: INVALID_ARG (grid mismatch, no free slot, too
+ * many receivers), CFL, WORKSPACE. */
+int stride_engine_attach(stride_engine_t* engine, const stride_plan_t* plan, int32_t mode,
+                         const float* vp, float vp_max, const float* wavelet,
+                         const float* observed, float* traces, double* misfit, float* dvp,
+                         void* ws, size_t ws_bytes, void* stream, int32_t* slot);
+
+/* Enqueues one chunk of ticks (a power of two, at most max_ticks; shorter
+ * only when every slot ends its phase sooner; a slot whose phase ends inside
+ * the chunk idles to its end) and the phase-end work of slots that reach it.  *ticks_run is the
+ * number of ticks enqueued (0 when no slot is active); finished[slot] is set
+ * to 1 (array of max_slots, may be NULL) for slots whose outputs are complete
+ * once the stream reaches this point. */
+int stride_engine_run(stride_engine_t* engine, int32_t max_ticks, void* stream,
+                      int32_t* ticks_run, int32_t* finished);
+
+/* Frees a slot (after it finished, or to abandon it). */
+int stride_engine_detach(stride_engine_t* engine, int32_t slot);
+
+/* Ticks a slot still needs (0 once finished). */
+int stride_engine_slot_ticks(const stride_engine_t* engine, int32_t slot, int64_t* ticks_left);
+
+/* dst[i] += src[i] on the device (shot-gradient summation in a fixed order). */
+int stride_accumulate(float* dst, const float* src, int64_t n, void* stream);
+
 /* Tracing of the time loops.  While enabled on the calling thread, every solve
  * records HIP event pairs on its stream around its forward time loop, its
  * adjoint time loop and each recomputation segment inside the adjoint loop.

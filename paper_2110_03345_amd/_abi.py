@@ -31,6 +31,8 @@ EXPORTS = (
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
     "stride_schedule_info", "stride_last_error", "stride_error_string",
     "stride_timing_enable", "stride_timing_read",
+    "stride_engine_create", "stride_engine_destroy", "stride_engine_attach", "stride_engine_run",
+    "stride_engine_detach", "stride_engine_slot_ticks", "stride_accumulate",
 )
 
 
@@ -84,6 +86,14 @@ def lib():
         L.stride_timing_enable.argtypes = [i32]
         L.stride_timing_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp,
                                          ctypes.POINTER(ctypes.c_int64)]
+        L.stride_engine_create.argtypes = [gp, i32, i32, i32, i32, ctypes.POINTER(vp_)]
+        L.stride_engine_destroy.argtypes = [vp_]
+        L.stride_engine_attach.argtypes = [vp_, vp_, i32, vp_, ctypes.c_float, vp_, vp_, vp_, vp_, vp_,
+                                           vp_, sz, vp_, ctypes.POINTER(i32)]
+        L.stride_engine_run.argtypes = [vp_, i32, vp_, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.stride_engine_detach.argtypes = [vp_, i32]
+        L.stride_engine_slot_ticks.argtypes = [vp_, i32, ctypes.POINTER(ctypes.c_int64)]
+        L.stride_accumulate.argtypes = [vp_, vp_, ctypes.c_int64, vp_]
         L.stride_last_error.restype = ctypes.c_char_p
         L.stride_error_string.restype = ctypes.c_char_p
         L.stride_error_string.argtypes = [ctypes.c_int]
@@ -237,6 +247,49 @@ def stride_gradient(grid: stride_grid_t, vp, wavelet, src_xyz, rec_xyz, observed
     _check(lib().stride_gradient(ctypes.byref(grid), _dev(vp), _dev(wavelet), src.shape[0], _dp(src),
                                  rec.shape[0], _dp(rec), _dev(observed), _dev(misfit), _dev(dvp),
                                  _dev(ws), ws.numel(), _stream(stream)))
+
+
+def stride_engine_create(grid: stride_grid_t, max_slots: int, max_receivers: int, max_chunk: int,
+                         use_graphs: bool) -> ctypes.c_void_p:
+    out = ctypes.c_void_p()
+    _check(lib().stride_engine_create(ctypes.byref(grid), max_slots, max_receivers, max_chunk,
+                                      1 if use_graphs else 0, ctypes.byref(out)))
+    return out
+
+
+def stride_engine_destroy(engine) -> None:
+    _check(lib().stride_engine_destroy(engine))
+
+
+def stride_engine_attach(engine, plan, mode, vp, vp_max, wavelet, observed, traces, misfit, dvp,
+                         ws, stream=None) -> int:
+    slot = ctypes.c_int32(-1)
+    _check(lib().stride_engine_attach(engine, plan, mode, _dev(vp), float(vp_max), _dev(wavelet),
+                                      _dev(observed), _dev(traces), _dev(misfit), _dev(dvp), _dev(ws),
+                                      ws.numel(), _stream(stream), ctypes.byref(slot)))
+    return int(slot.value)
+
+
+def stride_engine_run(engine, max_ticks: int, max_slots: int, stream=None):
+    """(ticks enqueued, list of slots finished by this call)."""
+    ticks = ctypes.c_int32(0)
+    fin = (ctypes.c_int32 * max_slots)()
+    _check(lib().stride_engine_run(engine, max_ticks, _stream(stream), ctypes.byref(ticks), fin))
+    return int(ticks.value), [i for i in range(max_slots) if fin[i]]
+
+
+def stride_engine_detach(engine, slot: int) -> None:
+    _check(lib().stride_engine_detach(engine, slot))
+
+
+def stride_engine_slot_ticks(engine, slot: int) -> int:
+    out = ctypes.c_int64(0)
+    _check(lib().stride_engine_slot_ticks(engine, slot, ctypes.byref(out)))
+    return int(out.value)
+
+
+def stride_accumulate(dst, src, stream=None) -> None:
+    _check(lib().stride_accumulate(_dev(dst), _dev(src), dst.numel(), _stream(stream)))
 
 
 # ------------------------------------------------------------- Plan object

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstride_hip.so")
-SOURCES = ["csrc/stride_kernels.hip", "csrc/stride_api.cpp", "csrc/revolve.cpp"]
+SOURCES = ["csrc/stride_kernels.hip", "csrc/stride_api.cpp", "csrc/stride_engine.cpp",
+           "csrc/revolve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("STRIDE_ARCH", "gfx950")
 
@@ -23,10 +24,7 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(build_dir, os.path.basename(src) + ".o")
         cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
                "-I" + os.path.join(ROOT, "include"), "-c", path, "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = ["-x", "hip"] + GPU_FLAGS
-        else:
-            cmd[1:1] = ["-x", "hip"] + GPU_FLAGS
+        cmd[1:1] = ["-x", "hip"] + GPU_FLAGS
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -1,0 +1,126 @@
+// Internal: the plan object, workspace layout, error reporting and the
+// step cursor over a checkpointing schedule, shared by the one-shot
+// executors (stride_api.cpp) and the batching engine (stride_engine.cpp).
+#pragma once
+
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/stride_hip.h"
+#include "common.h"
+#include "revolve.h"
+
+struct stride_plan {
+    stride_grid_t g;
+    int nd, R, nb, nt;
+    stride::Dims dims;
+    stride::StencilCoef cf;
+    stride::SpongeCoef sp;
+    stride::LaunchShape ls_fwd, ls_adj;
+    double nyquist;      // -(c0 + 2 sum_j cj (-1)^j): largest eigenvalue of -L per axis
+    double cellvol;
+    int nsrc, nrec;
+    int device;
+    void* blob;          // device memory of the tables below
+    stride::RowTable src_inj;    // sources, weights / cell volume
+    stride::RowTable rec_inj;    // receivers (adjoint injection), weights
+    const long long* rec_idx;
+    const float* rec_w;          // receiver sampling
+    const long long* src_idx;
+    const float* src_w;          // source sampling (adjoint w.r.t. the wavelet), weights / cell volume
+};
+
+namespace stride {
+
+// Records the calling thread's last error message and returns `code`.
+int fail(int code, const char* fmt, ...);
+
+#define STRIDE_HIP_TRY(expr)                                                                \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return ::stride::fail(STRIDE_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+struct Layout {
+    size_t field;      // bytes per wavefield
+    size_t scratch;    // small scalars
+    size_t traces;     // nrec * nt floats
+    size_t fixed_fwd;  // scratch + k + 2 fields
+    size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual
+};
+
+Layout layout_of(const stride_plan& P);
+
+// Views of a gradient workspace: [scratch | k | G | w0 | w1 | traces | residual | pool...].
+struct GradWs {
+    unsigned* flags;   // [0] = max vp bits, [1] = bad-value flag
+    float* k;
+    float* G;
+    float* w[2];
+    float* traces;
+    float* residual;
+    std::vector<float*> pool;
+    int snaps;
+};
+
+int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W);
+
+// Views of a forward workspace: [scratch | k | u0 | u1].
+struct FwdWs {
+    unsigned* flags;
+    float* k;
+    float* u[2];
+};
+
+int fwd_ws(const stride_plan& P, void* ws, size_t bytes, FwdWs& F);
+
+// Leapfrog stability bound for a known maximum speed.
+int check_cfl(const stride_plan& P, double vmax);
+
+// max(vp) and the bad-value flag read back from the device (one stream sync).
+int check_vp(const stride_plan& P, const float* vp, unsigned* flags, hipStream_t s);
+
+StepParams base_params(const stride_plan& P);
+
+// One step of a checkpointed gradient solve.
+struct StepOp {
+    bool reverse;      // adjoint step at `step` (field a = u^step); else forward step
+    int step;          // forward: n (u^n -> u^{n+1}); adjoint: m
+    int a, b, c;       // pool fields: forward A = u^n, B = u^{n-1}, C = u^{n+1}
+    bool first_sweep;  // forward step before the first adjoint step (records traces)
+};
+
+// Walks a binomial checkpointing schedule over a reference-counted pool of
+// wavefields, one forward or adjoint step at a time.  Store / Free / Restore
+// are pure bookkeeping (no copies): a stored state keeps its two fields
+// pinned; a step writes in place when its u^{n-1} field is pinned by nothing
+// else, and into a free field otherwise.  Fields 0 and 1 hold x_0 = (0, 0).
+class StepCursor {
+  public:
+    StepCursor(int nt, int snaps, int pool_fields);
+    bool next(StepOp& op);           // false when the schedule is finished
+    void unget(const StepOp& op);    // push back one op (to stop before it)
+    bool overflow() const { return overflow_; }
+    int cur() const { return cur_; }
+    long long forward_steps() const { return cs_->stats.forward_steps; }
+
+  private:
+    int alloc();
+    void release(int f);
+
+    std::shared_ptr<const CachedSchedule> cs_;
+    size_t pc_ = 0;
+    std::vector<int> ref_;
+    std::vector<int> freelist_;
+    std::unordered_map<int, std::pair<int, int>> snaps_;
+    int cur_ = 0, prev_ = 1, idx_ = 0;
+    int target_ = -1;
+    bool reversed_ = false;
+    bool overflow_ = false;
+    bool have_back_ = false;
+    StepOp back_{};
+};
+
+}  // namespace stride

@@ -2,8 +2,6 @@
 // bi/tri-linear taps, per-tile injection tables), workspace layout, the
 // forward and adjoint time loops, binomial checkpointing over a pool of
 // wavefields, and the exported C ABI (include/stride_hip.h).
-#include "../../include/stride_hip.h"
-
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -14,36 +12,15 @@
 #include <unordered_map>
 #include <vector>
 
-#include "common.h"
-#include "revolve.h"
+#include "plan.h"
 
 using namespace stride;
 
-struct stride_plan {
-    stride_grid_t g;
-    int nd, R, nb, nt;
-    Dims dims;
-    StencilCoef cf;
-    SpongeCoef sp;
-    LaunchShape ls_fwd, ls_adj;
-    double nyquist;      // -(c0 + 2 sum_j cj (-1)^j): largest eigenvalue of -L per axis
-    double cellvol;
-    int nsrc, nrec;
-    int device;
-    void* blob;          // device memory of the tables below
-    RowTable src_inj;    // sources, weights / cell volume
-    RowTable rec_inj;    // receivers (adjoint injection), weights
-    const long long* rec_idx;
-    const float* rec_w;  // receiver sampling
-    const long long* src_idx;
-    const float* src_w;  // source sampling (adjoint w.r.t. the wavelet), weights / cell volume
-};
-
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
-int fail(int code, const char* fmt, ...)
+int stride::fail(int code, const char* fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -54,12 +31,9 @@ int fail(int code, const char* fmt, ...)
     return code;
 }
 
-#define HIP_TRY(expr)                                                                    \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(STRIDE_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));    \
-    } while (0)
+#define HIP_TRY(expr) STRIDE_HIP_TRY(expr)
+
+namespace {
 
 long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
 
@@ -261,17 +235,11 @@ int validate_grid(const stride_grid_t* g)
     return STRIDE_OK;
 }
 
+}  // namespace
+
 // ------------------------------------------------------------ workspace
 
-struct Layout {
-    size_t field;      // bytes per wavefield
-    size_t scratch;    // small scalars
-    size_t traces;     // nrec * nt floats
-    size_t fixed_fwd;  // scratch + k + 2 fields
-    size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual
-};
-
-Layout layout_of(const stride_plan& P)
+Layout stride::layout_of(const stride_plan& P)
 {
     Layout L;
     L.field = (size_t)round_up(P.dims.total * 4, 256);
@@ -282,18 +250,7 @@ Layout layout_of(const stride_plan& P)
     return L;
 }
 
-struct GradWs {
-    unsigned* flags;   // [0] = max vp bits, [1] = bad-value flag
-    float* k;
-    float* G;
-    float* w[2];
-    float* traces;
-    float* residual;
-    std::vector<float*> pool;
-    int snaps;
-};
-
-int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
+int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
 {
     Layout L = layout_of(P);
     if (!ws)
@@ -332,13 +289,37 @@ int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
     return STRIDE_OK;
 }
 
-}  // namespace
+int stride::fwd_ws(const stride_plan& P, void* ws, size_t bytes, FwdWs& F)
+{
+    Layout L = layout_of(P);
+    if (!ws || (uintptr_t)ws % 256)
+        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.fixed_fwd)
+        return fail(STRIDE_E_WORKSPACE, "forward workspace needs %zu bytes (got %zu)", L.fixed_fwd,
+                    bytes);
+    char* b = (char*)ws;
+    F.flags = (unsigned*)b;
+    F.k = (float*)(b + L.scratch);
+    F.u[0] = (float*)(b + L.scratch + L.field);
+    F.u[1] = (float*)(b + L.scratch + 2 * L.field);
+    return STRIDE_OK;
+}
 
-namespace {
+int stride::check_cfl(const stride_plan& P, double vmax)
+{
+    double inv2 = 0;
+    for (int a = 0; a < P.nd; ++a)
+        inv2 += 1.0 / (P.g.spacing[a] * P.g.spacing[a]);
+    double courant = P.g.dt * vmax * std::sqrt(P.nyquist * inv2);
+    if (!(courant <= 2.0))
+        return fail(STRIDE_E_CFL,
+                    "dt %g with vp_max %g violates the leapfrog stability limit "
+                    "(dt vp sqrt(lambda sum 1/dx^2) = %.4f > 2)",
+                    P.g.dt, vmax, courant);
+    return STRIDE_OK;
+}
 
-// Reads max(vp) and a bad-value flag back from the device (one stream sync)
-// and applies the leapfrog stability bound.
-int check_vp(const stride_plan& P, const float* vp, unsigned* flags, hipStream_t s)
+int stride::check_vp(const stride_plan& P, const float* vp, unsigned* flags, hipStream_t s)
 {
     long long n = 1;
     for (int a = 0; a < P.nd; ++a)
@@ -351,19 +332,10 @@ int check_vp(const stride_plan& P, const float* vp, unsigned* flags, hipStream_t
         return fail(STRIDE_E_INVALID_ARG, "vp contains non-positive or non-finite values");
     float vmax;
     std::memcpy(&vmax, &host[0], sizeof(float));
-    double inv2 = 0;
-    for (int a = 0; a < P.nd; ++a)
-        inv2 += 1.0 / (P.g.spacing[a] * P.g.spacing[a]);
-    double courant = P.g.dt * vmax * std::sqrt(P.nyquist * inv2);
-    if (courant > 2.0)
-        return fail(STRIDE_E_CFL,
-                    "dt %g with vp_max %g violates the leapfrog stability limit "
-                    "(dt vp sqrt(lambda sum 1/dx^2) = %.4f > 2)",
-                    P.g.dt, (double)vmax, courant);
-    return STRIDE_OK;
+    return check_cfl(P, vmax);
 }
 
-StepParams base_params(const stride_plan& P)
+StepParams stride::base_params(const stride_plan& P)
 {
     StepParams p{};
     p.inj = P.src_inj;
@@ -372,6 +344,116 @@ StepParams base_params(const stride_plan& P)
     p.img_stride = P.nt;
     return p;
 }
+
+// ------------------------------------------------------------ step cursor
+
+StepCursor::StepCursor(int nt, int snaps, int pool_fields) : cs_(cached_schedule(nt, snaps))
+{
+    ref_.assign(pool_fields, 0);
+    for (int f = pool_fields - 1; f >= 2; --f)
+        freelist_.push_back(f);
+    ref_[0] = ref_[1] = 1;
+}
+
+int StepCursor::alloc()
+{
+    if (freelist_.empty()) {
+        overflow_ = true;
+        return -1;
+    }
+    int f = freelist_.back();
+    freelist_.pop_back();
+    ref_[f] = 1;
+    return f;
+}
+
+void StepCursor::release(int f)
+{
+    if (--ref_[f] == 0)
+        freelist_.push_back(f);
+}
+
+void StepCursor::unget(const StepOp& op)
+{
+    back_ = op;
+    have_back_ = true;
+}
+
+bool StepCursor::next(StepOp& op)
+{
+    if (have_back_) {
+        have_back_ = false;
+        op = back_;
+        return true;
+    }
+    const std::vector<Action>& sched = cs_->actions;
+    while (!overflow_) {
+        if (target_ >= 0 && idx_ < target_) {
+            // one forward step of the current Advance
+            int old_prev = prev_;
+            int out = ref_[prev_] == 1 ? prev_ : alloc();
+            if (out < 0)
+                return false;
+            op = StepOp{false, idx_, cur_, old_prev, out, !reversed_};
+            if (out != old_prev)
+                release(old_prev);
+            prev_ = cur_;
+            cur_ = out;
+            ++idx_;
+            if (idx_ >= target_) {
+                target_ = -1;
+                ++pc_;
+            }
+            return true;
+        }
+        if (pc_ >= sched.size())
+            return false;
+        const Action& a = sched[pc_];
+        switch (a.type) {
+        case Act::Advance:
+            if (idx_ < a.step) {
+                target_ = a.step;
+                continue;
+            }
+            ++pc_;
+            continue;
+        case Act::Store:
+            snaps_[a.step] = {cur_, prev_};
+            ++ref_[cur_];
+            ++ref_[prev_];
+            ++pc_;
+            continue;
+        case Act::Free: {
+            auto it = snaps_.find(a.step);
+            release(it->second.first);
+            release(it->second.second);
+            snaps_.erase(it);
+            ++pc_;
+            continue;
+        }
+        case Act::Restore: {
+            auto it = snaps_.find(a.step);
+            release(cur_);
+            release(prev_);
+            cur_ = it->second.first;
+            prev_ = it->second.second;
+            ++ref_[cur_];
+            ++ref_[prev_];
+            idx_ = a.step;
+            ++pc_;
+            continue;
+        }
+        case Act::Reverse:
+            op = StepOp{true, a.step, cur_, -1, -1, false};
+            reversed_ = true;
+            ++pc_;
+            return true;
+        }
+    }
+    return false;
+}
+
+namespace {
 
 // ------------------------------------------------------------ phase timing
 
@@ -425,159 +507,80 @@ thread_local PhaseTimer g_timer;
 
 // ------------------------------------------------------------ executors
 
-// Replays a checkpointing schedule over the wavefield pool.  forward_phase
-// runs the forward sweep up to the first reverse operation (sampling traces on
-// every step, since the first descent visits each index once); called with
-// run = false it only replays the bookkeeping, which stride_backward uses to
-// find the pool state the forward sweep left behind.  backward_phase then
-// runs the recomputation and adjoint steps.
+// Runs a checkpointed gradient on one stream.  forward_phase launches the
+// forward sweep up to the first adjoint step (recording traces: the first
+// sweep visits every index once); with run = false it only replays the
+// bookkeeping, which stride_backward uses to find the pool state the forward
+// sweep left behind.  backward_phase launches recomputation and adjoint steps.
 struct Runner {
     const stride_plan& P;
     GradWs& W;
     hipStream_t s;
     const float* wavelet;
-    std::vector<int> ref;
-    std::vector<int> freelist;
-    std::unordered_map<int, std::pair<int, int>> snaps;
-    int cur = 0, prev = 1, idx = 0;
-    std::shared_ptr<const CachedSchedule> cs;
-    const std::vector<Action>& sched;
-    size_t pc = 0;
-
-    Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
-        : P(p), W(w), s(st), wavelet(wav), cs(cached_schedule(p.nt, w.snaps)), sched(cs->actions)
-    {
-        ref.assign(W.pool.size(), 0);
-        for (int f = (int)W.pool.size() - 1; f >= 2; --f)
-            freelist.push_back(f);
-        ref[0] = ref[1] = 1;
-    }
-
-    bool overflow = false;   // the schedule needed more fields than the pool holds
+    StepCursor cursor;
     long long launches = 0;      // forward step launches
     long long adj_launches = 0;  // adjoint step launches
 
-    int alloc()
+    Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
+        : P(p), W(w), s(st), wavelet(wav), cursor(p.nt, w.snaps, (int)w.pool.size())
     {
-        if (freelist.empty()) {
-            overflow = true;
-            return -1;
-        }
-        int f = freelist.back();
-        freelist.pop_back();
-        ref[f] = 1;
-        return f;
-    }
-    void release(int f)
-    {
-        if (--ref[f] == 0)
-            freelist.push_back(f);
     }
 
-    void fwd_step(bool run, float* traces)
+    void fwd_launch(const StepOp& op, float* traces)
     {
-        int old_prev = prev;
-        int out;
-        if (ref[prev] == 1) {
-            out = prev;
-        } else {
-            out = alloc();
-            if (out < 0)
-                return;
-        }
-        if (run) {
-            StepParams p = base_params(P);
-            p.A = W.pool[cur];
-            p.B = W.pool[old_prev];
-            p.C = W.pool[out];
-            p.K = W.k;
-            p.step = idx;
-            p.inj_sig = wavelet;
-            if (traces)
-                p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
-            launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
-            ++launches;
-        }
-        if (out != old_prev)
-            release(old_prev);
-        prev = cur;
-        cur = out;
-        ++idx;
+        StepParams p = base_params(P);
+        p.A = W.pool[op.a];
+        p.B = W.pool[op.b];
+        p.C = W.pool[op.c];
+        p.K = W.k;
+        p.step = op.step;
+        p.inj_sig = wavelet;
+        if (traces && op.first_sweep)
+            p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+        launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
+        ++launches;
     }
 
-    // Executes actions until the first Reverse (phase 0) or to the end
-    // (phase 1).  `run` false replays bookkeeping only.
     void forward_phase(bool run, float* traces)
     {
-        for (; pc < sched.size() && !overflow; ++pc) {
-            const Action& a = sched[pc];
-            if (a.type == Act::Reverse)
+        StepOp op;
+        while (cursor.next(op)) {
+            if (op.reverse) {
+                cursor.unget(op);
                 return;
-            apply_bookkeeping(a, run, traces);
+            }
+            if (run)
+                fwd_launch(op, traces);
         }
     }
 
-    void apply_bookkeeping(const Action& a, bool run, float* traces)
-    {
-        switch (a.type) {
-        case Act::Advance:
-            while (idx < a.step && !overflow)
-                fwd_step(run, traces);
-            break;
-        case Act::Store:
-            snaps[a.step] = {cur, prev};
-            ++ref[cur];
-            ++ref[prev];
-            break;
-        case Act::Free: {
-            auto it = snaps.find(a.step);
-            release(it->second.first);
-            release(it->second.second);
-            snaps.erase(it);
-            break;
-        }
-        case Act::Restore: {
-            auto it = snaps.find(a.step);
-            release(cur);
-            release(prev);
-            cur = it->second.first;
-            prev = it->second.second;
-            ++ref[cur];
-            ++ref[prev];
-            idx = a.step;
-            break;
-        }
-        case Act::Reverse:
-            break;
-        }
-    }
-
-    // Phase 1: recomputation and adjoint steps.
     void backward_phase(const float* grad_traces, float* dwavelet)
     {
         int wa = 0;   // W.w[wa] = w^{m+1}, W.w[1-wa] = w^{m+2}
-        for (; pc < sched.size() && !overflow; ++pc) {
-            const Action& a = sched[pc];
-            if (a.type == Act::Advance) {
-                long long before = launches;
-                int tid = g_timer.begin(s);
-                apply_bookkeeping(a, true, nullptr);
-                g_timer.end(tid, s, 2, launches - before);
+        int seg = -1;
+        long long seg_start = 0;
+        StepOp op;
+        while (cursor.next(op)) {
+            if (!op.reverse) {
+                if (seg < 0) {
+                    seg = g_timer.begin(s);
+                    seg_start = launches;
+                }
+                fwd_launch(op, nullptr);
                 continue;
             }
-            if (a.type != Act::Reverse) {
-                apply_bookkeeping(a, true, nullptr);
-                continue;
+            if (seg >= 0) {
+                g_timer.end(seg, s, 2, launches - seg_start);
+                seg = -1;
             }
-            int m = a.step;
             StepParams p = base_params(P);
             p.A = W.w[wa];
             p.B = W.w[1 - wa];
             p.C = W.w[1 - wa];
             p.K = W.k;
-            p.U = W.pool[cur];
+            p.U = W.pool[op.a];
             p.G = W.G;
-            p.step = m;
+            p.step = op.step;
             p.inj = P.rec_inj;
             p.inj_sig = grad_traces;
             p.inj_stride = P.nt;
@@ -590,25 +593,23 @@ struct Runner {
             ++adj_launches;
             wa = 1 - wa;
         }
+        if (seg >= 0)
+            g_timer.end(seg, s, 2, launches - seg_start);
     }
 };
 
 int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
                   void* ws, size_t bytes, hipStream_t s)
 {
-    Layout L = layout_of(P);
     if (!vp || !wavelet || !traces)
         return fail(STRIDE_E_INVALID_ARG, "vp, wavelet and traces must be device pointers");
-    if (!ws || (uintptr_t)ws % 256)
-        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
-    if (bytes < L.fixed_fwd)
-        return fail(STRIDE_E_WORKSPACE, "forward workspace needs %zu bytes (got %zu)", L.fixed_fwd,
-                    bytes);
-    char* b = (char*)ws;
-    unsigned* flags = (unsigned*)b;
-    float* k = (float*)(b + L.scratch);
-    float* u[2] = {(float*)(b + L.scratch + L.field), (float*)(b + L.scratch + 2 * L.field)};
-    int rc = check_vp(P, vp, flags, s);
+    FwdWs F;
+    int rc = fwd_ws(P, ws, bytes, F);
+    if (rc)
+        return rc;
+    float* k = F.k;
+    float* const* u = F.u;
+    rc = check_vp(P, vp, F.flags, s);
     if (rc)
         return rc;
     launch_prep_k(P.dims, vp, P.g.dt, k, s);
@@ -653,10 +654,10 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     int tid = g_timer.begin(s);
     run.forward_phase(true, tr);
     g_timer.end(tid, s, 0, run.launches);
-    if (run.overflow)
+    if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     // last sample from the final state x_{nt-1}
-    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, tr, P.nt}, W.pool[run.cur], P.nt - 1, s);
+    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, tr, P.nt}, W.pool[run.cursor.cur()], P.nt - 1, s);
     if (traces && traces != W.traces)
         launch_copy(W.traces, traces, (long long)P.nrec * P.nt, s);
     HIP_TRY(hipGetLastError());
@@ -680,7 +681,7 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     int tid = g_timer.begin(s);
     run.backward_phase(grad_traces, dwavelet);
     g_timer.end(tid, s, 1, run.adj_launches);
-    if (run.overflow)
+    if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     launch_finalize_dvp(P.dims, W.G, vp, dvp, s);
     HIP_TRY(hipGetLastError());
