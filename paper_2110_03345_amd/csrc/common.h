@@ -11,7 +11,6 @@ namespace stride {
 constexpr int kMaxR = 5;        // stencil radius (10th order)
 constexpr int kThreads = 256;   // 4 wave64 per block
 constexpr int kTileX = 64;      // contiguous axis: one wave64 spans a tile row
-constexpr int kWaves = 4;       // waves per block, stacked along the row axis
 constexpr int kMaxTaps = 8;
 
 // Padded grid as laid out in the workspace.  Axis nd-1 is contiguous.
@@ -38,15 +37,30 @@ struct SpongeCoef {
     float half_dt;
 };
 
+// One injection entry of a 2D tile: adds w * sig[id][step] at tile-local
+// point `local` (= row * 64 + column within the tile).  A tile's entries are
+// sorted by point, in (point, tap) order within a point; the first entry of a
+// point holds the number of entries of that point in `run`, the others 0.
+struct TileEntry {
+    int local;
+    int run;
+    int id;
+    float w;
+};
+
 // Grid points that receive an injected signal, grouped by grid row (every
 // axis but the contiguous one: row = i0 in 2D, i0 * n1 + i1 in 3D).  Entries
 // of row r are [row_ptr[r], row_ptr[r+1]); entry e adds w[e] * sig[id[e]][step]
-// at column x[e] of that row, in entry order.
+// at column x[e] of that row, in entry order.  In 2D the same entries are also
+// grouped by tile of the launch shape that uses the table: tile t holds
+// tile_ent[tile_ptr[t] .. tile_ptr[t+1]).
 struct RowTable {
     const int* row_ptr;
     const int* x;
     const int* id;
     const float* w;
+    const int* tile_ptr;
+    const TileEntry* tile_ent;
 };
 
 // Point sampling: out[r * out_stride + step] = sum_t w[r*8+t] * field[idx[r*8+t]].
@@ -105,9 +119,13 @@ void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, cons
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s);
+// Misfit partial sums: kMisfitParts doubles of scratch.
+constexpr int kMisfitParts = 256;
 void launch_residual_misfit(const float* traces, const float* observed, float* residual,
-                            long long n, double* misfit, hipStream_t s);
-void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, hipStream_t s);
+                            long long n, double* misfit, double* partial, hipStream_t s);
+// dvp = P^T (2 G / vp_pad); tmp0 and tmp1 hold intermediates of up to one field each.
+void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, float* tmp0,
+                         float* tmp1, hipStream_t s);
 void launch_copy(float* dst, const float* src, long long n, hipStream_t s);
 // flags[0] = bits of max(vp) (vp > 0), flags[1] = 1 if any vp <= 0 or non-finite.
 void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s);

@@ -23,8 +23,9 @@ struct stride_plan {
     int nsrc, nrec;
     int device;
     void* blob;          // device memory of the tables below
-    stride::RowTable src_inj;    // sources, weights / cell volume
-    stride::RowTable rec_inj;    // receivers (adjoint injection), weights
+    stride::RowTable src_inj;    // sources, weights / cell volume (tiles of ls_fwd)
+    stride::RowTable src_img;    // the same entries, tiles of ls_adj (imaging source term)
+    stride::RowTable rec_inj;    // receivers (adjoint injection), weights (tiles of ls_adj)
     const long long* rec_idx;
     const float* rec_w;          // receiver sampling
     const long long* src_idx;
@@ -56,6 +57,7 @@ Layout layout_of(const stride_plan& P);
 // Views of a gradient workspace: [scratch | k | G | w0 | w1 | traces | residual | pool...].
 struct GradWs {
     unsigned* flags;   // [0] = max vp bits, [1] = bad-value flag
+    double* partial;   // misfit partial sums
     float* k;
     float* G;
     float* w[2];

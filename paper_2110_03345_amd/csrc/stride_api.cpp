@@ -191,6 +191,51 @@ HostTable build_rows(const stride_plan& P, const std::vector<Tap>& taps, double 
     return T;
 }
 
+struct HostTiles {
+    std::vector<int> ptr;
+    std::vector<TileEntry> ent;
+};
+
+// 2D: the entries of build_rows grouped by tile of a launch shape, sorted by
+// tile-local point and in (point, tap) order within a point (the order in
+// which the row table sums them).  3D plans get an empty table.
+HostTiles build_tiles(const stride_plan& P, const std::vector<Tap>& taps, double scale,
+                      const LaunchShape& ls)
+{
+    HostTiles T;
+    if (P.nd != 2) {
+        T.ptr.assign(2, 0);
+        return T;
+    }
+    std::vector<std::vector<TileEntry>> per(ls.tile_blocks);
+    for (size_t p = 0; p < taps.size(); ++p)
+        for (int t = 0; t < 4; ++t) {
+            if (taps[p].w[t] == 0.0)
+                continue;
+            const int* c = taps[p].coord[t];
+            const int ty = c[0] / ls.ty, tx = c[1] / kTileX;
+            const int local = (c[0] - ty * ls.ty) * kTileX + (c[1] - tx * kTileX);
+            per[(size_t)ty * ls.tiles_x + tx].push_back(
+                TileEntry{local, 0, (int)p, (float)(taps[p].w[t] * scale)});
+        }
+    T.ptr.assign(ls.tile_blocks + 1, 0);
+    for (int t = 0; t < ls.tile_blocks; ++t) {
+        auto& v = per[t];
+        std::stable_sort(v.begin(), v.end(),
+                         [](const TileEntry& a, const TileEntry& b) { return a.local < b.local; });
+        for (size_t i = 0; i < v.size();) {
+            size_t j = i;
+            while (j < v.size() && v[j].local == v[i].local)
+                ++j;
+            v[i].run = (int)(j - i);
+            i = j;
+        }
+        T.ptr[t + 1] = T.ptr[t] + (int)v.size();
+        T.ent.insert(T.ent.end(), v.begin(), v.end());
+    }
+    return T;
+}
+
 void flatten_sample(const std::vector<Tap>& taps, double scale, std::vector<long long>& idx,
                     std::vector<float>& w)
 {
@@ -243,7 +288,7 @@ Layout stride::layout_of(const stride_plan& P)
 {
     Layout L;
     L.field = (size_t)round_up(P.dims.total * 4, 256);
-    L.scratch = 256;
+    L.scratch = 256 + kMisfitParts * sizeof(double);   // flags | misfit partial sums
     L.traces = (size_t)round_up((long long)P.nrec * P.nt * 4, 256);
     L.fixed_fwd = L.scratch + 3 * L.field;
     L.fixed_grad = L.scratch + 4 * L.field + 2 * L.traces;
@@ -267,6 +312,7 @@ int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
     ScheduleStats st = cached_schedule(P.nt, s)->stats;
     char* b = (char*)ws;
     W.flags = (unsigned*)b;
+    W.partial = (double*)(b + 256);
     b += L.scratch;
     W.k = (float*)b;
     b += L.field;
@@ -340,7 +386,7 @@ StepParams stride::base_params(const stride_plan& P)
     StepParams p{};
     p.inj = P.src_inj;
     p.inj_stride = P.nt;
-    p.img = P.src_inj;
+    p.img = P.src_img;
     p.img_stride = P.nt;
     return p;
 }
@@ -584,7 +630,7 @@ struct Runner {
             p.inj = P.rec_inj;
             p.inj_sig = grad_traces;
             p.inj_stride = P.nt;
-            p.img = P.src_inj;
+            p.img = P.src_img;
             p.img_sig = wavelet;
             p.img_stride = P.nt;
             if (dwavelet)
@@ -683,7 +729,7 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     g_timer.end(tid, s, 1, run.adj_launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
-    launch_finalize_dvp(P.dims, W.G, vp, dvp, s);
+    launch_finalize_dvp(P.dims, W.G, vp, dvp, W.w[0], W.w[1], s);
     HIP_TRY(hipGetLastError());
     return STRIDE_OK;
 }
@@ -754,6 +800,13 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         d.st[0] = (long long)d.n[1] * pitch;
         d.total = (long long)d.n[0] * d.st[0];
     }
+    // kernels address a 2D field, or one 3D plane, with 32-bit byte offsets
+    const long long span = P->nd == 2 ? d.total : d.st[0];
+    if (span * 4 > 0x7fffffffLL) {
+        const char* what = P->nd == 2 ? "2D field" : "3D plane";
+        delete P;
+        return fail(STRIDE_E_INVALID_ARG, "%s exceeds 2 GiB", what);
+    }
 
     double c[kMaxR + 1] = {0};
     fd_weights(grid->space_order, c);
@@ -794,6 +847,9 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     }
     HostTable ts = build_rows(*P, st, 1.0 / P->cellvol);
     HostTable tr = build_rows(*P, rt, 1.0);
+    HostTiles tsf = build_tiles(*P, st, 1.0 / P->cellvol, P->ls_fwd);
+    HostTiles tsa = build_tiles(*P, st, 1.0 / P->cellvol, P->ls_adj);
+    HostTiles tra = build_tiles(*P, rt, 1.0, P->ls_adj);
     std::vector<long long> ridx, sidx;
     std::vector<float> rw, sw;
     flatten_sample(rt, 1.0, ridx, rw);
@@ -821,6 +877,12 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     size_t o_rw = add(rw.data(), rw.size(), 4);
     size_t o_sidx = add(sidx.data(), sidx.size(), 8);
     size_t o_sw = add(sw.data(), sw.size(), 4);
+    size_t o_tsf_ptr = add(tsf.ptr.data(), tsf.ptr.size(), 4);
+    size_t o_tsf_ent = add(tsf.ent.data(), tsf.ent.size(), sizeof(TileEntry));
+    size_t o_tsa_ptr = add(tsa.ptr.data(), tsa.ptr.size(), 4);
+    size_t o_tsa_ent = add(tsa.ent.data(), tsa.ent.size(), sizeof(TileEntry));
+    size_t o_tra_ptr = add(tra.ptr.data(), tra.ptr.size(), 4);
+    size_t o_tra_ent = add(tra.ent.data(), tra.ent.size(), sizeof(TileEntry));
     std::vector<char> host(off, 0);
     for (auto& pt : parts)
         if (pt.second.second)
@@ -838,9 +900,14 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     }
     char* B = (char*)P->blob;
     P->src_inj = RowTable{(const int*)(B + o_ts_ptr), (const int*)(B + o_ts_x),
-                          (const int*)(B + o_ts_id), (const float*)(B + o_ts_w)};
+                          (const int*)(B + o_ts_id), (const float*)(B + o_ts_w),
+                          (const int*)(B + o_tsf_ptr), (const TileEntry*)(B + o_tsf_ent)};
+    P->src_img = P->src_inj;
+    P->src_img.tile_ptr = (const int*)(B + o_tsa_ptr);
+    P->src_img.tile_ent = (const TileEntry*)(B + o_tsa_ent);
     P->rec_inj = RowTable{(const int*)(B + o_tr_ptr), (const int*)(B + o_tr_x),
-                          (const int*)(B + o_tr_id), (const float*)(B + o_tr_w)};
+                          (const int*)(B + o_tr_id), (const float*)(B + o_tr_w),
+                          (const int*)(B + o_tra_ptr), (const TileEntry*)(B + o_tra_ent)};
     P->rec_idx = (const long long*)(B + o_ridx);
     P->rec_w = (const float*)(B + o_rw);
     P->src_idx = (const long long*)(B + o_sidx);
@@ -945,7 +1012,8 @@ int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float
     int rc = forward_save(*plan, vp, wavelet, traces, ws, ws_bytes, s, W);
     if (rc)
         return rc;
-    launch_residual_misfit(W.traces, observed, W.residual, (long long)plan->nrec * plan->nt, misfit, s);
+    launch_residual_misfit(W.traces, observed, W.residual, (long long)plan->nrec * plan->nt, misfit,
+                           W.partial, s);
     return backward(*plan, vp, wavelet, W.residual, dvp, nullptr, ws, ws_bytes, s);
 }
 

@@ -133,7 +133,7 @@ int fill_tick(stride_engine* E, SlotJob& J, SlotStep* fwd, SlotStep* adj)
     t.p.inj = P.rec_inj;
     t.p.inj_sig = J.W.residual;
     t.p.inj_stride = P.nt;
-    t.p.img = P.src_inj;
+    t.p.img = P.src_img;
     t.p.img_sig = J.wavelet;
     t.p.img_stride = P.nt;
     t.sp = P.sp;
@@ -193,14 +193,14 @@ void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
         launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, J.W.traces, P.nt},
                       J.W.pool[J.cursor->cur()], P.nt - 1, s);
         launch_residual_misfit(J.W.traces, J.observed, J.W.residual, (long long)P.nrec * P.nt,
-                               J.misfit, s);
+                               J.misfit, J.W.partial, s);
         if (J.traces)
             launch_copy(J.traces, J.W.traces, (long long)P.nrec * P.nt, s);
         J.phase = 1;
         J.left = J.cursor->forward_steps() - (P.nt - 1) + P.nt;
         return;
     }
-    launch_finalize_dvp(P.dims, J.W.G, J.vp, J.dvp, s);
+    launch_finalize_dvp(P.dims, J.W.G, J.vp, J.dvp, J.W.w[0], J.W.w[1], s);
     J.finished = true;
 }
 

@@ -28,8 +28,19 @@ namespace stride {
 void tile_shape(int nd, bool adjoint, int* ry, int* waves)
 {
     if (nd == 2) {
-        *ry = 4;
-        *waves = 4;
+        const char* er = getenv(adjoint ? "STRIDE_RY2D_ADJ" : "STRIDE_RY2D");
+        const char* ew = getenv(adjoint ? "STRIDE_WAVES2D_ADJ" : "STRIDE_WAVES2D");
+        int r = er && *er ? atoi(er) : 4;
+        int w = ew && *ew ? atoi(ew) : 4;
+        if (w == 8) {
+            r = 4;
+        } else {
+            w = 4;
+            if (r != 2 && r != 8)
+                r = 4;
+        }
+        *ry = r;
+        *waves = w;
         return;
     }
     const char* er = getenv(adjoint ? "STRIDE_RY3D_ADJ" : "STRIDE_RY3D");
@@ -147,21 +158,43 @@ __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float
 
 // ----------------------------------------------------------------------- 2D
 //
-// One block = one 64 x 16 tile (4 waves x 4 rows per thread).  The point
-// loads of B, K (and G) are issued first so that their latency overlaps the
-// LDS tile load.
+// One block = one 64 x TY tile, TY = WAVES * RY rows (RY per thread).  The
+// tile of A (and U) with its R-wide halo is staged in LDS row by row: wave w
+// loads tile rows w, w + WAVES, ..., each lane one column and lanes 0..2R-1
+// one halo column as well.  Every load of the step is issued up front: the
+// point values of B, K (and G), the LDS tile, and the tile's injection
+// entries with their signal samples (the entry range comes from a uniform
+// table read), so a tile with injected points costs two dependent round trips
+// and any other tile one.  Injected values reach their points through a small
+// LDS array, used only by tiles that have entries.  The 2D field fits one
+// buffer descriptor (at most 2 GiB): offsets of points outside the grid are
+// set to 0xffffffff and read 0.
 
-template <int R, bool ADJ>
+// Sum of the signals of the point whose first entry is e (entry order).
+__device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEntry head,
+                                                   const float* sig, int stride, int step)
+{
+    float v = head.w * sig[(long long)head.id * stride + step];
+    for (int k = 1; k < head.run; ++k) {
+        const TileEntry e = ent[k];
+        v += e.w * sig[(long long)e.id * stride + step];
+    }
+    return v;
+}
+
+template <int R, bool ADJ, int RY, int WAVES>
 __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf,
                                             const SpongeCoef& sp, const StepParams& p,
                                             const LaunchShape& ls, const int b)
 {
-    constexpr int RY = 4;
-    constexpr int TY = kWaves * RY;
+    constexpr int NT = 64 * WAVES;
+    constexpr int TY = WAVES * RY;
     constexpr int LW = kTileX + 2 * R;
     constexpr int LH = TY + 2 * R;
-    __shared__ float sA[LH][LW];
-    __shared__ float sU[ADJ ? LH : 1][ADJ ? LW : 1];
+    constexpr int RW = (LH + WAVES - 1) / WAVES;    // tile rows loaded per wave
+    constexpr int NF = ADJ ? 2 : 1;                 // stencil fields A (and U)
+    __shared__ float sF[NF][LH * LW];
+    __shared__ float sS[NF][TY * kTileX];           // injected signal per tile point
 
     if (b >= ls.tile_blocks_pad) {
         sample_block(p.smp, p.A, p.step, b - ls.tile_blocks_pad);
@@ -170,81 +203,171 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     const int tile = xcd_logical(b, ls.tile_blocks_pad);
     if (tile >= ls.tile_blocks)
         return;
-    const int y0 = (tile / ls.tiles_x) * TY;
-    const int x0 = (tile % ls.tiles_x) * kTileX;
+    const int tyi = tile / ls.tiles_x;
+    const int y0 = tyi * TY;
+    const int x0 = (tile - tyi * ls.tiles_x) * kTileX;
     const int tid = threadIdx.x;
     const int lx = tid & 63;
     const int wy = tid >> 6;
     const int n0 = d.n[0], n1 = d.n[1];
-    const long long s0 = d.st[0];
+    const int s0 = (int)d.st[0];
+    const int fbytes = (int)(d.total * 4);
     const int gx = x0 + lx;
+    const bool xin = gx < n1;
 
+    // entry ranges of the tile (uniform)
+    const int eb0 = p.inj.tile_ptr[tile];
+    const int ne0 = p.inj.tile_ptr[tile + 1] - eb0;
+    int eb1 = 0, ne1 = 0;
+    if constexpr (ADJ) {
+        eb1 = p.img.tile_ptr[tile];
+        ne1 = p.img.tile_ptr[tile + 1] - eb1;
+    }
+
+    // tile rows with halo: byte offsets of the column and the halo column
+    const int hcol = lx < R ? x0 - R + lx : x0 + kTileX - R + lx;
+    const int hlds = lx < R ? lx : kTileX + lx;
+    const bool hin = lx < 2 * R && hcol >= 0 && hcol < n1;
+    int ro[RW], ho[RW];
+#pragma unroll
+    for (int i = 0; i < RW; ++i) {
+        const int r = wy + i * WAVES;
+        const int gy = y0 - R + r;
+        const bool rok = r < LH && gy >= 0 && gy < n0;
+        ro[i] = rok && xin ? (gy * s0 + gx) * 4 : -1;
+        ho[i] = rok && hin ? (gy * s0 + hcol) * 4 : -1;
+    }
+    float va[NF][RW], vh[NF][RW];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const auto rf = plane_rsrc(f == 0 ? p.A : p.U, fbytes);
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            va[f][i] = bload(rf, ro[i]);
+            vh[f][i] = bload(rf, ho[i]);
+        }
+    }
+    int po[RY];
     float bb[RY], kk[RY], gg[RY];
+    {
+        const auto rb = plane_rsrc(p.B, fbytes);
+        const auto rk = plane_rsrc(p.K, fbytes);
 #pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        const int gy = y0 + wy * RY + j;
-        const bool ok = gx < n1 && gy < n0;
-        const long long gi = (long long)gy * s0 + gx;
-        bb[j] = ok ? p.B[gi] : 0.f;
-        kk[j] = ok ? p.K[gi] : 0.f;
-        if constexpr (ADJ)
-            gg[j] = ok ? p.G[gi] : 0.f;
+        for (int j = 0; j < RY; ++j) {
+            const int gy = y0 + wy * RY + j;
+            po[j] = xin && gy < n0 ? gy * s0 + gx : -1;
+            const int bo = po[j] >= 0 ? po[j] * 4 : -1;
+            bb[j] = bload(rb, bo);
+            kk[j] = bload(rk, bo);
+        }
+        if constexpr (ADJ) {
+            const auto rg = plane_rsrc(p.G, fbytes);
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                gg[j] = bload(rg, po[j] >= 0 ? po[j] * 4 : -1);
+        }
     }
 
-    for (int i = tid; i < LH * LW; i += kThreads) {
-        int r = i / LW;
-        int c = i - r * LW;
-        int gy = y0 - R + r;
-        int gxx = x0 - R + c;
-        bool in = gy >= 0 && gy < n0 && gxx >= 0 && gxx < n1;
-        long long gi = (long long)gy * s0 + gxx;
-        sA[r][c] = in ? p.A[gi] : 0.f;
-        if constexpr (ADJ)
-            sU[r][c] = in ? p.U[gi] : 0.f;
+    // one entry per thread (more only in tiles with over NT entries)
+    int il0 = -1, il1 = -1;
+    float iv0 = 0.f, iv1 = 0.f;
+    if (tid < ne0) {
+        const TileEntry e = p.inj.tile_ent[eb0 + tid];
+        if (e.run > 0) {
+            il0 = e.local;
+            iv0 = tile_point_signal(p.inj.tile_ent + eb0 + tid, e, p.inj_sig, p.inj_stride, p.step);
+        }
     }
+    if constexpr (ADJ) {
+        if (tid < ne1) {
+            const TileEntry e = p.img.tile_ent[eb1 + tid];
+            if (e.run > 0) {
+                il1 = e.local;
+                iv1 = tile_point_signal(p.img.tile_ent + eb1 + tid, e, p.img_sig, p.img_stride, p.step);
+            }
+        }
+    }
+
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+#pragma unroll
+        for (int i = 0; i < RW; ++i) {
+            const int r = wy + i * WAVES;
+            if (r < LH) {
+                sF[f][r * LW + lx + R] = va[f][i];
+                if (lx < 2 * R)
+                    sF[f][r * LW + hlds] = vh[f][i];
+            }
+        }
+    }
+    const bool inj_any = ne0 > 0;
+    const bool img_any = ADJ && ne1 > 0;
+    if (inj_any)
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+            sS[0][(wy * RY + j) * kTileX + lx] = 0.f;
+    if (img_any)
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+            sS[NF - 1][(wy * RY + j) * kTileX + lx] = 0.f;
     __syncthreads();
+    if (inj_any || img_any) {
+        if (il0 >= 0)
+            sS[0][il0] = iv0;
+        for (int e = tid + NT; e < ne0; e += NT) {
+            const TileEntry en = p.inj.tile_ent[eb0 + e];
+            if (en.run > 0)
+                sS[0][en.local] =
+                    tile_point_signal(p.inj.tile_ent + eb0 + e, en, p.inj_sig, p.inj_stride, p.step);
+        }
+        if constexpr (ADJ) {
+            if (il1 >= 0)
+                sS[1][il1] = iv1;
+            for (int e = tid + NT; e < ne1; e += NT) {
+                const TileEntry en = p.img.tile_ent[eb1 + e];
+                if (en.run > 0)
+                    sS[1][en.local] =
+                        tile_point_signal(p.img.tile_ent + eb1 + e, en, p.img_sig, p.img_stride, p.step);
+            }
+        }
+        __syncthreads();
+    }
 
-    if (gx >= n1)
+    if (!xin)
         return;
-    const int ylast = min(y0 + TY, n0);
-    const bool inj_any = p.inj.row_ptr[y0] < p.inj.row_ptr[ylast];
-    bool img_any = false;
-    if constexpr (ADJ)
-        img_any = p.img.row_ptr[y0] < p.img.row_ptr[ylast];
     const int dxd = layer_depth(gx, n1, d.nb);
-
+    const float ex = sp.e[1] * (float)(dxd * dxd);
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-        const int ly = wy * RY + j;
-        const int gy = y0 + ly;
-        if (gy >= n0)
+        if (po[j] < 0)
             break;
-        const long long gi = (long long)gy * s0 + gx;
-        const float ctr = sA[ly + R][lx + R];
+        const int ly = wy * RY + j;
+        const float* SA = &sF[0][(ly + R) * LW + lx + R];
+        const float ctr = SA[0];
         float ay = 0.f, ax = 0.f;
 #pragma unroll
         for (int q = R; q >= 1; --q) {
-            ay = fmaf(cf.c[0][q], sA[ly + R + q][lx + R] + sA[ly + R - q][lx + R], ay);
-            ax = fmaf(cf.c[1][q], sA[ly + R][lx + R + q] + sA[ly + R][lx + R - q], ax);
+            ay = fmaf(cf.c[0][q], SA[q * LW] + SA[-q * LW], ay);
+            ax = fmaf(cf.c[1][q], SA[q] + SA[-q], ax);
         }
         float lap = fmaf(cf.c0, ctr, ay + ax);
         if (inj_any)
-            lap += row_signal(p.inj, gy, gx, p.inj_sig, p.inj_stride, p.step);
-        const int dyd = layer_depth(gy, n0, d.nb);
-        const float eta = sp.e[0] * (float)(dyd * dyd) + sp.e[1] * (float)(dxd * dxd);
-        p.C[gi] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
+            lap += sS[0][ly * kTileX + lx];
+        const int dyd = layer_depth(y0 + ly, n0, d.nb);
+        const float eta = sp.e[0] * (float)(dyd * dyd) + ex;
+        p.C[po[j]] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
         if constexpr (ADJ) {
-            const float uc = sU[ly + R][lx + R];
+            const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
             float uy = 0.f, ux = 0.f;
 #pragma unroll
             for (int q = R; q >= 1; --q) {
-                uy = fmaf(cf.c[0][q], sU[ly + R + q][lx + R] + sU[ly + R - q][lx + R], uy);
-                ux = fmaf(cf.c[1][q], sU[ly + R][lx + R + q] + sU[ly + R][lx + R - q], ux);
+                uy = fmaf(cf.c[0][q], SU[q * LW] + SU[-q * LW], uy);
+                ux = fmaf(cf.c[1][q], SU[q] + SU[-q], ux);
             }
-            float lu = fmaf(cf.c0, uc, uy + ux);
+            float lu = fmaf(cf.c0, SU[0], uy + ux);
             if (img_any)
-                lu += row_signal(p.img, gy, gx, p.img_sig, p.img_stride, p.step);
-            p.G[gi] = fmaf(ctr, lu, gg[j]);
+                lu += sS[NF - 1][ly * kTileX + lx];
+            p.G[po[j]] = fmaf(ctr, lu, gg[j]);
         }
     }
 }
@@ -499,21 +622,21 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
 // device table; inactive slots exit at once.  Both run the same body, so a
 // shot computes the same bits alone and in a batch.
 
-template <int R, bool ADJ>
-__global__ __launch_bounds__(kThreads) void step2d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
-                                                          StepParams p, LaunchShape ls)
+template <int R, bool ADJ, int RY, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void step2d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
+                                                            StepParams p, LaunchShape ls)
 {
-    step2d_body<R, ADJ>(d, cf, sp, p, ls, blockIdx.x);
+    step2d_body<R, ADJ, RY, WAVES>(d, cf, sp, p, ls, blockIdx.x);
 }
 
-template <int R, bool ADJ>
-__global__ __launch_bounds__(kThreads) void step2d_batched(Dims d, StencilCoef cf, LaunchShape ls,
-                                                           const SlotStep* table)
+template <int R, bool ADJ, int RY, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void step2d_batched(Dims d, StencilCoef cf, LaunchShape ls,
+                                                             const SlotStep* table)
 {
     const SlotStep st = table[blockIdx.y];
     if (!st.active)
         return;
-    step2d_body<R, ADJ>(d, cf, st.sp, st.p, ls, blockIdx.x);
+    step2d_body<R, ADJ, RY, WAVES>(d, cf, st.sp, st.p, ls, blockIdx.x);
 }
 
 template <int R, bool ADJ, int RY, int WAVES>
@@ -583,23 +706,45 @@ __global__ void prep_k_kernel(Dims d, const float* vp, double dt, float* k)
     }
 }
 
-// Residual and misfit J = 1/2 sum r^2 accumulated in FP64 by one block with a
-// fixed reduction order (bitwise reproducible).
-__global__ __launch_bounds__(1024) void residual_misfit_kernel(const float* traces,
+// Residual r = traces - observed and J = 1/2 sum r^2 in FP64.  Block b reduces
+// a fixed contiguous range in a fixed tree order and misfit_final_kernel adds
+// the partial sums in block order, so the result is bitwise reproducible.
+__global__ __launch_bounds__(256) void residual_partial_kernel(const float* traces,
                                                                const float* observed,
                                                                float* residual, long long n,
-                                                               double* misfit)
+                                                               double* partial)
 {
-    __shared__ double part[1024];
+    __shared__ double part[256];
+    const long long per = (n + gridDim.x - 1) / gridDim.x;
+    const long long lo = per * blockIdx.x;
+    const long long hi = min(n, lo + per);
     double acc = 0.0;
-    for (long long i = threadIdx.x; i < n; i += 1024) {
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
         float r = traces[i] - observed[i];
         residual[i] = r;
         acc += (double)r * (double)r;
     }
     part[threadIdx.x] = acc;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = part[0];
+}
+
+__global__ __launch_bounds__(256) void misfit_final_kernel(const double* partial, int nparts,
+                                                           double* misfit)
+{
+    __shared__ double part[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += 256)
+        acc += partial[i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
             part[threadIdx.x] += part[threadIdx.x + w];
         __syncthreads();
@@ -608,38 +753,30 @@ __global__ __launch_bounds__(1024) void residual_misfit_kernel(const float* trac
         *misfit = 0.5 * part[0];
 }
 
-// dvp = P^T (2 G / vp_pad): every physical cell collects the padded cells that
-// replicate it (the strip behind an edge cell, the corner block behind a corner).
-__global__ void finalize_dvp_kernel(Dims d, const float* G, const float* vp, float* dvp)
+// Transpose of edge-replicating padding along one axis.  The input is viewed
+// as [m0][nin][m2] with strides (s_outer, s_axis, 1), the output is dense
+// [m0][nout][m2] with nin = nout + 2 nb: output cell j collects input cell
+// j + nb, and the two edge cells also collect the nb cells replicated from
+// them.  With vp given, the output is 2 * sum / vp (the last pass of dvp).
+__global__ void pad_transpose_axis_kernel(const float* in, long long s_outer, long long s_axis,
+                                          float* out, long long m0, int nout, long long m2, int nb,
+                                          const float* vp)
 {
-    long long nphys = (long long)d.phys[0] * d.phys[1] * d.phys[2];
+    const long long total = m0 * nout * m2;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    long long stride = (long long)gridDim.x * blockDim.x;
-    for (; i < nphys; i += stride) {
-        int c[3];
-        long long r = i;
-        for (int a = 2; a >= 0; --a) {
-            c[a] = (int)(r % d.phys[a]);
-            r /= d.phys[a];
-        }
-        int lo[3], hi[3];
-        for (int a = 0; a < 3; ++a) {
-            if (a >= d.nd) {
-                lo[a] = hi[a] = 0;
-                continue;
-            }
-            lo[a] = c[a] == 0 ? 0 : c[a] + d.nb;
-            hi[a] = c[a] == d.phys[a] - 1 ? c[a] + 2 * d.nb : c[a] + d.nb;
-        }
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const long long i2 = i % m2;
+        const long long r = i / m2;
+        const int j = (int)(r % nout);
+        const long long i0 = r / nout;
+        const int lo = j == 0 ? 0 : j + nb;
+        const int hi = j == nout - 1 ? j + 2 * nb : j + nb;
+        const float* src = in + i0 * s_outer + i2;
         float acc = 0.f;
-        for (int a0 = lo[0]; a0 <= hi[0]; ++a0)
-            for (int a1 = lo[1]; a1 <= hi[1]; ++a1)
-                for (int a2 = lo[2]; a2 <= hi[2]; ++a2) {
-                    long long gi = (long long)a0 * d.st[0] + (long long)a1 * (d.nd > 1 ? d.st[1] : 0) +
-                                   (d.nd > 2 ? a2 : 0);
-                    acc += G[gi];
-                }
-        dvp[i] = 2.f * acc / vp[i];
+        for (int k = lo; k <= hi; ++k)
+            acc += src[(long long)k * s_axis];
+        out[i] = vp ? 2.f * acc / vp[i] : acc;
     }
 }
 
@@ -672,15 +809,32 @@ __global__ void vp_check_kernel(const float* vp, long long n, unsigned* flags)
     }
 }
 
+// 2D tile shapes with compiled kernels (rows per thread, waves); tile_shape()
+// returns one of these.
+#define STRIDE_DISPATCH2D(L)                                                                      \
+    do {                                                                                          \
+        if (ls.waves == 8)                                                                        \
+            L(4, 8);                                                                              \
+        else if (ls.ry == 2)                                                                      \
+            L(2, 4);                                                                              \
+        else if (ls.ry == 8)                                                                      \
+            L(8, 4);                                                                              \
+        else                                                                                      \
+            L(4, 4);                                                                              \
+    } while (0)
+
 template <int R, bool ADJ>
 void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                    const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
-    const int nt = d.nd == 2 ? kThreads : 64 * ls.waves;
+    const int nt = 64 * ls.waves;
     int smp_blocks = (p.smp.count + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks);
     if (d.nd == 2) {
-        hipLaunchKernelGGL((step2d_kernel<R, ADJ>), grid, dim3(kThreads), 0, s, d, cf, sp, p, ls);
+#define STRIDE_LAUNCH2D(RY_, W_)                                                                  \
+    hipLaunchKernelGGL((step2d_kernel<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, p, ls)
+        STRIDE_DISPATCH2D(STRIDE_LAUNCH2D);
+#undef STRIDE_LAUNCH2D
         return;
     }
 #define STRIDE_LAUNCH3D(RY_, W_)                                                                  \
@@ -705,11 +859,14 @@ template <int R, bool ADJ>
 void launch_batched_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
                       const SlotStep* table, int nslots, int max_samples, hipStream_t s)
 {
-    const int nt = d.nd == 2 ? kThreads : 64 * ls.waves;
+    const int nt = 64 * ls.waves;
     int smp_blocks = (max_samples + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks, nslots);
     if (d.nd == 2) {
-        hipLaunchKernelGGL((step2d_batched<R, ADJ>), grid, dim3(kThreads), 0, s, d, cf, ls, table);
+#define STRIDE_LAUNCH2DB(RY_, W_)                                                                  \
+    hipLaunchKernelGGL((step2d_batched<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, ls, table)
+        STRIDE_DISPATCH2D(STRIDE_LAUNCH2DB);
+#undef STRIDE_LAUNCH2DB
         return;
     }
 #define STRIDE_LAUNCH3DB(RY_, W_)                                                                  \
@@ -808,16 +965,37 @@ void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStrea
 }
 
 void launch_residual_misfit(const float* traces, const float* observed, float* residual,
-                            long long n, double* misfit, hipStream_t s)
+                            long long n, double* misfit, double* partial, hipStream_t s)
 {
-    hipLaunchKernelGGL(residual_misfit_kernel, dim3(1), dim3(1024), 0, s, traces, observed, residual,
-                       n, misfit);
+    hipLaunchKernelGGL(residual_partial_kernel, dim3(kMisfitParts), dim3(256), 0, s, traces,
+                       observed, residual, n, partial);
+    hipLaunchKernelGGL(misfit_final_kernel, dim3(1), dim3(256), 0, s, partial, kMisfitParts, misfit);
 }
 
-void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, hipStream_t s)
+void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, float* tmp0,
+                         float* tmp1, hipStream_t s)
 {
-    long long n = (long long)d.phys[0] * d.phys[1] * d.phys[2];
-    hipLaunchKernelGGL(finalize_dvp_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, d, G, vp, dvp);
+    // P^T one axis at a time, innermost first; the first pass reads the
+    // pitched field, later passes dense intermediates, the last writes dvp.
+    const int nd = d.nd;
+    long long ext[3] = {d.n[0], d.n[1], d.n[2]};
+    const float* in = G;
+    float* tmp[2] = {tmp0, tmp1};
+    for (int a = nd - 1; a >= 0; --a) {
+        long long m0 = 1, m2 = 1;
+        for (int q = 0; q < a; ++q)
+            m0 *= ext[q];
+        for (int q = a + 1; q < nd; ++q)
+            m2 *= ext[q];
+        const long long s_outer = a == nd - 1 ? d.st[nd - 2] : ext[a] * m2;
+        const long long s_axis = a == nd - 1 ? 1 : m2;
+        float* out = a == 0 ? dvp : tmp[a & 1];
+        const long long cnt = m0 * d.phys[a] * m2;
+        hipLaunchKernelGGL(pad_transpose_axis_kernel, dim3(grid_for(cnt, 256)), dim3(256), 0, s, in,
+                           s_outer, s_axis, out, m0, d.phys[a], m2, d.nb, a == 0 ? vp : nullptr);
+        ext[a] = d.phys[a];
+        in = out;
+    }
 }
 
 }  // namespace stride

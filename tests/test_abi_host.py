@@ -67,10 +67,11 @@ def test_workspace_sizes():
     g = _grid(nt=50)
     f = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_FORWARD)
     field = -(-(52 * 64 * 4) // 256) * 256          # 52 x 62 padded, pitch 64
-    assert f == 256 + 3 * field
+    scratch = 256 + 256 * 8                          # flags | 256 FP64 misfit partial sums
+    assert f == scratch + 3 * field
     full = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT)
     traces = -(-(3 * 50 * 4) // 256) * 256
-    fixed = 256 + 4 * field + 2 * traces
+    fixed = scratch + 4 * field + 2 * traces
     assert (full - fixed) % field == 0
     assert (full - fixed) // field == 51              # every state kept: u^-1 .. u^49
     small = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT, fixed + 10 * field)
