@@ -25,6 +25,39 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, averaged over the kernel's
+# dispatches) scaled by what the same counters read for a 1 GiB device copy.
+# Valid only for the kernel source they were taken with: the sha256 of the
+# kernel file and its header; any change makes `traffic` null until the
+# counters are taken again.
+MEASURED_TRAFFIC = {
+    "config2": {"sha256": "d23b93b9a857bef81c14fe4cd084bf8b77569fcc4555a48e12bf9b3cae826ccd",
+                "fetch_kib": 12284.75, "write_kib": 9522.35,
+                "copy_fetch_kib": 524307.69, "copy_write_kib": 1048576.0},
+}
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("csrc/stride_kernels.hip", "csrc/common.h"):
+        with open(os.path.join(ROOT, "paper_2110_03345_amd", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel, or None if not measured
+    for the current kernel source."""
+    m = MEASURED_TRAFFIC.get(workload)
+    if not m or m["sha256"] != kernel_source_sha():
+        return None
+    gib_kib = float(1 << 20)
+    reads = m["fetch_kib"] * 1024 * gib_kib / m["copy_fetch_kib"]
+    writes = m["write_kib"] * 1024 * gib_kib / m["copy_write_kib"]
+    return reads + writes
 FWD_BYTES = 16   # read u^n, u^{n-1}, k; write u^{n+1}
 ADJ_BYTES = 28   # read u^m, w^{m+1}, w^{m+2}, k, G; write w^m, G
 
@@ -294,6 +327,7 @@ def main():
         print(f"[bench] cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} threads",
               file=sys.stderr, flush=True)
 
+    traffic = measured_traffic(args.workload)
     line = {
         "metric": "grid-point updates/s (fwd, fwd+adj), % HBM peak; served solves/s + p50/p99",
         "value": value,
@@ -325,7 +359,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": adj_gbs / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch",
+            "traffic_over_algorithmic": traffic / (ADJ_BYTES * npad) if traffic else None,
             "bytes_per_point": ADJ_BYTES,
             "us_per_launch": adj_launch_s * 1e6,
             "forward_kernel_in_gradient_gbs": fwd_in_grad_gbs,
