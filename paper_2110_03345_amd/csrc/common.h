@@ -37,10 +37,13 @@ struct SpongeCoef {
     float half_dt;
 };
 
-// One injection entry of a 2D tile: adds w * sig[id][step] at tile-local
-// point `local` (= row * 64 + column within the tile).  A tile's entries are
-// sorted by point, in (point, tap) order within a point; the first entry of a
-// point holds the number of entries of that point in `run`, the others 0.
+// Injection entries grouped by step-kernel block (a 2D tile, or a 3D tile
+// over one chunk of planes) of the launch shape that uses the table.  Block b
+// holds ent[ptr[b] .. ptr[b+1]); entry e adds w * sig[id][step] at its
+// block-local point `local` = (plane in chunk * TY + tile row) * 64 + tile
+// column.  A block's entries are sorted by point, in (point, tap) order
+// within a point; the first entry of a point holds the number of entries of
+// that point in `run`, the others 0.
 struct TileEntry {
     int local;
     int run;
@@ -48,19 +51,9 @@ struct TileEntry {
     float w;
 };
 
-// Grid points that receive an injected signal, grouped by grid row (every
-// axis but the contiguous one: row = i0 in 2D, i0 * n1 + i1 in 3D).  Entries
-// of row r are [row_ptr[r], row_ptr[r+1]); entry e adds w[e] * sig[id[e]][step]
-// at column x[e] of that row, in entry order.  In 2D the same entries are also
-// grouped by tile of the launch shape that uses the table: tile t holds
-// tile_ent[tile_ptr[t] .. tile_ptr[t+1]).
-struct RowTable {
-    const int* row_ptr;
-    const int* x;
-    const int* id;
-    const float* w;
-    const int* tile_ptr;
-    const TileEntry* tile_ent;
+struct InjTable {
+    const int* ptr;
+    const TileEntry* ent;
 };
 
 // Point sampling: out[r * out_stride + step] = sum_t w[r*8+t] * field[idx[r*8+t]].
@@ -80,10 +73,10 @@ struct StepParams {
     const float* U;   // adjoint only: forward field u^m (second stencil)
     float* G;         // adjoint only: imaging accumulator
     int step;         // time index of the injected / sampled signals
-    RowTable inj;     // injection into C: sources (forward), receivers (adjoint)
+    InjTable inj;     // injection into C: sources (forward), receivers (adjoint)
     const float* inj_sig;
     int inj_stride;
-    RowTable img;     // adjoint only: source term S^m of the imaging condition
+    InjTable img;     // adjoint only: source term S^m of the imaging condition
     const float* img_sig;
     int img_stride;
     SampleSet smp;    // sampling of A at `step`

@@ -23,9 +23,9 @@ struct stride_plan {
     int nsrc, nrec;
     int device;
     void* blob;          // device memory of the tables below
-    stride::RowTable src_inj;    // sources, weights / cell volume (tiles of ls_fwd)
-    stride::RowTable src_img;    // the same entries, tiles of ls_adj (imaging source term)
-    stride::RowTable rec_inj;    // receivers (adjoint injection), weights (tiles of ls_adj)
+    stride::InjTable src_inj;    // sources, weights / cell volume (blocks of ls_fwd)
+    stride::InjTable src_img;    // the same entries, blocks of ls_adj (imaging source term)
+    stride::InjTable rec_inj;    // receivers (adjoint injection), weights (blocks of ls_adj)
     const long long* rec_idx;
     const float* rec_w;          // receiver sampling
     const long long* src_idx;

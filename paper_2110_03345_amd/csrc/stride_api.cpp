@@ -86,15 +86,14 @@ LaunchShape make_shape(const Dims& d, int zc, int ry, int waves)
 
 // Planes per 3D block.  Short chunks give many independent blocks (the march
 // is latency-bound, so parallelism wins over the 2R lead-in planes each chunk
-// re-reads, which mostly hit L2); 16 was fastest on 316^3 for both kernels.
-int default_zc(const Dims& d, int R, int ty)
+// re-reads, which mostly hit L2).  On 316^3: 32 for the 64 x 32 forward tile,
+// 16 for the 64 x 8 adjoint tile.
+int default_zc(const Dims& d, int ty)
 {
-    (void)R;
-    (void)ty;
     if (d.nd != 3)
         return 1;
     int want = env_int("STRIDE_ZC", 0);
-    return want > 0 ? want : 16;
+    return want > 0 ? want : (ty >= 32 ? 32 : 16);
 }
 
 struct Tap {
@@ -155,68 +154,37 @@ int make_taps(const stride_plan& P, const double* xyz, int count, std::vector<Ta
     return STRIDE_OK;
 }
 
-struct HostTable {
-    std::vector<int> ptr;
-    std::vector<int> x;
-    std::vector<int> id;
-    std::vector<float> w;
-};
-
-// Injection entries grouped by grid row (every axis but the contiguous one),
-// in (point, tap) order within a row so that the kernel sums in a fixed order.
-HostTable build_rows(const stride_plan& P, const std::vector<Tap>& taps, double scale)
-{
-    HostTable T;
-    const Dims& d = P.dims;
-    long long nrows = d.nd == 2 ? d.n[0] : (long long)d.n[0] * d.n[1];
-    std::vector<std::vector<std::pair<int, std::pair<int, float>>>> per(nrows);
-    int ntap = 1 << P.nd;
-    for (size_t p = 0; p < taps.size(); ++p)
-        for (int t = 0; t < ntap; ++t) {
-            if (taps[p].w[t] == 0.0)
-                continue;
-            const int* c = taps[p].coord[t];
-            long long row = d.nd == 2 ? c[0] : (long long)c[0] * d.n[1] + c[1];
-            per[row].push_back({c[d.nd - 1], {(int)p, (float)(taps[p].w[t] * scale)}});
-        }
-    T.ptr.assign(nrows + 1, 0);
-    for (long long r = 0; r < nrows; ++r) {
-        T.ptr[r + 1] = T.ptr[r] + (int)per[r].size();
-        for (auto& e : per[r]) {
-            T.x.push_back(e.first);
-            T.id.push_back(e.second.first);
-            T.w.push_back(e.second.second);
-        }
-    }
-    return T;
-}
-
 struct HostTiles {
     std::vector<int> ptr;
     std::vector<TileEntry> ent;
 };
 
-// 2D: the entries of build_rows grouped by tile of a launch shape, sorted by
-// tile-local point and in (point, tap) order within a point (the order in
-// which the row table sums them).  3D plans get an empty table.
+// Injection entries of every tap with a nonzero weight, grouped by block of a
+// launch shape (2D: tile; 3D: tile and chunk of zc planes, block index
+// chunk * tiles_xy + tile), sorted by block-local point and in (point, tap)
+// order within a point.
 HostTiles build_tiles(const stride_plan& P, const std::vector<Tap>& taps, double scale,
                       const LaunchShape& ls)
 {
     HostTiles T;
-    if (P.nd != 2) {
-        T.ptr.assign(2, 0);
-        return T;
-    }
+    const int ntap = 1 << P.nd;
+    const int plane = ls.ty * kTileX;   // block-local points per plane
     std::vector<std::vector<TileEntry>> per(ls.tile_blocks);
     for (size_t p = 0; p < taps.size(); ++p)
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < ntap; ++t) {
             if (taps[p].w[t] == 0.0)
                 continue;
             const int* c = taps[p].coord[t];
-            const int ty = c[0] / ls.ty, tx = c[1] / kTileX;
-            const int local = (c[0] - ty * ls.ty) * kTileX + (c[1] - tx * kTileX);
-            per[(size_t)ty * ls.tiles_x + tx].push_back(
-                TileEntry{local, 0, (int)p, (float)(taps[p].w[t] * scale)});
+            const int cy = c[P.nd - 2], cx = c[P.nd - 1];
+            const int ty = cy / ls.ty, tx = cx / kTileX;
+            int zci = 0, pz = 0;
+            if (P.nd == 3) {
+                zci = c[0] / ls.zc;
+                pz = c[0] - zci * ls.zc;
+            }
+            const int local = pz * plane + (cy - ty * ls.ty) * kTileX + (cx - tx * kTileX);
+            const size_t blk = (size_t)zci * ls.tiles_xy + (size_t)ty * ls.tiles_x + tx;
+            per[blk].push_back(TileEntry{local, 0, (int)p, (float)(taps[p].w[t] * scale)});
         }
     T.ptr.assign(ls.tile_blocks + 1, 0);
     for (int t = 0; t < ls.tile_blocks; ++t) {
@@ -836,8 +804,8 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     int ryf, wf, rya, wa;
     tile_shape(P->nd, false, &ryf, &wf);
     tile_shape(P->nd, true, &rya, &wa);
-    P->ls_fwd = make_shape(d, default_zc(d, P->R, ryf * wf), ryf, wf);
-    P->ls_adj = make_shape(d, default_zc(d, P->R, rya * wa), rya, wa);
+    P->ls_fwd = make_shape(d, default_zc(d, ryf * wf), ryf, wf);
+    P->ls_adj = make_shape(d, default_zc(d, rya * wa), rya, wa);
 
     std::vector<Tap> st, rt;
     if ((rc = make_taps(*P, src_xyz, nsrc, st, "source")) ||
@@ -845,8 +813,6 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         delete P;
         return rc;
     }
-    HostTable ts = build_rows(*P, st, 1.0 / P->cellvol);
-    HostTable tr = build_rows(*P, rt, 1.0);
     HostTiles tsf = build_tiles(*P, st, 1.0 / P->cellvol, P->ls_fwd);
     HostTiles tsa = build_tiles(*P, st, 1.0 / P->cellvol, P->ls_adj);
     HostTiles tra = build_tiles(*P, rt, 1.0, P->ls_adj);
@@ -855,7 +821,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     flatten_sample(rt, 1.0, ridx, rw);
     flatten_sample(st, 1.0 / P->cellvol, sidx, sw);
 
-    // one device blob: [ts.ptr | tr.ptr | ts.id | tr.id] ints, [pidx..] longs, floats
+    // one device blob of 256-byte aligned parts: sampling taps and injection tables
     auto bytes_of = [](size_t n, size_t sz) { return (size_t)round_up((long long)(n * sz), 256); };
     size_t off = 0;
     std::vector<std::pair<size_t, std::pair<const void*, size_t>>> parts;
@@ -865,14 +831,6 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         off += bytes_of(std::max<size_t>(n, 1), sz);
         return o;
     };
-    size_t o_ts_ptr = add(ts.ptr.data(), ts.ptr.size(), 4);
-    size_t o_ts_x = add(ts.x.data(), ts.x.size(), 4);
-    size_t o_ts_id = add(ts.id.data(), ts.id.size(), 4);
-    size_t o_ts_w = add(ts.w.data(), ts.w.size(), 4);
-    size_t o_tr_ptr = add(tr.ptr.data(), tr.ptr.size(), 4);
-    size_t o_tr_x = add(tr.x.data(), tr.x.size(), 4);
-    size_t o_tr_id = add(tr.id.data(), tr.id.size(), 4);
-    size_t o_tr_w = add(tr.w.data(), tr.w.size(), 4);
     size_t o_ridx = add(ridx.data(), ridx.size(), 8);
     size_t o_rw = add(rw.data(), rw.size(), 4);
     size_t o_sidx = add(sidx.data(), sidx.size(), 8);
@@ -899,15 +857,9 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         return fail(STRIDE_E_HIP, "plan tables: %s", hipGetErrorString(e));
     }
     char* B = (char*)P->blob;
-    P->src_inj = RowTable{(const int*)(B + o_ts_ptr), (const int*)(B + o_ts_x),
-                          (const int*)(B + o_ts_id), (const float*)(B + o_ts_w),
-                          (const int*)(B + o_tsf_ptr), (const TileEntry*)(B + o_tsf_ent)};
-    P->src_img = P->src_inj;
-    P->src_img.tile_ptr = (const int*)(B + o_tsa_ptr);
-    P->src_img.tile_ent = (const TileEntry*)(B + o_tsa_ent);
-    P->rec_inj = RowTable{(const int*)(B + o_tr_ptr), (const int*)(B + o_tr_x),
-                          (const int*)(B + o_tr_id), (const float*)(B + o_tr_w),
-                          (const int*)(B + o_tra_ptr), (const TileEntry*)(B + o_tra_ent)};
+    P->src_inj = InjTable{(const int*)(B + o_tsf_ptr), (const TileEntry*)(B + o_tsf_ent)};
+    P->src_img = InjTable{(const int*)(B + o_tsa_ptr), (const TileEntry*)(B + o_tsa_ent)};
+    P->rec_inj = InjTable{(const int*)(B + o_tra_ptr), (const TileEntry*)(B + o_tra_ent)};
     P->rec_idx = (const long long*)(B + o_ridx);
     P->rec_w = (const float*)(B + o_rw);
     P->src_idx = (const long long*)(B + o_sidx);

@@ -24,7 +24,7 @@
 namespace stride {
 
 // Tile shapes the kernels use (the host sizes launch shapes with these).
-// 3D defaults (fastest on 316^3): forward 4 rows x 4 waves, adjoint 2 rows x 4 waves.
+// 3D defaults (fastest on 316^3): forward 4 rows x 8 waves, adjoint 2 rows x 4 waves.
 void tile_shape(int nd, bool adjoint, int* ry, int* waves)
 {
     if (nd == 2) {
@@ -46,7 +46,7 @@ void tile_shape(int nd, bool adjoint, int* ry, int* waves)
     const char* er = getenv(adjoint ? "STRIDE_RY3D_ADJ" : "STRIDE_RY3D");
     const char* ew = getenv(adjoint ? "STRIDE_WAVES3D_ADJ" : "STRIDE_WAVES3D");
     int r = er && *er ? atoi(er) : (adjoint ? 2 : 4);
-    int w = ew && *ew ? atoi(ew) : 4;
+    int w = ew && *ew ? atoi(ew) : (adjoint ? 4 : 8);
     if (w != 8)
         w = 4;
     if (r != 1 && r != 2)
@@ -119,19 +119,6 @@ __device__ __forceinline__ int layer_depth(int i, int n, int nb)
     return i < nb ? nb - i : (i > hi ? i - hi : 0);
 }
 
-// Signal injected at column gx of grid row `row`: sum over the row's entries
-// at that column, in table order.
-__device__ __forceinline__ float row_signal(const RowTable& t, long long row, int gx,
-                                            const float* sig, int stride, int step)
-{
-    float s = 0.f;
-    const int b = t.row_ptr[row], e = t.row_ptr[row + 1];
-    for (int i = b; i < e; ++i)
-        if (t.x[i] == gx)
-            s += t.w[i] * sig[(long long)t.id[i] * stride + step];
-    return s;
-}
-
 __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* field, int step,
                                              int sb)
 {
@@ -170,7 +157,7 @@ __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float
 // buffer descriptor (at most 2 GiB): offsets of points outside the grid are
 // set to 0xffffffff and read 0.
 
-// Sum of the signals of the point whose first entry is e (entry order).
+// Sum of the signals of the point whose first entry is `head` (entry order).
 __device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEntry head,
                                                    const float* sig, int stride, int step)
 {
@@ -216,12 +203,12 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     const bool xin = gx < n1;
 
     // entry ranges of the tile (uniform)
-    const int eb0 = p.inj.tile_ptr[tile];
-    const int ne0 = p.inj.tile_ptr[tile + 1] - eb0;
+    const int eb0 = p.inj.ptr[tile];
+    const int ne0 = p.inj.ptr[tile + 1] - eb0;
     int eb1 = 0, ne1 = 0;
     if constexpr (ADJ) {
-        eb1 = p.img.tile_ptr[tile];
-        ne1 = p.img.tile_ptr[tile + 1] - eb1;
+        eb1 = p.img.ptr[tile];
+        ne1 = p.img.ptr[tile + 1] - eb1;
     }
 
     // tile rows with halo: byte offsets of the column and the halo column
@@ -272,18 +259,18 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     int il0 = -1, il1 = -1;
     float iv0 = 0.f, iv1 = 0.f;
     if (tid < ne0) {
-        const TileEntry e = p.inj.tile_ent[eb0 + tid];
+        const TileEntry e = p.inj.ent[eb0 + tid];
         if (e.run > 0) {
             il0 = e.local;
-            iv0 = tile_point_signal(p.inj.tile_ent + eb0 + tid, e, p.inj_sig, p.inj_stride, p.step);
+            iv0 = tile_point_signal(p.inj.ent + eb0 + tid, e, p.inj_sig, p.inj_stride, p.step);
         }
     }
     if constexpr (ADJ) {
         if (tid < ne1) {
-            const TileEntry e = p.img.tile_ent[eb1 + tid];
+            const TileEntry e = p.img.ent[eb1 + tid];
             if (e.run > 0) {
                 il1 = e.local;
-                iv1 = tile_point_signal(p.img.tile_ent + eb1 + tid, e, p.img_sig, p.img_stride, p.step);
+                iv1 = tile_point_signal(p.img.ent + eb1 + tid, e, p.img_sig, p.img_stride, p.step);
             }
         }
     }
@@ -315,19 +302,19 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         if (il0 >= 0)
             sS[0][il0] = iv0;
         for (int e = tid + NT; e < ne0; e += NT) {
-            const TileEntry en = p.inj.tile_ent[eb0 + e];
+            const TileEntry en = p.inj.ent[eb0 + e];
             if (en.run > 0)
                 sS[0][en.local] =
-                    tile_point_signal(p.inj.tile_ent + eb0 + e, en, p.inj_sig, p.inj_stride, p.step);
+                    tile_point_signal(p.inj.ent + eb0 + e, en, p.inj_sig, p.inj_stride, p.step);
         }
         if constexpr (ADJ) {
             if (il1 >= 0)
                 sS[1][il1] = iv1;
             for (int e = tid + NT; e < ne1; e += NT) {
-                const TileEntry en = p.img.tile_ent[eb1 + e];
+                const TileEntry en = p.img.ent[eb1 + e];
                 if (en.run > 0)
                     sS[1][en.local] =
-                        tile_point_signal(p.img.tile_ent + eb1 + e, en, p.img_sig, p.img_stride, p.step);
+                        tile_point_signal(p.img.ent + eb1 + e, en, p.img_sig, p.img_stride, p.step);
             }
         }
         __syncthreads();
@@ -400,7 +387,10 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     constexpr int HX = (NXH + NT - 1) / NT;
     constexpr int NF = ADJ ? 2 : 1;                 // stencil fields: A (and U)
     constexpr int PLANE = LH * LW;
+    constexpr int PL = TY * kTileX;                 // block-local points per plane
     __shared__ float sF[2][NF][PLANE];
+    __shared__ float sS[2][NF][PL];                 // injected signal per plane point
+    __shared__ int2 sE[NF][NT];                     // entry (local point, value) per thread
 
     if (b >= ls.tile_blocks_pad) {
         sample_block(p.smp, p.A, p.step, b - ls.tile_blocks_pad);
@@ -523,9 +513,68 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                 pg[j] = bload_stream(rg, rbo[j]);
         }
     };
-    prefetch(z0);
 
-    const int ylast = min(y0 + TY, n1);
+    // Injection entries of the block (uniform range).  Thread t takes entry t,
+    // sums the signal over the point's run and parks (local point, value) in
+    // LDS; before the barrier of each plane it writes the value of its entry
+    // of that plane to the LDS plane array, where the point's thread takes
+    // (and clears) it after the barrier.  Blocks with more than NT entries
+    // read the rest at every plane.
+    const int eb0 = p.inj.ptr[lb];
+    const int ne0 = p.inj.ptr[lb + 1] - eb0;
+    int eb1 = 0, ne1 = 0;
+    if constexpr (ADJ) {
+        eb1 = p.img.ptr[lb];
+        ne1 = p.img.ptr[lb + 1] - eb1;
+    }
+    const bool inj_any = ne0 > 0;
+    const bool img_any = ADJ && ne1 > 0;
+    prefetch(z0);
+    if (inj_any || img_any) {
+        int il0 = -1, il1 = -1;
+        float iv0 = 0.f, iv1 = 0.f;
+        if (tid < ne0) {
+            const TileEntry e = p.inj.ent[eb0 + tid];
+            if (e.run > 0) {
+                il0 = e.local;
+                iv0 = tile_point_signal(p.inj.ent + eb0 + tid, e, p.inj_sig, p.inj_stride, p.step);
+            }
+        }
+        if constexpr (ADJ) {
+            if (tid < ne1) {
+                const TileEntry e = p.img.ent[eb1 + tid];
+                if (e.run > 0) {
+                    il1 = e.local;
+                    iv1 = tile_point_signal(p.img.ent + eb1 + tid, e, p.img_sig, p.img_stride, p.step);
+                }
+            }
+        }
+#pragma unroll
+        for (int bsel = 0; bsel < 2; ++bsel)
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+#pragma unroll
+                for (int j = 0; j < RY; ++j)
+                    sS[bsel][f][(wy * RY + j) * kTileX + lx] = 0.f;
+        sE[0][tid] = make_int2(il0, __float_as_int(iv0));
+        if constexpr (ADJ)
+            sE[NF - 1][tid] = make_int2(il1, __float_as_int(iv1));
+        __syncthreads();
+        if (il0 >= 0 && il0 < PL)
+            sS[0][0][il0] = iv0;
+        if (il1 >= 0 && il1 < PL)
+            sS[0][NF - 1][il1] = iv1;
+    }
+    // entries beyond the first NT of the block: written at their plane
+    auto overflow = [&](const InjTable& T, int eb, int ne, const float* sig, int stride, int pz,
+                        float* dst) {
+        for (int e = tid + NT; e < ne; e += NT) {
+            const TileEntry en = T.ent[eb + e];
+            if (en.run > 0 && en.local / PL == pz)
+                dst[en.local - pz * PL] = tile_point_signal(T.ent + eb + e, en, sig, stride, p.step);
+        }
+    };
+
     int buf = 0;
     for (int zb = z0; zb < z1; zb += Q) {
         unrolled_while<Q>([&](auto uc) {
@@ -562,15 +611,24 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             }
             if (z + 1 < z1)
                 prefetch(z + 1);
+            const int pz = z - z0;
+            if (pz > 0 && (inj_any || img_any)) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const int2 e = sE[f][tid];
+                    if (e.x >= 0 && e.x / PL == pz)
+                        sS[buf][f][e.x - pz * PL] = __int_as_float(e.y);
+                }
+            }
+            if (ne0 > NT)
+                overflow(p.inj, eb0, ne0, p.inj_sig, p.inj_stride, pz, &sS[buf][0][0]);
+            if constexpr (ADJ)
+                if (ne1 > NT)
+                    overflow(p.img, eb1, ne1, p.img_sig, p.img_stride, pz, &sS[buf][NF - 1][0]);
             __syncthreads();
 
             float* Cz = p.C + (long long)z * s0;
             float* Gz = ADJ ? p.G + (long long)z * s0 : nullptr;
-            const long long rbase = (long long)z * n1;
-            const bool inj_any = p.inj.row_ptr[rbase + y0] < p.inj.row_ptr[rbase + ylast];
-            bool img_any = false;
-            if constexpr (ADJ)
-                img_any = p.img.row_ptr[rbase + y0] < p.img.row_ptr[rbase + ylast];
             const int dzd = layer_depth(z, n0, d.nb);
             const float ez = sp.e[0] * (float)(dzd * dzd);
 #pragma unroll
@@ -588,8 +646,10 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     ax = fmaf(cf.c[2][qq], SA[(ly + R) * LW + lx + R + qq] + SA[(ly + R) * LW + lx + R - qq], ax);
                 }
                 float lap = fmaf(cf.c0, ctr, az + ay + ax);
-                if (inj_any)
-                    lap += row_signal(p.inj, rbase + y0 + ly, gx, p.inj_sig, p.inj_stride, p.step);
+                if (inj_any) {
+                    lap += sS[buf][0][ly * kTileX + lx];
+                    sS[buf][0][ly * kTileX + lx] = 0.f;
+                }
                 const float eta = ez + ey[j];
                 __builtin_nontemporal_store(leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt),
                                             Cz + roff[j]);
@@ -604,8 +664,10 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                         ux = fmaf(cf.c[2][qq], SU[(ly + R) * LW + lx + R + qq] + SU[(ly + R) * LW + lx + R - qq], ux);
                     }
                     float lu = fmaf(cf.c0, uc0, uz + uy + ux);
-                    if (img_any)
-                        lu += row_signal(p.img, rbase + y0 + ly, gx, p.img_sig, p.img_stride, p.step);
+                    if (img_any) {
+                        lu += sS[buf][NF - 1][ly * kTileX + lx];
+                        sS[buf][NF - 1][ly * kTileX + lx] = 0.f;
+                    }
                     __builtin_nontemporal_store(fmaf(ctr, lu, gg[j]), Gz + roff[j]);
                 }
             }
@@ -639,8 +701,19 @@ __global__ __launch_bounds__(64 * WAVES) void step2d_batched(Dims d, StencilCoef
     step2d_body<R, ADJ, RY, WAVES>(d, cf, st.sp, st.p, ls, blockIdx.x);
 }
 
+// Occupancy target of a single-shot 3D kernel: 4 waves per SIMD (at most 128
+// VGPRs) where that costs no spills, else left to the compiler.  (The batched
+// kernels hold their slot's parameters in registers as well; they are left to
+// the compiler, which keeps them free of spills.)
+template <bool ADJ, int RY, int WAVES>
+constexpr int min_waves_3d()
+{
+    return RY <= 2 || (!ADJ && WAVES == 8) ? 4 : 1;
+}
+
 template <int R, bool ADJ, int RY, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(min_waves_3d<ADJ, RY, WAVES>())))
+void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
                                                             StepParams p, LaunchShape ls)
 {
     step3d_body<R, ADJ, RY, WAVES>(d, cf, sp, p, ls, blockIdx.x);
