@@ -99,7 +99,9 @@ def parse():
     ap.add_argument("--no-graphs", action="store_true", help="serving: direct launches, no hipGraphs")
     ap.add_argument("--no-baseline", action="store_true", help="serving: skip the one-at-a-time run")
     ap.add_argument("--load", type=float, default=1.5,
-                    help="serving: arrival rate in units of the one-at-a-time service rate")
+                    help="serving: arrival rate in units of the one-at-a-time service rate (1.5 "
+                         "is the specified stream; 4 saturates both systems, so solves/s then "
+                         "measures capacity)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (scale for HBM byte counters)")
     return ap.parse_args()
