@@ -11,9 +11,10 @@ value = grid-point updates per second of forward + adjoint propagation,
 counted as work).  A forward-only solve of the same workload is timed too.
 
 roofline: the dominant kernel is the fused adjoint + imaging step (28
-algorithmic bytes per grid point: reads u^m, w^{m+1}, w^{m+2}, k, G; writes
-w^m, G).  Its per-launch time comes from HIP events the library records on
-the solve stream around the adjoint time loop during the timed steps.
+algorithmic bytes per grid-point update: reads u^m, w^{m+1}, w^{m+2}, k, G;
+writes w^m, G).  Its time comes from HIP events the library records on the
+solve stream around the adjoint time loop during the timed steps, with the
+step and launch counts.
 """
 import argparse
 import json
@@ -33,11 +34,11 @@ HBM_PEAK_GBS = 8000.0
 # kernel file and its header; any change makes `traffic` null until the
 # counters are taken again.
 MEASURED_TRAFFIC = {
-    "config2": {"sha256": "c41ddeefa1411f64a7eecffa573f29eb8bdc0dba2f4dd974a2091116e88d2bd9",
-                "fetch_kib": 12284.25, "write_kib": 9522.30,
-                "copy_fetch_kib": 524308.62, "copy_write_kib": 1048576.0},
-    "config4": {"sha256": "c41ddeefa1411f64a7eecffa573f29eb8bdc0dba2f4dd974a2091116e88d2bd9",
-                "fetch_kib": 477523.50, "write_kib": 249640.00,
+    "config2": {"sha256": "6a142eccc59bb7949650c3b8d0725613000c399af55b6c85a22e6a128d10fa57",
+                "fetch_kib": 12284.25, "write_kib": 9522.53,
+                "copy_fetch_kib": 524308.94, "copy_write_kib": 1048576.0},
+    "config4": {"sha256": "6a142eccc59bb7949650c3b8d0725613000c399af55b6c85a22e6a128d10fa57",
+                "fetch_kib": 477532.47, "write_kib": 249640.00,
                 "copy_fetch_kib": 524315.25, "copy_write_kib": 1048576.0},
 }
 
@@ -288,17 +289,20 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     S.stride_timing_enable(False)
-    f_ms, f_n, a_ms, a_n = S.stride_timing_read()
+    f_ms, f_n, f_l, a_ms, a_n, a_l = S.stride_timing_read()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
     value = 2.0 * npad * (w.nt - 1) * args.steps / elapsed
-    adj_launch_s = a_ms * 1e-3 / max(a_n, 1)
-    fwd_launch_s = f_ms * 1e-3 / max(f_n, 1)
-    adj_gbs = ADJ_BYTES * npad / adj_launch_s / 1e9
-    fwd_in_grad_gbs = FWD_BYTES * npad / fwd_launch_s / 1e9
+    # per time step and per kernel launch (a 2D launch advances two steps)
+    adj_step_s = a_ms * 1e-3 / max(a_n, 1)
+    adj_launch_s = a_ms * 1e-3 / max(a_l, 1)
+    adj_spl = a_n / max(a_l, 1)
+    fwd_step_s = f_ms * 1e-3 / max(f_n, 1)
+    adj_gbs = ADJ_BYTES * npad / adj_step_s / 1e9
+    fwd_in_grad_gbs = FWD_BYTES * npad / fwd_step_s / 1e9
     recompute = f_n / max(1, args.steps * (w.nt - 1))
-    print(f"[bench] gradient: {ms_per_step:.2f} ms/step, adjoint kernel {adj_launch_s * 1e6:.2f} us/launch "
-          f"({adj_gbs:.0f} GB/s), forward kernel {fwd_launch_s * 1e6:.2f} us/launch, "
+    print(f"[bench] gradient: {ms_per_step:.2f} ms/step, adjoint {adj_step_s * 1e6:.2f} us/step "
+          f"({adj_gbs:.0f} GB/s, {adj_spl:.2f} steps/launch), forward {fwd_step_s * 1e6:.2f} us/step, "
           f"forward steps per step {f_n / args.steps:.0f}", file=sys.stderr, flush=True)
 
     fwd = {}
@@ -313,16 +317,17 @@ def main():
         torch.cuda.synchronize()
         tf1 = time.perf_counter()
         S.stride_timing_enable(False)
-        ff_ms, ff_n, _, _ = S.stride_timing_read()
-        f_launch = ff_ms * 1e-3 / max(ff_n, 1)
+        ff_ms, ff_n, ff_l, _, _, _ = S.stride_timing_read()
+        f_step = ff_ms * 1e-3 / max(ff_n, 1)
         fwd = {
             "fwd_updates_per_s": npad * (w.nt - 1) * args.steps / (tf1 - tf0),
             "fwd_ms_per_solve": 1e3 * (tf1 - tf0) / args.steps,
-            "fwd_kernel_us": f_launch * 1e6,
-            "fwd_kernel_gbs": FWD_BYTES * npad / f_launch / 1e9,
+            "fwd_us_per_step": f_step * 1e6,
+            "fwd_steps_per_launch": ff_n / max(ff_l, 1),
+            "fwd_kernel_gbs": FWD_BYTES * npad / f_step / 1e9,
         }
-        print(f"[bench] forward: {fwd['fwd_ms_per_solve']:.2f} ms/solve, kernel "
-              f"{fwd['fwd_kernel_us']:.2f} us ({fwd['fwd_kernel_gbs']:.0f} GB/s)",
+        print(f"[bench] forward: {fwd['fwd_ms_per_solve']:.2f} ms/solve, {fwd['fwd_us_per_step']:.2f} us/step "
+              f"({fwd['fwd_kernel_gbs']:.0f} GB/s, {fwd['fwd_steps_per_launch']:.2f} steps/launch)",
               file=sys.stderr, flush=True)
 
     cpu = None
@@ -366,9 +371,12 @@ def main():
             "frac": adj_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch",
-            "traffic_over_algorithmic": traffic / (ADJ_BYTES * npad) if traffic else None,
+            "traffic_over_algorithmic": (traffic / (ADJ_BYTES * npad * adj_spl)) if traffic else None,
             "bytes_per_point": ADJ_BYTES,
+            "algorithmic_bytes_per_launch": ADJ_BYTES * npad * adj_spl,
+            "steps_per_launch": adj_spl,
             "us_per_launch": adj_launch_s * 1e6,
+            "us_per_step": adj_step_s * 1e6,
             "forward_kernel_in_gradient_gbs": fwd_in_grad_gbs,
         },
         **fwd,

@@ -99,7 +99,7 @@ int stride_plan_padded_shape(const stride_plan_t* plan, int64_t out[3]);
  * (Griewank-Walther revolve) with as many snapshots as fit, and 0 asks for the
  * size that keeps every state (no recomputation).  The snapshot count a solve
  * uses is derived from the ws_bytes it is given.  Errors: INVALID_ARG,
- * WORKSPACE (budget below the minimum of 6 wavefields plus traces). */
+ * WORKSPACE (budget below the minimum of 8 wavefields plus traces). */
 int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budget_bytes,
                            size_t* out_bytes);
 
@@ -204,11 +204,14 @@ int stride_accumulate(float* dst, const float* src, int64_t n, void* stream);
  * records HIP event pairs on its stream around its forward time loop, its
  * adjoint time loop and each recomputation segment inside the adjoint loop.
  * stride_timing_read waits for the recorded events and returns, since the last
- * read, the time (ms) and launch count of forward steps (recomputation
- * included) and of adjoint steps (recomputation excluded), then clears them. */
+ * read, the time (ms), the time steps and the kernel launches of forward steps
+ * (recomputation included) and of adjoint steps (recomputation excluded), then
+ * clears them.  Every launch advances one step today; the counts are kept
+ * apart so that a launch that advances several steps can be reported.  Any
+ * output pointer may be NULL. */
 int stride_timing_enable(int32_t on);
-int stride_timing_read(double* fwd_ms, int64_t* fwd_launches, double* adj_ms,
-                       int64_t* adj_launches);
+int stride_timing_read(double* fwd_ms, int64_t* fwd_steps, int64_t* fwd_launches, double* adj_ms,
+                       int64_t* adj_steps, int64_t* adj_launches);
 
 /* Message of the calling thread's last error ("" if none). */
 const char* stride_last_error(void);

@@ -84,8 +84,8 @@ def lib():
         L.stride_schedule_info.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(i32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
         L.stride_timing_enable.argtypes = [i32]
-        L.stride_timing_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), dp,
-                                         ctypes.POINTER(ctypes.c_int64)]
+        L.stride_timing_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                         dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.stride_engine_create.argtypes = [gp, i32, i32, i32, i32, ctypes.POINTER(vp_)]
         L.stride_engine_destroy.argtypes = [vp_]
         L.stride_engine_attach.argtypes = [vp_, vp_, i32, vp_, ctypes.c_float, vp_, vp_, vp_, vp_, vp_,
@@ -204,12 +204,13 @@ def stride_timing_enable(on: bool) -> None:
 
 
 def stride_timing_read():
-    """(fwd_ms, fwd_launches, adj_ms, adj_launches) since the last read."""
+    """(fwd_ms, fwd_steps, fwd_launches, adj_ms, adj_steps, adj_launches) since
+    the last read."""
     f, a = ctypes.c_double(), ctypes.c_double()
-    nf, na = ctypes.c_int64(), ctypes.c_int64()
-    _check(lib().stride_timing_read(ctypes.byref(f), ctypes.byref(nf), ctypes.byref(a),
-                                    ctypes.byref(na)))
-    return f.value, int(nf.value), a.value, int(na.value)
+    nf, lf, na, la = (ctypes.c_int64() for _ in range(4))
+    _check(lib().stride_timing_read(ctypes.byref(f), ctypes.byref(nf), ctypes.byref(lf),
+                                    ctypes.byref(a), ctypes.byref(na), ctypes.byref(la)))
+    return f.value, int(nf.value), int(lf.value), a.value, int(na.value), int(la.value)
 
 
 def stride_plan_forward(plan, vp, wavelet, traces, ws, stream=None):

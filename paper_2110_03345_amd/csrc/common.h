@@ -109,6 +109,7 @@ void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& 
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);
+
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s);

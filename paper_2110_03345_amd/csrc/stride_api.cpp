@@ -479,7 +479,7 @@ struct PhaseTimer {
     struct Rec {
         hipEvent_t a, b;
         int kind;   // 0 forward loop, 1 adjoint loop, 2 recomputation inside 1
-        long long launches;
+        long long steps, launches;
     };
     std::vector<Rec> recs;
     std::vector<hipEvent_t> spare;
@@ -500,18 +500,19 @@ struct PhaseTimer {
     {
         if (!on)
             return -1;
-        Rec r{ev(), ev(), 0, 0};
+        Rec r{ev(), ev(), 0, 0, 0};
         if (!r.a || !r.b)
             return -1;
         (void)hipEventRecord(r.a, s);
         recs.push_back(r);
         return (int)recs.size() - 1;
     }
-    void end(int id, hipStream_t s, int kind, long long launches)
+    void end(int id, hipStream_t s, int kind, long long steps, long long launches)
     {
         if (id < 0)
             return;
         recs[id].kind = kind;
+        recs[id].steps = steps;
         recs[id].launches = launches;
         (void)hipEventRecord(recs[id].b, s);
     }
@@ -526,6 +527,7 @@ thread_local PhaseTimer g_timer;
 // sweep visits every index once); with run = false it only replays the
 // bookkeeping, which stride_backward uses to find the pool state the forward
 // sweep left behind.  backward_phase launches recomputation and adjoint steps.
+// One launch advances one step, so steps and launches count alike.
 struct Runner {
     const stride_plan& P;
     GradWs& W;
@@ -584,7 +586,7 @@ struct Runner {
                 continue;
             }
             if (seg >= 0) {
-                g_timer.end(seg, s, 2, launches - seg_start);
+                g_timer.end(seg, s, 2, launches - seg_start, launches - seg_start);
                 seg = -1;
             }
             StepParams p = base_params(P);
@@ -608,7 +610,7 @@ struct Runner {
             wa = 1 - wa;
         }
         if (seg >= 0)
-            g_timer.end(seg, s, 2, launches - seg_start);
+            g_timer.end(seg, s, 2, launches - seg_start, launches - seg_start);
     }
 };
 
@@ -643,7 +645,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
         launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
         cur = 1 - cur;
     }
-    g_timer.end(tid, s, 0, P.nt - 1);
+    g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
     launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
     return STRIDE_OK;
@@ -667,7 +669,7 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     Runner run(P, W, s, wavelet);
     int tid = g_timer.begin(s);
     run.forward_phase(true, tr);
-    g_timer.end(tid, s, 0, run.launches);
+    g_timer.end(tid, s, 0, run.launches, run.launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     // last sample from the final state x_{nt-1}
@@ -694,7 +696,7 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     launch_fill(W.w[1], P.dims.total, 0.f, s);
     int tid = g_timer.begin(s);
     run.backward_phase(grad_traces, dwavelet);
-    g_timer.end(tid, s, 1, run.adj_launches);
+    g_timer.end(tid, s, 1, run.adj_launches, run.adj_launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     launch_finalize_dvp(P.dims, W.G, vp, dvp, W.w[0], W.w[1], s);
@@ -807,6 +809,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->ls_fwd = make_shape(d, default_zc(d, ryf * wf), ryf, wf);
     P->ls_adj = make_shape(d, default_zc(d, rya * wa), rya, wa);
 
+
     std::vector<Tap> st, rt;
     if ((rc = make_taps(*P, src_xyz, nsrc, st, "source")) ||
         (rc = make_taps(*P, rec_xyz, nrec, rt, "receiver"))) {
@@ -860,6 +863,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->src_inj = InjTable{(const int*)(B + o_tsf_ptr), (const TileEntry*)(B + o_tsf_ent)};
     P->src_img = InjTable{(const int*)(B + o_tsa_ptr), (const TileEntry*)(B + o_tsa_ent)};
     P->rec_inj = InjTable{(const int*)(B + o_tra_ptr), (const TileEntry*)(B + o_tra_ent)};
+
     P->rec_idx = (const long long*)(B + o_ridx);
     P->rec_w = (const float*)(B + o_rw);
     P->src_idx = (const long long*)(B + o_sidx);
@@ -1038,16 +1042,18 @@ int stride_timing_enable(int32_t on)
     return STRIDE_OK;
 }
 
-int stride_timing_read(double* fwd_ms, int64_t* fwd_launches, double* adj_ms, int64_t* adj_launches)
+int stride_timing_read(double* fwd_ms, int64_t* fwd_steps, int64_t* fwd_launches, double* adj_ms,
+                       int64_t* adj_steps, int64_t* adj_launches)
 {
     double t[3] = {0, 0, 0};
-    long long n[3] = {0, 0, 0};
+    long long n[3] = {0, 0, 0}, l[3] = {0, 0, 0};
     for (auto& r : g_timer.recs) {
         HIP_TRY(hipEventSynchronize(r.b));
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
         t[r.kind] += ms;
-        n[r.kind] += r.launches;
+        n[r.kind] += r.steps;
+        l[r.kind] += r.launches;
         g_timer.spare.push_back(r.a);
         g_timer.spare.push_back(r.b);
     }
@@ -1056,12 +1062,16 @@ int stride_timing_read(double* fwd_ms, int64_t* fwd_launches, double* adj_ms, in
     // with the forward steps and take it out of the adjoint time
     if (fwd_ms)
         *fwd_ms = t[0] + t[2];
+    if (fwd_steps)
+        *fwd_steps = n[0] + n[2];
     if (fwd_launches)
-        *fwd_launches = n[0] + n[2];
+        *fwd_launches = l[0] + l[2];
     if (adj_ms)
         *adj_ms = t[1] - t[2];
+    if (adj_steps)
+        *adj_steps = n[1];
     if (adj_launches)
-        *adj_launches = n[1];
+        *adj_launches = l[1];
     return STRIDE_OK;
 }
 

@@ -18,6 +18,12 @@
 
 #include "common.h"
 
+// Implicit contraction is off: every fused multiply-add is written out as
+// fmaf, so the arithmetic of a point does not depend on how the compiler
+// schedules the surrounding code (any two kernels that evaluate the same
+// expressions compute the same bits).
+#pragma clang fp contract(off)
+
 #include <cstdlib>
 #include <type_traits>
 
@@ -128,7 +134,7 @@ __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* 
     float acc = 0.f;
 #pragma unroll
     for (int t = 0; t < kMaxTaps; ++t)
-        acc += smp.w[r * kMaxTaps + t] * field[smp.idx[r * kMaxTaps + t]];
+        acc = fmaf(smp.w[r * kMaxTaps + t], field[smp.idx[r * kMaxTaps + t]], acc);
     smp.out[(long long)r * smp.out_stride + step] = acc;
 }
 
@@ -136,11 +142,23 @@ __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float
                                           float half_dt)
 {
     if (eta == 0.f)
-        return fmaf(kk, rhs, 2.f * ctr - prev);
-    float h = eta * half_dt;
-    float a = 1.f / (1.f + h);
-    float b = (1.f - h) * a;
-    return a * (2.f * ctr + kk * rhs) - b * prev;
+        return fmaf(kk, rhs, fmaf(2.f, ctr, -prev));
+    const float a = 1.f / fmaf(eta, half_dt, 1.f);
+    const float b = fmaf(-eta, half_dt, 1.f) * a;
+    return fmaf(a, fmaf(kk, rhs, 2.f * ctr), -(b * prev));
+}
+
+// 2D Laplacian at S[0] of an LDS tile with row length LW_.
+template <int R, int LW_>
+__device__ __forceinline__ float lap2d(const float* S, const StencilCoef& cf)
+{
+    float ay = 0.f, ax = 0.f;
+#pragma unroll
+    for (int q = R; q >= 1; --q) {
+        ay = fmaf(cf.c[0][q], S[q * LW_] + S[-q * LW_], ay);
+        ax = fmaf(cf.c[1][q], S[q] + S[-q], ax);
+    }
+    return fmaf(cf.c0, S[0], ay + ax);
 }
 
 // ----------------------------------------------------------------------- 2D
@@ -164,7 +182,7 @@ __device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEnt
     float v = head.w * sig[(long long)head.id * stride + step];
     for (int k = 1; k < head.run; ++k) {
         const TileEntry e = ent[k];
-        v += e.w * sig[(long long)e.id * stride + step];
+        v = fmaf(e.w, sig[(long long)e.id * stride + step], v);
     }
     return v;
 }
@@ -331,27 +349,15 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         const int ly = wy * RY + j;
         const float* SA = &sF[0][(ly + R) * LW + lx + R];
         const float ctr = SA[0];
-        float ay = 0.f, ax = 0.f;
-#pragma unroll
-        for (int q = R; q >= 1; --q) {
-            ay = fmaf(cf.c[0][q], SA[q * LW] + SA[-q * LW], ay);
-            ax = fmaf(cf.c[1][q], SA[q] + SA[-q], ax);
-        }
-        float lap = fmaf(cf.c0, ctr, ay + ax);
+        float lap = lap2d<R, LW>(SA, cf);
         if (inj_any)
             lap += sS[0][ly * kTileX + lx];
         const int dyd = layer_depth(y0 + ly, n0, d.nb);
-        const float eta = sp.e[0] * (float)(dyd * dyd) + ex;
+        const float eta = fmaf(sp.e[0], (float)(dyd * dyd), ex);
         p.C[po[j]] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
         if constexpr (ADJ) {
             const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
-            float uy = 0.f, ux = 0.f;
-#pragma unroll
-            for (int q = R; q >= 1; --q) {
-                uy = fmaf(cf.c[0][q], SU[q * LW] + SU[-q * LW], uy);
-                ux = fmaf(cf.c[1][q], SU[q] + SU[-q], ux);
-            }
-            float lu = fmaf(cf.c0, SU[0], uy + ux);
+            float lu = lap2d<R, LW>(SU, cf);
             if (img_any)
                 lu += sS[NF - 1][ly * kTileX + lx];
             p.G[po[j]] = fmaf(ctr, lu, gg[j]);
@@ -429,7 +435,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         roff[j] = gy * s1 + gx;
         rbo[j] = rin[j] ? roff[j] * 4 : -1;
         const int dyd = layer_depth(gy, n1, d.nb);
-        ey[j] = sp.e[1] * (float)(dyd * dyd) + ex;
+        ey[j] = fmaf(sp.e[1], (float)(dyd * dyd), ex);
     }
     int hy_l[HY], hy_o[HY];
 #pragma unroll
