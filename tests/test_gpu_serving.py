@@ -170,6 +170,42 @@ def test_server_results_equal_solo_solves(realtime):
     assert out["p99_s"] >= out["p50_s"] > 0
 
 
+def test_served_requests_match_the_oracle():
+    """Sampled requests of a served mix (one forward, one gradient, each of
+    several shots) against the FP64 oracle."""
+    import oracle
+    specs = _small_mix(10, seed=11)
+    srv = Server(max_slots=6, max_chunk=16, use_graphs=True)
+    try:
+        out = srv.run(specs, realtime=False)
+    finally:
+        srv.close()
+    checked = set()
+    for r in sorted(out["requests"], key=lambda q: q.spec.rid):
+        sp = r.spec
+        if sp.kind in checked:
+            continue
+        checked.add(sp.kind)
+        print(f"oracle check: request {sp.rid} {sp.kind} n={sp.n} shots={sp.nshots}", flush=True)
+        g = oracle.Grid(**sp.grid_kwargs())
+        J, dvp = 0.0, np.zeros(sp.shape)
+        for i in range(sp.nshots):
+            src = sp.src_xyz[i:i + 1]
+            if sp.kind == "forward":
+                ref = oracle.forward(g, sp.vp, src, sp.wavelet, sp.rec_xyz)
+                got = r.result["traces"][i].cpu().numpy()
+                assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+            else:
+                _, j, d = oracle.gradient(g, sp.vp, src, sp.wavelet, sp.rec_xyz, sp.observed[i])
+                J += j
+                dvp += d
+        if sp.kind == "gradient":
+            got = r.result["dvp"].cpu().numpy()
+            assert np.linalg.norm(got - dvp) <= 1e-4 * np.linalg.norm(dvp)
+            assert abs(r.result["misfit"] - J) <= 1e-4 * J
+    assert checked == {"forward", "gradient"}
+
+
 def test_server_respects_the_hbm_budget():
     specs = _small_mix(8, seed=9)
     srv = Server(hbm_budget=64 << 20, max_slots=8, max_chunk=16)
