@@ -29,6 +29,8 @@
  *   - Arrays are C order (last axis contiguous).  vp and dvp have the physical
  *     shape; wavelets are [nsrc][nt]; traces, observed and grad_traces are
  *     [nrec][nt].  All of these are FP32 DEVICE pointers owned by the caller.
+ *     nsrc or nrec may be 0: the wavelet (nsrc = 0) and the trace arrays
+ *     (nrec = 0) may then be NULL.
  *   - Coordinates (src_xyz, rec_xyz) are FP64 HOST arrays [count][ndim] in
  *     metres, origin at physical node 0, axis order of the arrays.
  *   - ws is a caller-owned DEVICE workspace of ws_bytes bytes, 256-byte aligned,

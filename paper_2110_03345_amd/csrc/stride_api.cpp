@@ -617,7 +617,7 @@ struct Runner {
 int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
                   void* ws, size_t bytes, hipStream_t s)
 {
-    if (!vp || !wavelet || !traces)
+    if (!vp || (!wavelet && P.nsrc > 0) || (!traces && P.nrec > 0))
         return fail(STRIDE_E_INVALID_ARG, "vp, wavelet and traces must be device pointers");
     FwdWs F;
     int rc = fwd_ws(P, ws, bytes, F);
@@ -654,7 +654,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
 int forward_save(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
                  void* ws, size_t bytes, hipStream_t s, GradWs& W)
 {
-    if (!vp || !wavelet)
+    if (!vp || (!wavelet && P.nsrc > 0))
         return fail(STRIDE_E_INVALID_ARG, "vp and wavelet must be device pointers");
     int rc = grad_ws(P, ws, bytes, W);
     if (rc)
@@ -683,7 +683,7 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
 int backward(const stride_plan& P, const float* vp, const float* wavelet, const float* grad_traces,
              float* dvp, float* dwavelet, void* ws, size_t bytes, hipStream_t s)
 {
-    if (!vp || !wavelet || !grad_traces || !dvp)
+    if (!vp || (!wavelet && P.nsrc > 0) || (!grad_traces && P.nrec > 0) || !dvp)
         return fail(STRIDE_E_INVALID_ARG, "vp, wavelet, grad_traces and dvp must be device pointers");
     GradWs W;
     int rc = grad_ws(P, ws, bytes, W);
@@ -921,6 +921,9 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
             return fail(STRIDE_E_WORKSPACE, "budget too small for checkpointing");
         nfields = cached_schedule(plan->nt, s)->stats.peak_fields;
     }
+    // never below the pool a gradient solve accepts (a very short schedule
+    // can peak under it)
+    nfields = std::max<long long>(nfields, 4);
     *out_bytes = L.fixed_grad + (size_t)nfields * L.field;
     return STRIDE_OK;
 }
@@ -961,7 +964,7 @@ int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
-    if (!observed || !misfit || !dvp)
+    if ((!observed && plan->nrec > 0) || !misfit || !dvp)
         return fail(STRIDE_E_INVALID_ARG, "observed, misfit and dvp must be device pointers");
     hipStream_t s = as_stream(stream);
     GradWs W;

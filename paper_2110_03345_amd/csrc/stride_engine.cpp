@@ -282,7 +282,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
     if (plan->nrec > E->max_samples)
         return fail(STRIDE_E_INVALID_ARG, "plan has %d receivers; the engine samples at most %d",
                     plan->nrec, E->max_samples);
-    if (!vp || !wavelet)
+    if (!vp || (!wavelet && plan->nsrc > 0))
         return fail(STRIDE_E_INVALID_ARG, "vp and wavelet must be device pointers");
     int free_slot = -1;
     for (int i = 0; i < E->max_slots; ++i)
@@ -304,7 +304,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
     J.dvp = dvp;
     int rc;
     if (mode == STRIDE_MODE_FORWARD) {
-        if (!traces)
+        if (!traces && plan->nrec > 0)
             return fail(STRIDE_E_INVALID_ARG, "forward slots need traces");
         if ((rc = fwd_ws(*plan, ws, ws_bytes, J.F)))
             return rc;
@@ -316,7 +316,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         launch_fill(J.F.u[1], plan->dims.total, 0.f, s);
         J.left = plan->nt - 1;
     } else if (mode == STRIDE_MODE_GRADIENT) {
-        if (!observed || !misfit || !dvp)
+        if ((!observed && plan->nrec > 0) || !misfit || !dvp)
             return fail(STRIDE_E_INVALID_ARG, "gradient slots need observed, misfit and dvp");
         if ((rc = grad_ws(*plan, ws, ws_bytes, J.W)))
             return rc;

@@ -81,6 +81,17 @@ def test_workspace_sizes():
     assert e.value.code == _abi.STRIDE_E_WORKSPACE
 
 
+@pytest.mark.parametrize("nt", [2, 3, 4])
+def test_gradient_workspace_query_meets_the_solve_minimum(nt):
+    """Very short schedules peak below the 4-field pool a gradient solve
+    requires; the query still returns a size the solve accepts."""
+    g = _grid(nt=nt)
+    field = -(-(52 * 64 * 4) // 256) * 256
+    traces = -(-(3 * nt * 4) // 256) * 256
+    fixed = 256 + 256 * 8 + 4 * field + 2 * traces
+    assert S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT) >= fixed + 4 * field
+
+
 @lru_cache(None)
 def _dp(l, s):
     """Brute-force minimal forward steps to reverse l steps with s free slots."""

@@ -171,6 +171,64 @@ def test_dense_geometry_matches_oracle(maker, nsrc, nrec):
     assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
 
 
+def _aniso(w, factors):
+    w.spacing = tuple(w.spacing * f for f in factors)   # larger spacing: still inside, still stable
+    return w
+
+
+EDGE_CASES = [
+    ("one_step", lambda: W.tiny_2d(nt=2)),
+    ("grid_smaller_than_stencil_2d", lambda: W.tiny_2d(n=(5, 3), nb=0, nt=40)),
+    ("grid_smaller_than_stencil_3d", lambda: W.tiny_3d(n=(3, 4, 5), nb=0, nt=30)),
+    ("anisotropic_2d", lambda: _aniso(W.tiny_2d(), (1.0, 1.3))),
+    ("anisotropic_3d", lambda: _aniso(W.tiny_3d(), (1.0, 1.2, 1.4))),
+]
+
+
+@pytest.mark.parametrize("name,make", EDGE_CASES, ids=[c[0] for c in EDGE_CASES])
+def test_edge_cases_match_oracle(name, make):
+    w = make()
+    print(f"edge case {name}: shape={w.shape} spacing={w.spacing} nb={w.nb} nt={w.nt}", flush=True)
+    g = oracle.Grid(**w.grid_kwargs())
+    plan = S.Plan.from_workload(w)
+    ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    tr = plan.forward(dev(w.vp), dev(w.wavelet)).cpu().numpy()
+    if np.linalg.norm(ref) == 0:
+        assert np.all(tr == 0)
+    else:
+        assert rel(tr, ref) < 1e-4, rel(tr, ref)
+    rng = np.random.default_rng(6)
+    obs = (0.5 * ref + 1e-3 * rng.standard_normal(ref.shape)).astype(np.float32)
+    _, J, dvp_ref = oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, obs)
+    misfit, dvp = plan.gradient(dev(w.vp), dev(w.wavelet), dev(obs))
+    assert abs(misfit.item() - J) <= 1e-4 * abs(J)
+    if np.linalg.norm(dvp_ref) == 0:
+        assert np.all(dvp.cpu().numpy() == 0)
+    else:
+        assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
+
+
+@pytest.mark.parametrize("empty", ["receivers", "sources"])
+def test_empty_geometry(empty):
+    """No receivers: empty traces, zero misfit and gradient.  No sources: the
+    field stays zero, so traces and gradient are zero."""
+    w = W.tiny_2d()
+    if empty == "receivers":
+        w.rec_xyz = np.zeros((0, 2))
+    else:
+        w.src_xyz = np.zeros((0, 2))
+        w.wavelet = np.zeros((0, w.nt), dtype=np.float32)
+    plan = S.Plan.from_workload(w)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    tr = plan.forward(vp, wav)
+    assert tuple(tr.shape) == (w.rec_xyz.shape[0], w.nt)
+    assert torch.count_nonzero(tr).item() == 0
+    obs = torch.zeros_like(tr)
+    misfit, dvp = plan.gradient(vp, wav, obs)
+    assert misfit.item() == 0.0
+    assert torch.count_nonzero(dvp).item() == 0
+
+
 def test_config1_forward_matches_oracle():
     w = W.config1()
     g = oracle.Grid(**w.grid_kwargs())
