@@ -98,6 +98,8 @@ def parse():
                     help="serving: all six grid classes and nt 500-3000 (default: 2D classes and "
                          "128^3, nt 500-1500)")
     ap.add_argument("--no-graphs", action="store_true", help="serving: direct launches, no hipGraphs")
+    ap.add_argument("--max-slots", type=int, default=32, help="serving: shots per engine")
+    ap.add_argument("--max-chunk", type=int, default=64, help="serving: ticks per graph chunk")
     ap.add_argument("--no-baseline", action="store_true", help="serving: skip the one-at-a-time run")
     ap.add_argument("--load", type=float, default=1.5,
                     help="serving: arrival rate in units of the one-at-a-time service rate (1.5 "
@@ -176,7 +178,7 @@ def serving_bench(args):
           f"mean one-at-a-time service {mean_service * 1e3:.1f} ms, rate {rate:.2f}/s",
           file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    srv = Server(use_graphs=not args.no_graphs)
+    srv = Server(use_graphs=not args.no_graphs, max_slots=args.max_slots, max_chunk=args.max_chunk)
     try:
         served = srv.run(specs, realtime=True)
     finally:
@@ -216,6 +218,8 @@ def serving_bench(args):
             "nt_range": list(kw["nt_range"]),
             "arrival_rate_per_s": rate,
             "load": args.load,
+            "max_slots": args.max_slots,
+            "max_chunk": args.max_chunk,
         },
         "p50_s": served["p50_s"],
         "p99_s": served["p99_s"],

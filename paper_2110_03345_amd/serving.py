@@ -145,7 +145,7 @@ class Server:
     """Admits shots by free HBM budget and slot availability, runs them in
     continuous batches, and records per-request latency."""
 
-    def __init__(self, hbm_budget: Optional[int] = None, max_slots: int = 16, max_chunk: int = 64,
+    def __init__(self, hbm_budget: Optional[int] = None, max_slots: int = 32, max_chunk: int = 64,
                  use_graphs: bool = True, grad_cap: int = 24 << 30, max_inflight: int = 3,
                  max_receivers: int = 1024, device=None):
         self.device = torch.device(device or "cuda")
