@@ -32,6 +32,7 @@ class _CGrid(ctypes.Structure):
         ("vref", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("nt", ctypes.c_int),
+        ("time_order", ctypes.c_int),
     ]
 
 
@@ -45,6 +46,7 @@ class Grid:
     vref: float
     dt: float
     nt: int
+    time_order: int = 2      # 4: leapfrog with the modified-equation correction (forward only)
     ndim: int = field(init=False)
 
     def __post_init__(self):
@@ -65,6 +67,7 @@ class Grid:
         g.vref = self.vref
         g.dt = self.dt
         g.nt = self.nt
+        g.time_order = self.time_order
         return g
 
     @property

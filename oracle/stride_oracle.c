@@ -377,11 +377,54 @@ static void forward_step(const solve_t *S, const double *ucur, const double *upr
             }
 }
 
+/* Time-filtered source of the fourth-order scheme: (S^{n-1} + 10 S^n + S^{n+1}) / 12. */
+static void source_term4(const solve_t *S, const double *wavelet, int nt, int n, double *dense)
+{
+    memset(dense, 0, sizeof(double) * S->G.N);
+    for (int s = 0; s < S->nsrc; s++) {
+        const double *w = wavelet + (long)s * nt;
+        double wm = n >= 1 ? w[n - 1] : 0.0, wp = n + 1 < nt ? w[n + 1] : 0.0;
+        double ws = (wm + 10.0 * w[n] + wp) / 12.0;
+        for (int t = 0; t < S->ntap; t++)
+            dense[S->sidx[s * 8 + t]] += S->sw[s * 8 + t] * ws / S->G.cellvol;
+    }
+}
+
+/* One fourth-order step: p = k (L ucur + src); unext = a (2 ucur + p + (k/12) L p) - b uprev. */
+static void forward_step4(const solve_t *S, const double *ucur, const double *uprev,
+                          const double *src, double *p, double *unext)
+{
+    const geo_t *G = &S->G;
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G->np[0]; i0++)
+        for (long i1 = 0; i1 < G->np[1]; i1++)
+            for (long i2 = 0; i2 < G->np[2]; i2++) {
+                long q = pidx(G, i0, i1, i2);
+                p[q] = S->k[q] * (lap_at(G, ucur, i0, i1, i2) + src[q]);
+            }
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G->np[0]; i0++)
+        for (long i1 = 0; i1 < G->np[1]; i1++)
+            for (long i2 = 0; i2 < G->np[2]; i2++) {
+                long q = pidx(G, i0, i1, i2);
+                double lp = lap_at(G, p, i0, i1, i2);
+                unext[q] = S->a[q] * (2.0 * ucur[q] + p[q] + S->k[q] / 12.0 * lp) - S->b[q] * uprev[q];
+            }
+}
+
+static int time_order_of(const oracle_grid_t *g)
+{
+    return g->time_order == 0 ? 2 : g->time_order;
+}
+
 int oracle_forward(const oracle_grid_t *g, const double *vp,
                    int nsrc, const double *src_xyz, const double *wavelet,
                    int nrec, const double *rec_xyz, double *traces,
                    int nsnap, const int *snap_steps, double *snaps)
 {
+    const int order = time_order_of(g);
+    if (order != 2 && order != 4)
+        return -1;
     solve_t S;
     int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
     if (rc != 0)
@@ -392,8 +435,9 @@ int oracle_forward(const oracle_grid_t *g, const double *vp,
     double *uc = calloc(N, sizeof(double));
     double *un = calloc(N, sizeof(double));
     double *src = calloc(N, sizeof(double));
-    if (!up || !uc || !un || !src) {
-        free(up); free(uc); free(un); free(src);
+    double *pf = order == 4 ? calloc(N, sizeof(double)) : NULL;
+    if (!up || !uc || !un || !src || (order == 4 && !pf)) {
+        free(up); free(uc); free(un); free(src); free(pf);
         solve_free(&S);
         return -7;
     }
@@ -405,14 +449,19 @@ int oracle_forward(const oracle_grid_t *g, const double *vp,
                 memcpy(snaps + (long)q * N, uc, sizeof(double) * N);
         if (n == nt - 1)
             break;
-        source_term(&S, wavelet, nt, n, src);
-        forward_step(&S, uc, up, src, un);
+        if (order == 4) {
+            source_term4(&S, wavelet, nt, n, src);
+            forward_step4(&S, uc, up, src, pf, un);
+        } else {
+            source_term(&S, wavelet, nt, n, src);
+            forward_step(&S, uc, up, src, un);
+        }
         double *tmp = up;
         up = uc;
         uc = un;
         un = tmp;
     }
-    free(up); free(uc); free(un); free(src);
+    free(up); free(uc); free(un); free(src); free(pf);
     solve_free(&S);
     return 0;
 }
@@ -422,6 +471,8 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
                    int nrec, const double *rec_xyz, const double *grad_traces,
                    double *dvp, double *dwavelet, int seg)
 {
+    if (time_order_of(g) != 2)
+        return -1;
     solve_t S;
     int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
     if (rc != 0)
@@ -529,7 +580,7 @@ int oracle_gradient(const oracle_grid_t *g, const double *vp,
                     int nrec, const double *rec_xyz, const double *observed,
                     double *traces_out, double *misfit, double *dvp, int seg)
 {
-    if (!g || g->nt < 1 || nrec < 0)
+    if (!g || g->nt < 1 || nrec < 0 || time_order_of(g) != 2)
         return -1;
     size_t ntr = (size_t)nrec * g->nt;
     double *tr = malloc(sizeof(double) * (ntr + 1));

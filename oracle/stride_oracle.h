@@ -55,6 +55,8 @@ typedef struct {
     double vref;         /* sponge reference speed (m/s); 0 = no damping */
     double dt;           /* seconds */
     int nt;              /* number of time samples */
+    int time_order;      /* 2 (leapfrog) or 4 (leapfrog with the modified-equation
+                            correction; forward only); 0 means 2 */
 } oracle_grid_t;
 
 /* Central second-derivative weights c[0..order/2]. */
@@ -79,7 +81,16 @@ int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, 
 int oracle_laplacian(const oracle_grid_t *g, const double *u, double *lu);
 
 /* Forward solve.  vp: physical [shape]; wavelet [nsrc][nt]; traces [nrec][nt].
- * nsnap > 0 stores u^n for n = snap_steps[i] into snaps[i][padded]. */
+ * nsnap > 0 stores u^n for n = snap_steps[i] into snaps[i][padded].
+ *
+ * time_order 4 (the paper's solver is fourth-order accurate in time, Sec. 2.4):
+ * the leapfrog truncation error dt^2/12 u_tttt is cancelled by adding
+ * dt^4/12 u_tttt with u_tttt = v^2 (L (v^2 (L u + S)) + S_tt) and
+ * S_tt = (S^{n+1} - 2 S^n + S^{n-1}) / dt^2 (S^{-1} = 0).  With k = dt^2 v^2:
+ *   p       = k (L u^n + St^n),   St^n = (S^{n-1} + 10 S^n + S^{n+1}) / 12
+ *   u^{n+1} = a (2 u^n + p + (k/12) L p) - b u^{n-1}
+ * (p is zero beyond the padded array, like u).  The adjoint and gradient
+ * functions accept time_order 2 only. */
 int oracle_forward(const oracle_grid_t *g, const double *vp,
                    int nsrc, const double *src_xyz, const double *wavelet,
                    int nrec, const double *rec_xyz, double *traces,

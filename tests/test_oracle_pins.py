@@ -215,6 +215,87 @@ def test_analytic_3d_retarded():
     assert max(errs) < 0.02, errs
 
 
+# ------------------------------------ fourth-order time (modified equation)
+
+def _analytic_2d_error_order(cfl, time_order):
+    n, dx, c = 300, 0.2e-3, 1500.0
+    dt = cfl * dx / c
+    nt = int(round(26.67e-6 / dt)) + 1
+    g = oracle.Grid(shape=(n, n), spacing=dx, space_order=8, nb=20, vref=c, dt=dt, nt=nt,
+                    time_order=time_order)
+    src = np.array([[150 * dx, 150 * dx]])
+    rec = W.grid_node_ring_2d((150, 150), 75, dx)
+    tr = oracle.forward(g, np.full((n, n), c), src, W.tone_burst(nt, dt, dtype=np.float64), rec)
+    ref = green2d_trace(tone_burst_fn(), 75 * dx, c, np.arange(nt) * dt, 3 / 500e3)
+    return max(rel_l2(x, ref) for x in tr)
+
+
+@pytest.mark.slow
+def test_fourth_order_time_meets_the_analytic_bound_at_cfl_04():
+    """The config-1 geometry at CFL 0.4: the leapfrog misses the 2% bound by
+    time dispersion (4.2%); with the correction the error drops to the
+    spatial and quadrature floor."""
+    e = _analytic_2d_error_order(0.4, 4)
+    assert e < 1e-3, e
+
+
+def _self_convergence(time_order):
+    """Trace error at dt and dt/2 against dt/8 on one grid (time error only)."""
+    w = W.tiny_2d(n=(96, 96), nsrc=1, nrec=9)
+    dt0 = 0.4 * w.spacing / float(w.vp.max())
+    n0 = int(6e-6 / dt0) + 1
+
+    def run(dt, nt):
+        g = oracle.Grid(shape=w.shape, spacing=w.spacing, space_order=8, nb=0, vref=0.0, dt=dt,
+                        nt=nt, time_order=time_order)
+        wav = W.tone_burst(nt, dt, f0=1.0e6, dtype=np.float64)
+        return oracle.forward(g, w.vp, w.src_xyz[:1], wav, w.rec_xyz)
+
+    a, b = run(dt0, n0), run(dt0 / 2, 2 * (n0 - 1) + 1)
+    ref = run(dt0 / 8, 8 * (n0 - 1) + 1)
+    e1 = np.linalg.norm(a - ref[:, ::8]) / np.linalg.norm(ref)
+    e2 = np.linalg.norm(b - ref[:, ::4]) / np.linalg.norm(ref)
+    return e1, e2
+
+
+def test_fourth_order_time_converges_at_fourth_order():
+    """Halving dt cuts the time error about 16-fold with the correction (the
+    source term included, through its time filter) and about 4-fold without."""
+    e1, e2 = _self_convergence(4)
+    assert e1 / e2 > 9.0, (e1, e2)
+    f1, f2 = _self_convergence(2)
+    assert 2.5 < f1 / f2 < 5.0, (f1, f2)
+    assert e1 < 0.02 * f1
+
+
+def test_fourth_order_stability_limit():
+    """Stable up to sqrt(3) times the leapfrog limit (2/sqrt(lambda sum 1/dx^2)):
+    bounded at 0.9 x dx/v (the leapfrog limit is 0.555 for order 8 in 2D) and
+    unstable past 0.961."""
+    w = W.tiny_2d(n=(96, 96), nsrc=1, nrec=9)
+    vmax = float(w.vp.max())
+
+    def late_over_early(cfl):
+        dt = cfl * w.spacing / vmax
+        nt = 800
+        g = oracle.Grid(shape=w.shape, spacing=w.spacing, space_order=8, nb=0, vref=0.0, dt=dt,
+                        nt=nt, time_order=4)
+        tr = oracle.forward(g, w.vp, w.src_xyz[:1], W.tone_burst(nt, dt, f0=1.0e6, dtype=np.float64),
+                            w.rec_xyz)
+        return np.abs(tr[:, -100:]).max() / np.abs(tr[:, :200]).max()
+
+    assert late_over_early(0.90) < 1.0
+    assert late_over_early(0.98) > 1e6
+
+
+def test_fourth_order_has_no_adjoint_in_the_oracle():
+    w = W.tiny_2d()
+    g = oracle.Grid(**w.grid_kwargs())
+    g.time_order = 4
+    with pytest.raises(oracle.OracleError):
+        oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, np.zeros((7, w.nt)))
+
+
 # --------------------------------------------------- invariants of the scheme
 
 @pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
