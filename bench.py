@@ -63,6 +63,7 @@ def measured_traffic(workload):
     writes = m["write_kib"] * 1024 * gib_kib / m["copy_write_kib"]
     return reads + writes
 FWD_BYTES = 16   # read u^n, u^{n-1}, k; write u^{n+1}
+FWD4_BYTES = 32  # fourth order: read u^n, k, write p; read p, u^n, u^{n-1}, k, write u^{n+1}
 ADJ_BYTES = 28   # read u^m, w^{m+1}, w^{m+2}, k, G; write w^m, G
 
 WORKLOADS = {
@@ -91,6 +92,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forward", action="store_true")
+    ap.add_argument("--no-fourth-order", action="store_true",
+                    help="skip the forward solve with the fourth-order-in-time scheme")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
@@ -332,6 +335,36 @@ def main():
         }
         print(f"[bench] forward: {fwd['fwd_ms_per_solve']:.2f} ms/solve, {fwd['fwd_us_per_step']:.2f} us/step "
               f"({fwd['fwd_kernel_gbs']:.0f} GB/s, {fwd['fwd_steps_per_launch']:.2f} steps/launch)",
+              file=sys.stderr, flush=True)
+
+    if not args.no_forward and not args.no_fourth_order:
+        # the same forward solve with the fourth-order-in-time scheme (same dt)
+        plan4 = S.Plan.from_workload(w, time_order=4)
+        fws4 = plan4.workspace(S.STRIDE_MODE_FORWARD, device=dev)
+        plan4.forward(vp_m, wav, traces=traces, ws=fws4)
+        torch.cuda.synchronize()
+        S.stride_timing_read()
+        S.stride_timing_enable(True)
+        t40 = time.perf_counter()
+        for _ in range(args.steps):
+            plan4.forward(vp_m, wav, traces=traces, ws=fws4)
+        torch.cuda.synchronize()
+        t41 = time.perf_counter()
+        S.stride_timing_enable(False)
+        f4_ms, f4_n, f4_l, _, _, _ = S.stride_timing_read()
+        f4_step = f4_ms * 1e-3 / max(f4_n, 1)
+        fwd["fwd4"] = {
+            "scheme": "leapfrog + modified-equation correction (fourth order in time), two launches per step",
+            "updates_per_s": npad * (w.nt - 1) * args.steps / (t41 - t40),
+            "ms_per_solve": 1e3 * (t41 - t40) / args.steps,
+            "us_per_step": f4_step * 1e6,
+            "launches_per_step": f4_l / max(f4_n, 1),
+            "bytes_per_point": FWD4_BYTES,
+            "gbs": FWD4_BYTES * npad / f4_step / 1e9,
+        }
+        del fws4, plan4
+        print(f"[bench] forward, fourth order: {fwd['fwd4']['ms_per_solve']:.2f} ms/solve, "
+              f"{fwd['fwd4']['us_per_step']:.2f} us/step ({fwd['fwd4']['gbs']:.0f} GB/s)",
               file=sys.stderr, flush=True)
 
     cpu = None

@@ -59,7 +59,7 @@ extern "C" {
 enum {
     STRIDE_OK = 0,
     STRIDE_E_INVALID_ARG = -1, /* bad pointer, size, order, shape or mode */
-    STRIDE_E_CFL = -2,         /* dt * vp_max violates the leapfrog stability limit */
+    STRIDE_E_CFL = -2,         /* dt * vp_max violates the stability limit of the scheme */
     STRIDE_E_GEOMETRY = -3,    /* a source or receiver lies outside the physical grid */
     STRIDE_E_WORKSPACE = -4,   /* ws_bytes below what the call needs */
     STRIDE_E_HIP = -5,         /* a HIP runtime call failed */
@@ -78,6 +78,14 @@ typedef struct stride_grid {
     double spacing[3];    /* metres */
     double sponge_vref;   /* reference speed of the sponge (m/s); 0 disables damping */
     double dt;            /* seconds */
+    int32_t time_order;   /* 2 (leapfrog; 0 means 2) or 4: the leapfrog plus the
+                             modified-equation correction dt^4/12 u_tttt (the paper's
+                             solver is fourth-order in time, Sec. 2.4).  With 4:
+                               p       = k (L u^n + St^n),
+                               St^n    = (S^{n-1} + 10 S^n + S^{n+1}) / 12,
+                               u^{n+1} = a (2 u^n + p + (k/12) L p) - b u^{n-1};
+                             stable up to sqrt(3) times the leapfrog CFL limit;
+                             forward solves only (gradient calls return INVALID_ARG) */
 } stride_grid_t;
 
 /* A plan: the validated grid plus the source/receiver tap tables of one shot

@@ -102,6 +102,13 @@ struct LaunchShape {
 // and direction (the tile is 64 x ry*waves).
 void tile_shape(int nd, bool adjoint, int* ry, int* waves);
 
+// What a step launch computes.  Fourth-order time runs two launches per step.
+enum StepMode {
+    kStep = 0,    // C = a (2 A + k (L A + S)) - b B                 (leapfrog step)
+    kPrep = 1,    // C = k (L A + St), St: source filtered in time   (p of the corrected step)
+    kCorrect = 2  // C = a (2 U + A + (k/12) L A) - b B, A = p, U = u^n
+};
+
 // Kernel launchers (stride_kernels.hip).
 void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
                          const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
@@ -109,6 +116,9 @@ void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& 
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);
+// Forward launches of the fourth-order step (mode kPrep or kCorrect).
+void launch_step_mode(const Dims& d, int R, int mode, const StencilCoef& cf, const SpongeCoef& sp,
+                      const LaunchShape& ls, const StepParams& p, hipStream_t s);
 
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);

@@ -14,6 +14,7 @@
 struct stride_plan {
     stride_grid_t g;
     int nd, R, nb, nt;
+    int torder;          // 2 or 4 (forward only)
     stride::Dims dims;
     stride::StencilCoef cf;
     stride::SpongeCoef sp;
@@ -69,11 +70,12 @@ struct GradWs {
 
 int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W);
 
-// Views of a forward workspace: [scratch | k | u0 | u1].
+// Views of a forward workspace: [scratch | k | u0 | u1 (| p, fourth order)].
 struct FwdWs {
     unsigned* flags;
     float* k;
     float* u[2];
+    float* p;
 };
 
 int fwd_ws(const stride_plan& P, void* ws, size_t bytes, FwdWs& F);

@@ -228,6 +228,8 @@ int validate_grid(const stride_grid_t* g)
         return fail(STRIDE_E_INVALID_ARG, "sponge_cells must be >= 0");
     if (g->nt < 2)
         return fail(STRIDE_E_INVALID_ARG, "nt must be >= 2 (got %d)", g->nt);
+    if (g->time_order != 0 && g->time_order != 2 && g->time_order != 4)
+        return fail(STRIDE_E_INVALID_ARG, "time_order must be 2 or 4 (got %d)", g->time_order);
     if (!(g->dt > 0) || !std::isfinite(g->dt))
         return fail(STRIDE_E_INVALID_ARG, "dt must be positive");
     if (!(g->sponge_vref >= 0) || !std::isfinite(g->sponge_vref))
@@ -258,13 +260,15 @@ Layout stride::layout_of(const stride_plan& P)
     L.field = (size_t)round_up(P.dims.total * 4, 256);
     L.scratch = 256 + kMisfitParts * sizeof(double);   // flags | misfit partial sums
     L.traces = (size_t)round_up((long long)P.nrec * P.nt * 4, 256);
-    L.fixed_fwd = L.scratch + 3 * L.field;
+    L.fixed_fwd = L.scratch + (P.torder == 4 ? 4 : 3) * L.field;   // k, u, u (, p)
     L.fixed_grad = L.scratch + 4 * L.field + 2 * L.traces;
     return L;
 }
 
 int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
 {
+    if (P.torder != 2)
+        return fail(STRIDE_E_INVALID_ARG, "gradients are built for time_order 2 only");
     Layout L = layout_of(P);
     if (!ws)
         return fail(STRIDE_E_INVALID_ARG, "workspace is NULL");
@@ -316,6 +320,7 @@ int stride::fwd_ws(const stride_plan& P, void* ws, size_t bytes, FwdWs& F)
     F.k = (float*)(b + L.scratch);
     F.u[0] = (float*)(b + L.scratch + L.field);
     F.u[1] = (float*)(b + L.scratch + 2 * L.field);
+    F.p = P.torder == 4 ? (float*)(b + L.scratch + 3 * L.field) : nullptr;
     return STRIDE_OK;
 }
 
@@ -324,12 +329,15 @@ int stride::check_cfl(const stride_plan& P, double vmax)
     double inv2 = 0;
     for (int a = 0; a < P.nd; ++a)
         inv2 += 1.0 / (P.g.spacing[a] * P.g.spacing[a]);
+    // leapfrog: theta = dt^2 v^2 lambda sum 1/dx^2 <= 4; with the fourth-order
+    // correction the update factor is 2 - theta + theta^2/12, stable for theta <= 12
     double courant = P.g.dt * vmax * std::sqrt(P.nyquist * inv2);
-    if (!(courant <= 2.0))
+    const double limit = P.torder == 4 ? 2.0 * std::sqrt(3.0) : 2.0;
+    if (!(courant <= limit))
         return fail(STRIDE_E_CFL,
-                    "dt %g with vp_max %g violates the leapfrog stability limit "
-                    "(dt vp sqrt(lambda sum 1/dx^2) = %.4f > 2)",
-                    P.g.dt, vmax, courant);
+                    "dt %g with vp_max %g violates the stability limit of the order-%d scheme "
+                    "(dt vp sqrt(lambda sum 1/dx^2) = %.4f > %.4f)",
+                    P.g.dt, vmax, P.torder, courant, limit);
     return STRIDE_OK;
 }
 
@@ -633,6 +641,33 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
     launch_fill(u[1], P.dims.total, 0.f, s);
     int tid = g_timer.begin(s);
     int cur = 0;
+    if (P.torder == 4) {
+        // two launches per step: p = k (L u + St) (sampling u^n), then the
+        // corrected update from the stencil of p
+        for (int n = 0; n < P.nt - 1; ++n) {
+            StepParams p = base_params(P);
+            p.A = u[cur];
+            p.C = F.p;
+            p.K = k;
+            p.step = n;
+            p.inj_sig = wavelet;
+            p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+            launch_step_mode(P.dims, P.R, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
+            StepParams q = base_params(P);
+            q.A = F.p;
+            q.U = u[cur];
+            q.B = u[1 - cur];
+            q.C = u[1 - cur];
+            q.K = k;
+            q.step = n;
+            launch_step_mode(P.dims, P.R, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
+            cur = 1 - cur;
+        }
+        g_timer.end(tid, s, 0, P.nt - 1, 2LL * (P.nt - 1));
+        launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
+        HIP_TRY(hipGetLastError());
+        return STRIDE_OK;
+    }
     for (int n = 0; n < P.nt - 1; ++n) {
         StepParams p = base_params(P);
         p.A = u[cur];
@@ -746,6 +781,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->R = grid->space_order / 2;
     P->nb = grid->sponge_cells;
     P->nt = grid->nt;
+    P->torder = grid->time_order == 4 ? 4 : 2;
     P->nsrc = nsrc;
     P->nrec = nrec;
     P->blob = nullptr;
@@ -908,6 +944,8 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
     }
     if (mode != STRIDE_MODE_GRADIENT)
         return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD or GRADIENT");
+    if (plan->torder != 2)
+        return fail(STRIDE_E_INVALID_ARG, "gradients are built for time_order 2 only");
     long long nfields;
     if (budget_bytes == 0) {
         nfields = cached_schedule(plan->nt, plan->nt)->stats.peak_fields;
@@ -990,6 +1028,7 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
     P.g = *grid;
     P.nd = grid->ndim;
     P.nt = grid->nt;
+    P.torder = grid->time_order == 4 ? 4 : 2;
     P.nrec = nrec;
     P.nb = grid->sponge_cells;
     Dims& d = P.dims;

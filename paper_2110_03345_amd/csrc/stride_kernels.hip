@@ -175,19 +175,35 @@ __device__ __forceinline__ float lap2d(const float* S, const StencilCoef& cf)
 // buffer descriptor (at most 2 GiB): offsets of points outside the grid are
 // set to 0xffffffff and read 0.
 
+// Signal sample of row `id`: s[step], or with FILT (the fourth-order step's
+// source) (s[step-1] + 10 s[step] + s[step+1]) / 12, zero outside the record.
+template <bool FILT>
+__device__ __forceinline__ float sig_at(const float* sig, int id, int stride, int step)
+{
+    const float* s = sig + (long long)id * stride;
+    if constexpr (!FILT) {
+        return s[step];
+    } else {
+        const float sm = step >= 1 ? s[step - 1] : 0.f;
+        const float sp = step + 1 < stride ? s[step + 1] : 0.f;
+        return fmaf(10.f, s[step], sm + sp) / 12.f;
+    }
+}
+
 // Sum of the signals of the point whose first entry is `head` (entry order).
+template <bool FILT = false>
 __device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEntry head,
                                                    const float* sig, int stride, int step)
 {
-    float v = head.w * sig[(long long)head.id * stride + step];
+    float v = head.w * sig_at<FILT>(sig, head.id, stride, step);
     for (int k = 1; k < head.run; ++k) {
         const TileEntry e = ent[k];
-        v = fmaf(e.w, sig[(long long)e.id * stride + step], v);
+        v = fmaf(e.w, sig_at<FILT>(sig, e.id, stride, step), v);
     }
     return v;
 }
 
-template <int R, bool ADJ, int RY, int WAVES>
+template <int R, bool ADJ, int RY, int WAVES, int MODE = kStep>
 __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf,
                                             const SpongeCoef& sp, const StepParams& p,
                                             const LaunchShape& ls, const int b)
@@ -220,9 +236,12 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     const int gx = x0 + lx;
     const bool xin = gx < n1;
 
-    // entry ranges of the tile (uniform)
-    const int eb0 = p.inj.ptr[tile];
-    const int ne0 = p.inj.ptr[tile + 1] - eb0;
+    // entry ranges of the tile (uniform); the correction pass injects nothing
+    int eb0 = 0, ne0 = 0;
+    if constexpr (MODE != kCorrect) {
+        eb0 = p.inj.ptr[tile];
+        ne0 = p.inj.ptr[tile + 1] - eb0;
+    }
     int eb1 = 0, ne1 = 0;
     if constexpr (ADJ) {
         eb1 = p.img.ptr[tile];
@@ -253,17 +272,21 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
     }
     int po[RY];
-    float bb[RY], kk[RY], gg[RY];
+    float bb[RY], kk[RY], gg[RY], uu[RY];
     {
         const auto rb = plane_rsrc(p.B, fbytes);
         const auto rk = plane_rsrc(p.K, fbytes);
+        const auto ru = plane_rsrc(p.U, fbytes);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int gy = y0 + wy * RY + j;
             po[j] = xin && gy < n0 ? gy * s0 + gx : -1;
             const int bo = po[j] >= 0 ? po[j] * 4 : -1;
-            bb[j] = bload(rb, bo);
+            if constexpr (MODE != kPrep)
+                bb[j] = bload(rb, bo);
             kk[j] = bload(rk, bo);
+            if constexpr (MODE == kCorrect)
+                uu[j] = bload(ru, bo);
         }
         if constexpr (ADJ) {
             const auto rg = plane_rsrc(p.G, fbytes);
@@ -280,7 +303,8 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         const TileEntry e = p.inj.ent[eb0 + tid];
         if (e.run > 0) {
             il0 = e.local;
-            iv0 = tile_point_signal(p.inj.ent + eb0 + tid, e, p.inj_sig, p.inj_stride, p.step);
+            iv0 = tile_point_signal<MODE == kPrep>(p.inj.ent + eb0 + tid, e, p.inj_sig,
+                                                   p.inj_stride, p.step);
         }
     }
     if constexpr (ADJ) {
@@ -322,8 +346,8 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         for (int e = tid + NT; e < ne0; e += NT) {
             const TileEntry en = p.inj.ent[eb0 + e];
             if (en.run > 0)
-                sS[0][en.local] =
-                    tile_point_signal(p.inj.ent + eb0 + e, en, p.inj_sig, p.inj_stride, p.step);
+                sS[0][en.local] = tile_point_signal<MODE == kPrep>(p.inj.ent + eb0 + e, en, p.inj_sig,
+                                                                   p.inj_stride, p.step);
         }
         if constexpr (ADJ) {
             if (il1 >= 0)
@@ -354,7 +378,12 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
             lap += sS[0][ly * kTileX + lx];
         const int dyd = layer_depth(y0 + ly, n0, d.nb);
         const float eta = fmaf(sp.e[0], (float)(dyd * dyd), ex);
-        p.C[po[j]] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
+        if constexpr (MODE == kStep)
+            p.C[po[j]] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
+        else if constexpr (MODE == kPrep)
+            p.C[po[j]] = kk[j] * lap;
+        else
+            p.C[po[j]] = leapfrog(uu[j], bb[j], 1.f, fmaf(kk[j] / 12.f, lap, ctr), eta, sp.half_dt);
         if constexpr (ADJ) {
             const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
             float lu = lap2d<R, LW>(SU, cf);
@@ -377,7 +406,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
 // global accesses are raw buffer accesses with per-plane descriptors: offsets
 // outside the grid read 0 and drop stores, so no access needs a branch.
 
-template <int R, bool ADJ, int RY, int WAVES>
+template <int R, bool ADJ, int RY, int WAVES, int MODE = kStep>
 __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf,
                                             const SpongeCoef& sp, const StepParams& p,
                                             const LaunchShape& ls, const int b)
@@ -489,7 +518,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         }
 
     float pl[NF][RY], phy[NF][HY], phx[NF][HX];
-    float pb[RY], pk[RY], pg[RY];
+    float pb[RY], pk[RY], pg[RY], pu[RY];
     auto prefetch = [&](int z) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -509,8 +538,15 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         const auto rk = rsrc(p.K, z);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            pb[j] = bload_stream(rb, rbo[j]);
+            if constexpr (MODE != kPrep)
+                pb[j] = bload_stream(rb, rbo[j]);
             pk[j] = bload_stream(rk, rbo[j]);
+        }
+        if constexpr (MODE == kCorrect) {
+            const auto ru = rsrc(p.U, z);
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                pu[j] = bload_stream(ru, rbo[j]);
         }
         if constexpr (ADJ) {
             const auto rg = rsrc(p.G, z);
@@ -526,8 +562,11 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     // of that plane to the LDS plane array, where the point's thread takes
     // (and clears) it after the barrier.  Blocks with more than NT entries
     // read the rest at every plane.
-    const int eb0 = p.inj.ptr[lb];
-    const int ne0 = p.inj.ptr[lb + 1] - eb0;
+    int eb0 = 0, ne0 = 0;
+    if constexpr (MODE != kCorrect) {
+        eb0 = p.inj.ptr[lb];
+        ne0 = p.inj.ptr[lb + 1] - eb0;
+    }
     int eb1 = 0, ne1 = 0;
     if constexpr (ADJ) {
         eb1 = p.img.ptr[lb];
@@ -543,7 +582,8 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             const TileEntry e = p.inj.ent[eb0 + tid];
             if (e.run > 0) {
                 il0 = e.local;
-                iv0 = tile_point_signal(p.inj.ent + eb0 + tid, e, p.inj_sig, p.inj_stride, p.step);
+                iv0 = tile_point_signal<MODE == kPrep>(p.inj.ent + eb0 + tid, e, p.inj_sig,
+                                                       p.inj_stride, p.step);
             }
         }
         if constexpr (ADJ) {
@@ -572,12 +612,13 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             sS[0][NF - 1][il1] = iv1;
     }
     // entries beyond the first NT of the block: written at their plane
-    auto overflow = [&](const InjTable& T, int eb, int ne, const float* sig, int stride, int pz,
-                        float* dst) {
+    auto overflow = [&](auto filt, const InjTable& T, int eb, int ne, const float* sig, int stride,
+                        int pz, float* dst) {
         for (int e = tid + NT; e < ne; e += NT) {
             const TileEntry en = T.ent[eb + e];
             if (en.run > 0 && en.local / PL == pz)
-                dst[en.local - pz * PL] = tile_point_signal(T.ent + eb + e, en, sig, stride, p.step);
+                dst[en.local - pz * PL] =
+                    tile_point_signal<decltype(filt)::value>(T.ent + eb + e, en, sig, stride, p.step);
         }
     };
 
@@ -590,7 +631,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             const int z = zb + u;
             if (z >= z1)
                 return false;
-            float bb[RY], kk[RY], gg[RY];
+            float bb[RY], kk[RY], gg[RY], uu[RY];
             float* S = &sF[buf][0][0];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -611,9 +652,10 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             }
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
-                bb[j] = pb[j];
+                bb[j] = MODE != kPrep ? pb[j] : 0.f;
                 kk[j] = pk[j];
                 gg[j] = ADJ ? pg[j] : 0.f;
+                uu[j] = MODE == kCorrect ? pu[j] : 0.f;
             }
             if (z + 1 < z1)
                 prefetch(z + 1);
@@ -627,10 +669,12 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                 }
             }
             if (ne0 > NT)
-                overflow(p.inj, eb0, ne0, p.inj_sig, p.inj_stride, pz, &sS[buf][0][0]);
+                overflow(std::integral_constant<bool, MODE == kPrep>{}, p.inj, eb0, ne0, p.inj_sig,
+                         p.inj_stride, pz, &sS[buf][0][0]);
             if constexpr (ADJ)
                 if (ne1 > NT)
-                    overflow(p.img, eb1, ne1, p.img_sig, p.img_stride, pz, &sS[buf][NF - 1][0]);
+                    overflow(std::false_type{}, p.img, eb1, ne1, p.img_sig, p.img_stride, pz,
+                             &sS[buf][NF - 1][0]);
             __syncthreads();
 
             float* Cz = p.C + (long long)z * s0;
@@ -657,8 +701,14 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     sS[buf][0][ly * kTileX + lx] = 0.f;
                 }
                 const float eta = ez + ey[j];
-                __builtin_nontemporal_store(leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt),
-                                            Cz + roff[j]);
+                float out;
+                if constexpr (MODE == kStep)
+                    out = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
+                else if constexpr (MODE == kPrep)
+                    out = kk[j] * lap;
+                else
+                    out = leapfrog(uu[j], bb[j], 1.f, fmaf(kk[j] / 12.f, lap, ctr), eta, sp.half_dt);
+                __builtin_nontemporal_store(out, Cz + roff[j]);
                 if constexpr (ADJ) {
                     const float* SU = S + (NF - 1) * PLANE;
                     const float uc0 = q[NF - 1][j][slot_c];
@@ -690,11 +740,11 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
 // device table; inactive slots exit at once.  Both run the same body, so a
 // shot computes the same bits alone and in a batch.
 
-template <int R, bool ADJ, int RY, int WAVES>
+template <int R, bool ADJ, int RY, int WAVES, int MODE = kStep>
 __global__ __launch_bounds__(64 * WAVES) void step2d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
                                                             StepParams p, LaunchShape ls)
 {
-    step2d_body<R, ADJ, RY, WAVES>(d, cf, sp, p, ls, blockIdx.x);
+    step2d_body<R, ADJ, RY, WAVES, MODE>(d, cf, sp, p, ls, blockIdx.x);
 }
 
 template <int R, bool ADJ, int RY, int WAVES>
@@ -711,18 +761,18 @@ __global__ __launch_bounds__(64 * WAVES) void step2d_batched(Dims d, StencilCoef
 // VGPRs) where that costs no spills, else left to the compiler.  (The batched
 // kernels hold their slot's parameters in registers as well; they are left to
 // the compiler, which keeps them free of spills.)
-template <bool ADJ, int RY, int WAVES>
+template <bool ADJ, int RY, int WAVES, int MODE>
 constexpr int min_waves_3d()
 {
-    return RY <= 2 || (!ADJ && WAVES == 8) ? 4 : 1;
+    return MODE == kStep && (RY <= 2 || (!ADJ && WAVES == 8)) ? 4 : 1;
 }
 
-template <int R, bool ADJ, int RY, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(min_waves_3d<ADJ, RY, WAVES>())))
-void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
-                                                            StepParams p, LaunchShape ls)
+template <int R, bool ADJ, int RY, int WAVES, int MODE = kStep>
+__global__ __launch_bounds__(64 * WAVES)
+__attribute__((amdgpu_waves_per_eu(min_waves_3d<ADJ, RY, WAVES, MODE>())))
+void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp, StepParams p, LaunchShape ls)
 {
-    step3d_body<R, ADJ, RY, WAVES>(d, cf, sp, p, ls, blockIdx.x);
+    step3d_body<R, ADJ, RY, WAVES, MODE>(d, cf, sp, p, ls, blockIdx.x);
 }
 
 template <int R, bool ADJ, int RY, int WAVES>
@@ -934,6 +984,40 @@ void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
 #undef STRIDE_LAUNCH3D
 }
 
+template <int R, int MODE>
+void launch_mode_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
+                   const LaunchShape& ls, const StepParams& p, hipStream_t s)
+{
+    const int nt = 64 * ls.waves;
+    int smp_blocks = (p.smp.count + nt - 1) / nt;
+    dim3 grid(ls.tile_blocks_pad + smp_blocks);
+    if (d.nd == 2) {
+#define STRIDE_LAUNCH2DM(RY_, W_)                                                                 \
+    hipLaunchKernelGGL((step2d_kernel<R, false, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, \
+                       p, ls)
+        STRIDE_DISPATCH2D(STRIDE_LAUNCH2DM);
+#undef STRIDE_LAUNCH2DM
+        return;
+    }
+#define STRIDE_LAUNCH3DM(RY_, W_)                                                                 \
+    hipLaunchKernelGGL((step3d_kernel<R, false, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, \
+                       p, ls)
+    if (ls.waves == 8) {
+        if (ls.ry == 1)
+            STRIDE_LAUNCH3DM(1, 8);
+        else if (ls.ry == 2)
+            STRIDE_LAUNCH3DM(2, 8);
+        else
+            STRIDE_LAUNCH3DM(4, 8);
+    } else {
+        if (ls.ry == 2)
+            STRIDE_LAUNCH3DM(2, 4);
+        else
+            STRIDE_LAUNCH3DM(4, 4);
+    }
+#undef STRIDE_LAUNCH3DM
+}
+
 template <int R, bool ADJ>
 void launch_batched_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
                       const SlotStep* table, int nslots, int max_samples, hipStream_t s)
@@ -977,6 +1061,16 @@ int grid_for(long long n, int threads)
 }
 
 }  // namespace
+
+void launch_step_mode(const Dims& d, int R, int mode, const StencilCoef& cf, const SpongeCoef& sp,
+                      const LaunchShape& ls, const StepParams& p, hipStream_t s)
+{
+    if (mode == kPrep)
+        R == 4 ? launch_mode_t<4, kPrep>(d, cf, sp, ls, p, s) : launch_mode_t<5, kPrep>(d, cf, sp, ls, p, s);
+    else
+        R == 4 ? launch_mode_t<4, kCorrect>(d, cf, sp, ls, p, s)
+               : launch_mode_t<5, kCorrect>(d, cf, sp, ls, p, s);
+}
 
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s)

@@ -92,6 +92,24 @@ def test_gradient_workspace_query_meets_the_solve_minimum(nt):
     assert S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT) >= fixed + 4 * field
 
 
+def test_fourth_order_workspace_and_refusals():
+    """Fourth-order time: one more field for the forward (p); gradients and
+    unknown orders refused before anything runs."""
+    g2 = _grid(nt=20)
+    g4 = _grid(nt=20)
+    g4.time_order = 4
+    field = -(-(52 * 64 * 4) // 256) * 256
+    f2 = S.stride_workspace_query(g2, 1, 3, S.STRIDE_MODE_FORWARD)
+    assert S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_FORWARD) == f2 + field
+    with pytest.raises(S.StrideError) as e:
+        S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT)
+    assert e.value.code == _abi.STRIDE_E_INVALID_ARG
+    g3 = _grid(nt=20)
+    g3.time_order = 3
+    with pytest.raises(S.StrideError):
+        S.stride_workspace_query(g3, 1, 3, S.STRIDE_MODE_FORWARD)
+
+
 @lru_cache(None)
 def _dp(l, s):
     """Brute-force minimal forward steps to reverse l steps with s free slots."""
