@@ -471,7 +471,8 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
                    int nrec, const double *rec_xyz, const double *grad_traces,
                    double *dvp, double *dwavelet, int seg)
 {
-    if (time_order_of(g) != 2)
+    const int order = time_order_of(g);
+    if ((order != 2 && order != 4) || (order == 4 && dwavelet))
         return -1;
     solve_t S;
     int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
@@ -493,9 +494,13 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
     double *src = calloc(N, sizeof(double)), *q = calloc(N, sizeof(double));
     double *w1 = calloc(N, sizeof(double)), *w2 = calloc(N, sizeof(double)), *w0 = calloc(N, sizeof(double));
     double *G_acc = calloc(N, sizeof(double)), *lu = calloc(N, sizeof(double));
-    if (!ck || !useg || !up || !uc || !un || !src || !q || !w1 || !w2 || !w0 || !G_acc || !lu) {
+    double *pf = calloc(N, sizeof(double)), *lp = calloc(N, sizeof(double));
+    double *qf = calloc(N, sizeof(double)), *lq = calloc(N, sizeof(double));
+    if (!ck || !useg || !up || !uc || !un || !src || !q || !w1 || !w2 || !w0 || !G_acc || !lu ||
+        !pf || !lp || !qf || !lq) {
         free(ck); free(useg); free(up); free(uc); free(un); free(src); free(q);
         free(w1); free(w2); free(w0); free(G_acc); free(lu);
+        free(pf); free(lp); free(qf); free(lq);
         solve_free(&S);
         return -7;
     }
@@ -508,8 +513,13 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
         }
         if (n == nt - 1)
             break;
-        source_term(&S, wavelet, nt, n, src);
-        forward_step(&S, uc, up, src, un);
+        if (order == 4) {
+            source_term4(&S, wavelet, nt, n, src);
+            forward_step4(&S, uc, up, src, pf, un);
+        } else {
+            source_term(&S, wavelet, nt, n, src);
+            forward_step(&S, uc, up, src, un);
+        }
         double *tmp = up;
         up = uc;
         uc = un;
@@ -529,14 +539,51 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
             memcpy(useg + (size_t)(n - start) * N, uc, sizeof(double) * N);
             if (n == end - 1)
                 break;
-            source_term(&S, wavelet, nt, n, src);
-            forward_step(&S, uc, up, src, un);
+            if (order == 4) {
+                source_term4(&S, wavelet, nt, n, src);
+                forward_step4(&S, uc, up, src, pf, un);
+            } else {
+                source_term(&S, wavelet, nt, n, src);
+                forward_step(&S, uc, up, src, un);
+            }
             double *tmp = up;
             up = uc;
             uc = un;
             un = tmp;
         }
-        for (int m = end - 1; m >= start; m--) {
+        for (int m = end - 1; m >= start && order == 4; m--) {
+            /* fourth order, with T = K + (1/12) K L K and w = K A lambda:
+             *   v = L u^m + St^m, p = k v, q = k L w^{m+1}
+             *   G += w^{m+1} (v + (1/12) L p) + (1/12) q v
+             *   w^m = a (2 w^{m+1} + q + (k/12) L q + k R^T g^m) - b w^{m+2} */
+            const double *um = useg + (size_t)(m - start) * N;
+            oracle_laplacian(g, um, lu);
+            source_term4(&S, wavelet, nt, m, src);
+            for (long p = 0; p < N; p++)
+                pf[p] = S.k[p] * (lu[p] + src[p]);
+            oracle_laplacian(g, pf, lp);
+            oracle_laplacian(g, w1, lq);
+            for (long p = 0; p < N; p++)
+                qf[p] = S.k[p] * lq[p];
+#pragma omp parallel for
+            for (long p = 0; p < N; p++) {
+                double v = lu[p] + src[p];
+                G_acc[p] += w1[p] * (v + lp[p] / 12.0) + qf[p] * v / 12.0;
+            }
+            if (m == 0)
+                break;
+            oracle_laplacian(g, qf, lq);
+            receiver_transpose(&S, grad_traces, nt, m, q);
+#pragma omp parallel for
+            for (long p = 0; p < N; p++)
+                w0[p] = S.a[p] * (2.0 * w1[p] + qf[p] + S.k[p] / 12.0 * lq[p] + S.k[p] * q[p]) -
+                        S.b[p] * w2[p];
+            double *tmp = w2;
+            w2 = w1;
+            w1 = w0;
+            w0 = tmp;
+        }
+        for (int m = end - 1; m >= start && order == 2; m--) {
             const double *um = useg + (size_t)(m - start) * N;
             /* imaging: G += w^{m+1} (L u^m + S^m) */
             oracle_laplacian(g, um, lu);
@@ -571,6 +618,7 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
     }
     free(ck); free(useg); free(up); free(uc); free(un); free(src); free(q);
     free(w1); free(w2); free(w0); free(G_acc); free(lu);
+    free(pf); free(lp); free(qf); free(lq);
     solve_free(&S);
     return 0;
 }
@@ -580,7 +628,7 @@ int oracle_gradient(const oracle_grid_t *g, const double *vp,
                     int nrec, const double *rec_xyz, const double *observed,
                     double *traces_out, double *misfit, double *dvp, int seg)
 {
-    if (!g || g->nt < 1 || nrec < 0 || time_order_of(g) != 2)
+    if (!g || g->nt < 1 || nrec < 0 || (time_order_of(g) != 2 && time_order_of(g) != 4))
         return -1;
     size_t ntr = (size_t)nrec * g->nt;
     double *tr = malloc(sizeof(double) * (ntr + 1));

@@ -89,8 +89,15 @@ int oracle_laplacian(const oracle_grid_t *g, const double *u, double *lu);
  * S_tt = (S^{n+1} - 2 S^n + S^{n-1}) / dt^2 (S^{-1} = 0).  With k = dt^2 v^2:
  *   p       = k (L u^n + St^n),   St^n = (S^{n-1} + 10 S^n + S^{n+1}) / 12
  *   u^{n+1} = a (2 u^n + p + (k/12) L p) - b u^{n-1}
- * (p is zero beyond the padded array, like u).  The adjoint and gradient
- * functions accept time_order 2 only. */
+ * (p is zero beyond the padded array, like u).
+ *
+ * Its exact discrete adjoint (T = K + (1/12) K L K is symmetric, K = diag k;
+ * with w = K A lambda, A = diag a):
+ *   q   = k L w^{m+1}
+ *   w^m = a (2 w^{m+1} + q + (k/12) L q + k R^T g^m) - b w^{m+2}
+ * and k dJ/dk sums w^{m+1} (v + (1/12) L p) + (1/12) q v with v = L u^m + St^m,
+ * p = k v; dJ/dvp = P^T (2 G / vp) as in second order.  The wavelet
+ * cotangent is not provided for time_order 4 (dwavelet must be NULL). */
 int oracle_forward(const oracle_grid_t *g, const double *vp,
                    int nsrc, const double *src_xyz, const double *wavelet,
                    int nrec, const double *rec_xyz, double *traces,

@@ -288,12 +288,77 @@ def test_fourth_order_stability_limit():
     assert late_over_early(0.98) > 1e6
 
 
-def test_fourth_order_has_no_adjoint_in_the_oracle():
-    w = W.tiny_2d()
+def _fourth(w):
     g = oracle.Grid(**w.grid_kwargs())
     g.time_order = 4
-    with pytest.raises(oracle.OracleError):
-        oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, np.zeros((7, w.nt)))
+    return g
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_fourth_order_linearised_dot_product(maker):
+    """<dF/dvp . dm, d> by central differences of the fourth-order forward
+    equals <dm, adjoint(d)>: the adjoint is the transpose of the scheme's own
+    Jacobian (sponge on, heterogeneous vp, off-grid taps)."""
+    w = maker(nt=60)
+    g = _fourth(w)
+    rng = np.random.default_rng(21)
+    d = rng.standard_normal((w.rec_xyz.shape[0], w.nt))
+    dm = rng.standard_normal(w.shape)
+    vp = w.vp.astype(np.float64)
+    h = 0.02
+    Fp = oracle.forward(g, vp + h * dm, w.src_xyz, w.wavelet, w.rec_xyz)
+    Fm = oracle.forward(g, vp - h * dm, w.src_xyz, w.wavelet, w.rec_xyz)
+    lhs = np.sum((Fp - Fm) / (2 * h) * d)
+    dvp, dwav = oracle.adjoint(g, vp, w.src_xyz, w.wavelet, w.rec_xyz, d)
+    assert dwav is None
+    rhs = np.sum(dvp * dm)
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs), (lhs, rhs)
+
+
+def test_fourth_order_gradient_central_fd_and_taylor():
+    w, g, _, dm = _fd_setup()
+    g = _fourth(w)
+    vp = w.vp.astype(np.float64)
+    rng = np.random.default_rng(8)
+    obs = oracle.forward(g, vp * (1.0 + 0.02 * rng.uniform(-1, 1)), w.src_xyz, w.wavelet,
+                         w.rec_xyz)
+    _, J0, dvp = oracle.gradient(g, vp, w.src_xyz, w.wavelet, w.rec_xyz, obs)
+    gd = np.sum(dvp * dm)
+    h = 0.05
+    Jp = oracle.gradient(g, vp + h * dm, w.src_xyz, w.wavelet, w.rec_xyz, obs)[1]
+    Jm = oracle.gradient(g, vp - h * dm, w.src_xyz, w.wavelet, w.rec_xyz, obs)[1]
+    fd = (Jp - Jm) / (2 * h)
+    assert abs(fd - gd) <= 1e-6 * abs(gd), (fd, gd)
+    rs = []
+    for hh in (4.0, 2.0, 1.0):
+        Jh = oracle.gradient(g, vp + hh * dm, w.src_xyz, w.wavelet, w.rec_xyz, obs)[1]
+        rs.append(abs(Jh - J0 - hh * gd))
+    assert 3.5 < rs[0] / rs[1] < 4.5 and 3.5 < rs[1] / rs[2] < 4.5, rs
+
+
+def test_fourth_order_adjoint_independent_of_checkpoint_segment():
+    w = W.tiny_2d(nt=50)
+    g = _fourth(w)
+    rng = np.random.default_rng(6)
+    d = rng.standard_normal((w.rec_xyz.shape[0], w.nt))
+    ref = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, d, seg=50)[0]
+    for seg in (1, 7, 13):
+        out = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, d, seg=seg)[0]
+        np.testing.assert_array_equal(out, ref)
+
+
+def test_fourth_order_refuses_the_wavelet_cotangent():
+    import ctypes
+    w = W.tiny_2d(nt=20)
+    g = _fourth(w).c()
+    f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    vp, src, wav, rec = f(w.vp), f(w.src_xyz), f(w.wavelet), f(w.rec_xyz)
+    d = np.zeros((rec.shape[0], w.nt))
+    dvp, dwav = np.zeros(w.shape), np.zeros(wav.shape)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    rc = oracle.lib().oracle_adjoint(ctypes.byref(g), P(vp), src.shape[0], P(src), P(wav),
+                                     rec.shape[0], P(rec), P(d), P(dvp), P(dwav), 0)
+    assert rc == -1
 
 
 # --------------------------------------------------- invariants of the scheme
