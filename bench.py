@@ -65,6 +65,9 @@ def measured_traffic(workload):
 FWD_BYTES = 16   # read u^n, u^{n-1}, k; write u^{n+1}
 FWD4_BYTES = 32  # fourth order: read u^n, k, write p; read p, u^n, u^{n-1}, k, write u^{n+1}
 ADJ_BYTES = 28   # read u^m, w^{m+1}, w^{m+2}, k, G; write w^m, G
+# fourth-order adjoint step: read u^m, k, write p; read w^{m+1}, k, write q;
+# read q, p, w^{m+1}, w^{m+2}, k, H, write w^m, H
+ADJ4_BYTES = 56
 
 WORKLOADS = {
     "config2": "2D breast-like phantom, 1024^2 at 0.2 mm + 40-cell sponge (1104^2 padded), "
@@ -93,7 +96,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forward", action="store_true")
     ap.add_argument("--no-fourth-order", action="store_true",
-                    help="skip the forward solve with the fourth-order-in-time scheme")
+                    help="skip the forward and gradient solves with the fourth-order-in-time scheme")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
@@ -338,7 +341,8 @@ def main():
               file=sys.stderr, flush=True)
 
     if not args.no_forward and not args.no_fourth_order:
-        # the same forward solve with the fourth-order-in-time scheme (same dt)
+        # the same forward and gradient solves with the fourth-order-in-time
+        # scheme (same dt, same checkpoint budget)
         plan4 = S.Plan.from_workload(w, time_order=4)
         fws4 = plan4.workspace(S.STRIDE_MODE_FORWARD, device=dev)
         plan4.forward(vp_m, wav, traces=traces, ws=fws4)
@@ -353,19 +357,53 @@ def main():
         S.stride_timing_enable(False)
         f4_ms, f4_n, f4_l, _, _, _ = S.stride_timing_read()
         f4_step = f4_ms * 1e-3 / max(f4_n, 1)
-        fwd["fwd4"] = {
-            "scheme": "leapfrog + modified-equation correction (fourth order in time), two launches per step",
-            "updates_per_s": npad * (w.nt - 1) * args.steps / (t41 - t40),
-            "ms_per_solve": 1e3 * (t41 - t40) / args.steps,
-            "us_per_step": f4_step * 1e6,
-            "launches_per_step": f4_l / max(f4_n, 1),
-            "bytes_per_point": FWD4_BYTES,
-            "gbs": FWD4_BYTES * npad / f4_step / 1e9,
+        del fws4
+        four = {
+            "scheme": "leapfrog + modified-equation correction (fourth order in time); forward: two "
+                      "launches per step, adjoint: three",
+            "forward": {
+                "updates_per_s": npad * (w.nt - 1) * args.steps / (t41 - t40),
+                "ms_per_solve": 1e3 * (t41 - t40) / args.steps,
+                "us_per_step": f4_step * 1e6,
+                "launches_per_step": f4_l / max(f4_n, 1),
+                "bytes_per_point": FWD4_BYTES,
+                "gbs": FWD4_BYTES * npad / f4_step / 1e9,
+            },
         }
-        del fws4, plan4
-        print(f"[bench] forward, fourth order: {fwd['fwd4']['ms_per_solve']:.2f} ms/solve, "
-              f"{fwd['fwd4']['us_per_step']:.2f} us/step ({fwd['fwd4']['gbs']:.0f} GB/s)",
+        print(f"[bench] forward, fourth order: {four['forward']['ms_per_solve']:.2f} ms/solve, "
+              f"{four['forward']['us_per_step']:.2f} us/step ({four['forward']['gbs']:.0f} GB/s)",
               file=sys.stderr, flush=True)
+        full4 = plan4.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+        ws4_bytes = plan4.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full4, budget))
+        del ws
+        ws4 = torch.empty(ws4_bytes, dtype=torch.uint8, device=dev)
+        S.stride_plan_gradient(plan4.handle, vp_m, wav, obs, traces, misfit, dvp, ws4)
+        torch.cuda.synchronize()
+        S.stride_timing_read()
+        S.stride_timing_enable(True)
+        t40 = time.perf_counter()
+        for _ in range(args.steps):
+            S.stride_plan_gradient(plan4.handle, vp_m, wav, obs, traces, misfit, dvp, ws4)
+        torch.cuda.synchronize()
+        t41 = time.perf_counter()
+        S.stride_timing_enable(False)
+        g4 = S.stride_timing_read()
+        a4_step = g4[3] * 1e-3 / max(g4[4], 1)
+        four["gradient"] = {
+            "updates_per_s": 2.0 * npad * (w.nt - 1) * args.steps / (t41 - t40),
+            "ms_per_solve": 1e3 * (t41 - t40) / args.steps,
+            "workspace_gb": ws4_bytes / 2**30,
+            "forward_steps_per_gradient": g4[1] / args.steps,
+            "adjoint_us_per_step": a4_step * 1e6,
+            "adjoint_launches_per_step": g4[5] / max(g4[4], 1),
+            "adjoint_bytes_per_point": ADJ4_BYTES,
+            "adjoint_gbs": ADJ4_BYTES * npad / a4_step / 1e9,
+        }
+        del ws4, plan4
+        fwd["fourth_order"] = four
+        print(f"[bench] gradient, fourth order: {four['gradient']['ms_per_solve']:.2f} ms/solve, "
+              f"adjoint {four['gradient']['adjoint_us_per_step']:.2f} us/step "
+              f"({four['gradient']['adjoint_gbs']:.0f} GB/s)", file=sys.stderr, flush=True)
 
     cpu = None
     if not args.no_cpu_baseline:

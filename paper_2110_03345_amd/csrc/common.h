@@ -70,8 +70,9 @@ struct StepParams {
     const float* B;   // u^{n-1} or w^{m+2}
     float* C;         // result; may alias B
     const float* K;   // dt^2 vp^2
-    const float* U;   // adjoint only: forward field u^m (second stencil)
+    const float* U;   // adjoint only: second stencil field (u^m; p in the correction)
     float* G;         // adjoint only: imaging accumulator
+    const float* D;   // correction only: point field u^n (forward) or w^{m+1} (adjoint)
     int step;         // time index of the injected / sampled signals
     InjTable inj;     // injection into C: sources (forward), receivers (adjoint)
     const float* inj_sig;
@@ -102,11 +103,15 @@ struct LaunchShape {
 // and direction (the tile is 64 x ry*waves).
 void tile_shape(int nd, bool adjoint, int* ry, int* waves);
 
-// What a step launch computes.  Fourth-order time runs two launches per step.
+// What a step launch computes.  Fourth-order time runs two launches per
+// forward step and three per adjoint step (kPrep on u^m and on w^{m+1}, then
+// the adjoint kCorrect).
 enum StepMode {
     kStep = 0,    // C = a (2 A + k (L A + S)) - b B                 (leapfrog step)
     kPrep = 1,    // C = k (L A + St), St: source filtered in time   (p of the corrected step)
-    kCorrect = 2  // C = a (2 U + A + (k/12) L A) - b B, A = p, U = u^n
+    kCorrect = 2  // C = a (2 D + A + (k/12) L A) - b B, A = p, D = u^n;
+                  // adjoint: C = a (2 D + A + (k/12) L A + k R^T g) - b B with A = q,
+                  // D = w^{m+1}, and G += U (D + A/12) + (k/12) D L U with U = p
 };
 
 // Kernel launchers (stride_kernels.hip).
@@ -116,9 +121,9 @@ void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& 
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);
-// Forward launches of the fourth-order step (mode kPrep or kCorrect).
-void launch_step_mode(const Dims& d, int R, int mode, const StencilCoef& cf, const SpongeCoef& sp,
-                      const LaunchShape& ls, const StepParams& p, hipStream_t s);
+// Launches of the fourth-order steps: forward kPrep or kCorrect, adjoint kCorrect.
+void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
+                      const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s);
 
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
@@ -127,9 +132,10 @@ void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStrea
 constexpr int kMisfitParts = 256;
 void launch_residual_misfit(const float* traces, const float* observed, float* residual,
                             long long n, double* misfit, double* partial, hipStream_t s);
-// dvp = P^T (2 G / vp_pad); tmp0 and tmp1 hold intermediates of up to one field each.
-void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, float* tmp0,
-                         float* tmp1, hipStream_t s);
+// dvp = P^T (2 G / vp_pad), with G = H / kdiv where kdiv is given (else G = H);
+// tmp0 and tmp1 hold intermediates of up to one field each.
+void launch_finalize_dvp(const Dims& d, const float* H, const float* kdiv, const float* vp,
+                         float* dvp, float* tmp0, float* tmp1, hipStream_t s);
 void launch_copy(float* dst, const float* src, long long n, hipStream_t s);
 // flags[0] = bits of max(vp) (vp > 0), flags[1] = 1 if any vp <= 0 or non-finite.
 void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s);

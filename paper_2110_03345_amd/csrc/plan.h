@@ -14,7 +14,7 @@
 struct stride_plan {
     stride_grid_t g;
     int nd, R, nb, nt;
-    int torder;          // 2 or 4 (forward only)
+    int torder;          // 2 or 4
     stride::Dims dims;
     stride::StencilCoef cf;
     stride::SpongeCoef sp;
@@ -27,6 +27,7 @@ struct stride_plan {
     stride::InjTable src_inj;    // sources, weights / cell volume (blocks of ls_fwd)
     stride::InjTable src_img;    // the same entries, blocks of ls_adj (imaging source term)
     stride::InjTable rec_inj;    // receivers (adjoint injection), weights (blocks of ls_adj)
+    stride::InjTable no_inj;     // no entries (blocks of either shape)
     const long long* rec_idx;
     const float* rec_w;          // receiver sampling
     const long long* src_idx;
@@ -50,12 +51,13 @@ struct Layout {
     size_t scratch;    // small scalars
     size_t traces;     // nrec * nt floats
     size_t fixed_fwd;  // scratch + k + 2 fields
-    size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual
+    size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual (+ p, q)
 };
 
 Layout layout_of(const stride_plan& P);
 
-// Views of a gradient workspace: [scratch | k | G | w0 | w1 | traces | residual | pool...].
+// Views of a gradient workspace:
+// [scratch | k | G | w0 | w1 | traces | residual (| p | q, fourth order) | pool...].
 struct GradWs {
     unsigned* flags;   // [0] = max vp bits, [1] = bad-value flag
     double* partial;   // misfit partial sums
@@ -64,6 +66,8 @@ struct GradWs {
     float* w[2];
     float* traces;
     float* residual;
+    float* p;          // fourth order: k (L u^m + St^m), also the forward steps' p
+    float* q;          // fourth order: k L w^{m+1}
     std::vector<float*> pool;
     int snaps;
 };

@@ -261,14 +261,13 @@ Layout stride::layout_of(const stride_plan& P)
     L.scratch = 256 + kMisfitParts * sizeof(double);   // flags | misfit partial sums
     L.traces = (size_t)round_up((long long)P.nrec * P.nt * 4, 256);
     L.fixed_fwd = L.scratch + (P.torder == 4 ? 4 : 3) * L.field;   // k, u, u (, p)
-    L.fixed_grad = L.scratch + 4 * L.field + 2 * L.traces;
+    // k, G, w, w, traces, residual (, p and q of the fourth-order adjoint)
+    L.fixed_grad = L.scratch + (P.torder == 4 ? 6 : 4) * L.field + 2 * L.traces;
     return L;
 }
 
 int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
 {
-    if (P.torder != 2)
-        return fail(STRIDE_E_INVALID_ARG, "gradients are built for time_order 2 only");
     Layout L = layout_of(P);
     if (!ws)
         return fail(STRIDE_E_INVALID_ARG, "workspace is NULL");
@@ -298,6 +297,13 @@ int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
     b += L.traces;
     W.residual = (float*)b;
     b += L.traces;
+    W.p = W.q = nullptr;
+    if (P.torder == 4) {
+        W.p = (float*)b;
+        b += L.field;
+        W.q = (float*)b;
+        b += L.field;
+    }
     W.pool.clear();
     for (int f = 0; f < st.peak_fields; ++f) {
         W.pool.push_back((float*)b);
@@ -542,7 +548,9 @@ struct Runner {
     hipStream_t s;
     const float* wavelet;
     StepCursor cursor;
+    long long steps = 0;         // forward steps
     long long launches = 0;      // forward step launches
+    long long adj_steps = 0;     // adjoint steps
     long long adj_launches = 0;  // adjoint step launches
 
     Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
@@ -561,8 +569,56 @@ struct Runner {
         p.inj_sig = wavelet;
         if (traces && op.first_sweep)
             p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+        ++steps;
+        if (P.torder == 4) {
+            // p = k (L u^n + St^n), then u^{n+1} from the stencil of p
+            StepParams q = p;
+            p.C = W.p;
+            launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
+            q.A = W.p;
+            q.D = W.pool[op.a];
+            q.smp = SampleSet{};
+            launch_step_mode(P.dims, P.R, false, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
+            launches += 2;
+            return;
+        }
         launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
         ++launches;
+    }
+
+    // Fourth-order adjoint step m: p = k (L u^m + St^m) and q = k L w^{m+1}
+    // (no injection: the empty table), then w^m and the imaging update.
+    void adj4_launch(const StepOp& op, int wa, const float* grad_traces)
+    {
+        StepParams p = base_params(P);
+        p.A = W.pool[op.a];
+        p.C = W.p;
+        p.K = W.k;
+        p.step = op.step;
+        p.inj_sig = wavelet;
+        launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
+        StepParams q = base_params(P);
+        q.A = W.w[wa];
+        q.C = W.q;
+        q.K = W.k;
+        q.step = op.step;
+        q.inj = P.no_inj;
+        launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, q, s);
+        StepParams c = base_params(P);
+        c.A = W.q;
+        c.U = W.p;
+        c.D = W.w[wa];
+        c.B = W.w[1 - wa];
+        c.C = W.w[1 - wa];
+        c.K = W.k;
+        c.G = W.G;
+        c.step = op.step;
+        c.inj = P.rec_inj;
+        c.inj_sig = grad_traces;
+        c.inj_stride = P.nt;
+        c.img = P.no_inj;
+        launch_step_mode(P.dims, P.R, true, kCorrect, P.cf, P.sp, P.ls_adj, c, s);
+        adj_launches += 3;
     }
 
     void forward_phase(bool run, float* traces)
@@ -582,20 +638,27 @@ struct Runner {
     {
         int wa = 0;   // W.w[wa] = w^{m+1}, W.w[1-wa] = w^{m+2}
         int seg = -1;
-        long long seg_start = 0;
+        long long seg_steps = 0, seg_launches = 0;
         StepOp op;
         while (cursor.next(op)) {
             if (!op.reverse) {
                 if (seg < 0) {
                     seg = g_timer.begin(s);
-                    seg_start = launches;
+                    seg_steps = steps;
+                    seg_launches = launches;
                 }
                 fwd_launch(op, nullptr);
                 continue;
             }
             if (seg >= 0) {
-                g_timer.end(seg, s, 2, launches - seg_start, launches - seg_start);
+                g_timer.end(seg, s, 2, steps - seg_steps, launches - seg_launches);
                 seg = -1;
+            }
+            ++adj_steps;
+            if (P.torder == 4) {
+                adj4_launch(op, wa, grad_traces);
+                wa = 1 - wa;
+                continue;
             }
             StepParams p = base_params(P);
             p.A = W.w[wa];
@@ -618,7 +681,7 @@ struct Runner {
             wa = 1 - wa;
         }
         if (seg >= 0)
-            g_timer.end(seg, s, 2, launches - seg_start, launches - seg_start);
+            g_timer.end(seg, s, 2, steps - seg_steps, launches - seg_launches);
     }
 };
 
@@ -652,15 +715,15 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
             p.step = n;
             p.inj_sig = wavelet;
             p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
-            launch_step_mode(P.dims, P.R, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
+            launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
             StepParams q = base_params(P);
             q.A = F.p;
-            q.U = u[cur];
+            q.D = u[cur];
             q.B = u[1 - cur];
             q.C = u[1 - cur];
             q.K = k;
             q.step = n;
-            launch_step_mode(P.dims, P.R, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
+            launch_step_mode(P.dims, P.R, false, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
             cur = 1 - cur;
         }
         g_timer.end(tid, s, 0, P.nt - 1, 2LL * (P.nt - 1));
@@ -704,7 +767,7 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     Runner run(P, W, s, wavelet);
     int tid = g_timer.begin(s);
     run.forward_phase(true, tr);
-    g_timer.end(tid, s, 0, run.launches, run.launches);
+    g_timer.end(tid, s, 0, run.steps, run.launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     // last sample from the final state x_{nt-1}
@@ -720,6 +783,9 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
 {
     if (!vp || (!wavelet && P.nsrc > 0) || (!grad_traces && P.nrec > 0) || !dvp)
         return fail(STRIDE_E_INVALID_ARG, "vp, wavelet, grad_traces and dvp must be device pointers");
+    if (dwavelet && P.torder == 4)
+        return fail(STRIDE_E_INVALID_ARG,
+                    "the wavelet gradient is not provided for time_order 4 (pass dwavelet = NULL)");
     GradWs W;
     int rc = grad_ws(P, ws, bytes, W);
     if (rc)
@@ -731,10 +797,11 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     launch_fill(W.w[1], P.dims.total, 0.f, s);
     int tid = g_timer.begin(s);
     run.backward_phase(grad_traces, dwavelet);
-    g_timer.end(tid, s, 1, run.adj_launches, run.adj_launches);
+    g_timer.end(tid, s, 1, run.adj_steps, run.adj_launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
-    launch_finalize_dvp(P.dims, W.G, vp, dvp, W.w[0], W.w[1], s);
+    // the fourth-order accumulator holds k G
+    launch_finalize_dvp(P.dims, W.G, P.torder == 4 ? W.k : nullptr, vp, dvp, W.w[0], W.w[1], s);
     HIP_TRY(hipGetLastError());
     return STRIDE_OK;
 }
@@ -880,6 +947,8 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     size_t o_tsa_ent = add(tsa.ent.data(), tsa.ent.size(), sizeof(TileEntry));
     size_t o_tra_ptr = add(tra.ptr.data(), tra.ptr.size(), 4);
     size_t o_tra_ent = add(tra.ent.data(), tra.ent.size(), sizeof(TileEntry));
+    std::vector<int> none((size_t)std::max(P->ls_fwd.tile_blocks, P->ls_adj.tile_blocks) + 1, 0);
+    size_t o_none = add(none.data(), none.size(), 4);
     std::vector<char> host(off, 0);
     for (auto& pt : parts)
         if (pt.second.second)
@@ -899,6 +968,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->src_inj = InjTable{(const int*)(B + o_tsf_ptr), (const TileEntry*)(B + o_tsf_ent)};
     P->src_img = InjTable{(const int*)(B + o_tsa_ptr), (const TileEntry*)(B + o_tsa_ent)};
     P->rec_inj = InjTable{(const int*)(B + o_tra_ptr), (const TileEntry*)(B + o_tra_ent)};
+    P->no_inj = InjTable{(const int*)(B + o_none), (const TileEntry*)(B + o_tra_ent)};
 
     P->rec_idx = (const long long*)(B + o_ridx);
     P->rec_w = (const float*)(B + o_rw);
@@ -944,8 +1014,6 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
     }
     if (mode != STRIDE_MODE_GRADIENT)
         return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD or GRADIENT");
-    if (plan->torder != 2)
-        return fail(STRIDE_E_INVALID_ARG, "gradients are built for time_order 2 only");
     long long nfields;
     if (budget_bytes == 0) {
         nfields = cached_schedule(plan->nt, plan->nt)->stats.peak_fields;

@@ -200,7 +200,7 @@ void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
         J.left = J.cursor->forward_steps() - (P.nt - 1) + P.nt;
         return;
     }
-    launch_finalize_dvp(P.dims, J.W.G, J.vp, J.dvp, J.W.w[0], J.W.w[1], s);
+    launch_finalize_dvp(P.dims, J.W.G, nullptr, J.vp, J.dvp, J.W.w[0], J.W.w[1], s);
     J.finished = true;
 }
 

@@ -138,6 +138,8 @@ __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* 
     smp.out[(long long)r * smp.out_stride + step] = acc;
 }
 
+constexpr float kTwelfth = 1.f / 12.f;
+
 __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float rhs, float eta,
                                           float half_dt)
 {
@@ -203,6 +205,42 @@ __device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEnt
     return v;
 }
 
+// Output of a step launch at one point (see StepMode).  ctr and lap: centre
+// and Laplacian of the stencil field A; inj: the injected value at the point;
+// uu: the point field D; bb, kk: B and k.  The adjoint correction adds its
+// receiver injection as k inj (A = q = k L w^{m+1}, D = w^{m+1}):
+//   w^m = a (2 w^{m+1} + q + (k/12) L q + k inj) - b w^{m+2}.
+template <bool ADJ, int MODE>
+__device__ __forceinline__ float step_out(float ctr, float lap, float inj, float uu, float bb,
+                                          float kk, float eta, float half_dt)
+{
+    if constexpr (MODE == kStep) {
+        return leapfrog(ctr, bb, kk, lap + inj, eta, half_dt);
+    } else if constexpr (MODE == kPrep) {
+        return kk * (lap + inj);
+    } else {
+        float rhs = fmaf(kk * kTwelfth, lap, ctr);
+        if constexpr (ADJ)
+            rhs = fmaf(kk, inj, rhs);
+        return leapfrog(uu, bb, 1.f, rhs, eta, half_dt);
+    }
+}
+
+// Imaging accumulator update of an adjoint launch.  Second order:
+// G += w^{m+1} (L u^m + S^m) with ctr = w^{m+1}, lu = L u^m + S^m.  Fourth
+// order accumulates k G, the gradient with respect to k times k:
+//   H += p (w + q/12) + (k/12) w L p,   p = k (L u^m + St^m), q = k L w,
+// with ctr = q, pc = p, lu = L p and uu = w = w^{m+1}.
+template <int MODE>
+__device__ __forceinline__ float image_out(float ctr, float pc, float lu, float uu, float kk,
+                                           float gg)
+{
+    if constexpr (MODE == kCorrect)
+        return fmaf((kk * kTwelfth) * uu, lu, fmaf(pc, fmaf(ctr, kTwelfth, uu), gg));
+    else
+        return fmaf(ctr, lu, gg);
+}
+
 template <int R, bool ADJ, int RY, int WAVES, int MODE = kStep>
 __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf,
                                             const SpongeCoef& sp, const StepParams& p,
@@ -236,14 +274,17 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     const int gx = x0 + lx;
     const bool xin = gx < n1;
 
-    // entry ranges of the tile (uniform); the correction pass injects nothing
+    // entry ranges of the tile (uniform); the forward correction pass injects
+    // nothing, the adjoint one its receivers, and it images without a source term
+    constexpr bool INJ = MODE != kCorrect || ADJ;
+    constexpr bool IMG = ADJ && MODE != kCorrect;
     int eb0 = 0, ne0 = 0;
-    if constexpr (MODE != kCorrect) {
+    if constexpr (INJ) {
         eb0 = p.inj.ptr[tile];
         ne0 = p.inj.ptr[tile + 1] - eb0;
     }
     int eb1 = 0, ne1 = 0;
-    if constexpr (ADJ) {
+    if constexpr (IMG) {
         eb1 = p.img.ptr[tile];
         ne1 = p.img.ptr[tile + 1] - eb1;
     }
@@ -276,7 +317,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     {
         const auto rb = plane_rsrc(p.B, fbytes);
         const auto rk = plane_rsrc(p.K, fbytes);
-        const auto ru = plane_rsrc(p.U, fbytes);
+        const auto ru = plane_rsrc(p.D, fbytes);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             const int gy = y0 + wy * RY + j;
@@ -307,7 +348,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
                                                    p.inj_stride, p.step);
         }
     }
-    if constexpr (ADJ) {
+    if constexpr (IMG) {
         if (tid < ne1) {
             const TileEntry e = p.img.ent[eb1 + tid];
             if (e.run > 0) {
@@ -330,7 +371,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
     }
     const bool inj_any = ne0 > 0;
-    const bool img_any = ADJ && ne1 > 0;
+    const bool img_any = IMG && ne1 > 0;
     if (inj_any)
 #pragma unroll
         for (int j = 0; j < RY; ++j)
@@ -349,7 +390,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
                 sS[0][en.local] = tile_point_signal<MODE == kPrep>(p.inj.ent + eb0 + e, en, p.inj_sig,
                                                                    p.inj_stride, p.step);
         }
-        if constexpr (ADJ) {
+        if constexpr (IMG) {
             if (il1 >= 0)
                 sS[1][il1] = iv1;
             for (int e = tid + NT; e < ne1; e += NT) {
@@ -374,22 +415,18 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         const float* SA = &sF[0][(ly + R) * LW + lx + R];
         const float ctr = SA[0];
         float lap = lap2d<R, LW>(SA, cf);
+        float inj = 0.f;
         if (inj_any)
-            lap += sS[0][ly * kTileX + lx];
+            inj = sS[0][ly * kTileX + lx];
         const int dyd = layer_depth(y0 + ly, n0, d.nb);
         const float eta = fmaf(sp.e[0], (float)(dyd * dyd), ex);
-        if constexpr (MODE == kStep)
-            p.C[po[j]] = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
-        else if constexpr (MODE == kPrep)
-            p.C[po[j]] = kk[j] * lap;
-        else
-            p.C[po[j]] = leapfrog(uu[j], bb[j], 1.f, fmaf(kk[j] / 12.f, lap, ctr), eta, sp.half_dt);
+        p.C[po[j]] = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
         if constexpr (ADJ) {
             const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
             float lu = lap2d<R, LW>(SU, cf);
             if (img_any)
                 lu += sS[NF - 1][ly * kTileX + lx];
-            p.G[po[j]] = fmaf(ctr, lu, gg[j]);
+            p.G[po[j]] = image_out<MODE>(ctr, SU[0], lu, uu[j], kk[j], gg[j]);
         }
     }
 }
@@ -543,7 +580,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             pk[j] = bload_stream(rk, rbo[j]);
         }
         if constexpr (MODE == kCorrect) {
-            const auto ru = rsrc(p.U, z);
+            const auto ru = rsrc(p.D, z);
 #pragma unroll
             for (int j = 0; j < RY; ++j)
                 pu[j] = bload_stream(ru, rbo[j]);
@@ -562,18 +599,20 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     // of that plane to the LDS plane array, where the point's thread takes
     // (and clears) it after the barrier.  Blocks with more than NT entries
     // read the rest at every plane.
+    constexpr bool INJ = MODE != kCorrect || ADJ;
+    constexpr bool IMG = ADJ && MODE != kCorrect;
     int eb0 = 0, ne0 = 0;
-    if constexpr (MODE != kCorrect) {
+    if constexpr (INJ) {
         eb0 = p.inj.ptr[lb];
         ne0 = p.inj.ptr[lb + 1] - eb0;
     }
     int eb1 = 0, ne1 = 0;
-    if constexpr (ADJ) {
+    if constexpr (IMG) {
         eb1 = p.img.ptr[lb];
         ne1 = p.img.ptr[lb + 1] - eb1;
     }
     const bool inj_any = ne0 > 0;
-    const bool img_any = ADJ && ne1 > 0;
+    const bool img_any = IMG && ne1 > 0;
     prefetch(z0);
     if (inj_any || img_any) {
         int il0 = -1, il1 = -1;
@@ -586,7 +625,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                                                        p.inj_stride, p.step);
             }
         }
-        if constexpr (ADJ) {
+        if constexpr (IMG) {
             if (tid < ne1) {
                 const TileEntry e = p.img.ent[eb1 + tid];
                 if (e.run > 0) {
@@ -671,7 +710,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             if (ne0 > NT)
                 overflow(std::integral_constant<bool, MODE == kPrep>{}, p.inj, eb0, ne0, p.inj_sig,
                          p.inj_stride, pz, &sS[buf][0][0]);
-            if constexpr (ADJ)
+            if constexpr (IMG)
                 if (ne1 > NT)
                     overflow(std::false_type{}, p.img, eb1, ne1, p.img_sig, p.img_stride, pz,
                              &sS[buf][NF - 1][0]);
@@ -695,19 +734,14 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     ay = fmaf(cf.c[1][qq], SA[(ly + R + qq) * LW + lx + R] + SA[(ly + R - qq) * LW + lx + R], ay);
                     ax = fmaf(cf.c[2][qq], SA[(ly + R) * LW + lx + R + qq] + SA[(ly + R) * LW + lx + R - qq], ax);
                 }
-                float lap = fmaf(cf.c0, ctr, az + ay + ax);
+                const float lap = fmaf(cf.c0, ctr, az + ay + ax);
+                float inj = 0.f;
                 if (inj_any) {
-                    lap += sS[buf][0][ly * kTileX + lx];
+                    inj = sS[buf][0][ly * kTileX + lx];
                     sS[buf][0][ly * kTileX + lx] = 0.f;
                 }
                 const float eta = ez + ey[j];
-                float out;
-                if constexpr (MODE == kStep)
-                    out = leapfrog(ctr, bb[j], kk[j], lap, eta, sp.half_dt);
-                else if constexpr (MODE == kPrep)
-                    out = kk[j] * lap;
-                else
-                    out = leapfrog(uu[j], bb[j], 1.f, fmaf(kk[j] / 12.f, lap, ctr), eta, sp.half_dt);
+                const float out = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
                 __builtin_nontemporal_store(out, Cz + roff[j]);
                 if constexpr (ADJ) {
                     const float* SU = S + (NF - 1) * PLANE;
@@ -724,7 +758,8 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                         lu += sS[buf][NF - 1][ly * kTileX + lx];
                         sS[buf][NF - 1][ly * kTileX + lx] = 0.f;
                     }
-                    __builtin_nontemporal_store(fmaf(ctr, lu, gg[j]), Gz + roff[j]);
+                    __builtin_nontemporal_store(image_out<MODE>(ctr, uc0, lu, uu[j], kk[j], gg[j]),
+                                                Gz + roff[j]);
                 }
             }
             buf ^= 1;
@@ -887,9 +922,10 @@ __global__ __launch_bounds__(256) void misfit_final_kernel(const double* partial
 // [m0][nout][m2] with nin = nout + 2 nb: output cell j collects input cell
 // j + nb, and the two edge cells also collect the nb cells replicated from
 // them.  With vp given, the output is 2 * sum / vp (the last pass of dvp).
-__global__ void pad_transpose_axis_kernel(const float* in, long long s_outer, long long s_axis,
-                                          float* out, long long m0, int nout, long long m2, int nb,
-                                          const float* vp)
+// With div given (laid out like the input), each input cell is divided by it.
+__global__ void pad_transpose_axis_kernel(const float* in, const float* div, long long s_outer,
+                                          long long s_axis, float* out, long long m0, int nout,
+                                          long long m2, int nb, const float* vp)
 {
     const long long total = m0 * nout * m2;
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -901,10 +937,15 @@ __global__ void pad_transpose_axis_kernel(const float* in, long long s_outer, lo
         const long long i0 = r / nout;
         const int lo = j == 0 ? 0 : j + nb;
         const int hi = j == nout - 1 ? j + 2 * nb : j + nb;
-        const float* src = in + i0 * s_outer + i2;
+        const long long base = i0 * s_outer + i2;
+        const float* src = in + base;
         float acc = 0.f;
-        for (int k = lo; k <= hi; ++k)
-            acc += src[(long long)k * s_axis];
+        if (div)
+            for (int k = lo; k <= hi; ++k)
+                acc += src[(long long)k * s_axis] / div[base + (long long)k * s_axis];
+        else
+            for (int k = lo; k <= hi; ++k)
+                acc += src[(long long)k * s_axis];
         out[i] = vp ? 2.f * acc / vp[i] : acc;
     }
 }
@@ -952,7 +993,7 @@ __global__ void vp_check_kernel(const float* vp, long long n, unsigned* flags)
             L(4, 4);                                                                              \
     } while (0)
 
-template <int R, bool ADJ>
+template <int R, bool ADJ, int MODE>
 void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                    const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
@@ -961,13 +1002,15 @@ void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
     dim3 grid(ls.tile_blocks_pad + smp_blocks);
     if (d.nd == 2) {
 #define STRIDE_LAUNCH2D(RY_, W_)                                                                  \
-    hipLaunchKernelGGL((step2d_kernel<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, p, ls)
+    hipLaunchKernelGGL((step2d_kernel<R, ADJ, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, \
+                       p, ls)
         STRIDE_DISPATCH2D(STRIDE_LAUNCH2D);
 #undef STRIDE_LAUNCH2D
         return;
     }
 #define STRIDE_LAUNCH3D(RY_, W_)                                                                  \
-    hipLaunchKernelGGL((step3d_kernel<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, p, ls)
+    hipLaunchKernelGGL((step3d_kernel<R, ADJ, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, \
+                       p, ls)
     if (ls.waves == 8) {
         if (ls.ry == 1)
             STRIDE_LAUNCH3D(1, 8);
@@ -982,40 +1025,6 @@ void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
             STRIDE_LAUNCH3D(4, 4);
     }
 #undef STRIDE_LAUNCH3D
-}
-
-template <int R, int MODE>
-void launch_mode_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
-                   const LaunchShape& ls, const StepParams& p, hipStream_t s)
-{
-    const int nt = 64 * ls.waves;
-    int smp_blocks = (p.smp.count + nt - 1) / nt;
-    dim3 grid(ls.tile_blocks_pad + smp_blocks);
-    if (d.nd == 2) {
-#define STRIDE_LAUNCH2DM(RY_, W_)                                                                 \
-    hipLaunchKernelGGL((step2d_kernel<R, false, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, \
-                       p, ls)
-        STRIDE_DISPATCH2D(STRIDE_LAUNCH2DM);
-#undef STRIDE_LAUNCH2DM
-        return;
-    }
-#define STRIDE_LAUNCH3DM(RY_, W_)                                                                 \
-    hipLaunchKernelGGL((step3d_kernel<R, false, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, sp, \
-                       p, ls)
-    if (ls.waves == 8) {
-        if (ls.ry == 1)
-            STRIDE_LAUNCH3DM(1, 8);
-        else if (ls.ry == 2)
-            STRIDE_LAUNCH3DM(2, 8);
-        else
-            STRIDE_LAUNCH3DM(4, 8);
-    } else {
-        if (ls.ry == 2)
-            STRIDE_LAUNCH3DM(2, 4);
-        else
-            STRIDE_LAUNCH3DM(4, 4);
-    }
-#undef STRIDE_LAUNCH3DM
 }
 
 template <int R, bool ADJ>
@@ -1062,23 +1071,27 @@ int grid_for(long long n, int threads)
 
 }  // namespace
 
-void launch_step_mode(const Dims& d, int R, int mode, const StencilCoef& cf, const SpongeCoef& sp,
-                      const LaunchShape& ls, const StepParams& p, hipStream_t s)
+void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
+                      const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
-    if (mode == kPrep)
-        R == 4 ? launch_mode_t<4, kPrep>(d, cf, sp, ls, p, s) : launch_mode_t<5, kPrep>(d, cf, sp, ls, p, s);
+    if (adjoint)   // the adjoint of the fourth-order step runs kCorrect only
+        R == 4 ? launch_step_t<4, true, kCorrect>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, true, kCorrect>(d, cf, sp, ls, p, s);
+    else if (mode == kPrep)
+        R == 4 ? launch_step_t<4, false, kPrep>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, false, kPrep>(d, cf, sp, ls, p, s);
     else
-        R == 4 ? launch_mode_t<4, kCorrect>(d, cf, sp, ls, p, s)
-               : launch_mode_t<5, kCorrect>(d, cf, sp, ls, p, s);
+        R == 4 ? launch_step_t<4, false, kCorrect>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, false, kCorrect>(d, cf, sp, ls, p, s);
 }
 
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
     if (R == 4)
-        adjoint ? launch_step_t<4, true>(d, cf, sp, ls, p, s) : launch_step_t<4, false>(d, cf, sp, ls, p, s);
+        adjoint ? launch_step_t<4, true, kStep>(d, cf, sp, ls, p, s) : launch_step_t<4, false, kStep>(d, cf, sp, ls, p, s);
     else
-        adjoint ? launch_step_t<5, true>(d, cf, sp, ls, p, s) : launch_step_t<5, false>(d, cf, sp, ls, p, s);
+        adjoint ? launch_step_t<5, true, kStep>(d, cf, sp, ls, p, s) : launch_step_t<5, false, kStep>(d, cf, sp, ls, p, s);
 }
 
 void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
@@ -1145,8 +1158,8 @@ void launch_residual_misfit(const float* traces, const float* observed, float* r
     hipLaunchKernelGGL(misfit_final_kernel, dim3(1), dim3(256), 0, s, partial, kMisfitParts, misfit);
 }
 
-void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* dvp, float* tmp0,
-                         float* tmp1, hipStream_t s)
+void launch_finalize_dvp(const Dims& d, const float* G, const float* kdiv, const float* vp,
+                         float* dvp, float* tmp0, float* tmp1, hipStream_t s)
 {
     // P^T one axis at a time, innermost first; the first pass reads the
     // pitched field, later passes dense intermediates, the last writes dvp.
@@ -1165,7 +1178,8 @@ void launch_finalize_dvp(const Dims& d, const float* G, const float* vp, float* 
         float* out = a == 0 ? dvp : tmp[a & 1];
         const long long cnt = m0 * d.phys[a] * m2;
         hipLaunchKernelGGL(pad_transpose_axis_kernel, dim3(grid_for(cnt, 256)), dim3(256), 0, s, in,
-                           s_outer, s_axis, out, m0, d.phys[a], m2, d.nb, a == 0 ? vp : nullptr);
+                           a == nd - 1 ? kdiv : nullptr, s_outer, s_axis, out, m0, d.phys[a], m2,
+                           d.nb, a == 0 ? vp : nullptr);
         ext[a] = d.phys[a];
         in = out;
     }

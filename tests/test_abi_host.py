@@ -93,17 +93,24 @@ def test_gradient_workspace_query_meets_the_solve_minimum(nt):
 
 
 def test_fourth_order_workspace_and_refusals():
-    """Fourth-order time: one more field for the forward (p); gradients and
-    unknown orders refused before anything runs."""
+    """Fourth-order time: one more field for the forward (p), two more for the
+    gradient (p and q of the adjoint step), the same checkpoint pool; unknown
+    orders refused before anything runs."""
     g2 = _grid(nt=20)
     g4 = _grid(nt=20)
     g4.time_order = 4
     field = -(-(52 * 64 * 4) // 256) * 256
     f2 = S.stride_workspace_query(g2, 1, 3, S.STRIDE_MODE_FORWARD)
     assert S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_FORWARD) == f2 + field
+    full2 = S.stride_workspace_query(g2, 1, 3, S.STRIDE_MODE_GRADIENT)
+    assert S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT) == full2 + 2 * field
+    traces = -(-(3 * 20 * 4) // 256) * 256
+    fixed4 = 256 + 256 * 8 + 6 * field + 2 * traces
+    small = S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT, fixed4 + 6 * field)
+    assert fixed4 + 4 * field <= small <= fixed4 + 6 * field
     with pytest.raises(S.StrideError) as e:
-        S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT)
-    assert e.value.code == _abi.STRIDE_E_INVALID_ARG
+        S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT, fixed4 + 3 * field)
+    assert e.value.code == _abi.STRIDE_E_WORKSPACE
     g3 = _grid(nt=20)
     g3.time_order = 3
     with pytest.raises(S.StrideError):

@@ -1,7 +1,8 @@
 """Fourth-order time (leapfrog with the modified-equation correction and the
-time-filtered source): HIP forward traces against the FP64 oracle's, at the
-workloads' CFL and near the larger stability limit of the corrected scheme;
-the CFL check of each order; gradients refused for the fourth-order scheme."""
+time-filtered source): HIP forward traces and gradients against the FP64
+oracle's, at the workloads' CFL and near the larger stability limit of the
+corrected scheme; the CFL check of each order; checkpointing invisible in the
+gradient; the autograd operator; the wavelet gradient refused."""
 import numpy as np
 import pytest
 
@@ -70,9 +71,82 @@ def test_stability_limit_per_order():
     assert e.value.code == -2
 
 
-def test_gradients_refuse_the_fourth_order_scheme():
-    w = W.tiny_2d()
+GRAD_CASES = [
+    ("2d_o8", lambda: W.tiny_2d()),
+    ("2d_o10_ragged", lambda: W.tiny_2d(space_order=10, n=(83, 141), nb=7, nt=150)),
+    ("2d_o8_cfl085", lambda: _at_cfl(W.tiny_2d(nt=160), 0.85)),
+    ("3d_o10", lambda: W.tiny_3d()),
+    ("3d_o8_ragged", lambda: W.tiny_3d(space_order=8, n=(37, 21, 70), nb=4, nt=70)),
+]
+
+
+@pytest.mark.parametrize("name,make", GRAD_CASES, ids=[c[0] for c in GRAD_CASES])
+def test_fourth_order_gradient_matches_oracle(name, make):
+    w = make()
+    print(f"fourth-order gradient {name}: shape={w.shape} nt={w.nt}", flush=True)
+    g = oracle.Grid(**w.grid_kwargs(), time_order=4)
+    rng = np.random.default_rng(7)
+    obs = oracle.forward(g, w.vp * (1 + 0.02 * rng.standard_normal(w.shape).clip(-2, 2)),
+                         w.src_xyz, w.wavelet, w.rec_xyz).astype(np.float32)
+    tr_ref, J, dvp_ref = oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, obs)
     plan = S.Plan.from_workload(w, time_order=4)
-    with pytest.raises(S.StrideError) as e:
-        plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+    tr = torch.empty((plan.nrec, w.nt), dtype=torch.float32, device="cuda")
+    misfit, dvp = plan.gradient(dev(w.vp), dev(w.wavelet), dev(obs), traces=tr)
+    assert rel(tr.cpu().numpy(), tr_ref) < 1e-4
+    assert abs(misfit.item() - J) <= 1e-4 * abs(J)
+    assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_fourth_order_backward_vjp_matches_oracle(maker):
+    w = maker()
+    g = oracle.Grid(**w.grid_kwargs(), time_order=4)
+    plan = S.Plan.from_workload(w, time_order=4)
+    rng = np.random.default_rng(3)
+    gt = rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32)
+    dvp_ref, _ = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, gt)
+    ws = plan.workspace(S.STRIDE_MODE_GRADIENT)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    plan.forward_save(vp, wav, ws)
+    dvp, _ = plan.backward(vp, wav, dev(gt), ws)
+    assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
+    plan.forward_save(vp, wav, ws)
+    with pytest.raises(S.StrideError) as e:       # no wavelet gradient for this scheme
+        plan.backward(vp, wav, dev(gt), ws, want_dwavelet=True)
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("maker,kw", [(W.tiny_2d, dict(nt=90)), (W.tiny_3d, dict(nt=50))])
+def test_fourth_order_checkpointing_is_bitwise_invisible(maker, kw):
+    w = maker(**kw)
+    plan = S.Plan.from_workload(w, time_order=4)
+    rng = np.random.default_rng(5)
+    obs = dev(rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32) * 1e-3)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    m0, g0 = plan.gradient(vp, wav, obs)
+    full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+    for frac in (0.5, 0.25):
+        budget = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT, int(full * frac))
+        assert budget < full
+        print(f"budget {budget} of {full}", flush=True)
+        m1, g1 = plan.gradient(vp, wav, obs, budget_bytes=budget)
+        assert torch.equal(g0, g1) and torch.equal(m0, m1)
+
+
+def test_fourth_order_autograd_matches_oracle():
+    from paper_2110_03345_amd.autograd import wave_traces
+    w = W.tiny_2d(nt=120)
+    g = oracle.Grid(**w.grid_kwargs(), time_order=4)
+    plan = S.Plan.from_workload(w, time_order=4)
+    rng = np.random.default_rng(9)
+    obs = (0.5 * oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+           + 1e-3 * rng.standard_normal((w.rec_xyz.shape[0], w.nt))).astype(np.float32)
+    _, J, dvp_ref = oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, obs)
+    vp = dev(w.vp).requires_grad_(True)
+    tr = wave_traces(vp, dev(w.wavelet), plan, plan.workspace_bytes(S.STRIDE_MODE_GRADIENT) // 2)
+    loss = 0.5 * ((tr.double() - dev(obs).double()) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - J) <= 1e-4 * abs(J)
+    assert rel(vp.grad.cpu().numpy(), dvp_ref) < 1e-4
+    with pytest.raises(ValueError):
+        wave_traces(dev(w.vp), dev(w.wavelet).requires_grad_(True), plan)
