@@ -1,5 +1,12 @@
-"""Build libstride_hip.so (HIP kernels for gfx950 + host library + C ABI) in-tree."""
+"""Build libstride_hip.so (HIP kernels for gfx950 + host library + C ABI) in-tree.
+
+The kernel source is compiled with the compiler's per-kernel resource remarks;
+they are kept in _build/kernel_resources.json (registers, scratch, occupancy
+per kernel) so that register spills of the step kernels are caught on the
+build host."""
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -13,6 +20,25 @@ ARCH = os.environ.get("STRIDE_ARCH", "gfx950")
 
 # Packed-FP32 instructions stay disabled: the kernels are plain scalar FP32.
 GPU_FLAGS = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+RESOURCES = os.path.join(HERE, "_build", "kernel_resources.json")
+_KEYS = {"VGPRs": "vgpr", "AGPRs": "agpr", "SGPRs": "sgpr", "ScratchSize [bytes/lane]": "scratch",
+         "Occupancy [waves/SIMD]": "occupancy", "LDS Size [bytes/block]": "lds"}
+
+
+def parse_resources(remarks: str) -> dict:
+    """{mangled kernel name: {vgpr, sgpr, scratch, occupancy, lds, ...}} from
+    the compiler's kernel-resource-usage remarks."""
+    out, cur = {}, None
+    for line in remarks.splitlines():
+        m = re.search(r"Function Name: (\S+)", line)
+        if m:
+            cur = out.setdefault(m.group(1), {})
+            continue
+        for key, short in _KEYS.items():
+            m = re.search(re.escape(key) + r": (\d+)", line)
+            if m and cur is not None:
+                cur[short] = int(m.group(1))
+    return out
 
 
 def build(verbose: bool = False) -> str:
@@ -25,9 +51,22 @@ def build(verbose: bool = False) -> str:
         cmd = [HIPCC, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
                "-I" + os.path.join(ROOT, "include"), "-c", path, "-o", obj]
         cmd[1:1] = ["-x", "hip"] + GPU_FLAGS
+        kernels = src.endswith(".hip")
+        if kernels:
+            cmd.append("-Rpass-analysis=kernel-resource-usage")
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        r = subprocess.run(cmd, stderr=subprocess.PIPE, text=True)
+        if kernels:
+            with open(RESOURCES, "w") as f:
+                json.dump(parse_resources(r.stderr), f, indent=0, sort_keys=True)
+            errs = "\n".join(l for l in r.stderr.splitlines() if "remark" not in l and l.strip()
+                             and "packed-fp32-ops" not in l and "Function Name" not in l)
+        else:
+            errs = r.stderr
+        if r.returncode:
+            sys.stderr.write(errs)
+            raise subprocess.CalledProcessError(r.returncode, cmd)
         objs.append(obj)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]

@@ -206,18 +206,22 @@ __device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEnt
 }
 
 // Output of a step launch at one point (see StepMode).  ctr and lap: centre
-// and Laplacian of the stencil field A; inj: the injected value at the point;
-// uu: the point field D; bb, kk: B and k.  The adjoint correction adds its
-// receiver injection as k inj (A = q = k L w^{m+1}, D = w^{m+1}):
+// and Laplacian of the stencil field A, with the injected value already added
+// except in the adjoint correction, which takes it apart as inj and adds it
+// as k inj (A = q = k L w^{m+1}, D = w^{m+1}):
 //   w^m = a (2 w^{m+1} + q + (k/12) L q + k inj) - b w^{m+2}.
+// uu: the point field D; bb, kk: B and k.
+template <bool ADJ, int MODE>
+constexpr bool kInjApart = ADJ && MODE == kCorrect;
+
 template <bool ADJ, int MODE>
 __device__ __forceinline__ float step_out(float ctr, float lap, float inj, float uu, float bb,
                                           float kk, float eta, float half_dt)
 {
     if constexpr (MODE == kStep) {
-        return leapfrog(ctr, bb, kk, lap + inj, eta, half_dt);
+        return leapfrog(ctr, bb, kk, lap, eta, half_dt);
     } else if constexpr (MODE == kPrep) {
-        return kk * (lap + inj);
+        return kk * lap;
     } else {
         float rhs = fmaf(kk * kTwelfth, lap, ctr);
         if constexpr (ADJ)
@@ -416,8 +420,12 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         const float ctr = SA[0];
         float lap = lap2d<R, LW>(SA, cf);
         float inj = 0.f;
-        if (inj_any)
-            inj = sS[0][ly * kTileX + lx];
+        if (inj_any) {
+            if constexpr (kInjApart<ADJ, MODE>)
+                inj = sS[0][ly * kTileX + lx];
+            else
+                lap += sS[0][ly * kTileX + lx];
+        }
         const int dyd = layer_depth(y0 + ly, n0, d.nb);
         const float eta = fmaf(sp.e[0], (float)(dyd * dyd), ex);
         p.C[po[j]] = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
@@ -734,10 +742,13 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     ay = fmaf(cf.c[1][qq], SA[(ly + R + qq) * LW + lx + R] + SA[(ly + R - qq) * LW + lx + R], ay);
                     ax = fmaf(cf.c[2][qq], SA[(ly + R) * LW + lx + R + qq] + SA[(ly + R) * LW + lx + R - qq], ax);
                 }
-                const float lap = fmaf(cf.c0, ctr, az + ay + ax);
+                float lap = fmaf(cf.c0, ctr, az + ay + ax);
                 float inj = 0.f;
                 if (inj_any) {
-                    inj = sS[buf][0][ly * kTileX + lx];
+                    if constexpr (kInjApart<ADJ, MODE>)
+                        inj = sS[buf][0][ly * kTileX + lx];
+                    else
+                        lap += sS[buf][0][ly * kTileX + lx];
                     sS[buf][0][ly * kTileX + lx] = 0.f;
                 }
                 const float eta = ez + ey[j];
