@@ -104,6 +104,10 @@ def lib():
         L.oracle_gradient.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp,
                                       dp, dp, dp, ctypes.c_int]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_fd1_weights.argtypes = [ctypes.c_int, dp]
+        L.oracle_medium_operator.argtypes = [gp, dp, dp, dp]
+        L.oracle_forward_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
+                                            ctypes.c_int, dp, dp]
         _LIB = L
     return _LIB
 
@@ -232,3 +236,39 @@ def gradient(grid: Grid, vp, src_xyz, wavelet, rec_xyz, observed, seg: int = 0):
                                _d(dvp), seg)
     _check(rc, "gradient")
     return traces, float(J.value), dvp
+
+
+def fd1_weights(space_order: int) -> np.ndarray:
+    """[0, d_1 .. d_r]: centred first-derivative weights."""
+    d = np.zeros(6)
+    _check(lib().oracle_fd1_weights(space_order, _d(d)), "fd1_weights")
+    return d[: space_order // 2 + 1].copy()
+
+
+def medium_operator(grid: Grid, rho, u) -> np.ndarray:
+    """L u + sum_a gamma_a D_a u on the padded grid (rho physical, None = 1)."""
+    rho = None if rho is None else _f64(rho, grid.shape)
+    u = _f64(u, grid.padded_shape)
+    out = np.zeros(grid.padded_shape)
+    g = grid.c()
+    _check(lib().oracle_medium_operator(ctypes.byref(g), _d(rho), _d(u), _d(out)), "medium_operator")
+    return out
+
+
+def forward_medium(grid: Grid, vp, src_xyz, wavelet, rec_xyz, rho=None, alpha0=None,
+                   att_power: int = 0):
+    """Receiver traces [nrec][nt] in a medium with variable density (rho) and
+    power-law attenuation alpha0 * omega^att_power, att_power 0 or 2."""
+    vp = _f64(vp, grid.shape)
+    rho = None if rho is None else _f64(rho, grid.shape)
+    alpha0 = None if alpha0 is None else _f64(alpha0, grid.shape)
+    src = _f64(src_xyz).reshape(-1, grid.ndim)
+    rec = _f64(rec_xyz).reshape(-1, grid.ndim)
+    wav = _f64(wavelet).reshape(src.shape[0], grid.nt)
+    traces = np.zeros((rec.shape[0], grid.nt))
+    g = grid.c()
+    rc = lib().oracle_forward_medium(ctypes.byref(g), _d(vp), _d(rho), _d(alpha0), int(att_power),
+                                     src.shape[0], _d(src), _d(wav), rec.shape[0], _d(rec),
+                                     _d(traces))
+    _check(rc, "forward_medium")
+    return traces

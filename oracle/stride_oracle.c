@@ -68,6 +68,23 @@ int oracle_fd_weights(int space_order, double *c)
     return 0;
 }
 
+/* Centred first-derivative weights: the unique antisymmetric (2r+1)-point
+ * stencil exact on polynomials of degree <= 2r; exact rationals. */
+int oracle_fd1_weights(int space_order, double *d)
+{
+    switch (space_order) {
+    case 2:  d[1] = 1.0 / 2.0; break;
+    case 4:  d[1] = 2.0 / 3.0; d[2] = -1.0 / 12.0; break;
+    case 6:  d[1] = 3.0 / 4.0; d[2] = -3.0 / 20.0; d[3] = 1.0 / 60.0; break;
+    case 8:  d[1] = 4.0 / 5.0; d[2] = -1.0 / 5.0; d[3] = 4.0 / 105.0; d[4] = -1.0 / 280.0; break;
+    case 10: d[1] = 5.0 / 6.0; d[2] = -5.0 / 21.0; d[3] = 5.0 / 84.0; d[4] = -5.0 / 504.0;
+             d[5] = 1.0 / 1260.0; break;
+    default: return -1;
+    }
+    d[0] = 0.0;
+    return 0;
+}
+
 static int make_geo(const oracle_grid_t *g, geo_t *G)
 {
     if (!g || (g->ndim != 2 && g->ndim != 3) || g->nb < 0 || g->nt < 1 || !(g->dt > 0))
@@ -652,5 +669,197 @@ int oracle_gradient(const oracle_grid_t *g, const double *vp,
     }
     free(tr);
     free(res);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Heterogeneous medium: variable density and power-law attenuation (y = 0, 2).
+ * See the header for the equation and the readings. */
+
+typedef struct {
+    double *gam[3];   /* gamma_a = -D_a ln(rho_pad) */
+    double d[6];      /* first-derivative weights */
+    double inv_dx[3];
+} medium_t;
+
+static void medium_free(medium_t *M)
+{
+    for (int a = 0; a < 3; a++)
+        free(M->gam[a]);
+}
+
+/* gamma_a on the padded grid; ln rho repeats its edge value beyond the array. */
+static int medium_init(medium_t *M, const oracle_grid_t *g, const geo_t *G, const double *rho)
+{
+    memset(M, 0, sizeof(*M));
+    if (oracle_fd1_weights(g->space_order, M->d) != 0)
+        return -1;
+    long N = G->N;
+    double *lr = malloc(sizeof(double) * N);
+    if (!lr)
+        return -7;
+    for (int a = 0; a < G->nd; a++) {
+        M->inv_dx[a] = 1.0 / g->spacing[a];
+        M->gam[a] = calloc(N, sizeof(double));
+        if (!M->gam[a]) {
+            free(lr);
+            medium_free(M);
+            return -7;
+        }
+    }
+    if (rho) {
+        long nphys = G->n[0] * G->n[1] * G->n[2];
+        for (long i = 0; i < nphys; i++)
+            if (!(rho[i] > 0.0) || !isfinite(rho[i])) {
+                free(lr);
+                medium_free(M);
+                return -1;
+            }
+        oracle_pad(g, rho, lr);
+        for (long p = 0; p < N; p++)
+            lr[p] = log(lr[p]);
+        for (int a = 0; a < G->nd; a++) {
+#pragma omp parallel for
+            for (long i0 = 0; i0 < G->np[0]; i0++)
+                for (long i1 = 0; i1 < G->np[1]; i1++)
+                    for (long i2 = 0; i2 < G->np[2]; i2++) {
+                        long ii[3] = {i0, i1, i2};
+                        long p = pidx(G, i0, i1, i2);
+                        double s = 0.0;
+                        for (int j = 1; j <= G->r; j++) {
+                            long ip = clampl(ii[a] + j, 0, G->np[a] - 1) - ii[a];
+                            long im = clampl(ii[a] - j, 0, G->np[a] - 1) - ii[a];
+                            s += M->d[j] * (lr[p + ip * G->st[a]] - lr[p + im * G->st[a]]);
+                        }
+                        M->gam[a][p] = -s * M->inv_dx[a];
+                    }
+        }
+    }
+    free(lr);
+    return 0;
+}
+
+/* sum_a gamma_a D_a u at one point (u is zero beyond the padded array). */
+static double density_term_at(const geo_t *G, const medium_t *M, const double *u,
+                              long i0, long i1, long i2)
+{
+    long ii[3] = {i0, i1, i2};
+    long p = pidx(G, i0, i1, i2);
+    double total = 0.0;
+    for (int a = 0; a < G->nd; a++) {
+        double s = 0.0;
+        for (int j = 1; j <= G->r; j++) {
+            double up = (ii[a] + j < G->np[a]) ? u[p + j * G->st[a]] : 0.0;
+            double um = (ii[a] - j >= 0) ? u[p - j * G->st[a]] : 0.0;
+            s += M->d[j] * (up - um);
+        }
+        total += M->gam[a][p] * s * M->inv_dx[a];
+    }
+    return total;
+}
+
+int oracle_medium_operator(const oracle_grid_t *g, const double *rho, const double *u,
+                           double *out)
+{
+    geo_t G;
+    if (make_geo(g, &G) != 0)
+        return -1;
+    medium_t M;
+    int rc = medium_init(&M, g, &G, rho);
+    if (rc != 0)
+        return rc;
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G.np[0]; i0++)
+        for (long i1 = 0; i1 < G.np[1]; i1++)
+            for (long i2 = 0; i2 < G.np[2]; i2++)
+                out[pidx(&G, i0, i1, i2)] =
+                    lap_at(&G, u, i0, i1, i2) + density_term_at(&G, &M, u, i0, i1, i2);
+    medium_free(&M);
+    return 0;
+}
+
+int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double *rho,
+                          const double *alpha0, int att_power,
+                          int nsrc, const double *src_xyz, const double *wavelet,
+                          int nrec, const double *rec_xyz, double *traces)
+{
+    if (!g || time_order_of(g) != 2 || (att_power != 0 && att_power != 2))
+        return -1;
+    solve_t S;
+    int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
+    if (rc != 0)
+        return rc;
+    const geo_t *G = &S.G;
+    long N = G->N;
+    int nt = g->nt;
+    double dt = g->dt;
+    medium_t M;
+    if ((rc = medium_init(&M, g, G, rho)) != 0) {
+        solve_free(&S);
+        return rc;
+    }
+    double *beta = calloc(N, sizeof(double));
+    double *up = calloc(N, sizeof(double)), *uc = calloc(N, sizeof(double));
+    double *un = calloc(N, sizeof(double)), *src = calloc(N, sizeof(double));
+    double *al = calloc(N, sizeof(double));
+    if (!beta || !up || !uc || !un || !src || !al) {
+        free(beta); free(up); free(uc); free(un); free(src); free(al);
+        medium_free(&M);
+        solve_free(&S);
+        return -7;
+    }
+    if (alpha0) {
+        long nphys = G->n[0] * G->n[1] * G->n[2];
+        for (long i = 0; i < nphys; i++)
+            if (!(alpha0[i] >= 0.0) || !isfinite(alpha0[i])) {
+                rc = -1;
+                break;
+            }
+        if (rc == 0) {
+            oracle_pad(g, alpha0, al);
+            /* y = 0: eta += 2 alpha0 vp (a and b rebuilt); y = 2: beta = 2 alpha0 vp / dt */
+            double *eta = calloc(N, sizeof(double));
+            if (!eta) {
+                rc = -7;
+            } else {
+                oracle_eta(g, eta);
+                for (long p = 0; p < N; p++) {
+                    if (att_power == 0) {
+                        double e = eta[p] + 2.0 * al[p] * S.vpp[p];
+                        S.a[p] = 1.0 / (1.0 + e * dt / 2.0);
+                        S.b[p] = (1.0 - e * dt / 2.0) * S.a[p];
+                    } else {
+                        beta[p] = 2.0 * al[p] * S.vpp[p] / dt;
+                    }
+                }
+                free(eta);
+            }
+        }
+    }
+    for (int n = 0; n < nt && rc == 0; n++) {
+        for (int r = 0; r < nrec; r++)
+            traces[(long)r * nt + n] = sample(&S, S.ridx, S.rw, r, uc);
+        if (n == nt - 1)
+            break;
+        source_term(&S, wavelet, nt, n, src);
+#pragma omp parallel for
+        for (long i0 = 0; i0 < G->np[0]; i0++)
+            for (long i1 = 0; i1 < G->np[1]; i1++)
+                for (long i2 = 0; i2 < G->np[2]; i2++) {
+                    long p = pidx(G, i0, i1, i2);
+                    double lap = lap_at(G, uc, i0, i1, i2);
+                    double v = lap + density_term_at(G, &M, uc, i0, i1, i2) + src[p];
+                    if (att_power == 2)
+                        v += beta[p] * (lap - lap_at(G, up, i0, i1, i2));
+                    un[p] = S.a[p] * (2.0 * uc[p] + S.k[p] * v) - S.b[p] * up[p];
+                }
+        double *tmp = up;
+        up = uc;
+        uc = un;
+        un = tmp;
+    }
+    free(beta); free(up); free(uc); free(un); free(src); free(al);
+    medium_free(&M);
+    solve_free(&S);
     return rc;
 }

@@ -56,7 +56,7 @@ typedef struct {
     double dt;           /* seconds */
     int nt;              /* number of time samples */
     int time_order;      /* 2 (leapfrog) or 4 (leapfrog with the modified-equation
-                            correction; forward only); 0 means 2 */
+                            correction); 0 means 2 */
 } oracle_grid_t;
 
 /* Central second-derivative weights c[0..order/2]. */
@@ -121,6 +121,38 @@ int oracle_gradient(const oracle_grid_t *g, const double *vp,
                     double *traces_out, double *misfit, double *dvp, int seg);
 
 /* Number of OpenMP threads the oracle will use. */
+/* Centred first-derivative weights d[1..r] of the (2r+1)-point antisymmetric
+ * stencil exact on polynomials of degree <= 2r: du/dx ~ sum_j d_j (u_{+j} - u_{-j}) / dx. */
+int oracle_fd1_weights(int space_order, double *d);
+
+/* Heterogeneous medium (Sec. 2.4 acoustic equation with variable density and
+ * power-law attenuation of exponent y = 0 or 2):
+ *   (1/vp^2) p_tt = rho div(rho^{-1} grad p) + eta d/dt (-lap)^{y/2} p + s,
+ *   eta = -2 alpha0 vp^{y-1}.
+ * Discretisation (readings):
+ *   rho div(rho^{-1} grad p) = lap p - grad(ln rho) . grad p, written
+ *     L u + sum_a gamma_a D_a u with gamma_a = -D_a ln(rho_pad) and D_a the
+ *     centred first derivative of the stencil's order; rho is edge-replicated
+ *     into the sponge like vp, and ln rho beyond the padded array repeats its
+ *     edge value (so gamma is the derivative of a field that is constant outward);
+ *   y = 0: the term is -2 alpha0 vp^{-1} p_t, a damping that adds 2 alpha0 vp to
+ *     the sponge's eta in the same centred form (a, b);
+ *   y = 2: the term is 2 alpha0 vp dt(lap p); with k = dt^2 vp^2 it enters the
+ *     update as k beta (L u^n - L u^{n-1}), beta = 2 alpha0 vp / dt (a backward
+ *     difference, which keeps the step explicit);
+ *   u^{n+1} = a (2 u^n + k (L u^n + sum_a gamma_a D_a u^n + S^n [+ beta (L u^n - L u^{n-1})]))
+ *             - b u^{n-1}.
+ * alpha0 is in Np/m for y = 0 and Np/m/(rad/s)^2 for y = 2 (amplitude decay
+ * exp(-alpha0 omega^y r)).  rho (NULL = 1) and alpha0 (NULL = 0) are physical
+ * arrays; rho must be positive and alpha0 non-negative.  Second-order time only
+ * (time_order 4 returns -1), forward only. */
+int oracle_medium_operator(const oracle_grid_t *g, const double *rho, const double *u,
+                           double *out);
+int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double *rho,
+                          const double *alpha0, int att_power,
+                          int nsrc, const double *src_xyz, const double *wavelet,
+                          int nrec, const double *rec_xyz, double *traces);
+
 int oracle_num_threads(void);
 
 #ifdef __cplusplus

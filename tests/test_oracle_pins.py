@@ -511,3 +511,170 @@ def test_sponge_reflection_is_small(nb, bound):
     ref = oracle.forward(gb, np.full((400, 400), c), srcb, wav, recb)[0]
     refl = np.max(np.abs(tr - ref)) / np.max(np.abs(ref))
     assert refl < bound, refl
+
+
+# ------------------------------------- heterogeneous medium (density, attenuation)
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8, 10])
+def test_fd1_weights_exact(order):
+    """Centred first-derivative weights solve the Taylor moment conditions of
+    the antisymmetric stencil: 2 sum_j d_j j = 1 and sum_j d_j j^p = 0 for odd
+    p = 3 .. 2r-1 (solved here with exact rationals)."""
+    r = order // 2
+    A = [[Fraction(2 * j ** p) for j in range(1, r + 1)] for p in range(1, 2 * r, 2)]
+    b = [Fraction(1)] + [Fraction(0)] * (r - 1)
+    for i in range(r):                       # Gauss-Jordan over the rationals
+        piv = next(k for k in range(i, r) if A[k][i] != 0)
+        A[i], A[piv], b[i], b[piv] = A[piv], A[i], b[piv], b[i]
+        for k in range(r):
+            if k != i and A[k][i] != 0:
+                f = A[k][i] / A[i][i]
+                A[k] = [x - f * y for x, y in zip(A[k], A[i])]
+                b[k] -= f * b[i]
+    exact = [float(b[i] / A[i][i]) for i in range(r)]
+    d = oracle.fd1_weights(order)
+    assert d[0] == 0.0
+    np.testing.assert_allclose(d[1:], exact, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_medium_operator_exact_for_exponential_density(ndim):
+    """rho = exp(c . x): rho div(rho^-1 grad p) = lap p - c . grad p, which the
+    discrete operator reproduces exactly for polynomials of degree <= order
+    (L and D are both exact there, and D ln rho = c), away from the array edge."""
+    order = 8
+    r = order // 2
+    shape = (26, 24) if ndim == 2 else (18, 17, 16)
+    dx = (0.5, 0.7, 0.6)[:ndim]
+    g = oracle.Grid(shape=shape, spacing=dx, space_order=order, nb=0, vref=0.0, dt=1e-7, nt=2)
+    cvec = np.array([0.3, -0.2, 0.25])[:ndim]
+    X = np.meshgrid(*[np.arange(n) * h for n, h in zip(shape, dx)], indexing="ij")
+    rho = np.exp(sum(ci * xi for ci, xi in zip(cvec, X)))
+    # p = x0^3 x1^2 (+ x2^4 in 3D): degree per axis within the stencil's exactness
+    p = X[0] ** 3 * X[1] ** 2 + (X[2] ** 4 if ndim == 3 else 0.0)
+    lap = 6 * X[0] * X[1] ** 2 + 2 * X[0] ** 3 + (12 * X[2] ** 2 if ndim == 3 else 0.0)
+    grad = [3 * X[0] ** 2 * X[1] ** 2, 2 * X[0] ** 3 * X[1]] + ([4 * X[2] ** 3] if ndim == 3 else [])
+    want = lap - sum(ci * gi for ci, gi in zip(cvec, grad))
+    got = oracle.medium_operator(g, rho, p)
+    inner = tuple(slice(r, n - r) for n in shape)
+    scale = np.abs(want[inner]).max()
+    np.testing.assert_allclose(got[inner], want[inner], rtol=0, atol=1e-9 * scale)
+    # without the density term the same field misses -c . grad p
+    plain = oracle.laplacian(g, p)
+    assert np.abs(plain[inner] - want[inner]).max() > 1e-3 * scale
+
+
+@pytest.mark.parametrize("att_power", [0, 2])
+def test_medium_reduces_to_the_plain_scheme(att_power):
+    """Constant density (any value) and alpha0 = 0: the same traces, bit for bit."""
+    w = W.tiny_2d()
+    g = oracle.Grid(**w.grid_kwargs())
+    ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    got = oracle.forward_medium(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz,
+                                rho=np.full(w.shape, 1732.0), alpha0=np.zeros(w.shape),
+                                att_power=att_power)
+    np.testing.assert_array_equal(got, ref)
+
+
+def _attenuation_run(att_power, alpha0):
+    """2D homogeneous medium, receiver 20 mm from a point source; traces with
+    and without attenuation."""
+    c, dx, f0 = 1500.0, 2e-4, 5e5
+    n, rc = 300, 100
+    dt = 0.3 * dx / c
+    nt = int((rc * dx / c + 8e-6) / dt)
+    g = oracle.Grid(shape=(n, n), spacing=dx, space_order=8, nb=20, vref=c, dt=dt, nt=nt)
+    vp = np.full((n, n), c)
+    src = np.array([[150 * dx, 150 * dx]])
+    rec = np.array([[(150 + rc) * dx, 150 * dx]])
+    wav = W.tone_burst(nt, dt, f0=f0, nsrc=1, dtype=np.float64)
+    p0 = oracle.forward_medium(g, vp, src, wav, rec)
+    p1 = oracle.forward_medium(g, vp, src, wav, rec, alpha0=np.full((n, n), alpha0),
+                               att_power=att_power)
+    t = np.arange(nt) * dt
+    spec = lambda tr, f: abs(np.sum(tr * np.exp(-2j * np.pi * f * t)))
+    return [(f, spec(p1[0], f) / spec(p0[0], f)) for f in np.array([0.7, 0.85, 1.0, 1.15, 1.3]) * f0], rc * dx
+
+
+def test_attenuation_y0_decays_as_exp_minus_alpha0_r():
+    """y = 0: the amplitude spectrum decays by exp(-alpha0 r) at every frequency
+    of the band (the telegraph equation's decay, to first order in alpha0 c/omega)."""
+    alpha0 = 20.0   # Np/m
+    ratios, r = _attenuation_run(0, alpha0)
+    for f, q in ratios:
+        assert abs(q / np.exp(-alpha0 * r) - 1) < 5e-3, (f, q)
+
+
+def test_attenuation_y2_decays_as_exp_minus_alpha0_omega2_r():
+    """y = 2: the decay is exp(-alpha0 omega^2 r), so it steepens across the band."""
+    f0 = 5e5
+    alpha0 = 20.0 / (2 * np.pi * f0) ** 2
+    ratios, r = _attenuation_run(2, alpha0)
+    for f, q in ratios:
+        assert abs(q / np.exp(-alpha0 * (2 * np.pi * f) ** 2 * r) - 1) < 1e-2, (f, q)
+    assert ratios[0][1] > ratios[2][1] + 0.1 > ratios[4][1] + 0.2
+
+
+def test_density_interface_reflects_and_transmits_by_impedance():
+    """A density step at equal speed reflects with R = (rho2 - rho1)/(rho2 + rho1)
+    and transmits T = 1 + R at every angle, so the reflected wave is R times the
+    field of the image source and the transmitted one T times the direct field."""
+    c, dx, f0 = 1500.0, 2e-4, 2.5e5
+    n, i_s, d, s = 360, 130, 60, 20
+    dt = 0.3 * dx / c
+    nt = int(((2 * d - s) * dx / c + 3.5 / f0 + 4e-6) / dt)
+    g = oracle.Grid(shape=(n, n), spacing=dx, space_order=8, nb=20, vref=c, dt=dt, nt=nt)
+    vp = np.full((n, n), c)
+    rho1, rho2 = 1000.0, 2000.0
+    rho = np.full((n, n), rho1)
+    rho[i_s + d:, :] = rho2                     # interface half a cell before row i_s + d
+    src = np.array([[i_s * dx, 180 * dx]])
+    rec = np.array([[(i_s + s) * dx, 180 * dx],                  # between source and interface
+                    [(i_s + 2 * d - 1 - s) * dx, 180 * dx],      # image-source distance
+                    [(i_s + d + 40) * dx, 180 * dx]])            # beyond the interface
+    wav = W.tone_burst(nt, dt, f0=f0, nsrc=1, dtype=np.float64)
+    A = oracle.forward_medium(g, vp, src, wav, rec, rho=rho)
+    B = oracle.forward_medium(g, vp, src, wav, rec)
+    R = (rho2 - rho1) / (rho2 + rho1)
+    refl = A[0] - B[0]
+    assert np.linalg.norm(refl - R * B[1]) <= 0.03 * np.linalg.norm(R * B[1])
+    assert np.linalg.norm(A[2] - (1 + R) * B[2]) <= 0.01 * np.linalg.norm((1 + R) * B[2])
+
+
+def test_y2_attenuation_stability_limit():
+    """The backward-differenced viscous term moves the stability limit to
+    theta (1 + 2 beta) <= 4 (theta = k lambda_max): with beta = 1, bounded at
+    Courant number 1.10 and growing at 1.25, both below leapfrog's 2."""
+    w = W.tiny_2d(n=(60, 60), nb=0)
+    vmax = float(w.vp.max())
+    c = oracle.fd_weights(8)
+    lam = -(c[0] + 2 * sum(c[j] * (-1) ** j for j in range(1, 5)))   # Nyquist symbol of one axis
+
+    def late_over_early(courant):
+        dt = courant / (vmax * np.sqrt(lam * 2 / w.spacing ** 2))
+        nt = 600
+        g = oracle.Grid(shape=w.shape, spacing=w.spacing, space_order=8, nb=0, vref=0.0, dt=dt, nt=nt)
+        vpc = np.full(w.shape, vmax)
+        alpha0 = 1.0 * dt / (2 * vmax)          # beta = 2 alpha0 vp / dt = 1
+        wav = W.tone_burst(nt, dt, f0=1.0e6, dtype=np.float64)
+        tr = oracle.forward_medium(g, vpc, w.src_xyz[:1], wav, w.rec_xyz,
+                                   alpha0=np.full(w.shape, alpha0), att_power=2)
+        return np.abs(tr[:, -100:]).max() / np.abs(tr[:, :200]).max()
+
+    assert late_over_early(1.10) < 1.0
+    assert late_over_early(1.25) > 1e6
+
+
+def test_medium_rejects_bad_values():
+    w = W.tiny_2d(nt=10)
+    g = oracle.Grid(**w.grid_kwargs())
+    args = (g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    with pytest.raises(oracle.OracleError):
+        oracle.forward_medium(*args, rho=np.full(w.shape, -1.0))
+    with pytest.raises(oracle.OracleError):
+        oracle.forward_medium(*args, alpha0=np.full(w.shape, -1.0))
+    with pytest.raises(oracle.OracleError):
+        oracle.forward_medium(*args, att_power=1)
+    g4 = oracle.Grid(**w.grid_kwargs(), time_order=4)
+    with pytest.raises(oracle.OracleError):
+        oracle.forward_medium(g4, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
