@@ -66,7 +66,9 @@ enum {
     STRIDE_E_NONFINITE = -6    /* non-finite values detected */
 };
 
-enum { STRIDE_MODE_FORWARD = 0, STRIDE_MODE_GRADIENT = 1 };
+/* Workspace modes: FORWARD (stride_plan_forward), GRADIENT (gradients,
+ * forward_save/backward, the engine), FORWARD_MEDIUM (stride_plan_forward_medium). */
+enum { STRIDE_MODE_FORWARD = 0, STRIDE_MODE_GRADIENT = 1, STRIDE_MODE_FORWARD_MEDIUM = 2 };
 
 /* Physical grid, stencil, sponge and time axis of a solve. */
 typedef struct stride_grid {
@@ -84,8 +86,10 @@ typedef struct stride_grid {
                                p       = k (L u^n + St^n),
                                St^n    = (S^{n-1} + 10 S^n + S^{n+1}) / 12,
                                u^{n+1} = a (2 u^n + p + (k/12) L p) - b u^{n-1};
-                             stable up to sqrt(3) times the leapfrog CFL limit;
-                             forward solves only (gradient calls return INVALID_ARG) */
+                             stable up to sqrt(3) times the leapfrog CFL limit.
+                             Forward solves, gradients and stride_backward's dvp; the
+                             wavelet gradient (dwavelet) and the batching engine
+                             return INVALID_ARG for it */
 } stride_grid_t;
 
 /* A plan: the validated grid plus the source/receiver tap tables of one shot
@@ -109,7 +113,8 @@ int stride_plan_padded_shape(const stride_plan_t* plan, int64_t out[3]);
  * (Griewank-Walther revolve) with as many snapshots as fit, and 0 asks for the
  * size that keeps every state (no recomputation).  The snapshot count a solve
  * uses is derived from the ws_bytes it is given.  Errors: INVALID_ARG,
- * WORKSPACE (budget below the minimum of 8 wavefields plus traces). */
+ * WORKSPACE (budget below the minimum of 8 wavefields plus traces; 10 with
+ * time_order 4).  FORWARD_MEDIUM ignores budget_bytes and needs time_order 2. */
 int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budget_bytes,
                            size_t* out_bytes);
 
@@ -119,6 +124,29 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
  * synchronises the stream once.  Errors: INVALID_ARG, CFL, WORKSPACE, HIP. */
 int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float* wavelet,
                         float* traces, void* ws, size_t ws_bytes, void* stream);
+
+/* Forward solve in a heterogeneous medium (Sec. 2.4 acoustic equation with
+ * variable density and power-law attenuation, y = att_power in {0, 2}):
+ *   (1/vp^2) p_tt = rho div(rho^{-1} grad p) + eta d/dt (-lap)^{y/2} p + s,
+ *   eta = -2 alpha0 vp^{y-1},
+ * discretised as
+ *   u^{n+1} = a (2 u^n + k (L u^n + sum_a gamma_a D_a u^n + S^n
+ *                           [+ beta (L u^n - L u^{n-1})  if y = 2])) - b u^{n-1},
+ * gamma_a = -D_a ln rho (D_a the centred first derivative of the stencil's
+ * order; rho edge-replicated into the sponge, ln rho constant beyond the padded
+ * array), beta = 2 alpha0 vp / dt; for y = 0 the damping of a and b becomes
+ * the sponge's eta + 2 alpha0 vp.  alpha0 is in Np/m (y = 0) or
+ * Np/m/(rad/s)^2 (y = 2): amplitudes decay as exp(-alpha0 omega^y r).
+ * vp, rho and alpha0 are device arrays of the physical shape; rho NULL means
+ * constant density, alpha0 NULL no attenuation.  rho must be positive and
+ * finite, alpha0 non-negative and finite.  Stability: with y = 2 the limit
+ * becomes dt sqrt(max vp^2 (1 + 2 beta)) sqrt(lambda sum 1/dx^2) <= 2 (checked
+ * on the device, one stream sync).  time_order must be 2.  ws: FORWARD_MEDIUM
+ * bytes (k, three wavefields, ndim + 1 medium fields).  Forward only.  Errors:
+ * INVALID_ARG, CFL, WORKSPACE, HIP. */
+int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const float* rho,
+                               const float* alpha0, int32_t att_power, const float* wavelet,
+                               float* traces, void* ws, size_t ws_bytes, void* stream);
 
 /* Forward solve that also keeps the checkpoints of the forward wavefield in
  * ws (GRADIENT-sized) for a later stride_backward with the same ws, vp and

@@ -12,6 +12,7 @@ Layers:
 from ._abi import (  # noqa: F401
     LIB_PATH,
     STRIDE_MODE_FORWARD,
+    STRIDE_MODE_FORWARD_MEDIUM,
     STRIDE_MODE_GRADIENT,
     Plan,
     StrideError,
@@ -24,6 +25,7 @@ from ._abi import (  # noqa: F401
     stride_plan_create,
     stride_plan_destroy,
     stride_plan_forward,
+    stride_plan_forward_medium,
     stride_plan_gradient,
     stride_plan_padded_shape,
     stride_schedule_info,

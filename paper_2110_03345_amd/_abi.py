@@ -24,10 +24,12 @@ STRIDE_E_HIP = -5
 STRIDE_E_NONFINITE = -6
 STRIDE_MODE_FORWARD = 0
 STRIDE_MODE_GRADIENT = 1
+STRIDE_MODE_FORWARD_MEDIUM = 2
 
 EXPORTS = (
     "stride_plan_create", "stride_plan_destroy", "stride_plan_padded_shape",
-    "stride_workspace_bytes", "stride_plan_forward", "stride_forward_save", "stride_backward",
+    "stride_workspace_bytes", "stride_plan_forward", "stride_plan_forward_medium",
+    "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
     "stride_schedule_info", "stride_last_error", "stride_error_string",
     "stride_timing_enable", "stride_timing_read",
@@ -76,6 +78,7 @@ def lib():
         L.stride_plan_padded_shape.argtypes = [vp_, ctypes.POINTER(ctypes.c_int64)]
         L.stride_workspace_bytes.argtypes = [vp_, i32, sz, ctypes.POINTER(sz)]
         L.stride_plan_forward.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_plan_forward_medium.argtypes = [vp_, vp_, vp_, vp_, i32, vp_, vp_, vp_, sz, vp_]
         L.stride_forward_save.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
         L.stride_backward.argtypes = [vp_, vp_, vp_, vp_, vp_, vp_, vp_, sz, vp_]
         L.stride_plan_gradient.argtypes = [vp_, vp_, vp_, vp_, vp_, vp_, vp_, vp_, sz, vp_]
@@ -218,6 +221,12 @@ def stride_timing_read():
 def stride_plan_forward(plan, vp, wavelet, traces, ws, stream=None):
     _check(lib().stride_plan_forward(plan, _dev(vp), _dev(wavelet), _dev(traces), _dev(ws),
                                      ws.numel(), _stream(stream)))
+
+
+def stride_plan_forward_medium(plan, vp, rho, alpha0, att_power, wavelet, traces, ws, stream=None):
+    _check(lib().stride_plan_forward_medium(plan, _dev(vp), _dev(rho), _dev(alpha0), int(att_power),
+                                            _dev(wavelet), _dev(traces), _dev(ws), ws.numel(),
+                                            _stream(stream)))
 
 
 def stride_forward_save(plan, vp, wavelet, traces, ws, stream=None):
@@ -365,6 +374,26 @@ class Plan:
         if ws is None:
             ws = self.workspace(STRIDE_MODE_FORWARD, device=vp.device)
         stride_plan_forward(self.handle, vp, wavelet, traces, ws, stream)
+        return traces
+
+    def forward_medium(self, vp, wavelet, rho=None, alpha0=None, att_power: int = 0, traces=None,
+                       ws=None, stream=None):
+        """Traces of a forward solve with variable density rho and power-law
+        attenuation alpha0 * omega^att_power (att_power 0 or 2); None = constant
+        density / no attenuation."""
+        import torch
+        self._vp(vp)
+        self._wavelet(wavelet)
+        for a, name in ((rho, "rho"), (alpha0, "alpha0")):
+            if a is not None:
+                _dev(a, self.shape, torch.float32, name)
+        if traces is None:
+            traces = torch.empty((self.nrec, self.nt), dtype=torch.float32, device=vp.device)
+        self._traces_like(traces, "traces")
+        if ws is None:
+            ws = self.workspace(STRIDE_MODE_FORWARD_MEDIUM, device=vp.device)
+        stride_plan_forward_medium(self.handle, vp, rho, alpha0, att_power, wavelet, traces, ws,
+                                   stream)
         return traces
 
     def gradient(self, vp, wavelet, observed, ws=None, budget_bytes: int = 0, traces=None,

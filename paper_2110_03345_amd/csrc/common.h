@@ -29,6 +29,7 @@ struct Dims {
 struct StencilCoef {
     float c0;
     float c[3][kMaxR + 1];
+    float d[3][kMaxR + 1];   // centred first-derivative weights / dx_axis (medium steps)
 };
 
 // Sponge: eta = sum_axes e[a] * depth_a^2, e[a] = eta_max_a / nb^2.
@@ -81,6 +82,11 @@ struct StepParams {
     const float* img_sig;
     int img_stride;
     SampleSet smp;    // sampling of A at `step`
+    // medium steps only: gamma_a = -D_a ln rho per axis, and the attenuation
+    // field (att_power 0: 2 alpha0 vp added to the damping; 2: beta = 2 alpha0 vp / dt)
+    const float* gam[3];
+    const float* att;
+    int att_power;
 };
 
 // One slot's step in a batched launch.
@@ -109,9 +115,12 @@ void tile_shape(int nd, bool adjoint, int* ry, int* waves);
 enum StepMode {
     kStep = 0,    // C = a (2 A + k (L A + S)) - b B                 (leapfrog step)
     kPrep = 1,    // C = k (L A + St), St: source filtered in time   (p of the corrected step)
-    kCorrect = 2  // C = a (2 D + A + (k/12) L A) - b B, A = p, D = u^n;
+    kCorrect = 2, // C = a (2 D + A + (k/12) L A) - b B, A = p, D = u^n;
                   // adjoint: C = a (2 D + A + (k/12) L A + k R^T g) - b B with A = q,
                   // D = w^{m+1}, and G += U (D + A/12) + (k/12) D L U with U = p
+    kMedium = 3   // forward step in a heterogeneous medium, B a stencil field too:
+                  // C = a (2 A + k (L A + sum_a gam_a D_a A + S [+ att (L A - L B)])) - b B,
+                  // with att added to the damping instead when att_power is 0
 };
 
 // Kernel launchers (stride_kernels.hip).
@@ -121,13 +130,31 @@ void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& 
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);
-// Launches of the fourth-order steps: forward kPrep or kCorrect, adjoint kCorrect.
+// Launches of the mode steps: forward kPrep, kCorrect or kMedium, adjoint kCorrect.
 void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                       const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s);
 
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s);
+// First-derivative weights in FP64 for the medium preparation.
+struct Fd1 {
+    double d[kMaxR + 1];
+    double inv_dx[3];
+    int r;
+};
+
+// Medium fields on the padded grid: gam[a] = -D_a ln rho_pad (rho NULL: zero;
+// ln rho repeats its edge value beyond the array) and att (alpha0 NULL: zero;
+// att_power 0: 2 alpha0 vp, 2: 2 alpha0 vp / dt), computed in FP64, rounded once.
+void launch_prep_medium(const Dims& d, const Fd1& fd, const float* vp, const float* rho,
+                        const float* alpha0, int att_power, double dt, float* const gam[3],
+                        float* att, hipStream_t s);
+// flags[2] = 1 if rho has a non-positive or non-finite value or alpha0 a negative
+// or non-finite one; flags[3] = max over points of vp^2 (1 + 2 beta) as float bits
+// (beta = 2 alpha0 vp / dt for att_power 2, else 0).
+void launch_medium_check(const float* vp, const float* rho, const float* alpha0, long long n,
+                         int att_power, double dt, unsigned* flags, hipStream_t s);
 // Misfit partial sums: kMisfitParts doubles of scratch.
 constexpr int kMisfitParts = 256;
 void launch_residual_misfit(const float* traces, const float* observed, float* residual,

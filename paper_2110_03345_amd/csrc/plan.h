@@ -17,6 +17,7 @@ struct stride_plan {
     int torder;          // 2 or 4
     stride::Dims dims;
     stride::StencilCoef cf;
+    stride::Fd1 fd1;     // first-derivative weights in FP64 (medium preparation)
     stride::SpongeCoef sp;
     stride::LaunchShape ls_fwd, ls_adj;
     double nyquist;      // -(c0 + 2 sum_j cj (-1)^j): largest eigenvalue of -L per axis
@@ -52,6 +53,7 @@ struct Layout {
     size_t traces;     // nrec * nt floats
     size_t fixed_fwd;  // scratch + k + 2 fields
     size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual (+ p, q)
+    size_t medium;     // scratch + k + 3 wavefields + ndim gamma fields + attenuation
 };
 
 Layout layout_of(const stride_plan& P);

@@ -61,6 +61,23 @@ bool fd_weights(int order, double* c)
     return false;
 }
 
+// Centred first-derivative weights d_1..d_r of the (2r+1)-point antisymmetric
+// stencil (exact rationals of the Taylor moment conditions).
+bool fd1_weights(int order, double* dw)
+{
+    if (order == 8) {
+        const double w[] = {0.0, 4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+        std::memcpy(dw, w, sizeof(w));
+        return true;
+    }
+    if (order == 10) {
+        const double w[] = {0.0, 5.0 / 6.0, -5.0 / 21.0, 5.0 / 84.0, -5.0 / 504.0, 1.0 / 1260.0};
+        std::memcpy(dw, w, sizeof(w));
+        return true;
+    }
+    return false;
+}
+
 LaunchShape make_shape(const Dims& d, int zc, int ry, int waves)
 {
     LaunchShape ls{};
@@ -263,6 +280,7 @@ Layout stride::layout_of(const stride_plan& P)
     L.fixed_fwd = L.scratch + (P.torder == 4 ? 4 : 3) * L.field;   // k, u, u (, p)
     // k, G, w, w, traces, residual (, p and q of the fourth-order adjoint)
     L.fixed_grad = L.scratch + (P.torder == 4 ? 6 : 4) * L.field + 2 * L.traces;
+    L.medium = L.scratch + (size_t)(4 + P.nd + 1) * L.field;
     return L;
 }
 
@@ -749,6 +767,92 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
     return STRIDE_OK;
 }
 
+// Forward solve in a heterogeneous medium: three rotating wavefields (the
+// step reads u^{n-1} as a stencil field, so u^{n+1} cannot overwrite it), the
+// medium fields prepared once, one kMedium launch per step on the two-field
+// launch shape (whose source table is src_img).
+int forward_medium(const stride_plan& P, const float* vp, const float* rho, const float* alpha0,
+                   int att_power, const float* wavelet, float* traces, void* ws, size_t bytes,
+                   hipStream_t s)
+{
+    if (!vp || (!wavelet && P.nsrc > 0) || (!traces && P.nrec > 0))
+        return fail(STRIDE_E_INVALID_ARG, "vp, wavelet and traces must be device pointers");
+    if (P.torder != 2)
+        return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
+    if (att_power != 0 && att_power != 2)
+        return fail(STRIDE_E_INVALID_ARG, "att_power must be 0 or 2 (got %d)", att_power);
+    Layout L = layout_of(P);
+    if (!ws || (uintptr_t)ws % 256)
+        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.medium)
+        return fail(STRIDE_E_WORKSPACE, "medium forward workspace needs %zu bytes (got %zu)",
+                    L.medium, bytes);
+    char* b = (char*)ws;
+    unsigned* flags = (unsigned*)b;
+    b += L.scratch;
+    float* k = (float*)b;
+    b += L.field;
+    float* u[3];
+    for (int i = 0; i < 3; ++i, b += L.field)
+        u[i] = (float*)b;
+    float* gam[3] = {nullptr, nullptr, nullptr};
+    for (int a = 0; a < P.nd; ++a, b += L.field)
+        gam[a] = (float*)b;
+    float* att = (float*)b;
+
+    long long nphys = 1;
+    for (int a = 0; a < P.nd; ++a)
+        nphys *= P.g.shape[a];
+    launch_vp_check(vp, nphys, flags, s);
+    launch_medium_check(vp, rho, alpha0, nphys, att_power, P.g.dt, flags, s);
+    unsigned host[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(host, flags, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (host[1])
+        return fail(STRIDE_E_INVALID_ARG, "vp contains non-positive or non-finite values");
+    if (host[2])
+        return fail(STRIDE_E_INVALID_ARG,
+                    "rho must be positive and finite, alpha0 non-negative and finite");
+    float vmax, veff2;
+    std::memcpy(&vmax, &host[0], sizeof(float));
+    std::memcpy(&veff2, &host[3], sizeof(float));
+    // with y = 2 the limit is on vp^2 (1 + 2 beta) (frozen coefficients)
+    int rc = check_cfl(P, std::max((double)vmax, std::sqrt((double)veff2)));
+    if (rc)
+        return rc;
+
+    launch_prep_k(P.dims, vp, P.g.dt, k, s);
+    launch_prep_medium(P.dims, P.fd1, vp, rho, alpha0, att_power, P.g.dt, gam, att, s);
+    launch_fill(u[0], P.dims.total, 0.f, s);
+    launch_fill(u[1], P.dims.total, 0.f, s);
+    int tid = g_timer.begin(s);
+    int cur = 0, prev = 1, next = 2;
+    for (int n = 0; n < P.nt - 1; ++n) {
+        StepParams p = base_params(P);
+        p.A = u[cur];
+        p.B = u[prev];
+        p.C = u[next];
+        p.K = k;
+        p.step = n;
+        p.inj = P.src_img;
+        p.inj_sig = wavelet;
+        p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+        for (int a = 0; a < 3; ++a)
+            p.gam[a] = gam[a] ? gam[a] : gam[0];
+        p.att = att;
+        p.att_power = att_power;
+        launch_step_mode(P.dims, P.R, false, kMedium, P.cf, P.sp, P.ls_adj, p, s);
+        const int t = prev;
+        prev = cur;
+        cur = next;
+        next = t;
+    }
+    g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
+    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
+    HIP_TRY(hipGetLastError());
+    return STRIDE_OK;
+}
+
 int forward_save(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
                  void* ws, size_t bytes, hipStream_t s, GradWs& W)
 {
@@ -898,6 +1002,14 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         P->cellvol *= grid->spacing[a];
     }
     P->cf.c0 = (float)c0;
+    std::memset(&P->fd1, 0, sizeof(P->fd1));
+    fd1_weights(grid->space_order, P->fd1.d);
+    P->fd1.r = P->R;
+    for (int a = 0; a < P->nd; ++a) {
+        P->fd1.inv_dx[a] = 1.0 / grid->spacing[a];
+        for (int j = 1; j <= P->R; ++j)
+            P->cf.d[a][j] = (float)(P->fd1.d[j] * P->fd1.inv_dx[a]);
+    }
     std::memset(&P->sp, 0, sizeof(P->sp));
     if (P->nb > 0 && grid->sponge_vref > 0)
         for (int a = 0; a < P->nd; ++a) {
@@ -1012,8 +1124,14 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
         *out_bytes = L.fixed_fwd;
         return STRIDE_OK;
     }
+    if (mode == STRIDE_MODE_FORWARD_MEDIUM) {
+        if (plan->torder != 2)
+            return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
+        *out_bytes = L.medium;
+        return STRIDE_OK;
+    }
     if (mode != STRIDE_MODE_GRADIENT)
-        return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD or GRADIENT");
+        return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD, GRADIENT or FORWARD_MEDIUM");
     long long nfields;
     if (budget_bytes == 0) {
         nfields = cached_schedule(plan->nt, plan->nt)->stats.peak_fields;
@@ -1041,6 +1159,17 @@ int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float*
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
     return forward_solve(*plan, vp, wavelet, traces, ws, ws_bytes, as_stream(stream));
+}
+
+int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const float* rho,
+                               const float* alpha0, int32_t att_power, const float* wavelet,
+                               float* traces, void* ws, size_t ws_bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    return forward_medium(*plan, vp, rho, alpha0, att_power, wavelet, traces, ws, ws_bytes,
+                          as_stream(stream));
 }
 
 int stride_forward_save(const stride_plan_t* plan, const float* vp, const float* wavelet,

@@ -212,7 +212,7 @@ __device__ __forceinline__ float tile_point_signal(const TileEntry* ent, TileEnt
 //   w^m = a (2 w^{m+1} + q + (k/12) L q + k inj) - b w^{m+2}.
 // uu: the point field D; bb, kk: B and k.
 template <bool ADJ, int MODE>
-constexpr bool kInjApart = ADJ && MODE == kCorrect;
+constexpr bool kInjApart = (ADJ && MODE == kCorrect) || MODE == kMedium;
 
 template <bool ADJ, int MODE>
 __device__ __forceinline__ float step_out(float ctr, float lap, float inj, float uu, float bb,
@@ -228,6 +228,21 @@ __device__ __forceinline__ float step_out(float ctr, float lap, float inj, float
             rhs = fmaf(kk, inj, rhs);
         return leapfrog(uu, bb, 1.f, rhs, eta, half_dt);
     }
+}
+
+// Output of a medium step.  lap = L u, dens = sum_a gamma_a D_a u, inj the
+// injected value, lapb = L u^{n-1}, prev = u^{n-1}; at is the attenuation
+// field: added to the damping (att_power 0) or weighting L u - L u^{n-1} (2).
+__device__ __forceinline__ float medium_out(float ctr, float lap, float dens, float inj,
+                                            float lapb, float prev, float kk, float at,
+                                            int att_power, float eta, float half_dt)
+{
+    float rhs = lap + dens + inj;
+    if (att_power == 2)
+        rhs = fmaf(at, lap - lapb, rhs);
+    else
+        eta += at;
+    return leapfrog(ctr, prev, kk, rhs, eta, half_dt);
 }
 
 // Imaging accumulator update of an adjoint launch.  Second order:
@@ -255,7 +270,8 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     constexpr int LW = kTileX + 2 * R;
     constexpr int LH = TY + 2 * R;
     constexpr int RW = (LH + WAVES - 1) / WAVES;    // tile rows loaded per wave
-    constexpr int NF = ADJ ? 2 : 1;                 // stencil fields A (and U)
+    constexpr bool MED = MODE == kMedium;
+    constexpr int NF = ADJ || MED ? 2 : 1;          // stencil fields A (and U, or B)
     __shared__ float sF[NF][LH * LW];
     __shared__ float sS[NF][TY * kTileX];           // injected signal per tile point
 
@@ -307,9 +323,10 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         ho[i] = rok && hin ? (gy * s0 + hcol) * 4 : -1;
     }
     float va[NF][RW], vh[NF][RW];
+    const float* F1 = ADJ ? p.U : p.B;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        const auto rf = plane_rsrc(f == 0 ? p.A : p.U, fbytes);
+        const auto rf = plane_rsrc(f == 0 ? p.A : F1, fbytes);
 #pragma unroll
         for (int i = 0; i < RW; ++i) {
             va[f][i] = bload(rf, ro[i]);
@@ -317,7 +334,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
     }
     int po[RY];
-    float bb[RY], kk[RY], gg[RY], uu[RY];
+    float bb[RY], kk[RY], gg[RY], uu[RY], mgy[RY], mgx[RY], mat[RY];
     {
         const auto rb = plane_rsrc(p.B, fbytes);
         const auto rk = plane_rsrc(p.K, fbytes);
@@ -327,11 +344,16 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
             const int gy = y0 + wy * RY + j;
             po[j] = xin && gy < n0 ? gy * s0 + gx : -1;
             const int bo = po[j] >= 0 ? po[j] * 4 : -1;
-            if constexpr (MODE != kPrep)
+            if constexpr (MODE != kPrep && !MED)
                 bb[j] = bload(rb, bo);
             kk[j] = bload(rk, bo);
             if constexpr (MODE == kCorrect)
                 uu[j] = bload(ru, bo);
+            if constexpr (MED) {
+                mgy[j] = bload(plane_rsrc(p.gam[0], fbytes), bo);
+                mgx[j] = bload(plane_rsrc(p.gam[1], fbytes), bo);
+                mat[j] = bload(plane_rsrc(p.att, fbytes), bo);
+            }
         }
         if constexpr (ADJ) {
             const auto rg = plane_rsrc(p.G, fbytes);
@@ -428,6 +450,19 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
         const int dyd = layer_depth(y0 + ly, n0, d.nb);
         const float eta = fmaf(sp.e[0], (float)(dyd * dyd), ex);
+        if constexpr (MED) {
+            float dy = 0.f, dx = 0.f;
+#pragma unroll
+            for (int q = R; q >= 1; --q) {
+                dy = fmaf(cf.d[0][q], SA[q * LW] - SA[-q * LW], dy);
+                dx = fmaf(cf.d[1][q], SA[q] - SA[-q], dx);
+            }
+            const float* SB = &sF[1][(ly + R) * LW + lx + R];
+            const float lapb = lap2d<R, LW>(SB, cf);
+            p.C[po[j]] = medium_out(ctr, lap, fmaf(mgy[j], dy, mgx[j] * dx), inj, lapb, SB[0], kk[j],
+                                    mat[j], p.att_power, eta, sp.half_dt);
+            continue;
+        }
         p.C[po[j]] = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
         if constexpr (ADJ) {
             const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
@@ -465,7 +500,8 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     constexpr int NXH = 2 * R * TY;                 // halo columns left/right
     constexpr int HY = (NYH + NT - 1) / NT;
     constexpr int HX = (NXH + NT - 1) / NT;
-    constexpr int NF = ADJ ? 2 : 1;                 // stencil fields: A (and U)
+    constexpr bool MED = MODE == kMedium;
+    constexpr int NF = ADJ || MED ? 2 : 1;          // stencil fields: A (and U, or B)
     constexpr int PLANE = LH * LW;
     constexpr int PL = TY * kTileX;                 // block-local points per plane
     __shared__ float sF[2][NF][PLANE];
@@ -493,7 +529,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     const int wy = tid >> 6;
     const int gx = x0 + lx;
     const bool xin = gx < n2;
-    const float* F[2] = {p.A, ADJ ? p.U : p.A};
+    const float* F[2] = {p.A, ADJ ? p.U : (MED ? p.B : p.A)};
 
     // plane-independent geometry: byte offsets within a plane (-1 = outside)
     const int plane_bytes = (int)(s0 * 4);
@@ -563,7 +599,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         }
 
     float pl[NF][RY], phy[NF][HY], phx[NF][HX];
-    float pb[RY], pk[RY], pg[RY], pu[RY];
+    float pb[RY], pk[RY], pg[RY], pu[RY], pm[4][RY];
     auto prefetch = [&](int z) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -583,9 +619,18 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         const auto rk = rsrc(p.K, z);
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            if constexpr (MODE != kPrep)
+            if constexpr (MODE != kPrep && !MED)
                 pb[j] = bload_stream(rb, rbo[j]);
             pk[j] = bload_stream(rk, rbo[j]);
+        }
+        if constexpr (MED) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const auto rm = rsrc(m < 3 ? p.gam[m] : p.att, z);
+#pragma unroll
+                for (int j = 0; j < RY; ++j)
+                    pm[m][j] = bload_stream(rm, rbo[j]);
+            }
         }
         if constexpr (MODE == kCorrect) {
             const auto ru = rsrc(p.D, z);
@@ -678,7 +723,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             const int z = zb + u;
             if (z >= z1)
                 return false;
-            float bb[RY], kk[RY], gg[RY], uu[RY];
+            float bb[RY], kk[RY], gg[RY], uu[RY], mm[4][RY];
             float* S = &sF[buf][0][0];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -699,10 +744,13 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             }
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
-                bb[j] = MODE != kPrep ? pb[j] : 0.f;
+                bb[j] = MODE != kPrep && !MED ? pb[j] : 0.f;
                 kk[j] = pk[j];
                 gg[j] = ADJ ? pg[j] : 0.f;
                 uu[j] = MODE == kCorrect ? pu[j] : 0.f;
+#pragma unroll
+                for (int m = 0; m < 4; ++m)
+                    mm[m][j] = MED ? pm[m][j] : 0.f;
             }
             if (z + 1 < z1)
                 prefetch(z + 1);
@@ -752,6 +800,26 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     sS[buf][0][ly * kTileX + lx] = 0.f;
                 }
                 const float eta = ez + ey[j];
+                if constexpr (MED) {
+                    const float* SB = S + PLANE;
+                    float dz = 0.f, dy = 0.f, dx = 0.f, bz = 0.f, by = 0.f, bx = 0.f;
+#pragma unroll
+                    for (int qq = R; qq >= 1; --qq) {
+                        dz = fmaf(cf.d[0][qq], q[0][j][(u + R + qq) % Q] - q[0][j][(u + R - qq) % Q], dz);
+                        dy = fmaf(cf.d[1][qq], SA[(ly + R + qq) * LW + lx + R] - SA[(ly + R - qq) * LW + lx + R], dy);
+                        dx = fmaf(cf.d[2][qq], SA[(ly + R) * LW + lx + R + qq] - SA[(ly + R) * LW + lx + R - qq], dx);
+                        bz = fmaf(cf.c[0][qq], q[1][j][(u + R + qq) % Q] + q[1][j][(u + R - qq) % Q], bz);
+                        by = fmaf(cf.c[1][qq], SB[(ly + R + qq) * LW + lx + R] + SB[(ly + R - qq) * LW + lx + R], by);
+                        bx = fmaf(cf.c[2][qq], SB[(ly + R) * LW + lx + R + qq] + SB[(ly + R) * LW + lx + R - qq], bx);
+                    }
+                    const float prev = q[1][j][slot_c];
+                    const float lapb = fmaf(cf.c0, prev, bz + by + bx);
+                    const float dens = fmaf(mm[0][j], dz, fmaf(mm[1][j], dy, mm[2][j] * dx));
+                    __builtin_nontemporal_store(medium_out(ctr, lap, dens, inj, lapb, prev, kk[j], mm[3][j],
+                                                           p.att_power, eta, sp.half_dt),
+                                                Cz + roff[j]);
+                    continue;
+                }
                 const float out = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
                 __builtin_nontemporal_store(out, Cz + roff[j]);
                 if constexpr (ADJ) {
@@ -878,6 +946,103 @@ __global__ void prep_k_kernel(Dims d, const float* vp, double dt, float* k)
         }
         double v = (double)vp[src];
         k[dst] = (float)(dt * dt * v * v);
+    }
+}
+
+// Medium fields on the padded grid (see launch_prep_medium).  The physical
+// index of any padded (or beyond-padded) coordinate is its clamp into the
+// physical grid, which is both the edge replication into the sponge and the
+// constant continuation of ln rho beyond the array.
+__device__ __forceinline__ long long phys_index(const Dims& d, const int c[3])
+{
+    long long src = 0;
+    for (int a = 0; a < 3; ++a) {
+        int pa = a < d.nd ? min(max(c[a] - d.nb, 0), d.phys[a] - 1) : 0;
+        src = src * d.phys[a] + pa;
+    }
+    return src;
+}
+
+__global__ void prep_medium_kernel(Dims d, Fd1 fd, const float* vp, const float* rho,
+                                   const float* alpha0, int att_power, double dt, float* g0,
+                                   float* g1, float* g2, float* att)
+{
+    const long long npts = (long long)d.n[0] * d.n[1] * d.n[2];
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    float* gam[3] = {g0, g1, g2};
+    for (; i < npts; i += stride) {
+        int c[3];
+        long long r = i;
+        for (int a = 2; a >= 0; --a) {
+            c[a] = (int)(r % d.n[a]);
+            r /= d.n[a];
+        }
+        long long dst = 0;
+        for (int a = 0; a < d.nd; ++a)
+            dst += (long long)c[a] * d.st[a];
+        const long long src = phys_index(d, c);
+        for (int a = 0; a < d.nd; ++a) {
+            double sum = 0.0;
+            if (rho) {
+                for (int j = 1; j <= fd.r; ++j) {
+                    int cp[3] = {c[0], c[1], c[2]}, cm[3] = {c[0], c[1], c[2]};
+                    cp[a] += j;
+                    cm[a] -= j;
+                    sum += fd.d[j] * (log((double)rho[phys_index(d, cp)]) -
+                                      log((double)rho[phys_index(d, cm)]));
+                }
+            }
+            gam[a][dst] = (float)(-sum * fd.inv_dx[a]);
+        }
+        double at = 0.0;
+        if (alpha0) {
+            at = 2.0 * (double)alpha0[src] * (double)vp[src];
+            if (att_power == 2)
+                at /= dt;
+        }
+        att[dst] = (float)at;
+    }
+}
+
+// Value checks of rho and alpha0, and max vp^2 (1 + 2 beta) for the stability
+// limit of the y = 2 term (see launch_medium_check).
+__global__ void medium_check_kernel(const float* vp, const float* rho, const float* alpha0,
+                                    long long n, int att_power, double dt, unsigned* flags)
+{
+    __shared__ unsigned smax, sbad;
+    if (threadIdx.x == 0) {
+        smax = 0u;
+        sbad = 0u;
+    }
+    __syncthreads();
+    unsigned m = 0u, bad = 0u;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) {
+        if (rho && !(rho[i] > 0.f && isfinite(rho[i])))
+            bad = 1u;
+        double beta = 0.0;
+        if (alpha0) {
+            const float al = alpha0[i];
+            if (!(al >= 0.f && isfinite(al)))
+                bad = 1u;
+            else if (att_power == 2)
+                beta = 2.0 * (double)al * (double)vp[i] / dt;
+        }
+        const double v = (double)vp[i];
+        const float e = (float)(v * v * (1.0 + 2.0 * beta));
+        if (e >= 0.f && isfinite(e))
+            m = max(m, __float_as_uint(e));
+        else
+            bad = 1u;
+    }
+    atomicMax(&smax, m);
+    atomicOr(&sbad, bad);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        atomicMax(&flags[3], smax);
+        atomicOr(&flags[2], sbad);
     }
 }
 
@@ -1088,6 +1253,9 @@ void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const Stenci
     if (adjoint)   // the adjoint of the fourth-order step runs kCorrect only
         R == 4 ? launch_step_t<4, true, kCorrect>(d, cf, sp, ls, p, s)
                : launch_step_t<5, true, kCorrect>(d, cf, sp, ls, p, s);
+    else if (mode == kMedium)
+        R == 4 ? launch_step_t<4, false, kMedium>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, false, kMedium>(d, cf, sp, ls, p, s);
     else if (mode == kPrep)
         R == 4 ? launch_step_t<4, false, kPrep>(d, cf, sp, ls, p, s)
                : launch_step_t<5, false, kPrep>(d, cf, sp, ls, p, s);
@@ -1153,6 +1321,23 @@ void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t 
     launch_fill(reinterpret_cast<float*>(flags), 2, 0.f, s);
     hipLaunchKernelGGL(vp_check_kernel, dim3(grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024),
                        dim3(256), 0, s, vp, n, flags);
+}
+
+void launch_prep_medium(const Dims& d, const Fd1& fd, const float* vp, const float* rho,
+                        const float* alpha0, int att_power, double dt, float* const gam[3],
+                        float* att, hipStream_t s)
+{
+    long long n = (long long)d.n[0] * d.n[1] * d.n[2];
+    hipLaunchKernelGGL(prep_medium_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, d, fd, vp, rho,
+                       alpha0, att_power, dt, gam[0], gam[1], d.nd == 3 ? gam[2] : gam[1], att);
+}
+
+void launch_medium_check(const float* vp, const float* rho, const float* alpha0, long long n,
+                         int att_power, double dt, unsigned* flags, hipStream_t s)
+{
+    launch_fill(reinterpret_cast<float*>(flags + 2), 2, 0.f, s);
+    hipLaunchKernelGGL(medium_check_kernel, dim3(grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024),
+                       dim3(256), 0, s, vp, rho, alpha0, n, att_power, dt, flags);
 }
 
 void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s)

@@ -117,6 +117,19 @@ def test_fourth_order_workspace_and_refusals():
         S.stride_workspace_query(g3, 1, 3, S.STRIDE_MODE_FORWARD)
 
 
+def test_medium_workspace_size():
+    """FORWARD_MEDIUM: k, three wavefields, ndim density-gradient fields and the
+    attenuation field; refused for fourth-order time."""
+    g = _grid(nt=20)
+    field = -(-(52 * 64 * 4) // 256) * 256
+    scratch = 256 + 256 * 8
+    assert S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_FORWARD_MEDIUM) == scratch + 7 * field
+    g.time_order = 4
+    with pytest.raises(S.StrideError) as e:
+        S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_FORWARD_MEDIUM)
+    assert e.value.code == _abi.STRIDE_E_INVALID_ARG
+
+
 @lru_cache(None)
 def _dp(l, s):
     """Brute-force minimal forward steps to reverse l steps with s free slots."""

@@ -1,0 +1,151 @@
+"""Heterogeneous medium (variable density, power-law attenuation y = 0 and 2):
+HIP forward traces against the FP64 oracle's in 2D and 3D, orders 8 and 10,
+ragged shapes, and at the benchmark grids; the constant medium against the
+plain forward; value, order and stability checks before any launch."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2110_03345_amd as S
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def _fields(w, seed, att_power):
+    """Smooth density 700-1900 kg/m^3 with a sharp inclusion, and attenuation
+    of up to about 60 Np/m at 500 kHz."""
+    rng = np.random.default_rng(seed)
+    from scipy.ndimage import gaussian_filter
+    n = gaussian_filter(rng.standard_normal(w.shape), 2.0)
+    n /= np.abs(n).max()
+    rho = 1300.0 + 600.0 * n
+    sl = tuple(slice(s // 3, s // 2) for s in w.shape)
+    rho[sl] = 1900.0
+    a = gaussian_filter(rng.standard_normal(w.shape), 2.0)
+    alpha = 30.0 * (1.0 + a / np.abs(a).max())
+    alpha0 = alpha / (2 * np.pi * 5e5) ** att_power
+    return rho, alpha0
+
+
+CASES = [
+    ("2d_o8", lambda: W.tiny_2d()),
+    ("2d_o10_ragged", lambda: W.tiny_2d(space_order=10, n=(83, 141), nb=7, nt=150)),
+    ("3d_o10", lambda: W.tiny_3d()),
+    ("3d_o8_ragged", lambda: W.tiny_3d(space_order=8, n=(37, 21, 70), nb=4, nt=70)),
+]
+
+
+@pytest.mark.parametrize("att_power", [0, 2])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_medium_forward_matches_oracle(name, make, att_power):
+    w = make()
+    rho, alpha0 = _fields(w, 3, att_power)
+    print(f"medium {name} y={att_power}: shape={w.shape} nt={w.nt}", flush=True)
+    g = oracle.Grid(**w.grid_kwargs())
+    ref = oracle.forward_medium(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, rho=rho, alpha0=alpha0,
+                                att_power=att_power)
+    plan = S.Plan.from_workload(w)
+    tr = plan.forward_medium(dev(w.vp), dev(w.wavelet), rho=dev(rho), alpha0=dev(alpha0),
+                             att_power=att_power).cpu().numpy()
+    plain = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    assert rel(plain, ref) > 1e-2            # the medium changes the traces
+    assert rel(tr, ref) < 1e-4, rel(tr, ref)
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_density_only_and_attenuation_only(maker):
+    w = maker()
+    rho, alpha0 = _fields(w, 5, 0)
+    g = oracle.Grid(**w.grid_kwargs())
+    plan = S.Plan.from_workload(w)
+    for kw in (dict(rho=rho), dict(alpha0=alpha0)):
+        ref = oracle.forward_medium(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, **kw)
+        tr = plan.forward_medium(dev(w.vp), dev(w.wavelet),
+                                 **{k: dev(v) for k, v in kw.items()}).cpu().numpy()
+        assert rel(tr, ref) < 1e-4, (list(kw), rel(tr, ref))
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_constant_medium_equals_the_plain_forward(maker):
+    w = maker()
+    plan = S.Plan.from_workload(w)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    a = plan.forward(vp, wav)
+    b = plan.forward_medium(vp, wav)
+    c = plan.forward_medium(vp, wav, rho=dev(np.full(w.shape, 1234.0)),
+                            alpha0=dev(np.zeros(w.shape)), att_power=2)
+    print("bitwise:", torch.equal(a, b), torch.equal(a, c), flush=True)
+    assert rel(b.cpu().numpy(), a.cpu().numpy().astype(np.float64)) < 1e-6
+    assert rel(c.cpu().numpy(), a.cpu().numpy().astype(np.float64)) < 1e-6
+
+
+def test_config2_grid_medium_matches_oracle():
+    """The benchmark's 2D grid (1104^2 padded) with the breast phantom's
+    density and attenuation, 500 steps."""
+    w = W.config2(nt=500)
+    rho, alpha0 = W.medium(w.vp, w.spacing, 7, att_power=2)
+    g = oracle.Grid(**w.grid_kwargs())
+    ref = oracle.forward_medium(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, rho=rho, alpha0=alpha0,
+                                att_power=2)
+    tr = S.Plan.from_workload(w).forward_medium(dev(w.vp), dev(w.wavelet), rho=dev(rho),
+                                                alpha0=dev(alpha0), att_power=2).cpu().numpy()
+    assert rel(tr, ref) < 1e-4, rel(tr, ref)
+
+
+def test_config4_grid_medium_matches_oracle():
+    """The benchmark's 3D grid (316^3 padded) with the head phantom's skull
+    density and attenuation, 30 steps (receivers sampled where the wave has
+    arrived: the whole trace set is compared)."""
+    w = W.config4(nt=30)
+    rho, alpha0 = W.medium(w.vp, w.spacing, 8, att_power=0)
+    g = oracle.Grid(**w.grid_kwargs())
+    # a source near the receivers so that the 30 steps reach some of them
+    src = w.rec_xyz[:1] + np.array([[0.0, 0.0, 2e-3]]) * np.sign(
+        (np.array(w.shape) - 1) * w.spacing / 2 - w.rec_xyz[0])
+    ref = oracle.forward_medium(g, w.vp, src, w.wavelet[:1], w.rec_xyz, rho=rho, alpha0=alpha0)
+    plan = S.Plan.from_workload(w, src_xyz=src)
+    tr = plan.forward_medium(dev(w.vp), dev(w.wavelet[:1]), rho=dev(rho),
+                             alpha0=dev(alpha0)).cpu().numpy()
+    assert np.abs(ref).max() > 0
+    assert rel(tr, ref) < 1e-4, rel(tr, ref)
+
+
+def test_medium_checks_before_launch():
+    w = W.tiny_2d()
+    plan = S.Plan.from_workload(w)
+    vp, wav = dev(w.vp), dev(w.wavelet)
+    with pytest.raises(S.StrideError) as e:
+        plan.forward_medium(vp, wav, rho=dev(np.full(w.shape, -1.0)))
+    assert e.value.code == -1
+    with pytest.raises(S.StrideError) as e:
+        plan.forward_medium(vp, wav, alpha0=dev(np.full(w.shape, -1.0)))
+    assert e.value.code == -1
+    with pytest.raises(S.StrideError) as e:
+        plan.forward_medium(vp, wav, att_power=1)
+    assert e.value.code == -1
+    ws = plan.workspace(S.STRIDE_MODE_FORWARD)
+    with pytest.raises(S.StrideError) as e:
+        plan.forward_medium(vp, wav, ws=ws)
+    assert e.value.code == -4
+    # y = 2: beta = 2 alpha0 vp / dt large enough to break the limit that vp alone meets
+    alpha0 = np.full(w.shape, 3.0 * w.dt / (2 * float(w.vp.max())))    # beta = 3
+    with pytest.raises(S.StrideError) as e:
+        plan.forward_medium(vp, wav, alpha0=dev(alpha0), att_power=2)
+    assert e.value.code == -2
+    plan.forward_medium(vp, wav, alpha0=dev(alpha0), att_power=0)   # the same alpha0 as damping
+    p4 = S.Plan.from_workload(w, time_order=4)
+    with pytest.raises(S.StrideError) as e:
+        p4.forward_medium(vp, wav)
+    assert e.value.code == -1
