@@ -34,12 +34,12 @@ HBM_PEAK_GBS = 8000.0
 # kernel file and its header; any change makes `traffic` null until the
 # counters are taken again.
 MEASURED_TRAFFIC = {
-    "config2": {"sha256": "d3ea8a9e3ce314996a9ebf68909d72c6b848b211841e459c3bccf7f62d94bc62",
-                "fetch_kib": 12284.25, "write_kib": 9522.49,
-                "copy_fetch_kib": 524308.38, "copy_write_kib": 1048576.0},
-    "config4": {"sha256": "d3ea8a9e3ce314996a9ebf68909d72c6b848b211841e459c3bccf7f62d94bc62",
-                "fetch_kib": 477552.82, "write_kib": 249640.00,
-                "copy_fetch_kib": 524315.81, "copy_write_kib": 1048576.0},
+    "config2": {"sha256": "3f93d0f64d17dd5e5f5eeb931aef460b337e60ff9dff83d03e7189ec8ac5ed8d",
+                "fetch_kib": 12281.75, "write_kib": 9522.54,
+                "copy_fetch_kib": 524307.88, "copy_write_kib": 1048576.0},
+    "config4": {"sha256": "3f93d0f64d17dd5e5f5eeb931aef460b337e60ff9dff83d03e7189ec8ac5ed8d",
+                "fetch_kib": 477746.64, "write_kib": 249640.00,
+                "copy_fetch_kib": 524315.69, "copy_write_kib": 1048576.0},
 }
 
 
@@ -68,6 +68,11 @@ ADJ_BYTES = 28   # read u^m, w^{m+1}, w^{m+2}, k, G; write w^m, G
 # fourth-order adjoint step: read u^m, k, write p; read w^{m+1}, k, write q;
 # read q, p, w^{m+1}, w^{m+2}, k, H, write w^m, H
 ADJ4_BYTES = 56
+# medium forward step: read u^n, u^{n-1}, k, ndim density gradients, attenuation; write u^{n+1}
+
+
+def medium_bytes(ndim):
+    return 4 * (5 + ndim)
 
 WORKLOADS = {
     "config2": "2D breast-like phantom, 1024^2 at 0.2 mm + 40-cell sponge (1104^2 padded), "
@@ -93,10 +98,12 @@ def parse():
     ap.add_argument("--budget-gb", type=float, default=200.0,
                     help="HBM budget of the gradient workspace (checkpointing beyond it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-forward", action="store_true")
     ap.add_argument("--no-fourth-order", action="store_true",
                     help="skip the forward and gradient solves with the fourth-order-in-time scheme")
+    ap.add_argument("--no-medium", action="store_true",
+                    help="skip the forward solves in a heterogeneous medium (density, attenuation)")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
@@ -404,6 +411,43 @@ def main():
         print(f"[bench] gradient, fourth order: {four['gradient']['ms_per_solve']:.2f} ms/solve, "
               f"adjoint {four['gradient']['adjoint_us_per_step']:.2f} us/step "
               f"({four['gradient']['adjoint_gbs']:.0f} GB/s)", file=sys.stderr, flush=True)
+
+    if not args.no_forward and not args.no_medium:
+        # forward solves on the phantom with its density and attenuation (y = 0 and 2)
+        import workloads as W
+        mws = plan.workspace(S.STRIDE_MODE_FORWARD_MEDIUM, device=dev)
+        med = {"bytes_per_point": medium_bytes(w.ndim)}
+        for y in (0, 2):
+            # y = 2 at 500 kHz: bone at 10 Np/m keeps the explicit viscous term
+            # within the stability limit at the workload's dt (40 Np/m would not)
+            rho, alpha0 = W.medium(vp_true, w.spacing, 11, att_power=y,
+                                   alpha_bone=40.0 if y == 0 else 10.0)
+            rho_t, al_t = torch.from_numpy(rho).to(dev), torch.from_numpy(alpha0).to(dev)
+            plan.forward_medium(vp_t, wav, rho=rho_t, alpha0=al_t, att_power=y, traces=traces, ws=mws)
+            torch.cuda.synchronize()
+            S.stride_timing_read()
+            S.stride_timing_enable(True)
+            tm0 = time.perf_counter()
+            for _ in range(args.steps):
+                plan.forward_medium(vp_t, wav, rho=rho_t, alpha0=al_t, att_power=y, traces=traces,
+                                    ws=mws)
+            torch.cuda.synchronize()
+            tm1 = time.perf_counter()
+            S.stride_timing_enable(False)
+            m_ms, m_n, m_l, _, _, _ = S.stride_timing_read()
+            m_step = m_ms * 1e-3 / max(m_n, 1)
+            med[f"y{y}"] = {
+                "updates_per_s": npad * (w.nt - 1) * args.steps / (tm1 - tm0),
+                "ms_per_solve": 1e3 * (tm1 - tm0) / args.steps,
+                "us_per_step": m_step * 1e6,
+                "gbs": medium_bytes(w.ndim) * npad / m_step / 1e9,
+            }
+            print(f"[bench] forward, medium y={y}: {med[f'y{y}']['ms_per_solve']:.2f} ms/solve, "
+                  f"{med[f'y{y}']['us_per_step']:.2f} us/step ({med[f'y{y}']['gbs']:.0f} GB/s)",
+                  file=sys.stderr, flush=True)
+            del rho_t, al_t
+        del mws
+        fwd["medium"] = med
 
     cpu = None
     if not args.no_cpu_baseline:

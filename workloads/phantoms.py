@@ -94,14 +94,15 @@ def head_3d_skull_only(shape, dx: float, seed: int, background: float = 1500.0) 
     return vp
 
 
-def medium(vp: np.ndarray, dx: float, seed: int, att_power: int = 0, f0: float = 500e3):
+def medium(vp: np.ndarray, dx: float, seed: int, att_power: int = 0, f0: float = 500e3,
+           alpha_bone: float = 40.0):
     """Density (kg/m^3) and attenuation alpha0 for a speed model, float32.
 
     rho: 1000 where vp is within 1 m/s of 1500 (water), 1000 + 0.5 (vp - 1500)
     clipped to [950, 1100] for soft tissue (vp below 2500 m/s), 1900 for bone
     (vp >= 2500); then x (1 + 0.02 n), n Gaussian-smoothed (sigma 1 mm) white
     noise scaled to max |n| = 1.  Attenuation at f0: 0.5 Np/m water, 4 Np/m
-    soft tissue, 40 Np/m bone; alpha0 = alpha(f0) / (2 pi f0)^att_power, so
+    soft tissue, alpha_bone (default 40 Np/m) bone; alpha0 = alpha(f0) / (2 pi f0)^att_power, so
     that alpha0 omega^y is alpha(f0) at f0.  Only the value ranges follow
     tissue; the draws come from numpy.random.default_rng(seed)."""
     rng = np.random.default_rng(seed)
@@ -116,6 +117,6 @@ def medium(vp: np.ndarray, dx: float, seed: int, att_power: int = 0, f0: float =
     rho *= 1.0 + 0.02 * noise
     alpha = np.full(vp.shape, 4.0)
     alpha[water] = 0.5
-    alpha[bone] = 40.0
+    alpha[bone] = alpha_bone
     alpha0 = alpha / (2.0 * np.pi * f0) ** att_power
     return rho.astype(np.float32), alpha0.astype(np.float32)
