@@ -33,6 +33,7 @@ class _CGrid(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("nt", ctypes.c_int),
         ("time_order", ctypes.c_int),
+        ("interp", ctypes.c_int),
     ]
 
 
@@ -47,6 +48,7 @@ class Grid:
     dt: float
     nt: int
     time_order: int = 2      # 4: leapfrog with the modified-equation correction
+    interp: int = 0          # off-grid points: 0 linear, 1 Kaiser-windowed sinc
     ndim: int = field(init=False)
 
     def __post_init__(self):
@@ -68,6 +70,7 @@ class Grid:
         g.dt = self.dt
         g.nt = self.nt
         g.time_order = self.time_order
+        g.interp = self.interp
         return g
 
     @property
@@ -105,6 +108,8 @@ def lib():
                                       dp, dp, dp, ctypes.c_int]
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_fd1_weights.argtypes = [ctypes.c_int, dp]
+        L.oracle_taps_per_point.argtypes = [gp]
+        L.oracle_taps_per_point.restype = ctypes.c_int
         L.oracle_medium_operator.argtypes = [gp, dp, dp, dp]
         L.oracle_forward_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
                                             ctypes.c_int, dp, dp]
@@ -164,10 +169,14 @@ def eta(grid: Grid) -> np.ndarray:
 
 
 def taps(grid: Grid, xyz):
+    """(idx, w): [npts][taps per point] flat padded indices and weights."""
     xyz = _f64(xyz).reshape(-1, grid.ndim)
     n = xyz.shape[0]
-    idx = np.zeros((n, 8), dtype=np.int64)
-    w = np.zeros((n, 8))
+    g0 = grid.c()
+    T = lib().oracle_taps_per_point(ctypes.byref(g0))
+    _check(min(T, 0), "taps")
+    idx = np.zeros((n, T), dtype=np.int64)
+    w = np.zeros((n, T))
     g = grid.c()
     _check(lib().oracle_taps(ctypes.byref(g), n, _d(xyz),
                              idx.ctypes.data_as(ctypes.POINTER(ctypes.c_long)), _d(w)), "taps")

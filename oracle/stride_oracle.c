@@ -215,14 +215,57 @@ int oracle_eta(const oracle_grid_t *g, double *eta)
     return 0;
 }
 
+/* Zeroth-order modified Bessel function of the first kind, by its power
+ * series sum_k ((z/2)^k / k!)^2 (all terms positive; converges for all z). */
+static double bessel_i0(double z)
+{
+    double term = 1.0, sum = 1.0, q = 0.25 * z * z;
+    for (int k = 1; k < 200 && term > 1e-17 * sum; k++) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+    }
+    return sum;
+}
+
+/* Kaiser-windowed sinc weight of a node at offset x (in cells) from the point
+ * (Hicks 2002): sinc(x) I0(b sqrt(1 - (x/r)^2)) / I0(b) for |x| <= r. */
+static double windowed_sinc(double x)
+{
+    const double r = ORACLE_SINC_HALF_WIDTH, b = ORACLE_SINC_KAISER_B;
+    if (fabs(x) > r)
+        return 0.0;
+    const double pi = 3.14159265358979323846;
+    double s = x == 0.0 ? 1.0 : sin(pi * x) / (pi * x);
+    double q = x / r;
+    return s * bessel_i0(b * sqrt(1.0 - q * q)) / bessel_i0(b);
+}
+
+int oracle_taps_per_point(const oracle_grid_t *g)
+{
+    if (!g || (g->ndim != 2 && g->ndim != 3))
+        return -1;
+    if (g->interp == 1) {
+        int n = 1;
+        for (int a = 0; a < g->ndim; a++)
+            n *= 2 * ORACLE_SINC_HALF_WIDTH;
+        return n;
+    }
+    return g->interp == 0 ? 1 << g->ndim : -1;
+}
+
 int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, double *w)
 {
     geo_t G;
     if (make_geo(g, &G) != 0 || npts < 0)
         return -1;
+    const int T = oracle_taps_per_point(g);
+    if (T < 0)
+        return -1;
+    const int sinc = g->interp == 1;
+    const int m = sinc ? 2 * ORACLE_SINC_HALF_WIDTH : 2;    /* nodes per axis */
     for (int p = 0; p < npts; p++) {
-        long lo[3] = {0, 0, 0};
-        double fr[3] = {0, 0, 0};
+        long first[3] = {0, 0, 0};
+        double w1[3][2 * ORACLE_SINC_HALF_WIDTH];
         for (int a = 0; a < G.nd; a++) {
             double x = xyz[(long)p * G.nd + a];
             double xmax = (double)(G.n[a] - 1) * g->spacing[a];
@@ -237,24 +280,38 @@ int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, 
                 f = 0.0;
             if (fabs(1.0 - f) < 1e-9)
                 f = 1.0;
-            lo[a] = i;
-            fr[a] = f;
+            if (!sinc) {
+                first[a] = i;
+                w1[a][0] = 1.0 - f;
+                w1[a][1] = f;
+                continue;
+            }
+            /* nodes i - r + 1 .. i + r; the point sits at i + f */
+            if (f == 1.0) {
+                i += 1;
+                f = 0.0;
+            }
+            first[a] = i - ORACLE_SINC_HALF_WIDTH + 1;
+            if (first[a] < 0 || first[a] + m - 1 > G.np[a] - 1)
+                return -3;    /* taps beyond the padded array */
+            for (int j = 0; j < m; j++) {
+                long node = first[a] + j;
+                w1[a][j] = f == 0.0 ? (node == i ? 1.0 : 0.0)
+                                    : windowed_sinc((double)node - ((double)i + f));
+            }
         }
-        for (int t = 0; t < 8; t++) {
-            idx[(long)p * 8 + t] = 0;
-            w[(long)p * 8 + t] = 0.0;
-        }
-        int ntap = 1 << G.nd;
-        for (int t = 0; t < ntap; t++) {
+        for (int t = 0; t < T; t++) {
             long lin = 0;
             double wt = 1.0;
+            int rem = t;
             for (int a = 0; a < G.nd; a++) {
-                int bit = (t >> a) & 1;
-                lin += (lo[a] + bit) * G.st[a];
-                wt *= bit ? fr[a] : 1.0 - fr[a];
+                int j = rem % m;
+                rem /= m;
+                lin += (first[a] + j) * G.st[a];
+                wt *= w1[a][j];
             }
-            idx[(long)p * 8 + t] = lin;
-            w[(long)p * 8 + t] = wt;
+            idx[(long)p * T + t] = lin;
+            w[(long)p * T + t] = wt;
         }
     }
     return 0;
@@ -323,15 +380,17 @@ static int solve_init(solve_t *S, const oracle_grid_t *g, const double *vp,
     long N = S->G.N;
     S->nsrc = nsrc;
     S->nrec = nrec;
-    S->ntap = 1 << S->G.nd;
+    S->ntap = oracle_taps_per_point(g);
+    if (S->ntap < 0)
+        return -1;
     S->k = malloc(sizeof(double) * N);
     S->a = malloc(sizeof(double) * N);
     S->b = malloc(sizeof(double) * N);
     S->vpp = malloc(sizeof(double) * N);
-    S->sidx = malloc(sizeof(long) * 8 * (nsrc + 1));
-    S->ridx = malloc(sizeof(long) * 8 * (nrec + 1));
-    S->sw = malloc(sizeof(double) * 8 * (nsrc + 1));
-    S->rw = malloc(sizeof(double) * 8 * (nrec + 1));
+    S->sidx = malloc(sizeof(long) * S->ntap * (nsrc + 1));
+    S->ridx = malloc(sizeof(long) * S->ntap * (nrec + 1));
+    S->sw = malloc(sizeof(double) * S->ntap * (nsrc + 1));
+    S->rw = malloc(sizeof(double) * S->ntap * (nrec + 1));
     if (!S->k || !S->a || !S->b || !S->vpp || !S->sidx || !S->ridx || !S->sw || !S->rw) {
         solve_free(S);
         return -7;
@@ -359,7 +418,8 @@ static void source_term(const solve_t *S, const double *wavelet, int nt, int n, 
     memset(dense, 0, sizeof(double) * S->G.N);
     for (int s = 0; s < S->nsrc; s++)
         for (int t = 0; t < S->ntap; t++)
-            dense[S->sidx[s * 8 + t]] += S->sw[s * 8 + t] * wavelet[(long)s * nt + n] / S->G.cellvol;
+            dense[S->sidx[(long)s * S->ntap + t]] +=
+                S->sw[(long)s * S->ntap + t] * wavelet[(long)s * nt + n] / S->G.cellvol;
 }
 
 /* Dense adjoint source R^T g^m (no volume factor: sampling has none). */
@@ -368,14 +428,14 @@ static void receiver_transpose(const solve_t *S, const double *gtr, int nt, int 
     memset(dense, 0, sizeof(double) * S->G.N);
     for (int r = 0; r < S->nrec; r++)
         for (int t = 0; t < S->ntap; t++)
-            dense[S->ridx[r * 8 + t]] += S->rw[r * 8 + t] * gtr[(long)r * nt + m];
+            dense[S->ridx[(long)r * S->ntap + t]] += S->rw[(long)r * S->ntap + t] * gtr[(long)r * nt + m];
 }
 
 static double sample(const solve_t *S, const long *idx, const double *w, int p, const double *u)
 {
     double acc = 0.0;
     for (int t = 0; t < S->ntap; t++)
-        acc += w[p * 8 + t] * u[idx[p * 8 + t]];
+        acc += w[(long)p * S->ntap + t] * u[idx[(long)p * S->ntap + t]];
     return acc;
 }
 
@@ -403,7 +463,7 @@ static void source_term4(const solve_t *S, const double *wavelet, int nt, int n,
         double wm = n >= 1 ? w[n - 1] : 0.0, wp = n + 1 < nt ? w[n + 1] : 0.0;
         double ws = (wm + 10.0 * w[n] + wp) / 12.0;
         for (int t = 0; t < S->ntap; t++)
-            dense[S->sidx[s * 8 + t]] += S->sw[s * 8 + t] * ws / S->G.cellvol;
+            dense[S->sidx[(long)s * S->ntap + t]] += S->sw[(long)s * S->ntap + t] * ws / S->G.cellvol;
     }
 }
 

@@ -57,7 +57,16 @@ typedef struct {
     int nt;              /* number of time samples */
     int time_order;      /* 2 (leapfrog) or 4 (leapfrog with the modified-equation
                             correction); 0 means 2 */
+    int interp;          /* off-grid points: 0 bi/tri-linear, 1 Kaiser-windowed sinc */
 } oracle_grid_t;
+
+/* Windowed-sinc taps (Sec. 2.4 cites Hicks' Kaiser-windowed sinc functions for
+ * off-grid sources and receivers): per axis the 2r nodes around the point,
+ * weight sinc(x) I0(b sqrt(1 - (x/r)^2)) / I0(b) at offset x, the product over
+ * the axes; a point on a node gets that node alone.  r = 4 and b = 6.31 are
+ * readings (the window width and the Kaiser shape Hicks tabulates for it). */
+#define ORACLE_SINC_HALF_WIDTH 4
+#define ORACLE_SINC_KAISER_B 6.31
 
 /* Central second-derivative weights c[0..order/2]. */
 int oracle_fd_weights(int space_order, double *c);
@@ -76,6 +85,9 @@ int oracle_eta(const oracle_grid_t *g, double *eta);
 /* Linear-interpolation taps of npts points: idx[p*8+t] padded linear index,
  * w[p*8+t] weight; 2^ndim taps used, the rest are set to (0, 0.0). */
 int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, double *w);
+/* Taps per point: 2^ndim (linear) or (2 r)^ndim (sinc); idx and w of
+ * oracle_taps hold that many entries per point. */
+int oracle_taps_per_point(const oracle_grid_t *g);
 
 /* Apply the 2r-order Laplacian on the padded grid (zero outside). */
 int oracle_laplacian(const oracle_grid_t *g, const double *u, double *lu);
