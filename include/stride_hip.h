@@ -90,6 +90,13 @@ typedef struct stride_grid {
                              Forward solves, gradients and stride_backward's dvp; the
                              wavelet gradient (dwavelet) and the batching engine
                              return INVALID_ARG for it */
+    int32_t interp;       /* off-grid sources and receivers (Sec. 2.4): 0 bi/tri-linear
+                             (2 nodes per axis), 1 Kaiser-windowed sinc after Hicks
+                             (8 nodes per axis: weight sinc(x) I0(b sqrt(1 - (x/4)^2)) /
+                             I0(b), b = 6.31, at offset x cells; product over axes; a
+                             point on a node gets that node alone).  Sinc taps must lie
+                             in the padded grid: points within 4 cells of its edge (with
+                             sponge_cells < 4) return GEOMETRY. */
 } stride_grid_t;
 
 /* A plan: the validated grid plus the source/receiver tap tables of one shot

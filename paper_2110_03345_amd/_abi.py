@@ -55,6 +55,7 @@ class stride_grid_t(ctypes.Structure):
         ("sponge_vref", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("time_order", ctypes.c_int32),
+        ("interp", ctypes.c_int32),
     ]
 
 
@@ -112,7 +113,7 @@ def _check(rc: int):
 
 
 def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: float, dt: float,
-              nt: int, time_order: int = 2) -> stride_grid_t:
+              nt: int, time_order: int = 2, interp: int = 0) -> stride_grid_t:
     g = stride_grid_t()
     nd = len(shape)
     sp = (float(spacing),) * nd if np.isscalar(spacing) else tuple(float(s) for s in spacing)
@@ -126,6 +127,7 @@ def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: fl
     g.sponge_vref = float(vref)
     g.dt = float(dt)
     g.time_order = int(time_order)
+    g.interp = int(interp)
     return g
 
 
@@ -310,9 +312,10 @@ class Plan:
     """A validated grid + shot geometry with its tap tables on the current device."""
 
     def __init__(self, shape, spacing, space_order, nb, vref, dt, nt, src_xyz, rec_xyz,
-                 time_order: int = 2):
-        self.grid = make_grid(shape, spacing, space_order, nb, vref, dt, nt, time_order)
+                 time_order: int = 2, interp: int = 0):
+        self.grid = make_grid(shape, spacing, space_order, nb, vref, dt, nt, time_order, interp)
         self.time_order = int(time_order)
+        self.interp = int(interp)
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.nt = int(nt)
@@ -323,11 +326,12 @@ class Plan:
         self.handle = stride_plan_create(self.grid, self.src_xyz, self.rec_xyz)
 
     @classmethod
-    def from_workload(cls, w, src_xyz=None, rec_xyz=None, nt=None, time_order: int = 2):
+    def from_workload(cls, w, src_xyz=None, rec_xyz=None, nt=None, time_order: int = 2,
+                      interp: int = 0):
         return cls(w.shape, w.spacing, w.space_order, w.nb, w.vref, w.dt,
                    w.nt if nt is None else nt,
                    w.src_xyz if src_xyz is None else src_xyz,
-                   w.rec_xyz if rec_xyz is None else rec_xyz, time_order)
+                   w.rec_xyz if rec_xyz is None else rec_xyz, time_order, interp)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -11,7 +11,7 @@ namespace stride {
 constexpr int kMaxR = 5;        // stencil radius (10th order)
 constexpr int kThreads = 256;   // 4 wave64 per block
 constexpr int kTileX = 64;      // contiguous axis: one wave64 spans a tile row
-constexpr int kMaxTaps = 8;
+constexpr int kSincHalfWidth = 4;   // windowed-sinc taps: 2 r nodes per axis
 
 // Padded grid as laid out in the workspace.  Axis nd-1 is contiguous.
 // 2D: axis 0 = rows, axis 1 = columns.  3D: axis 0 is the marching axis.
@@ -57,13 +57,14 @@ struct InjTable {
     const TileEntry* ent;
 };
 
-// Point sampling: out[r * out_stride + step] = sum_t w[r*8+t] * field[idx[r*8+t]].
+// Point sampling: out[r * out_stride + step] = sum_t w[r*ntap+t] * field[idx[r*ntap+t]].
 struct SampleSet {
     int count;
     const long long* idx;
     const float* w;
     float* out;
     int out_stride;
+    int ntap;         // taps per point: 2^ndim (linear) or (2 r)^ndim (windowed sinc)
 };
 
 struct StepParams {

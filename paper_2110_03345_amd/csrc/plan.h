@@ -23,6 +23,7 @@ struct stride_plan {
     double nyquist;      // -(c0 + 2 sum_j cj (-1)^j): largest eigenvalue of -L per axis
     double cellvol;
     int nsrc, nrec;
+    int ntap;            // taps per source / receiver (2^nd linear, 8^nd windowed sinc)
     int device;
     void* blob;          // device memory of the tables below
     stride::InjTable src_inj;    // sources, weights / cell volume (blocks of ls_fwd)
@@ -93,6 +94,16 @@ int check_cfl(const stride_plan& P, double vmax);
 int check_vp(const stride_plan& P, const float* vp, unsigned* flags, hipStream_t s);
 
 StepParams base_params(const stride_plan& P);
+
+// Receiver sampling of a field into out[nrec][nt]; source sampling into out[nsrc][nt].
+inline SampleSet rec_samples(const stride_plan& P, float* out)
+{
+    return SampleSet{P.nrec, P.rec_idx, P.rec_w, out, P.nt, P.ntap};
+}
+inline SampleSet src_samples(const stride_plan& P, float* out)
+{
+    return SampleSet{P.nsrc, P.src_idx, P.src_w, out, P.nt, P.ntap};
+}
 
 // One step of a checkpointed gradient solve.
 struct StepOp {

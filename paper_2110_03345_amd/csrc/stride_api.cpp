@@ -113,20 +113,58 @@ int default_zc(const Dims& d, int ty)
     return want > 0 ? want : (ty >= 32 ? 32 : 16);
 }
 
-struct Tap {
-    long long idx[kMaxTaps];
-    double w[kMaxTaps];
-    int coord[kMaxTaps][3];
+// Taps of a set of points: T per point, flat.
+struct TapSet {
+    int T = 0;
+    std::vector<long long> idx;   // flat padded index
+    std::vector<double> w;
+    std::vector<int> coord;       // padded coordinates, 3 per tap
 };
 
-// Bi/tri-linear taps of a physical coordinate (metres from physical node 0).
-int make_taps(const stride_plan& P, const double* xyz, int count, std::vector<Tap>& out,
-              const char* what)
+// Zeroth-order modified Bessel function of the first kind (power series).
+double bessel_i0(double z)
 {
-    out.resize(count);
+    double term = 1.0, sum = 1.0;
+    const double q = 0.25 * z * z;
+    for (int k = 1; k < 200 && term > 1e-17 * sum; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+    }
+    return sum;
+}
+
+// Kaiser-windowed sinc (Hicks 2002) at a node offset x cells from the point:
+// sinc(x) I0(b sqrt(1 - (x/r)^2)) / I0(b), r = kSincHalfWidth, b = 6.31.
+double windowed_sinc(double x)
+{
+    const double r = kSincHalfWidth, b = 6.31, pi = 3.14159265358979323846;
+    if (std::fabs(x) > r)
+        return 0.0;
+    const double sc = x == 0.0 ? 1.0 : std::sin(pi * x) / (pi * x);
+    const double q = x / r;
+    return sc * bessel_i0(b * std::sqrt(1.0 - q * q)) / bessel_i0(b);
+}
+
+int taps_per_point(int nd, int interp)
+{
+    const int m = interp == 1 ? 2 * kSincHalfWidth : 2;
+    return nd == 3 ? m * m * m : m * m;
+}
+
+// Taps of physical coordinates (metres from physical node 0): bi/tri-linear
+// (2 nodes per axis) or windowed sinc (2 r nodes per axis, weights the
+// product of the per-axis weights; a point on a node gets that node alone).
+int make_taps(const stride_plan& P, const double* xyz, int count, TapSet& out, const char* what)
+{
+    const bool sinc = P.g.interp == 1;
+    const int m = sinc ? 2 * kSincHalfWidth : 2;
+    out.T = taps_per_point(P.nd, P.g.interp);
+    out.idx.assign((size_t)count * out.T, 0);
+    out.w.assign((size_t)count * out.T, 0.0);
+    out.coord.assign((size_t)count * out.T * 3, 0);
     for (int p = 0; p < count; ++p) {
-        int lo[3] = {0, 0, 0};
-        double fr[3] = {0, 0, 0};
+        int first[3] = {0, 0, 0};
+        double w1[3][2 * kSincHalfWidth] = {};
         for (int a = 0; a < P.nd; ++a) {
             double x = xyz[(size_t)p * P.nd + a];
             double dx = P.g.spacing[a];
@@ -144,28 +182,43 @@ int make_taps(const stride_plan& P, const double* xyz, int count, std::vector<Ta
                 f = 0.0;
             if (std::fabs(1.0 - f) < 1e-9)
                 f = 1.0;
-            lo[a] = (int)i;
-            fr[a] = f;
+            if (!sinc) {
+                first[a] = (int)i;
+                w1[a][0] = 1.0 - f;
+                w1[a][1] = f;
+                continue;
+            }
+            if (f == 1.0) {
+                i += 1;
+                f = 0.0;
+            }
+            first[a] = (int)i - kSincHalfWidth + 1;
+            if (first[a] < 0 || first[a] + m - 1 > P.dims.n[a] - 1)
+                return fail(STRIDE_E_GEOMETRY,
+                            "%s %d: the windowed-sinc taps on axis %d reach beyond the padded "
+                            "grid (needs %d cells from its edge; sponge_cells is %d)",
+                            what, p, a, kSincHalfWidth, P.nb);
+            for (int j = 0; j < m; ++j) {
+                const long long node = first[a] + j;
+                w1[a][j] = f == 0.0 ? (node == i ? 1.0 : 0.0)
+                                    : windowed_sinc((double)node - ((double)i + f));
+            }
         }
-        Tap& T = out[p];
-        for (int t = 0; t < kMaxTaps; ++t) {
-            T.idx[t] = 0;
-            T.w[t] = 0.0;
-            T.coord[t][0] = T.coord[t][1] = T.coord[t][2] = 0;
-        }
-        int ntap = 1 << P.nd;
-        for (int t = 0; t < ntap; ++t) {
+        for (int t = 0; t < out.T; ++t) {
             long long lin = 0;
             double w = 1.0;
+            int rem = t;
+            const size_t k = (size_t)p * out.T + t;
             for (int a = 0; a < P.nd; ++a) {
-                int bit = (t >> a) & 1;
-                int c = lo[a] + bit;
-                T.coord[t][a] = c;
+                const int j = rem % m;
+                rem /= m;
+                const int c = first[a] + j;
+                out.coord[k * 3 + a] = c;
                 lin += (long long)c * P.dims.st[a];
-                w *= bit ? fr[a] : 1.0 - fr[a];
+                w *= w1[a][j];
             }
-            T.idx[t] = lin;
-            T.w[t] = w;
+            out.idx[k] = lin;
+            out.w[k] = w;
         }
     }
     return STRIDE_OK;
@@ -180,18 +233,19 @@ struct HostTiles {
 // launch shape (2D: tile; 3D: tile and chunk of zc planes, block index
 // chunk * tiles_xy + tile), sorted by block-local point and in (point, tap)
 // order within a point.
-HostTiles build_tiles(const stride_plan& P, const std::vector<Tap>& taps, double scale,
+HostTiles build_tiles(const stride_plan& P, const TapSet& taps, double scale,
                       const LaunchShape& ls)
 {
     HostTiles T;
-    const int ntap = 1 << P.nd;
     const int plane = ls.ty * kTileX;   // block-local points per plane
+    const size_t npts = taps.T ? taps.w.size() / taps.T : 0;
     std::vector<std::vector<TileEntry>> per(ls.tile_blocks);
-    for (size_t p = 0; p < taps.size(); ++p)
-        for (int t = 0; t < ntap; ++t) {
-            if (taps[p].w[t] == 0.0)
+    for (size_t p = 0; p < npts; ++p)
+        for (int t = 0; t < taps.T; ++t) {
+            const size_t k = p * taps.T + t;
+            if (taps.w[k] == 0.0)
                 continue;
-            const int* c = taps[p].coord[t];
+            const int* c = &taps.coord[k * 3];
             const int cy = c[P.nd - 2], cx = c[P.nd - 1];
             const int ty = cy / ls.ty, tx = cx / kTileX;
             int zci = 0, pz = 0;
@@ -201,7 +255,7 @@ HostTiles build_tiles(const stride_plan& P, const std::vector<Tap>& taps, double
             }
             const int local = pz * plane + (cy - ty * ls.ty) * kTileX + (cx - tx * kTileX);
             const size_t blk = (size_t)zci * ls.tiles_xy + (size_t)ty * ls.tiles_x + tx;
-            per[blk].push_back(TileEntry{local, 0, (int)p, (float)(taps[p].w[t] * scale)});
+            per[blk].push_back(TileEntry{local, 0, (int)p, (float)(taps.w[k] * scale)});
         }
     T.ptr.assign(ls.tile_blocks + 1, 0);
     for (int t = 0; t < ls.tile_blocks; ++t) {
@@ -221,16 +275,13 @@ HostTiles build_tiles(const stride_plan& P, const std::vector<Tap>& taps, double
     return T;
 }
 
-void flatten_sample(const std::vector<Tap>& taps, double scale, std::vector<long long>& idx,
+void flatten_sample(const TapSet& taps, double scale, std::vector<long long>& idx,
                     std::vector<float>& w)
 {
-    idx.assign(taps.size() * kMaxTaps, 0);
-    w.assign(taps.size() * kMaxTaps, 0.f);
-    for (size_t p = 0; p < taps.size(); ++p)
-        for (int t = 0; t < kMaxTaps; ++t) {
-            idx[p * kMaxTaps + t] = taps[p].idx[t];
-            w[p * kMaxTaps + t] = (float)(taps[p].w[t] * scale);
-        }
+    idx = taps.idx;
+    w.resize(taps.w.size());
+    for (size_t k = 0; k < taps.w.size(); ++k)
+        w[k] = (float)(taps.w[k] * scale);
 }
 
 int validate_grid(const stride_grid_t* g)
@@ -247,6 +298,9 @@ int validate_grid(const stride_grid_t* g)
         return fail(STRIDE_E_INVALID_ARG, "nt must be >= 2 (got %d)", g->nt);
     if (g->time_order != 0 && g->time_order != 2 && g->time_order != 4)
         return fail(STRIDE_E_INVALID_ARG, "time_order must be 2 or 4 (got %d)", g->time_order);
+    if (g->interp != 0 && g->interp != 1)
+        return fail(STRIDE_E_INVALID_ARG, "interp must be 0 (linear) or 1 (windowed sinc), got %d",
+                    g->interp);
     if (!(g->dt > 0) || !std::isfinite(g->dt))
         return fail(STRIDE_E_INVALID_ARG, "dt must be positive");
     if (!(g->sponge_vref >= 0) || !std::isfinite(g->sponge_vref))
@@ -586,7 +640,7 @@ struct Runner {
         p.step = op.step;
         p.inj_sig = wavelet;
         if (traces && op.first_sweep)
-            p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+            p.smp = rec_samples(P, traces);
         ++steps;
         if (P.torder == 4) {
             // p = k (L u^n + St^n), then u^{n+1} from the stencil of p
@@ -693,7 +747,7 @@ struct Runner {
             p.img_sig = wavelet;
             p.img_stride = P.nt;
             if (dwavelet)
-                p.smp = SampleSet{P.nsrc, P.src_idx, P.src_w, dwavelet, P.nt};
+                p.smp = src_samples(P, dwavelet);
             launch_step(P.dims, P.R, true, P.cf, P.sp, P.ls_adj, p, s);
             ++adj_launches;
             wa = 1 - wa;
@@ -732,7 +786,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
             p.K = k;
             p.step = n;
             p.inj_sig = wavelet;
-            p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+            p.smp = rec_samples(P, traces);
             launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
             StepParams q = base_params(P);
             q.A = F.p;
@@ -745,7 +799,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
             cur = 1 - cur;
         }
         g_timer.end(tid, s, 0, P.nt - 1, 2LL * (P.nt - 1));
-        launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
+        launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
         HIP_TRY(hipGetLastError());
         return STRIDE_OK;
     }
@@ -757,12 +811,12 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
         p.K = k;
         p.step = n;
         p.inj_sig = wavelet;
-        p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+        p.smp = rec_samples(P, traces);
         launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
         cur = 1 - cur;
     }
     g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
-    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
+    launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
     return STRIDE_OK;
 }
@@ -836,7 +890,7 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
         p.step = n;
         p.inj = P.src_img;
         p.inj_sig = wavelet;
-        p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt};
+        p.smp = rec_samples(P, traces);
         for (int a = 0; a < 3; ++a)
             p.gam[a] = gam[a] ? gam[a] : gam[0];
         p.att = att;
@@ -848,7 +902,7 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
         next = t;
     }
     g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
-    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, traces, P.nt}, u[cur], P.nt - 1, s);
+    launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
     return STRIDE_OK;
 }
@@ -875,7 +929,7 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     // last sample from the final state x_{nt-1}
-    launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, tr, P.nt}, W.pool[run.cursor.cur()], P.nt - 1, s);
+    launch_sample(rec_samples(P, tr), W.pool[run.cursor.cur()], P.nt - 1, s);
     if (traces && traces != W.traces)
         launch_copy(W.traces, traces, (long long)P.nrec * P.nt, s);
     HIP_TRY(hipGetLastError());
@@ -954,6 +1008,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->nt = grid->nt;
     P->torder = grid->time_order == 4 ? 4 : 2;
     P->nsrc = nsrc;
+    P->ntap = taps_per_point(P->nd, grid->interp);
     P->nrec = nrec;
     P->blob = nullptr;
 
@@ -1025,7 +1080,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->ls_adj = make_shape(d, default_zc(d, rya * wa), rya, wa);
 
 
-    std::vector<Tap> st, rt;
+    TapSet st, rt;
     if ((rc = make_taps(*P, src_xyz, nsrc, st, "source")) ||
         (rc = make_taps(*P, rec_xyz, nrec, rt, "receiver"))) {
         delete P;

@@ -96,7 +96,7 @@ int fill_tick(stride_engine* E, SlotJob& J, SlotStep* fwd, SlotStep* adj)
         t.p.K = J.F.k;
         t.p.step = J.n;
         t.p.inj_sig = J.wavelet;
-        t.p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, J.traces, P.nt};
+        t.p.smp = rec_samples(P, J.traces);
         t.sp = P.sp;
         t.active = 1;
         J.cur = 1 - J.cur;
@@ -116,7 +116,7 @@ int fill_tick(stride_engine* E, SlotJob& J, SlotStep* fwd, SlotStep* adj)
         t.p.step = op.step;
         t.p.inj_sig = J.wavelet;
         if (op.first_sweep)
-            t.p.smp = SampleSet{P.nrec, P.rec_idx, P.rec_w, J.W.traces, P.nt};
+            t.p.smp = rec_samples(P, J.W.traces);
         t.sp = P.sp;
         t.active = 1;
         return 1;
@@ -184,13 +184,13 @@ void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
 {
     const stride_plan& P = *J.P;
     if (J.mode == STRIDE_MODE_FORWARD) {
-        launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, J.traces, P.nt}, J.F.u[J.cur], P.nt - 1, s);
+        launch_sample(rec_samples(P, J.traces), J.F.u[J.cur], P.nt - 1, s);
         J.finished = true;
         return;
     }
     if (J.phase == 0) {
         // the forward sweep ended in x_{nt-1}: last sample, residual, misfit
-        launch_sample(SampleSet{P.nrec, P.rec_idx, P.rec_w, J.W.traces, P.nt},
+        launch_sample(rec_samples(P, J.W.traces),
                       J.W.pool[J.cursor->cur()], P.nt - 1, s);
         launch_residual_misfit(J.W.traces, J.observed, J.W.residual, (long long)P.nrec * P.nt,
                                J.misfit, J.W.partial, s);

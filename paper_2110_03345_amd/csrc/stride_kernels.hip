@@ -132,9 +132,9 @@ __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* 
     if (r >= smp.count)
         return;
     float acc = 0.f;
-#pragma unroll
-    for (int t = 0; t < kMaxTaps; ++t)
-        acc = fmaf(smp.w[r * kMaxTaps + t], field[smp.idx[r * kMaxTaps + t]], acc);
+    const long long base = (long long)r * smp.ntap;
+    for (int t = 0; t < smp.ntap; ++t)
+        acc = fmaf(smp.w[base + t], field[smp.idx[base + t]], acc);
     smp.out[(long long)r * smp.out_stride + step] = acc;
 }
 
