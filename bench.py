@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--no-forward", action="store_true")
     ap.add_argument("--no-fourth-order", action="store_true",
                     help="skip the forward and gradient solves with the fourth-order-in-time scheme")
+    ap.add_argument("--no-sinc", action="store_true",
+                    help="skip the shot gradient with windowed-sinc sources and receivers")
     ap.add_argument("--no-medium", action="store_true",
                     help="skip the forward solves in a heterogeneous medium (density, attenuation)")
     ap.add_argument("--nt", type=int, default=0,
@@ -411,6 +413,36 @@ def main():
         print(f"[bench] gradient, fourth order: {four['gradient']['ms_per_solve']:.2f} ms/solve, "
               f"adjoint {four['gradient']['adjoint_us_per_step']:.2f} us/step "
               f"({four['gradient']['adjoint_gbs']:.0f} GB/s)", file=sys.stderr, flush=True)
+
+    if not args.no_sinc:
+        # the same shot gradient with Kaiser-windowed sinc sources and receivers
+        ws = None                     # release the first gradient's workspace
+        plan_s = S.Plan.from_workload(w, interp=1)
+        full_s = plan_s.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+        ws_s = torch.empty(plan_s.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full_s, budget)),
+                           dtype=torch.uint8, device=dev)
+        S.stride_plan_gradient(plan_s.handle, vp_m, wav, obs, traces, misfit, dvp, ws_s)
+        torch.cuda.synchronize()
+        S.stride_timing_read()
+        S.stride_timing_enable(True)
+        ts0 = time.perf_counter()
+        for _ in range(args.steps):
+            S.stride_plan_gradient(plan_s.handle, vp_m, wav, obs, traces, misfit, dvp, ws_s)
+        torch.cuda.synchronize()
+        ts1 = time.perf_counter()
+        S.stride_timing_enable(False)
+        gs = S.stride_timing_read()
+        fwd["sinc_taps"] = {
+            "taps_per_point": 8 ** w.ndim,
+            "gradient_ms_per_solve": 1e3 * (ts1 - ts0) / args.steps,
+            "updates_per_s": 2.0 * npad * (w.nt - 1) * args.steps / (ts1 - ts0),
+            "forward_us_per_step": gs[0] * 1e3 / max(gs[1], 1),
+            "adjoint_us_per_step": gs[3] * 1e3 / max(gs[4], 1),
+        }
+        del ws_s, plan_s
+        print(f"[bench] gradient, windowed-sinc taps: {fwd['sinc_taps']['gradient_ms_per_solve']:.2f} "
+              f"ms/solve, forward {fwd['sinc_taps']['forward_us_per_step']:.2f} us/step, adjoint "
+              f"{fwd['sinc_taps']['adjoint_us_per_step']:.2f} us/step", file=sys.stderr, flush=True)
 
     if not args.no_forward and not args.no_medium:
         # forward solves on the phantom with its density and attenuation (y = 0 and 2)

@@ -67,6 +67,13 @@ struct SampleSet {
     int ntap;         // taps per point: 2^ndim (linear) or (2 r)^ndim (windowed sinc)
 };
 
+// Threads that sample one point: one for up to 8 taps, a wave64 (lanes over
+// the taps, then a wave reduction) for the windowed-sinc tap sets.
+__host__ __device__ inline int sample_lanes(int ntap)
+{
+    return ntap > 8 ? 64 : 1;
+}
+
 struct StepParams {
     const float* A;   // stencil field: u^n (forward) or w^{m+1} (adjoint)
     const float* B;   // u^{n-1} or w^{m+2}
@@ -125,9 +132,10 @@ enum StepMode {
 };
 
 // Kernel launchers (stride_kernels.hip).
+// max_sample_threads: the largest count * sample_lanes(ntap) over the slots.
 void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
-                         const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
-                         hipStream_t s);
+                         const LaunchShape& ls, const SlotStep* table, int nslots,
+                         int max_sample_threads, hipStream_t s);
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);

@@ -70,6 +70,7 @@ struct stride_engine {
     StencilCoef cf;
     LaunchShape ls_fwd, ls_adj;
     int max_slots, max_samples, tmax;
+    int ntap;                 // taps per receiver of the engine's grid (linear or sinc)
     bool graphs;
     stride_plan_t* shape_plan = nullptr;   // geometry-free plan fixing the layout
     std::vector<SlotJob> slots;
@@ -148,7 +149,8 @@ void launch_chunk(stride_engine* E, int ticks, int gy_fwd, int gy_adj, hipStream
     for (int t = 0; t < ticks; ++t) {
         const SlotStep* base = E->d_table + (size_t)t * 2 * E->max_slots;
         if (gy_fwd)
-            launch_step_batched(E->dims, E->R, false, E->cf, E->ls_fwd, base, gy_fwd, E->max_samples, s);
+            launch_step_batched(E->dims, E->R, false, E->cf, E->ls_fwd, base, gy_fwd,
+                                E->max_samples * sample_lanes(E->ntap), s);
         if (gy_adj)
             launch_step_batched(E->dims, E->R, true, E->cf, E->ls_adj, base + E->max_slots, gy_adj, 0, s);
     }
@@ -227,6 +229,7 @@ int stride_engine_create(const stride_grid_t* grid, int32_t max_slots, int32_t m
     E->ls_adj = sp->ls_adj;
     E->max_slots = max_slots;
     E->max_samples = max_receivers;
+    E->ntap = sp->ntap;
     int t = 1;
     while (t * 2 <= max_chunk)
         t *= 2;
@@ -276,7 +279,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
 {
     if (!E || !plan || !slot)
         return fail(STRIDE_E_INVALID_ARG, "NULL engine, plan or slot");
-    if (!same_layout(E->dims, plan->dims) || E->R != plan->R ||
+    if (!same_layout(E->dims, plan->dims) || E->R != plan->R || E->ntap != plan->ntap ||
         std::memcmp(&E->cf, &plan->cf, sizeof(StencilCoef)) != 0)
         return fail(STRIDE_E_INVALID_ARG, "plan grid does not match the engine grid");
     if (plan->torder != 2)

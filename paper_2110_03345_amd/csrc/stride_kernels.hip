@@ -128,14 +128,32 @@ __device__ __forceinline__ int layer_depth(int i, int n, int nb)
 __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* field, int step,
                                              int sb)
 {
-    int r = sb * (int)blockDim.x + (int)threadIdx.x;
+    if (sample_lanes(smp.ntap) == 1) {
+        const int r = sb * (int)blockDim.x + (int)threadIdx.x;
+        if (r >= smp.count)
+            return;
+        float acc = 0.f;
+        const long long base = (long long)r * smp.ntap;
+        for (int t = 0; t < smp.ntap; ++t)
+            acc = fmaf(smp.w[base + t], field[smp.idx[base + t]], acc);
+        smp.out[(long long)r * smp.out_stride + step] = acc;
+        return;
+    }
+    // one wave per point: lane l sums taps l, l + 64, ...; then a butterfly
+    // reduction over the wave (a fixed order, so results are reproducible)
+    const int lane = (int)threadIdx.x & 63;
+    const int r = sb * ((int)blockDim.x >> 6) + ((int)threadIdx.x >> 6);
     if (r >= smp.count)
         return;
-    float acc = 0.f;
     const long long base = (long long)r * smp.ntap;
-    for (int t = 0; t < smp.ntap; ++t)
+    float acc = 0.f;
+    for (int t = lane; t < smp.ntap; t += 64)
         acc = fmaf(smp.w[base + t], field[smp.idx[base + t]], acc);
-    smp.out[(long long)r * smp.out_stride + step] = acc;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        acc += __shfl_xor(acc, off, 64);
+    if (lane == 0)
+        smp.out[(long long)r * smp.out_stride + step] = acc;
 }
 
 constexpr float kTwelfth = 1.f / 12.f;
@@ -1174,7 +1192,7 @@ void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                    const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
     const int nt = 64 * ls.waves;
-    int smp_blocks = (p.smp.count + nt - 1) / nt;
+    int smp_blocks = (p.smp.count * sample_lanes(p.smp.ntap) + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks);
     if (d.nd == 2) {
 #define STRIDE_LAUNCH2D(RY_, W_)                                                                  \
@@ -1205,10 +1223,10 @@ void launch_step_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
 
 template <int R, bool ADJ>
 void launch_batched_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
-                      const SlotStep* table, int nslots, int max_samples, hipStream_t s)
+                      const SlotStep* table, int nslots, int max_sample_threads, hipStream_t s)
 {
     const int nt = 64 * ls.waves;
-    int smp_blocks = (max_samples + nt - 1) / nt;
+    int smp_blocks = (max_sample_threads + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks, nslots);
     if (d.nd == 2) {
 #define STRIDE_LAUNCH2DB(RY_, W_)                                                                  \
@@ -1302,7 +1320,7 @@ void launch_sample(const SampleSet& smp, const float* field, int step, hipStream
 {
     if (smp.count <= 0)
         return;
-    int blocks = (smp.count + kThreads - 1) / kThreads;
+    int blocks = (smp.count * sample_lanes(smp.ntap) + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(sample_kernel, dim3(blocks), dim3(kThreads), 0, s, smp, field, step);
 }
 
