@@ -109,6 +109,8 @@ def lib():
         L.oracle_num_threads.restype = ctypes.c_int
         L.oracle_fd1_weights.argtypes = [ctypes.c_int, dp]
         L.oracle_taps_per_point.argtypes = [gp]
+        L.oracle_lowpass.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     ctypes.c_double]
         L.oracle_taps_per_point.restype = ctypes.c_int
         L.oracle_medium_operator.argtypes = [gp, dp, dp, dp]
         L.oracle_forward_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
@@ -281,3 +283,14 @@ def forward_medium(grid: Grid, vp, src_xyz, wavelet, rec_xyz, rho=None, alpha0=N
                                      _d(traces))
     _check(rc, "forward_medium")
     return traces
+
+
+def lowpass(signals, dt: float, f_max: float) -> np.ndarray:
+    """Zero-phase Hann-windowed-sinc low-pass of [count][nt] signals."""
+    x = np.ascontiguousarray(np.asarray(signals, dtype=np.float64))
+    shape = x.shape
+    x = x.reshape(-1, shape[-1])
+    out = np.zeros_like(x)
+    rc = lib().oracle_lowpass(_d(x), _d(out), x.shape[0], x.shape[1], float(dt), float(f_max))
+    _check(min(rc, 0), "lowpass")
+    return out.reshape(shape)

@@ -923,3 +923,38 @@ int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double
     solve_free(&S);
     return rc;
 }
+
+/* ------------------------------------------------------------------------
+ * Zero-phase FIR low-pass (see the header). */
+int oracle_lowpass(const double *in, double *out, int count, int nt, double dt, double f_max)
+{
+    if (!in || !out || count < 0 || nt < 1 || !(dt > 0) || !(f_max > 0) || f_max * dt >= 0.5)
+        return -1;
+    const double pi = 3.14159265358979323846;
+    int K = (int)ceil(2.0 / (f_max * dt));
+    double *h = malloc(sizeof(double) * (2 * K + 1));
+    if (!h)
+        return -7;
+    double sum = 0.0;
+    for (int k = -K; k <= K; k++) {
+        double x = 2.0 * f_max * dt * k;
+        double sc = k == 0 ? 1.0 : sin(pi * x) / (pi * x);
+        double win = 0.5 + 0.5 * cos(pi * k / (K + 1.0));
+        h[k + K] = 2.0 * f_max * dt * sc * win;
+        sum += h[k + K];
+    }
+    for (int k = 0; k <= 2 * K; k++)
+        h[k] /= sum;
+    for (int c = 0; c < count; c++)
+        for (int n = 0; n < nt; n++) {
+            double acc = 0.0;
+            for (int k = -K; k <= K; k++) {
+                int m = n - k;
+                if (m >= 0 && m < nt)
+                    acc += h[k + K] * in[(long)c * nt + m];
+            }
+            out[(long)c * nt + n] = acc;
+        }
+    free(h);
+    return K;
+}

@@ -165,6 +165,14 @@ int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double
                           int nsrc, const double *src_xyz, const double *wavelet,
                           int nrec, const double *rec_xyz, double *traces);
 
+/* Zero-phase low-pass of [count][nt] signals sampled at dt (the band-limiting
+ * of wavelets and traces per frequency block, Sec. 3.2): out = h * in with
+ * zeros outside the record, where h is a Hann-windowed sinc of cutoff f_max,
+ *   h_k = 2 f_max dt sinc(2 f_max k dt) (0.5 + 0.5 cos(pi k / (K + 1))),
+ *   |k| <= K = ceil(2 / (f_max dt)) (two periods of the cutoff each side),
+ * scaled so that sum_k h_k = 1.  Returns the number of taps K, or -1. */
+int oracle_lowpass(const double *in, double *out, int count, int nt, double dt, double f_max);
+
 int oracle_num_threads(void);
 
 #ifdef __cplusplus

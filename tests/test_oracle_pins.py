@@ -760,3 +760,43 @@ def test_sinc_taps_beyond_the_padded_array_refused():
     with pytest.raises(oracle.OracleError):
         oracle.taps(g, np.array([[0.5, 10.5]]))
     oracle.taps(g, np.array([[3.5, 10.5]]))
+
+
+# ------------------------------------------ band-limiting for frequency blocks
+
+def _gain(f, f_max, dt=8e-8, nt=2000):
+    t = np.arange(nt) * dt
+    x = np.sin(2 * np.pi * f * t + 0.4)
+    y = oracle.lowpass(x[None], dt, f_max)[0]
+    sl = slice(300, nt - 300)                    # away from the record ends
+    return np.linalg.norm(y[sl]) / np.linalg.norm(x[sl]), np.abs(y[sl] - x[sl]).max()
+
+
+def test_lowpass_passes_dc_and_the_passband_without_phase():
+    """Unit gain at DC; sines at 0.3 and 0.5 of the cutoff come through within
+    0.5 % in amplitude and without a phase shift (zero-phase filter)."""
+    y = oracle.lowpass(np.ones((1, 1000)), 8e-8, 3e5)[0]
+    np.testing.assert_allclose(y[200:800], 1.0, rtol=0, atol=1e-12)
+    for frac in (0.3, 0.5):
+        g, err = _gain(frac * 3e5, 3e5)
+        assert abs(g - 1) < 5e-3 and err < 6e-3, (frac, g, err)
+
+
+def test_lowpass_cutoff_and_stopband():
+    """Half amplitude at the cutoff (the symmetric transition of a windowed
+    sinc) and below 5e-3 from 1.6 times the cutoff on."""
+    g, _ = _gain(3e5, 3e5)
+    assert abs(g - 0.5) < 0.01, g
+    for frac in (1.6, 2.0, 3.0):
+        g, _ = _gain(frac * 3e5, 3e5)
+        assert g < 5e-3, (frac, g)
+
+
+def test_lowpass_impulse_response_is_symmetric_and_linear():
+    x = np.zeros((2, 600))
+    x[0, 300] = 1.0
+    x[1] = np.random.default_rng(1).standard_normal(600)
+    y = oracle.lowpass(x, 8e-8, 3e5)
+    np.testing.assert_allclose(y[0, 300 - 80:300], y[0, 301:301 + 80][::-1], rtol=0, atol=1e-15)
+    z = oracle.lowpass((2 * x[0] - 3 * x[1])[None], 8e-8, 3e5)[0]
+    np.testing.assert_allclose(z, 2 * y[0] - 3 * y[1], rtol=0, atol=1e-12)
