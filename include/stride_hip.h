@@ -155,6 +155,26 @@ int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const
                                const float* alpha0, int32_t att_power, const float* wavelet,
                                float* traces, void* ws, size_t ws_bytes, void* stream);
 
+/* One gradient-descent step of an inversion loop (Sec. 2.2 local optimiser):
+ *   vp[i] = clamp(vp[i] - step_size m[i] g[i] / max_j |m[j] g[j]|, vmin, vmax),
+ * m the mask (NULL = 1 everywhere; e.g. 0 outside a region of interest), so
+ * step_size is the largest change of vp.  All arrays device, n values; work is
+ * one device uint32 of scratch (it receives max |m g| as float bits).  A zero
+ * gradient leaves vp clamped but unchanged.  Errors: INVALID_ARG, HIP. */
+int stride_descent_step(float* vp, const float* grad, const float* mask, int64_t n, float step_size,
+                        float vmin, float vmax, uint32_t* work, void* stream);
+
+/* Zero-phase low-pass of [count][nt] device rows sampled at dt, for the
+ * frequency blocks of an inversion (Sec. 3.2 band-limits wavelets and traces
+ * per block): out = h * in with zeros beyond the record, h the Hann-windowed
+ * sinc of cutoff f_max over |k| <= K = ceil(2 / (f_max dt)),
+ *   h_k = 2 f_max dt sinc(2 f_max k dt) (0.5 + 0.5 cos(pi k / (K + 1))),
+ * scaled to unit sum (unit gain at DC, half amplitude at f_max).  out may alias
+ * in.  Needs f_max < 1/(2 dt) and nt + 2K + 1 <= 15360 samples.  Errors:
+ * INVALID_ARG, HIP. */
+int stride_lowpass(const float* in, float* out, int32_t count, int32_t nt, double dt,
+                   double f_max, void* stream);
+
 /* Forward solve that also keeps the checkpoints of the forward wavefield in
  * ws (GRADIENT-sized) for a later stride_backward with the same ws, vp and
  * wavelet. */

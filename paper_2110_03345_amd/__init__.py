@@ -19,9 +19,11 @@ from ._abi import (  # noqa: F401
     lib,
     make_grid,
     stride_backward,
+    stride_descent_step,
     stride_forward,
     stride_forward_save,
     stride_gradient,
+    stride_lowpass,
     stride_plan_create,
     stride_plan_destroy,
     stride_plan_forward,

@@ -28,7 +28,8 @@ STRIDE_MODE_FORWARD_MEDIUM = 2
 
 EXPORTS = (
     "stride_plan_create", "stride_plan_destroy", "stride_plan_padded_shape",
-    "stride_workspace_bytes", "stride_plan_forward", "stride_plan_forward_medium",
+    "stride_workspace_bytes", "stride_plan_forward", "stride_plan_forward_medium", "stride_lowpass",
+    "stride_descent_step",
     "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
     "stride_schedule_info", "stride_last_error", "stride_error_string",
@@ -80,6 +81,9 @@ def lib():
         L.stride_workspace_bytes.argtypes = [vp_, i32, sz, ctypes.POINTER(sz)]
         L.stride_plan_forward.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
         L.stride_plan_forward_medium.argtypes = [vp_, vp_, vp_, vp_, i32, vp_, vp_, vp_, sz, vp_]
+        L.stride_lowpass.argtypes = [vp_, vp_, i32, i32, ctypes.c_double, ctypes.c_double, vp_]
+        L.stride_descent_step.argtypes = [vp_, vp_, vp_, ctypes.c_int64, ctypes.c_float,
+                                          ctypes.c_float, ctypes.c_float, vp_, vp_]
         L.stride_forward_save.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
         L.stride_backward.argtypes = [vp_, vp_, vp_, vp_, vp_, vp_, vp_, sz, vp_]
         L.stride_plan_gradient.argtypes = [vp_, vp_, vp_, vp_, vp_, vp_, vp_, vp_, sz, vp_]
@@ -229,6 +233,31 @@ def stride_plan_forward_medium(plan, vp, rho, alpha0, att_power, wavelet, traces
     _check(lib().stride_plan_forward_medium(plan, _dev(vp), _dev(rho), _dev(alpha0), int(att_power),
                                             _dev(wavelet), _dev(traces), _dev(ws), ws.numel(),
                                             _stream(stream)))
+
+
+def stride_lowpass(x, dt: float, f_max: float, out=None, stream=None):
+    """Zero-phase low-pass of a [count][nt] float32 CUDA tensor (out may be x)."""
+    import torch
+    _dev(x, None, torch.float32, "signals")
+    if out is None:
+        out = torch.empty_like(x)
+    nt = x.shape[-1]
+    count = x.numel() // nt if nt else 0
+    _check(lib().stride_lowpass(_dev(x), _dev(out), count, nt, float(dt), float(f_max),
+                                _stream(stream)))
+    return out
+
+
+def stride_descent_step(vp, grad, step_size: float, vmin: float, vmax: float, work, mask=None,
+                        stream=None):
+    """vp = clamp(vp - step_size * m g / max|m g|, vmin, vmax) in place."""
+    import torch
+    _dev(vp, None, torch.float32, "vp")
+    _dev(grad, tuple(vp.shape), torch.float32, "grad")
+    if mask is not None:
+        _dev(mask, tuple(vp.shape), torch.float32, "mask")
+    _check(lib().stride_descent_step(_dev(vp), _dev(grad), _dev(mask), vp.numel(), float(step_size),
+                                     float(vmin), float(vmax), _dev(work), _stream(stream)))
 
 
 def stride_forward_save(plan, vp, wavelet, traces, ws, stream=None):

@@ -145,6 +145,13 @@ void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const Stenci
 
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
+// Zero-phase FIR low-pass of [count][nt] rows (out may alias in); K taps per side.
+int lowpass_taps(double dt, double f_max);
+void launch_lowpass(const float* in, float* out, int count, int nt, double dt, double f_max,
+                    hipStream_t s);
+// vp = clamp(vp - step m g / max|m g|, vmin, vmax); work: one device word.
+void launch_descent(float* vp, const float* g, const float* mask, long long n, float step,
+                    float vmin, float vmax, unsigned* work, hipStream_t s);
 void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s);
 // First-derivative weights in FP64 for the medium preparation.
 struct Fd1 {

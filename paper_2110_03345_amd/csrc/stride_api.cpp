@@ -1227,6 +1227,41 @@ int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const
                           as_stream(stream));
 }
 
+int stride_descent_step(float* vp, const float* grad, const float* mask, int64_t n, float step_size,
+                        float vmin, float vmax, uint32_t* work, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || (n > 0 && (!vp || !grad || !work)))
+        return fail(STRIDE_E_INVALID_ARG, "vp, grad and work must be device pointers");
+    if (!(step_size >= 0.f) || !(vmin <= vmax))
+        return fail(STRIDE_E_INVALID_ARG, "step_size must be >= 0 and vmin <= vmax");
+    if (n == 0)
+        return STRIDE_OK;
+    launch_descent(vp, grad, mask, n, step_size, vmin, vmax, work, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return STRIDE_OK;
+}
+
+int stride_lowpass(const float* in, float* out, int32_t count, int32_t nt, double dt,
+                   double f_max, void* stream)
+{
+    g_err.clear();
+    if (count < 0 || nt < 1 || (count > 0 && (!in || !out)))
+        return fail(STRIDE_E_INVALID_ARG, "bad low-pass arguments");
+    if (!(dt > 0) || !(f_max > 0) || !(f_max * dt < 0.5))
+        return fail(STRIDE_E_INVALID_ARG, "f_max must lie in (0, 1/(2 dt)) (got %g at dt %g)", f_max,
+                    dt);
+    const long long lds = 4LL * (2LL * lowpass_taps(dt, f_max) + 1 + nt);
+    if (lds > 60 * 1024)
+        return fail(STRIDE_E_INVALID_ARG,
+                    "low-pass row too long: nt + 2 ceil(2/(f_max dt)) + 1 must stay within 15360");
+    if (count == 0)
+        return STRIDE_OK;
+    launch_lowpass(in, out, count, nt, dt, f_max, as_stream(stream));
+    HIP_TRY(hipGetLastError());
+    return STRIDE_OK;
+}
+
 int stride_forward_save(const stride_plan_t* plan, const float* vp, const float* wavelet,
                         float* traces, void* ws, size_t ws_bytes, void* stream)
 {

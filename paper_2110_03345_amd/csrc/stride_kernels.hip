@@ -1064,6 +1064,88 @@ __global__ void medium_check_kernel(const float* vp, const float* rho, const flo
     }
 }
 
+// Zero-phase low-pass of one [nt] row per block (band-limiting for the
+// frequency blocks of an inversion): the Hann-windowed sinc taps
+// h_k = 2 fc dt sinc(2 fc k dt) (0.5 + 0.5 cos(pi k / (K + 1))), |k| <= K,
+// normalised to unit sum, are built in LDS (FP64, rounded once), the row is
+// staged in LDS (so out may alias in), and each thread convolves its samples
+// with zeros beyond the record.
+__global__ __launch_bounds__(256) void lowpass_kernel(const float* in, float* out, int nt,
+                                                      double fdt, int K)
+{
+    extern __shared__ float lds[];
+    float* h = lds;                  // 2K + 1 taps
+    float* row = lds + 2 * K + 1;    // nt samples
+    __shared__ double part[256];
+    const double pi = 3.14159265358979323846;
+    double sum = 0.0;
+    for (int k = -K + (int)threadIdx.x; k <= K; k += 256) {
+        const double x = 2.0 * fdt * k;
+        const double sc = k == 0 ? 1.0 : sin(pi * x) / (pi * x);
+        const double v = 2.0 * fdt * sc * (0.5 + 0.5 * cos(pi * k / (K + 1.0)));
+        sum += v;
+    }
+    part[threadIdx.x] = sum;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    const double total = part[0];
+    for (int k = -K + (int)threadIdx.x; k <= K; k += 256) {
+        const double x = 2.0 * fdt * k;
+        const double sc = k == 0 ? 1.0 : sin(pi * x) / (pi * x);
+        h[k + K] = (float)(2.0 * fdt * sc * (0.5 + 0.5 * cos(pi * k / (K + 1.0))) / total);
+    }
+    const float* src = in + (long long)blockIdx.x * nt;
+    for (int n = threadIdx.x; n < nt; n += 256)
+        row[n] = src[n];
+    __syncthreads();
+    float* dst = out + (long long)blockIdx.x * nt;
+    for (int n = threadIdx.x; n < nt; n += 256) {
+        const int klo = max(-K, n - nt + 1), khi = min(K, n);
+        float acc = 0.f;
+        for (int k = klo; k <= khi; ++k)
+            acc = fmaf(h[k + K], row[n - k], acc);
+        dst[n] = acc;
+    }
+}
+
+// Gradient-descent step of the inversion loop: gmax = max |m g| (as float
+// bits; order-independent, so reproducible), then vp = clamp(vp - step m g /
+// gmax, vmin, vmax) with the mask m (1 where absent).
+__global__ __launch_bounds__(256) void grad_absmax_kernel(const float* g, const float* mask,
+                                                          long long n, unsigned* gmax)
+{
+    __shared__ unsigned smax;
+    if (threadIdx.x == 0)
+        smax = 0u;
+    __syncthreads();
+    unsigned m = 0u;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float v = fabsf(mask ? mask[i] * g[i] : g[i]);
+        m = max(m, __float_as_uint(v));
+    }
+    atomicMax(&smax, m);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(gmax, smax);
+}
+
+__global__ void descent_kernel(float* vp, const float* g, const float* mask, long long n,
+                               float step, float vmin, float vmax, const unsigned* gmax)
+{
+    const float gm = __uint_as_float(*gmax);
+    const float scale = gm > 0.f ? step / gm : 0.f;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float d = mask ? mask[i] * g[i] : g[i];
+        vp[i] = fminf(fmaxf(fmaf(-scale, d, vp[i]), vmin), vmax);
+    }
+}
+
 // Residual r = traces - observed and J = 1/2 sum r^2 in FP64.  Block b reduces
 // a fixed contiguous range in a fixed tree order and misfit_final_kernel adds
 // the partial sums in block order, so the result is bitwise reproducible.
@@ -1356,6 +1438,29 @@ void launch_medium_check(const float* vp, const float* rho, const float* alpha0,
     launch_fill(reinterpret_cast<float*>(flags + 2), 2, 0.f, s);
     hipLaunchKernelGGL(medium_check_kernel, dim3(grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024),
                        dim3(256), 0, s, vp, rho, alpha0, n, att_power, dt, flags);
+}
+
+int lowpass_taps(double dt, double f_max)
+{
+    return (int)std::ceil(2.0 / (f_max * dt));
+}
+
+void launch_lowpass(const float* in, float* out, int count, int nt, double dt, double f_max,
+                    hipStream_t s)
+{
+    const int K = lowpass_taps(dt, f_max);
+    const size_t lds = sizeof(float) * (size_t)(2 * K + 1 + nt);
+    hipLaunchKernelGGL(lowpass_kernel, dim3(count), dim3(256), lds, s, in, out, nt, f_max * dt, K);
+}
+
+void launch_descent(float* vp, const float* g, const float* mask, long long n, float step,
+                    float vmin, float vmax, unsigned* work, hipStream_t s)
+{
+    launch_fill(reinterpret_cast<float*>(work), 1, 0.f, s);
+    const int blocks = grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024;
+    hipLaunchKernelGGL(grad_absmax_kernel, dim3(blocks), dim3(256), 0, s, g, mask, n, work);
+    hipLaunchKernelGGL(descent_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, vp, g, mask, n, step,
+                       vmin, vmax, work);
 }
 
 void launch_prep_k(const Dims& d, const float* vp, double dt, float* k, hipStream_t s)

@@ -1,0 +1,90 @@
+"""The inversion loop: the library's low-pass and descent step against their
+definitions, and a frequency-block FWI run (random mini-batches of shots
+through the batching engine) against the same loop driven by the FP64
+oracle, reconstructing two inclusions."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2110_03345_amd as S
+    from paper_2110_03345_amd import fwi
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).cuda()
+
+
+def test_lowpass_matches_oracle_and_runs_in_place():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((5, 700))
+    for f_max in (2e5, 4e5):
+        ref = oracle.lowpass(x, 8e-8, f_max)
+        got = S.stride_lowpass(dev(x), 8e-8, f_max).cpu().numpy()
+        assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+        t = dev(x)
+        S.stride_lowpass(t, 8e-8, f_max, out=t)
+        assert np.abs(t.cpu().numpy() - ref).max() <= 1e-5 * np.abs(ref).max()
+    with pytest.raises(S.StrideError):
+        S.stride_lowpass(dev(x), 8e-8, 7e6)          # above the Nyquist frequency
+
+
+def test_descent_step_matches_its_definition():
+    rng = np.random.default_rng(4)
+    vp = 1500 + 20 * rng.standard_normal((30, 40))
+    g = rng.standard_normal((30, 40))
+    m = (rng.uniform(size=(30, 40)) > 0.3).astype(np.float64)
+    want = np.clip(vp - 8.0 * m * g / np.abs(m * g).max(), 1480.0, 1530.0)
+    v = dev(vp)
+    work = torch.zeros(1, dtype=torch.int32, device="cuda")
+    S.stride_descent_step(v, dev(g), 8.0, 1480.0, 1530.0, work, mask=dev(m))
+    np.testing.assert_allclose(v.cpu().numpy(), want, rtol=0, atol=2e-3)
+
+
+def _oracle_loop(sv, observed, freqs, iters, per_iter, step, seed):
+    g = oracle.Grid(**sv.grid_kwargs())
+    rng = np.random.default_rng(seed)
+    vp = sv.vp_start.astype(np.float64)
+    m = sv.roi.astype(np.float64)
+    wav = sv.wavelet.astype(np.float64)
+    for f_max in freqs:
+        wf = oracle.lowpass(wav[None], sv.dt, f_max)
+        of = [oracle.lowpass(o, sv.dt, f_max) for o in observed]
+        for batch in fwi.shot_batches(len(observed), per_iter, iters, rng):
+            G = np.zeros(sv.shape)
+            for i in batch:
+                G += oracle.gradient(g, vp, sv.positions[i:i + 1], wf, sv.positions, of[i])[2]
+            G *= m
+            vp = np.clip(vp - step * G / np.abs(G).max(), 1400.0, 1700.0)
+    return vp
+
+
+def test_fwi_loop_matches_the_oracle_loop_and_reconstructs():
+    sv = W.ring_survey_2d()
+    g = oracle.Grid(**sv.grid_kwargs())
+    observed = [oracle.forward(g, sv.vp_true, sv.positions[i:i + 1], sv.wavelet[None].astype(np.float64),
+                               sv.positions) for i in range(len(sv.positions))]
+    freqs, iters, per_iter, step = (3e5, 4e5, 5e5), 4, 4, 10.0
+    survey = fwi.Survey(sv.shape, sv.spacing, sv.space_order, sv.nb, sv.vref, sv.dt, sv.nt,
+                        sv.positions, sv.positions, dev(sv.wavelet),
+                        dev(np.stack(observed)))
+    opt = fwi.GradientDescent(step, bounds=(1400.0, 1700.0), mask=dev(sv.roi))
+    vp, hist = fwi.invert(survey, dev(sv.vp_start), freqs, iters, per_iter, opt, seed=0,
+                          log=lambda s: print(s, flush=True))
+    assert hist.shot_gradients == len(freqs) * iters * per_iter
+    # every shot once per band
+    for b in range(len(freqs)):
+        used = sorted(i for sh in hist.shots[b * iters:(b + 1) * iters] for i in sh)
+        assert used == list(range(16))
+    ref = _oracle_loop(sv, observed, freqs, iters, per_iter, step, seed=0)
+    got = vp.cpu().numpy()
+    assert np.abs(got - ref).max() < 0.5, np.abs(got - ref).max()
+    err0 = np.abs(sv.vp_start - sv.vp_true)[sv.roi].mean()
+    err = np.abs(got - sv.vp_true)[sv.roi].mean()
+    print(f"ROI model error {err0:.2f} -> {err:.2f} m/s", flush=True)
+    assert err < 0.6 * err0

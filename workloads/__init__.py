@@ -7,7 +7,7 @@ arithmetic, and it imports neither the HIP product package nor the oracle.
 from .wavelets import tone_burst
 from .geometry import ring, fibonacci_hemisphere, grid_node_ring_2d
 from .phantoms import homogeneous, breast_2d, head_3d, head_3d_skull_only, medium
-from .configs import Workload, config1, config2, config3, config4, tiny_2d, tiny_3d, CONFIG_NAMES
+from .configs import Workload, config1, config2, config3, config4, tiny_2d, tiny_3d, CONFIG_NAMES, RingSurvey, ring_survey_2d
 
 __all__ = [
     "tone_burst", "ring", "fibonacci_hemisphere", "grid_node_ring_2d",

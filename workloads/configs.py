@@ -166,3 +166,49 @@ def tiny_3d(n=(20, 22, 24), nt: int = 60, space_order: int = 10, nb: int = 5, se
     wav = tone_burst(nt, dt, f0=0.6e6, nsrc=nsrc)
     wav *= rng.uniform(0.5, 1.5, size=(nsrc, 1)).astype(np.float32)
     return Workload("tiny_3d", tuple(n), dx, space_order, nb, vref, dt, nt, vp, wav, src, rec)
+
+
+@dataclass
+class RingSurvey:
+    """A 2D ring survey for inversion runs: every transducer fires once and
+    all record (Sec. 3.2 imaging setup, at a reduced size)."""
+    shape: tuple
+    spacing: float
+    space_order: int
+    nb: int
+    vref: float
+    dt: float
+    nt: int
+    vp_true: np.ndarray
+    vp_start: np.ndarray
+    positions: np.ndarray      # [n][2] transducers (sources and receivers)
+    wavelet: np.ndarray        # [nt]
+    roi: np.ndarray            # bool, the region inside the ring the inversion updates
+
+    def grid_kwargs(self):
+        return dict(shape=self.shape, spacing=self.spacing, space_order=self.space_order,
+                    nb=self.nb, vref=self.vref, dt=self.dt, nt=self.nt)
+
+
+def ring_survey_2d(n: int = 100, dx: float = 0.5e-3, ntrans: int = 16, seed: int = 0) -> RingSurvey:
+    """n x n grid at dx; water 1500 m/s with a 1560 m/s disc (radius 8 mm)
+    and a 1460 m/s disc (4 mm) whose centres are jittered by the seed;
+    ntrans transducers on a ring of radius 0.44 n dx; 500 kHz 3-cycle burst;
+    dt at CFL 0.3 of the fastest speed; records long enough to cross the ring
+    and back out; the region of interest is the disc 4 mm inside the ring."""
+    rng = np.random.default_rng(seed)
+    X = np.meshgrid(np.arange(n) * dx, np.arange(n) * dx, indexing="ij")
+    cen = (n - 1) * dx / 2
+    vp = np.full((n, n), 1500.0)
+    j = rng.uniform(-1e-3, 1e-3, size=4)
+    vp[(X[0] - cen - 4e-3 - j[0]) ** 2 + (X[1] - cen + 2e-3 - j[1]) ** 2 < (8e-3) ** 2] = 1560.0
+    vp[(X[0] - cen + 7e-3 - j[2]) ** 2 + (X[1] - cen - 6e-3 - j[3]) ** 2 < (4e-3) ** 2] = 1460.0
+    R = 0.44 * n * dx
+    ang = np.arange(ntrans) * 2 * np.pi / ntrans
+    pos = np.stack([cen + R * np.cos(ang), cen + R * np.sin(ang)], axis=1)
+    dt = 0.3 * dx / 1560.0
+    nt = int((2 * R * 0.95 / 1500.0 + 8e-6) / dt)
+    roi = (X[0] - cen) ** 2 + (X[1] - cen) ** 2 < (R - 4e-3) ** 2
+    return RingSurvey((n, n), dx, 8, 16, 1500.0, dt, nt, vp.astype(np.float32),
+                      np.full((n, n), 1500.0, dtype=np.float32), pos,
+                      tone_burst(nt, dt, nsrc=1)[0], roi)
