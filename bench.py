@@ -83,6 +83,10 @@ WORKLOADS = {
                "model, binomial checkpointing within the HBM budget",
     "config3": "2D breast-like phantom, 512^2 at 0.2 mm + 40-cell sponge (592^2 padded), 8th order, "
                "1500 steps, shot 0 of the 64-shot ring survey; gradient at 1500 m/s",
+    "fwi": "frequency-block inversion of the 2D breast-like phantom of config 3 (512^2 at 0.2 mm, "
+           "1500 steps, 64 shots on a 256-element ring): bands 300/400/500/600 kHz, 4 iterations of 16 "
+           "random shots per band (each shot once per band), masked normalised gradient descent of "
+           "10 m/s from 1500 m/s",
     "serving": "seeded Poisson stream of forward (70%) and gradient (30%) requests of 1-16 shots, each "
                "with its own phantom and ring/hemisphere geometry; served with continuous batching vs "
                "one request at a time through the plain entry points",
@@ -167,6 +171,67 @@ def cpu_baseline(w, vp_model, obs_np, seconds):
         "sample": f"{w.name} grid, first {nt_s} of {w.nt} steps, one shot gradient "
                   f"(FP64 C, OpenMP), {el:.1f} s",
     }
+
+
+def fwi_bench(args):
+    """Shot gradients per second inside the frequency-block inversion loop and
+    the reconstruction it reaches (mean |vp - vp_true| inside the ring)."""
+    import numpy as np
+    import torch
+
+    import paper_2110_03345_amd as S
+    import workloads as W
+    from paper_2110_03345_amd import fwi
+
+    dev = torch.device("cuda:0")
+    w = W.config3()
+    shots = w.shot_src_xyz
+    wav = torch.from_numpy(w.wavelet[0]).to(dev)
+    vp_t = torch.from_numpy(w.vp_true).to(dev)
+    obs = torch.empty((shots.shape[0], w.rec_xyz.shape[0], w.nt), dtype=torch.float32, device=dev)
+    fws = None
+    for i in range(shots.shape[0]):          # observed data: forward solves on the phantom
+        plan = S.Plan.from_workload(w, src_xyz=shots[i:i + 1])
+        if fws is None:
+            fws = plan.workspace(S.STRIDE_MODE_FORWARD, device=dev)
+        plan.forward(vp_t, wav.reshape(1, -1), traces=obs[i], ws=fws)
+    torch.cuda.synchronize()
+    del fws
+    X = np.meshgrid(*[np.arange(n) * w.spacing for n in w.shape], indexing="ij")
+    cen = (w.shape[0] - 1) * w.spacing / 2
+    roi = (X[0] - cen) ** 2 + (X[1] - cen) ** 2 < (45e-3 - 4e-3) ** 2
+    survey = fwi.Survey(w.shape, w.spacing, w.space_order, w.nb, w.vref, w.dt, w.nt, shots,
+                        w.rec_xyz, wav, obs)
+    opt = fwi.GradientDescent(10.0, bounds=(1400.0, 1650.0),
+                              mask=torch.from_numpy(roi.astype(np.float32)).to(dev))
+    vp0 = torch.from_numpy(w.vp_start).to(dev)
+    freqs = (3e5, 4e5, 5e5, 6e5)
+    vp, hist = fwi.invert(survey, vp0, freqs, 4, 16, opt, seed=0,
+                          log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
+    err0 = float(np.abs(w.vp_start - w.vp_true)[roi].mean())
+    err = float(np.abs(vp.cpu().numpy() - w.vp_true)[roi].mean())
+    line = {
+        "metric": "shot gradients/s inside the frequency-block inversion loop",
+        "value": hist.shot_gradients / hist.seconds,
+        "unit": "shot gradients/s",
+        "n_gpus": 1,
+        "steps": len(hist.misfit),
+        "warmup": 0,
+        "ms_per_step": 1e3 * hist.seconds / len(hist.misfit),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded breast-like phantom; observed data from forward solves on it)",
+        "config": {"workload": f"fwi: {WORKLOADS['fwi']}", "padded_points": w.padded_points,
+                   "nt": w.nt, "shots": int(shots.shape[0]), "shot_gradients": hist.shot_gradients},
+        "seconds": hist.seconds,
+        "misfit_per_iteration": hist.misfit,
+        "roi_model_error_m_s": {"start": err0, "final": err},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 def serving_bench(args):
@@ -264,6 +329,9 @@ def main():
     if args.workload == "serving":
         torch.cuda.set_device(0)
         return serving_bench(args)
+    if args.workload == "fwi":
+        torch.cuda.set_device(0)
+        return fwi_bench(args)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.calibrate_copy:
