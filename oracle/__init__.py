@@ -214,19 +214,17 @@ def forward(grid: Grid, vp, src_xyz, wavelet, rec_xyz, snap_steps: Sequence[int]
 
 
 def adjoint(grid: Grid, vp, src_xyz, wavelet, rec_xyz, grad_traces, seg: int = 0):
-    """(dvp, dwavelet): the transpose of the forward Jacobian applied to grad_traces.
-    The fourth-order-in-time scheme returns dwavelet None (not provided)."""
+    """(dvp, dwavelet): the transpose of the forward Jacobian applied to grad_traces."""
     vp = _f64(vp, grid.shape)
     src = _f64(src_xyz).reshape(-1, grid.ndim)
     rec = _f64(rec_xyz).reshape(-1, grid.ndim)
     wav = _f64(wavelet).reshape(src.shape[0], grid.nt)
     gtr = _f64(grad_traces).reshape(rec.shape[0], grid.nt)
     dvp = np.zeros(grid.shape)
-    dwav = np.zeros((src.shape[0], grid.nt)) if grid.time_order != 4 else None
+    dwav = np.zeros((src.shape[0], grid.nt))
     g = grid.c()
     rc = lib().oracle_adjoint(ctypes.byref(g), _d(vp), src.shape[0], _d(src), _d(wav),
-                              rec.shape[0], _d(rec), _d(gtr), _d(dvp),
-                              _d(dwav) if dwav is not None else None, seg)
+                              rec.shape[0], _d(rec), _d(gtr), _d(dvp), _d(dwav), seg)
     _check(rc, "adjoint")
     return dvp, dwav
 

@@ -549,7 +549,7 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
                    double *dvp, double *dwavelet, int seg)
 {
     const int order = time_order_of(g);
-    if ((order != 2 && order != 4) || (order == 4 && dwavelet))
+    if (order != 2 && order != 4)
         return -1;
     solve_t S;
     int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
@@ -647,6 +647,17 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
                 double v = lu[p] + src[p];
                 G_acc[p] += w1[p] * (v + lp[p] / 12.0) + qf[p] * v / 12.0;
             }
+            /* source cotangent before the time filter: dJ/dSt^m = w^{m+1} + q/12,
+             * sampled with the source taps / cell volume */
+            if (dwavelet)
+                for (int s = 0; s < nsrc; s++) {
+                    double acc = 0.0;
+                    for (int t = 0; t < S.ntap; t++) {
+                        long i = S.sidx[(long)s * S.ntap + t];
+                        acc += S.sw[(long)s * S.ntap + t] * (w1[i] + qf[i] / 12.0);
+                    }
+                    dwavelet[(long)s * nt + m] = acc / G->cellvol;
+                }
             if (m == 0)
                 break;
             oracle_laplacian(g, qf, lq);
@@ -687,6 +698,19 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
         }
     }
 
+    if (dwavelet && order == 4) {
+        /* transpose of St^n = (S^{n-1} + 10 S^n + S^{n+1}) / 12 (zero outside 0..nt-1) */
+        double *h = malloc(sizeof(double) * (size_t)nt);
+        if (!h)
+            rc = -7;
+        for (int s = 0; s < nsrc && h; s++) {
+            double *row = dwavelet + (long)s * nt;
+            memcpy(h, row, sizeof(double) * (size_t)nt);
+            for (int j = 0; j < nt; j++)
+                row[j] = ((j >= 1 ? h[j - 1] : 0.0) + 10.0 * h[j] + (j + 1 < nt ? h[j + 1] : 0.0)) / 12.0;
+        }
+        free(h);
+    }
     if (dvp) {
         /* dJ/dvp_pad = 2 G / vp_pad, then the transpose of the padding */
         for (long p = 0; p < N; p++)
@@ -697,7 +721,7 @@ int oracle_adjoint(const oracle_grid_t *g, const double *vp,
     free(w1); free(w2); free(w0); free(G_acc); free(lu);
     free(pf); free(lp); free(qf); free(lq);
     solve_free(&S);
-    return 0;
+    return rc;
 }
 
 int oracle_gradient(const oracle_grid_t *g, const double *vp,

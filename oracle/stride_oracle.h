@@ -109,7 +109,8 @@ int oracle_laplacian(const oracle_grid_t *g, const double *u, double *lu);
  *   w^m = a (2 w^{m+1} + q + (k/12) L q + k R^T g^m) - b w^{m+2}
  * and k dJ/dk sums w^{m+1} (v + (1/12) L p) + (1/12) q v with v = L u^m + St^m,
  * p = k v; dJ/dvp = P^T (2 G / vp) as in second order.  The wavelet
- * cotangent is not provided for time_order 4 (dwavelet must be NULL). */
+ * cotangent: dJ/dSt^m = w^{m+1} + q/12 sampled with the source taps / cell
+ * volume, then the transpose of the time filter, (h^{j-1} + 10 h^j + h^{j+1}) / 12. */
 int oracle_forward(const oracle_grid_t *g, const double *vp,
                    int nsrc, const double *src_xyz, const double *wavelet,
                    int nrec, const double *rec_xyz, double *traces,
