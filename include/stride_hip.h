@@ -87,9 +87,9 @@ typedef struct stride_grid {
                                St^n    = (S^{n-1} + 10 S^n + S^{n+1}) / 12,
                                u^{n+1} = a (2 u^n + p + (k/12) L p) - b u^{n-1};
                              stable up to sqrt(3) times the leapfrog CFL limit.
-                             Forward solves, gradients and stride_backward's dvp; the
-                             wavelet gradient (dwavelet) and the batching engine
-                             return INVALID_ARG for it */
+                             Forward solves, gradients and stride_backward (dvp, and
+                             dwavelet for nt <= 15360); the batching engine returns
+                             INVALID_ARG for it */
     int32_t interp;       /* off-grid sources and receivers (Sec. 2.4): 0 bi/tri-linear
                              (2 nodes per axis), 1 Kaiser-windowed sinc after Hicks
                              (8 nodes per axis: weight sinc(x) I0(b sqrt(1 - (x/4)^2)) /

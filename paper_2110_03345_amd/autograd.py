@@ -7,8 +7,7 @@ with needs_grad collects its gradient).  Here the same role is played by a
 torch.autograd.Function: forward runs the HIP forward solve and keeps binomial
 checkpoints of the forward wavefield in a device workspace; backward runs the
 HIP adjoint solve fused with the imaging condition and returns dJ/dvp (and,
-when asked, dJ/dwavelet: second-order time only) for any loss torch builds on
-the traces.
+when asked, dJ/dwavelet) for any loss torch builds on the traces.
 """
 from __future__ import annotations
 
@@ -29,8 +28,6 @@ class StrideWave(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, vp, wavelet, plan: Plan, budget_bytes: int = 0):
-        if plan.time_order == 4 and ctx.needs_input_grad[1]:
-            raise ValueError("the wavelet gradient is not provided for time_order 4")
         vp = vp.contiguous()
         wavelet = wavelet.contiguous()
         ws = plan.workspace(STRIDE_MODE_GRADIENT, budget_bytes, device=vp.device)

@@ -57,7 +57,8 @@ struct InjTable {
     const TileEntry* ent;
 };
 
-// Point sampling: out[r * out_stride + step] = sum_t w[r*ntap+t] * field[idx[r*ntap+t]].
+// Point sampling: v = scale * sum_t w[r*ntap+t] * field[idx[r*ntap+t]], stored to
+// out[r * out_stride + step] or, with accumulate, added to it.
 struct SampleSet {
     int count;
     const long long* idx;
@@ -65,6 +66,8 @@ struct SampleSet {
     float* out;
     int out_stride;
     int ntap;         // taps per point: 2^ndim (linear) or (2 r)^ndim (windowed sinc)
+    float scale;
+    int accumulate;
 };
 
 // Threads that sample one point: one for up to 8 taps, a wave64 (lanes over
@@ -145,6 +148,9 @@ void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const Stenci
 
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
+// In place, per [nt] row: h[j] = (h[j-1] + 10 h[j] + h[j+1]) / 12 (zero outside),
+// the transpose of the fourth-order scheme's source filter.
+void launch_time_filter3(float* rows, int count, int nt, hipStream_t s);
 // Zero-phase FIR low-pass of [count][nt] rows (out may alias in); K taps per side.
 int lowpass_taps(double dt, double f_max);
 void launch_lowpass(const float* in, float* out, int count, int nt, double dt, double f_max,

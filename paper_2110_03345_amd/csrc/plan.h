@@ -98,11 +98,11 @@ StepParams base_params(const stride_plan& P);
 // Receiver sampling of a field into out[nrec][nt]; source sampling into out[nsrc][nt].
 inline SampleSet rec_samples(const stride_plan& P, float* out)
 {
-    return SampleSet{P.nrec, P.rec_idx, P.rec_w, out, P.nt, P.ntap};
+    return SampleSet{P.nrec, P.rec_idx, P.rec_w, out, P.nt, P.ntap, 1.f, 0};
 }
 inline SampleSet src_samples(const stride_plan& P, float* out)
 {
-    return SampleSet{P.nsrc, P.src_idx, P.src_w, out, P.nt, P.ntap};
+    return SampleSet{P.nsrc, P.src_idx, P.src_w, out, P.nt, P.ntap, 1.f, 0};
 }
 
 // One step of a checkpointed gradient solve.

@@ -660,7 +660,7 @@ struct Runner {
 
     // Fourth-order adjoint step m: p = k (L u^m + St^m) and q = k L w^{m+1}
     // (no injection: the empty table), then w^m and the imaging update.
-    void adj4_launch(const StepOp& op, int wa, const float* grad_traces)
+    void adj4_launch(const StepOp& op, int wa, const float* grad_traces, float* dwavelet)
     {
         StepParams p = base_params(P);
         p.A = W.pool[op.a];
@@ -675,6 +675,10 @@ struct Runner {
         q.K = W.k;
         q.step = op.step;
         q.inj = P.no_inj;
+        // wavelet cotangent before the time filter: W_s (w + q/12) / cell volume,
+        // the w part sampled here, the q part added by the correction launch
+        if (dwavelet)
+            q.smp = src_samples(P, dwavelet);
         launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, q, s);
         StepParams c = base_params(P);
         c.A = W.q;
@@ -689,6 +693,11 @@ struct Runner {
         c.inj_sig = grad_traces;
         c.inj_stride = P.nt;
         c.img = P.no_inj;
+        if (dwavelet) {
+            c.smp = src_samples(P, dwavelet);
+            c.smp.scale = 1.f / 12.f;
+            c.smp.accumulate = 1;
+        }
         launch_step_mode(P.dims, P.R, true, kCorrect, P.cf, P.sp, P.ls_adj, c, s);
         adj_launches += 3;
     }
@@ -728,7 +737,7 @@ struct Runner {
             }
             ++adj_steps;
             if (P.torder == 4) {
-                adj4_launch(op, wa, grad_traces);
+                adj4_launch(op, wa, grad_traces, dwavelet);
                 wa = 1 - wa;
                 continue;
             }
@@ -941,9 +950,9 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
 {
     if (!vp || (!wavelet && P.nsrc > 0) || (!grad_traces && P.nrec > 0) || !dvp)
         return fail(STRIDE_E_INVALID_ARG, "vp, wavelet, grad_traces and dvp must be device pointers");
-    if (dwavelet && P.torder == 4)
+    if (dwavelet && P.torder == 4 && P.nt > 15360)
         return fail(STRIDE_E_INVALID_ARG,
-                    "the wavelet gradient is not provided for time_order 4 (pass dwavelet = NULL)");
+                    "the fourth-order wavelet gradient filters rows of at most 15360 samples");
     GradWs W;
     int rc = grad_ws(P, ws, bytes, W);
     if (rc)
@@ -958,6 +967,8 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     g_timer.end(tid, s, 1, run.adj_steps, run.adj_launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
+    if (dwavelet && P.torder == 4)
+        launch_time_filter3(dwavelet, P.nsrc, P.nt, s);
     // the fourth-order accumulator holds k G
     launch_finalize_dvp(P.dims, W.G, P.torder == 4 ? W.k : nullptr, vp, dvp, W.w[0], W.w[1], s);
     HIP_TRY(hipGetLastError());

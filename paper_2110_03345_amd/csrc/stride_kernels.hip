@@ -136,7 +136,8 @@ __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* 
         const long long base = (long long)r * smp.ntap;
         for (int t = 0; t < smp.ntap; ++t)
             acc = fmaf(smp.w[base + t], field[smp.idx[base + t]], acc);
-        smp.out[(long long)r * smp.out_stride + step] = acc;
+        float* o = smp.out + (long long)r * smp.out_stride + step;
+        *o = smp.accumulate ? fmaf(smp.scale, acc, *o) : smp.scale * acc;
         return;
     }
     // one wave per point: lane l sums taps l, l + 64, ...; then a butterfly
@@ -152,8 +153,10 @@ __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* 
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
         acc += __shfl_xor(acc, off, 64);
-    if (lane == 0)
-        smp.out[(long long)r * smp.out_stride + step] = acc;
+    if (lane == 0) {
+        float* o = smp.out + (long long)r * smp.out_stride + step;
+        *o = smp.accumulate ? fmaf(smp.scale, acc, *o) : smp.scale * acc;
+    }
 }
 
 constexpr float kTwelfth = 1.f / 12.f;
@@ -1064,6 +1067,22 @@ __global__ void medium_check_kernel(const float* vp, const float* rho, const flo
     }
 }
 
+// Transposed source filter of the fourth-order scheme, one row per block,
+// in place (the row is staged in LDS first).
+__global__ __launch_bounds__(256) void time_filter3_kernel(float* rows, int nt)
+{
+    extern __shared__ float row[];
+    float* r = rows + (long long)blockIdx.x * nt;
+    for (int j = threadIdx.x; j < nt; j += 256)
+        row[j] = r[j];
+    __syncthreads();
+    for (int j = threadIdx.x; j < nt; j += 256) {
+        const float lo = j >= 1 ? row[j - 1] : 0.f;
+        const float hi = j + 1 < nt ? row[j + 1] : 0.f;
+        r[j] = fmaf(10.f, row[j], lo + hi) / 12.f;
+    }
+}
+
 // Zero-phase low-pass of one [nt] row per block (band-limiting for the
 // frequency blocks of an inversion): the Hann-windowed sinc taps
 // h_k = 2 fc dt sinc(2 fc k dt) (0.5 + 0.5 cos(pi k / (K + 1))), |k| <= K,
@@ -1438,6 +1457,14 @@ void launch_medium_check(const float* vp, const float* rho, const float* alpha0,
     launch_fill(reinterpret_cast<float*>(flags + 2), 2, 0.f, s);
     hipLaunchKernelGGL(medium_check_kernel, dim3(grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024),
                        dim3(256), 0, s, vp, rho, alpha0, n, att_power, dt, flags);
+}
+
+void launch_time_filter3(float* rows, int count, int nt, hipStream_t s)
+{
+    if (count <= 0 || nt <= 0)
+        return;
+    hipLaunchKernelGGL(time_filter3_kernel, dim3(count), dim3(256), sizeof(float) * (size_t)nt, s, rows,
+                       nt);
 }
 
 int lowpass_taps(double dt, double f_max)

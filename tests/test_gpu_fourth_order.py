@@ -2,7 +2,7 @@
 time-filtered source): HIP forward traces and gradients against the FP64
 oracle's, at the workloads' CFL and near the larger stability limit of the
 corrected scheme; the CFL check of each order; checkpointing invisible in the
-gradient; the autograd operator; the wavelet gradient refused."""
+gradient; the wavelet gradient and the FP32 dot product; the autograd operator."""
 import numpy as np
 import pytest
 
@@ -104,16 +104,33 @@ def test_fourth_order_backward_vjp_matches_oracle(maker):
     plan = S.Plan.from_workload(w, time_order=4)
     rng = np.random.default_rng(3)
     gt = rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32)
-    dvp_ref, _ = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, gt)
+    dvp_ref, dwav_ref = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, gt)
     ws = plan.workspace(S.STRIDE_MODE_GRADIENT)
     vp, wav = dev(w.vp), dev(w.wavelet)
     plan.forward_save(vp, wav, ws)
     dvp, _ = plan.backward(vp, wav, dev(gt), ws)
     assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
     plan.forward_save(vp, wav, ws)
-    with pytest.raises(S.StrideError) as e:       # no wavelet gradient for this scheme
-        plan.backward(vp, wav, dev(gt), ws, want_dwavelet=True)
-    assert e.value.code == -1
+    dvp2, dwav = plan.backward(vp, wav, dev(gt), ws, want_dwavelet=True)
+    assert torch.equal(dvp, dvp2)
+    assert rel(dwav.cpu().numpy(), dwav_ref) < 1e-4, rel(dwav.cpu().numpy(), dwav_ref)
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_fourth_order_dot_product_fp32(maker):
+    """<F s, d> = <s, F^T d> for the fourth-order wavelet -> traces map on the GPU."""
+    w = maker()
+    plan = S.Plan.from_workload(w, time_order=4)
+    rng = np.random.default_rng(12)
+    s = rng.standard_normal(w.wavelet.shape).astype(np.float32)
+    d = rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32)
+    vp, sd = dev(w.vp), dev(s)
+    ws = plan.workspace(S.STRIDE_MODE_GRADIENT)
+    Fs = plan.forward_save(vp, sd, ws).cpu().numpy().astype(np.float64)
+    _, FTd = plan.backward(vp, sd, dev(d), ws, want_dwavelet=True)
+    lhs = np.sum(Fs * d)
+    rhs = np.sum(s.astype(np.float64) * FTd.cpu().numpy())
+    assert abs(lhs - rhs) <= 1e-5 * max(abs(lhs), abs(rhs)), (lhs, rhs)
 
 
 @pytest.mark.parametrize("maker,kw", [(W.tiny_2d, dict(nt=90)), (W.tiny_3d, dict(nt=50))])
@@ -148,5 +165,11 @@ def test_fourth_order_autograd_matches_oracle():
     loss.backward()
     assert abs(loss.item() - J) <= 1e-4 * abs(J)
     assert rel(vp.grad.cpu().numpy(), dvp_ref) < 1e-4
-    with pytest.raises(ValueError):
-        wave_traces(dev(w.vp), dev(w.wavelet).requires_grad_(True), plan)
+    # the wavelet gradient through the operator against the oracle's VJP of its
+    # own residual
+    wav = dev(w.wavelet).requires_grad_(True)
+    tr = wave_traces(dev(w.vp), wav, plan)
+    (0.5 * ((tr.double() - dev(obs).double()) ** 2).sum()).backward()
+    res_ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz) - obs
+    _, dwav_ref = oracle.adjoint(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, res_ref)
+    assert rel(wav.grad.cpu().numpy(), dwav_ref) < 1e-4
