@@ -98,6 +98,7 @@ struct StepParams {
     const float* gam[3];
     const float* att;
     int att_power;
+    float* V;         // kStepV: L u^n + S^n out; kImageV: that of u^m in
 };
 
 // One slot's step in a batched launch.
@@ -129,9 +130,12 @@ enum StepMode {
     kCorrect = 2, // C = a (2 D + A + (k/12) L A) - b B, A = p, D = u^n;
                   // adjoint: C = a (2 D + A + (k/12) L A + k R^T g) - b B with A = q,
                   // D = w^{m+1}, and G += U (D + A/12) + (k/12) D L U with U = p
-    kMedium = 3   // forward step in a heterogeneous medium, B a stencil field too:
+    kMedium = 3,  // forward step in a heterogeneous medium, B a stencil field too:
                   // C = a (2 A + k (L A + sum_a gam_a D_a A + S [+ att (L A - L B)])) - b B,
                   // with att added to the damping instead when att_power is 0
+    kStepV = 4,   // forward kStep that also stores V = L A + S (full-history gradients)
+    kImageV = 5   // adjoint kStep whose imaging reads V = L u^m + S^m instead of the
+                  // stencil of u^m: G += A V
 };
 
 // Kernel launchers (stride_kernels.hip).
@@ -142,7 +146,8 @@ void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& 
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);
 void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, const SpongeCoef& sp,
                  const LaunchShape& ls, const StepParams& p, hipStream_t s);
-// Launches of the mode steps: forward kPrep, kCorrect or kMedium, adjoint kCorrect.
+// Launches of the mode steps: forward kPrep, kCorrect, kMedium or kStepV; adjoint
+// kCorrect or kImageV.
 void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                       const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s);
 

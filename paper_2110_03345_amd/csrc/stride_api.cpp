@@ -624,10 +624,72 @@ struct Runner {
     long long launches = 0;      // forward step launches
     long long adj_steps = 0;     // adjoint steps
     long long adj_launches = 0;  // adjoint step launches
+    // Full history, second order: the forward keeps v^n = L u^n + S^n (pool
+    // field n) instead of the states, u rotates in the adjoint fields (free
+    // until the adjoint starts), and the adjoint images from v^m pointwise
+    // instead of a second stencil of u^m.  The same arithmetic as the
+    // checkpointed path, so the results are the same bits.
+    bool vpath = false;
 
     Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
         : P(p), W(w), s(st), wavelet(wav), cursor(p.nt, w.snaps, (int)w.pool.size())
     {
+        vpath = P.torder == 2 && cursor.forward_steps() <= P.nt - 1 &&
+                (long long)W.pool.size() >= P.nt;
+    }
+
+    // Forward sweep of the full-history path; returns the field of u^{nt-1}.
+    const float* forward_v(float* traces)
+    {
+        float* u[2] = {W.w[0], W.w[1]};
+        launch_fill(u[0], P.dims.total, 0.f, s);
+        launch_fill(u[1], P.dims.total, 0.f, s);
+        int cur = 0;
+        for (int n = 0; n < P.nt - 1; ++n) {
+            StepParams p = base_params(P);
+            p.A = u[cur];
+            p.B = u[1 - cur];
+            p.C = u[1 - cur];
+            p.K = W.k;
+            p.V = W.pool[n];
+            p.step = n;
+            p.inj_sig = wavelet;
+            if (traces)
+                p.smp = rec_samples(P, traces);
+            launch_step_mode(P.dims, P.R, false, kStepV, P.cf, P.sp, P.ls_fwd, p, s);
+            cur = 1 - cur;
+        }
+        // v^{nt-1} is never formed (no step leaves u^{nt-1}); the adjoint step
+        // at nt-1 multiplies it by w^{nt} = 0, so it is held at zero
+        launch_fill(W.pool[P.nt - 1], P.dims.total, 0.f, s);
+        steps += P.nt - 1;
+        launches += P.nt - 1;
+        return u[cur];
+    }
+
+    void backward_v(const float* grad_traces, float* dwavelet)
+    {
+        int wa = 0;
+        for (int m = P.nt - 1; m >= 0; --m) {
+            StepParams p = base_params(P);
+            p.A = W.w[wa];
+            p.B = W.w[1 - wa];
+            p.C = W.w[1 - wa];
+            p.K = W.k;
+            p.G = W.G;
+            p.V = W.pool[m];
+            p.step = m;
+            p.inj = P.rec_inj;
+            p.inj_sig = grad_traces;
+            p.inj_stride = P.nt;
+            p.img = P.no_inj;
+            if (dwavelet)
+                p.smp = src_samples(P, dwavelet);
+            launch_step_mode(P.dims, P.R, true, kImageV, P.cf, P.sp, P.ls_adj, p, s);
+            ++adj_steps;
+            ++adj_launches;
+            wa = 1 - wa;
+        }
     }
 
     void fwd_launch(const StepOp& op, float* traces)
@@ -929,16 +991,23 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
         return rc;
     float* tr = traces ? traces : W.traces;
     launch_prep_k(P.dims, vp, P.g.dt, W.k, s);
-    launch_fill(W.pool[0], P.dims.total, 0.f, s);
-    launch_fill(W.pool[1], P.dims.total, 0.f, s);
     Runner run(P, W, s, wavelet);
+    const float* last;
     int tid = g_timer.begin(s);
-    run.forward_phase(true, tr);
-    g_timer.end(tid, s, 0, run.steps, run.launches);
-    if (run.cursor.overflow())
-        return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
+    if (run.vpath) {
+        last = run.forward_v(tr);
+        g_timer.end(tid, s, 0, run.steps, run.launches);
+    } else {
+        launch_fill(W.pool[0], P.dims.total, 0.f, s);
+        launch_fill(W.pool[1], P.dims.total, 0.f, s);
+        run.forward_phase(true, tr);
+        g_timer.end(tid, s, 0, run.steps, run.launches);
+        if (run.cursor.overflow())
+            return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
+        last = W.pool[run.cursor.cur()];
+    }
     // last sample from the final state x_{nt-1}
-    launch_sample(rec_samples(P, tr), W.pool[run.cursor.cur()], P.nt - 1, s);
+    launch_sample(rec_samples(P, tr), last, P.nt - 1, s);
     if (traces && traces != W.traces)
         launch_copy(W.traces, traces, (long long)P.nrec * P.nt, s);
     HIP_TRY(hipGetLastError());
@@ -958,12 +1027,16 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     if (rc)
         return rc;
     Runner run(P, W, s, wavelet);
-    run.forward_phase(false, nullptr);
+    if (!run.vpath)
+        run.forward_phase(false, nullptr);
     launch_fill(W.G, P.dims.total, 0.f, s);
     launch_fill(W.w[0], P.dims.total, 0.f, s);
     launch_fill(W.w[1], P.dims.total, 0.f, s);
     int tid = g_timer.begin(s);
-    run.backward_phase(grad_traces, dwavelet);
+    if (run.vpath)
+        run.backward_v(grad_traces, dwavelet);
+    else
+        run.backward_phase(grad_traces, dwavelet);
     g_timer.end(tid, s, 1, run.adj_steps, run.adj_launches);
     if (run.cursor.overflow())
         return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");

@@ -239,7 +239,7 @@ template <bool ADJ, int MODE>
 __device__ __forceinline__ float step_out(float ctr, float lap, float inj, float uu, float bb,
                                           float kk, float eta, float half_dt)
 {
-    if constexpr (MODE == kStep) {
+    if constexpr (MODE == kStep || MODE == kStepV || MODE == kImageV) {
         return leapfrog(ctr, bb, kk, lap, eta, half_dt);
     } else if constexpr (MODE == kPrep) {
         return kk * lap;
@@ -292,7 +292,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     constexpr int LH = TY + 2 * R;
     constexpr int RW = (LH + WAVES - 1) / WAVES;    // tile rows loaded per wave
     constexpr bool MED = MODE == kMedium;
-    constexpr int NF = ADJ || MED ? 2 : 1;          // stencil fields A (and U, or B)
+    constexpr int NF = (ADJ && MODE != kImageV) || MED ? 2 : 1;   // stencil fields A (and U, or B)
     __shared__ float sF[NF][LH * LW];
     __shared__ float sS[NF][TY * kTileX];           // injected signal per tile point
 
@@ -318,7 +318,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     // entry ranges of the tile (uniform); the forward correction pass injects
     // nothing, the adjoint one its receivers, and it images without a source term
     constexpr bool INJ = MODE != kCorrect || ADJ;
-    constexpr bool IMG = ADJ && MODE != kCorrect;
+    constexpr bool IMG = ADJ && MODE != kCorrect && MODE != kImageV;
     int eb0 = 0, ne0 = 0;
     if constexpr (INJ) {
         eb0 = p.inj.ptr[tile];
@@ -355,7 +355,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
     }
     int po[RY];
-    float bb[RY], kk[RY], gg[RY], uu[RY], mgy[RY], mgx[RY], mat[RY];
+    float bb[RY], kk[RY], gg[RY], uu[RY], mgy[RY], mgx[RY], mat[RY], vv[RY];
     {
         const auto rb = plane_rsrc(p.B, fbytes);
         const auto rk = plane_rsrc(p.K, fbytes);
@@ -381,6 +381,12 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
 #pragma unroll
             for (int j = 0; j < RY; ++j)
                 gg[j] = bload(rg, po[j] >= 0 ? po[j] * 4 : -1);
+        }
+        if constexpr (MODE == kImageV) {
+            const auto rv = plane_rsrc(p.V, fbytes);
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                vv[j] = bload(rv, po[j] >= 0 ? po[j] * 4 : -1);
         }
     }
 
@@ -485,7 +491,11 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
             continue;
         }
         p.C[po[j]] = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
-        if constexpr (ADJ) {
+        if constexpr (MODE == kStepV)
+            p.V[po[j]] = lap;
+        if constexpr (MODE == kImageV) {
+            p.G[po[j]] = fmaf(ctr, vv[j], gg[j]);
+        } else if constexpr (ADJ) {
             const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
             float lu = lap2d<R, LW>(SU, cf);
             if (img_any)
@@ -522,7 +532,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     constexpr int HY = (NYH + NT - 1) / NT;
     constexpr int HX = (NXH + NT - 1) / NT;
     constexpr bool MED = MODE == kMedium;
-    constexpr int NF = ADJ || MED ? 2 : 1;          // stencil fields: A (and U, or B)
+    constexpr int NF = (ADJ && MODE != kImageV) || MED ? 2 : 1;   // stencil fields: A (and U, or B)
     constexpr int PLANE = LH * LW;
     constexpr int PL = TY * kTileX;                 // block-local points per plane
     __shared__ float sF[2][NF][PLANE];
@@ -620,7 +630,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         }
 
     float pl[NF][RY], phy[NF][HY], phx[NF][HX];
-    float pb[RY], pk[RY], pg[RY], pu[RY], pm[4][RY];
+    float pb[RY], pk[RY], pg[RY], pu[RY], pm[4][RY], pv[RY];
     auto prefetch = [&](int z) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -665,6 +675,12 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             for (int j = 0; j < RY; ++j)
                 pg[j] = bload_stream(rg, rbo[j]);
         }
+        if constexpr (MODE == kImageV) {
+            const auto rv = rsrc(p.V, z);
+#pragma unroll
+            for (int j = 0; j < RY; ++j)
+                pv[j] = bload_stream(rv, rbo[j]);
+        }
     };
 
     // Injection entries of the block (uniform range).  Thread t takes entry t,
@@ -674,7 +690,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     // (and clears) it after the barrier.  Blocks with more than NT entries
     // read the rest at every plane.
     constexpr bool INJ = MODE != kCorrect || ADJ;
-    constexpr bool IMG = ADJ && MODE != kCorrect;
+    constexpr bool IMG = ADJ && MODE != kCorrect && MODE != kImageV;
     int eb0 = 0, ne0 = 0;
     if constexpr (INJ) {
         eb0 = p.inj.ptr[lb];
@@ -716,13 +732,14 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                 for (int j = 0; j < RY; ++j)
                     sS[bsel][f][(wy * RY + j) * kTileX + lx] = 0.f;
         sE[0][tid] = make_int2(il0, __float_as_int(iv0));
-        if constexpr (ADJ)
-            sE[NF - 1][tid] = make_int2(il1, __float_as_int(iv1));
+        if constexpr (IMG)
+            sE[1][tid] = make_int2(il1, __float_as_int(iv1));
         __syncthreads();
         if (il0 >= 0 && il0 < PL)
             sS[0][0][il0] = iv0;
-        if (il1 >= 0 && il1 < PL)
-            sS[0][NF - 1][il1] = iv1;
+        if constexpr (IMG)
+            if (il1 >= 0 && il1 < PL)
+                sS[0][1][il1] = iv1;
     }
     // entries beyond the first NT of the block: written at their plane
     auto overflow = [&](auto filt, const InjTable& T, int eb, int ne, const float* sig, int stride,
@@ -744,7 +761,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             const int z = zb + u;
             if (z >= z1)
                 return false;
-            float bb[RY], kk[RY], gg[RY], uu[RY], mm[4][RY];
+            float bb[RY], kk[RY], gg[RY], uu[RY], mm[4][RY], vw[RY];
             float* S = &sF[buf][0][0];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -772,13 +789,15 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
                     mm[m][j] = MED ? pm[m][j] : 0.f;
+                vw[j] = MODE == kImageV ? pv[j] : 0.f;
             }
             if (z + 1 < z1)
                 prefetch(z + 1);
             const int pz = z - z0;
             if (pz > 0 && (inj_any || img_any)) {
+                // parked entry sets: the injection, and the imaging source term
 #pragma unroll
-                for (int f = 0; f < NF; ++f) {
+                for (int f = 0; f < (IMG ? 2 : 1); ++f) {
                     const int2 e = sE[f][tid];
                     if (e.x >= 0 && e.x / PL == pz)
                         sS[buf][f][e.x - pz * PL] = __int_as_float(e.y);
@@ -795,6 +814,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
 
             float* Cz = p.C + (long long)z * s0;
             float* Gz = ADJ ? p.G + (long long)z * s0 : nullptr;
+            float* Vz = MODE == kStepV ? p.V + (long long)z * s0 : nullptr;
             const int dzd = layer_depth(z, n0, d.nb);
             const float ez = sp.e[0] * (float)(dzd * dzd);
 #pragma unroll
@@ -843,7 +863,11 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                 }
                 const float out = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
                 __builtin_nontemporal_store(out, Cz + roff[j]);
-                if constexpr (ADJ) {
+                if constexpr (MODE == kStepV)
+                    __builtin_nontemporal_store(lap, Vz + roff[j]);
+                if constexpr (MODE == kImageV) {
+                    __builtin_nontemporal_store(fmaf(ctr, vw[j], gg[j]), Gz + roff[j]);
+                } else if constexpr (ADJ) {
                     const float* SU = S + (NF - 1) * PLANE;
                     const float uc0 = q[NF - 1][j][slot_c];
                     float uz = 0.f, uy = 0.f, ux = 0.f;
@@ -899,7 +923,9 @@ __global__ __launch_bounds__(64 * WAVES) void step2d_batched(Dims d, StencilCoef
 template <bool ADJ, int RY, int WAVES, int MODE>
 constexpr int min_waves_3d()
 {
-    return MODE == kStep && (RY <= 2 || (!ADJ && WAVES == 8)) ? 4 : 1;
+    return (MODE == kStep || MODE == kStepV || MODE == kImageV) && (RY <= 2 || (!ADJ && WAVES == 8))
+               ? 4
+               : 1;
 }
 
 template <int R, bool ADJ, int RY, int WAVES, int MODE = kStep>
@@ -1369,9 +1395,15 @@ int grid_for(long long n, int threads)
 void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                       const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s)
 {
-    if (adjoint)   // the adjoint of the fourth-order step runs kCorrect only
+    if (adjoint && mode == kImageV)
+        R == 4 ? launch_step_t<4, true, kImageV>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, true, kImageV>(d, cf, sp, ls, p, s);
+    else if (adjoint)   // the adjoint of the fourth-order step runs kCorrect
         R == 4 ? launch_step_t<4, true, kCorrect>(d, cf, sp, ls, p, s)
                : launch_step_t<5, true, kCorrect>(d, cf, sp, ls, p, s);
+    else if (mode == kStepV)
+        R == 4 ? launch_step_t<4, false, kStepV>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, false, kStepV>(d, cf, sp, ls, p, s);
     else if (mode == kMedium)
         R == 4 ? launch_step_t<4, false, kMedium>(d, cf, sp, ls, p, s)
                : launch_step_t<5, false, kMedium>(d, cf, sp, ls, p, s);
