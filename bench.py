@@ -386,7 +386,10 @@ def main():
     adj_spl = a_n / max(a_l, 1)
     fwd_step_s = f_ms * 1e-3 / max(f_n, 1)
     adj_gbs = ADJ_BYTES * npad / adj_step_s / 1e9
-    fwd_in_grad_gbs = FWD_BYTES * npad / fwd_step_s / 1e9
+    # with every state kept the forward also stores v = L u + S (4 B more) and
+    # the adjoint images from it (mode 5); otherwise the fused adjoint (mode 0)
+    full_history = f_n <= args.steps * (w.nt - 1)
+    fwd_in_grad_gbs = (FWD_BYTES + (4 if full_history else 0)) * npad / fwd_step_s / 1e9
     recompute = f_n / max(1, args.steps * (w.nt - 1))
     print(f"[bench] gradient: {ms_per_step:.2f} ms/step, adjoint {adj_step_s * 1e6:.2f} us/step "
           f"({adj_gbs:.0f} GB/s, {adj_spl:.2f} steps/launch), forward {fwd_step_s * 1e6:.2f} us/step, "
@@ -583,7 +586,8 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., 0>)" % w.ndim,
+            "kernel": "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., %d>)"
+                      % (w.ndim, 5 if full_history else 0),
             "achieved": adj_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -491,8 +491,8 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
             continue;
         }
         p.C[po[j]] = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
-        if constexpr (MODE == kStepV)
-            p.V[po[j]] = lap;
+        if constexpr (MODE == kStepV)   // read once, by the adjoint much later
+            __builtin_nontemporal_store(lap, p.V + po[j]);
         if constexpr (MODE == kImageV) {
             p.G[po[j]] = fmaf(ctr, vv[j], gg[j]);
         } else if constexpr (ADJ) {
