@@ -67,6 +67,9 @@ def measured_traffic(workload):
 FWD_BYTES = 16   # read u^n, u^{n-1}, k; write u^{n+1}
 FWD4_BYTES = 32  # fourth order: read u^n, k, write p; read p, u^n, u^{n-1}, k, write u^{n+1}
 ADJ_BYTES = 28   # read u^m, w^{m+1}, w^{m+2}, k, G; write w^m, G
+# full history: the adjoint reads v^m instead of u^m and G is read and written
+# every other step (two imaging terms per even step): 16 B and 32 B in turn
+ADJ_BYTES_PAIRED = 24
 # fourth-order adjoint step: read u^m, k, write p; read w^{m+1}, k, write q;
 # read q, p, w^{m+1}, w^{m+2}, k, H, write w^m, H
 ADJ4_BYTES = 56
@@ -387,10 +390,12 @@ def main():
     adj_launch_s = a_ms * 1e-3 / max(a_l, 1)
     adj_spl = a_n / max(a_l, 1)
     fwd_step_s = f_ms * 1e-3 / max(f_n, 1)
-    adj_gbs = ADJ_BYTES * npad / adj_step_s / 1e9
     # with every state kept the forward also stores v = L u + S (4 B more) and
-    # the adjoint images from it (mode 5); otherwise the fused adjoint (mode 0)
+    # the adjoint images from it two terms at a time (modes 6 and 5 in turn);
+    # otherwise the fused adjoint (mode 0)
     full_history = f_n <= args.steps * (w.nt - 1)
+    adj_bytes = ADJ_BYTES_PAIRED if full_history else ADJ_BYTES
+    adj_gbs = adj_bytes * npad / adj_step_s / 1e9
     fwd_in_grad_gbs = (FWD_BYTES + (4 if full_history else 0)) * npad / fwd_step_s / 1e9
     recompute = f_n / max(1, args.steps * (w.nt - 1))
     print(f"[bench] gradient: {ms_per_step:.2f} ms/step, adjoint {adj_step_s * 1e6:.2f} us/step "
@@ -588,17 +593,19 @@ def main():
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., %d>)"
-                      % (w.ndim, 5 if full_history else 0),
+            "kernel": ("adjoint leapfrog steps, imaging from the stored v two terms per even step "
+                       "(step%dd_kernel<R, true, ., ., 6> and <..., 5> in turn; per-launch figures "
+                       "average the pair)" % w.ndim) if full_history else
+                      "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., 0>)" % w.ndim,
             "achieved": adj_gbs,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": adj_gbs / HBM_PEAK_GBS,
             "traffic": traffic,
             "traffic_unit": "HBM bytes per launch",
-            "traffic_over_algorithmic": (traffic / (ADJ_BYTES * npad * adj_spl)) if traffic else None,
-            "bytes_per_point": ADJ_BYTES,
-            "algorithmic_bytes_per_launch": ADJ_BYTES * npad * adj_spl,
+            "traffic_over_algorithmic": (traffic / (adj_bytes * npad * adj_spl)) if traffic else None,
+            "bytes_per_point": adj_bytes,
+            "algorithmic_bytes_per_launch": adj_bytes * npad * adj_spl,
             "steps_per_launch": adj_spl,
             "us_per_launch": adj_launch_s * 1e6,
             "us_per_step": adj_step_s * 1e6,

@@ -99,6 +99,7 @@ struct StepParams {
     const float* att;
     int att_power;
     float* V;         // kStepV: L u^n + S^n out; kImageV: that of u^m in
+    const float* V2;  // kImageV: that of u^{m+1} (NULL: one imaging term per step)
 };
 
 // One slot's step in a batched launch.
@@ -134,8 +135,10 @@ enum StepMode {
                   // C = a (2 A + k (L A + sum_a gam_a D_a A + S [+ att (L A - L B)])) - b B,
                   // with att added to the damping instead when att_power is 0
     kStepV = 4,   // forward kStep that also stores V = L A + S (full-history gradients)
-    kImageV = 5   // adjoint kStep whose imaging reads V = L u^m + S^m instead of the
-                  // stencil of u^m: G += A V
+    kImageV = 5,  // adjoint kStep whose imaging reads V = L u^m + S^m instead of the
+                  // stencil of u^m: G += A V, and with V2 the previous step's term as
+                  // well, G = fma(A, V, fma(B, V2, G)) (B = w^{m+2})
+    kAdjPlain = 6 // adjoint kStep without imaging (the step before a kImageV with V2)
 };
 
 // Kernel launchers (stride_kernels.hip).

@@ -667,10 +667,15 @@ struct Runner {
         return u[cur];
     }
 
+    // Imaging terms in pairs: an odd step m+1 leaves G alone (kAdjPlain), the
+    // even step m after it adds both, G = fma(w^{m+1}, v^m, fma(w^{m+2}, v^{m+1}, G)),
+    // the same operations in the same order as one term per step, with G read
+    // and written every other step.
     void backward_v(const float* grad_traces, float* dwavelet)
     {
         int wa = 0;
         for (int m = P.nt - 1; m >= 0; --m) {
+            const bool image = (m % 2) == 0;
             StepParams p = base_params(P);
             p.A = W.w[wa];
             p.B = W.w[1 - wa];
@@ -678,6 +683,7 @@ struct Runner {
             p.K = W.k;
             p.G = W.G;
             p.V = W.pool[m];
+            p.V2 = m + 1 <= P.nt - 1 ? W.pool[m + 1] : nullptr;
             p.step = m;
             p.inj = P.rec_inj;
             p.inj_sig = grad_traces;
@@ -685,7 +691,8 @@ struct Runner {
             p.img = P.no_inj;
             if (dwavelet)
                 p.smp = src_samples(P, dwavelet);
-            launch_step_mode(P.dims, P.R, true, kImageV, P.cf, P.sp, P.ls_adj, p, s);
+            launch_step_mode(P.dims, P.R, true, image ? kImageV : kAdjPlain, P.cf, P.sp, P.ls_adj, p,
+                             s);
             ++adj_steps;
             ++adj_launches;
             wa = 1 - wa;

@@ -239,7 +239,7 @@ template <bool ADJ, int MODE>
 __device__ __forceinline__ float step_out(float ctr, float lap, float inj, float uu, float bb,
                                           float kk, float eta, float half_dt)
 {
-    if constexpr (MODE == kStep || MODE == kStepV || MODE == kImageV) {
+    if constexpr (MODE == kStep || MODE == kStepV || MODE == kImageV || MODE == kAdjPlain) {
         return leapfrog(ctr, bb, kk, lap, eta, half_dt);
     } else if constexpr (MODE == kPrep) {
         return kk * lap;
@@ -292,7 +292,8 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     constexpr int LH = TY + 2 * R;
     constexpr int RW = (LH + WAVES - 1) / WAVES;    // tile rows loaded per wave
     constexpr bool MED = MODE == kMedium;
-    constexpr int NF = (ADJ && MODE != kImageV) || MED ? 2 : 1;   // stencil fields A (and U, or B)
+    constexpr bool ONE = MODE == kImageV || MODE == kAdjPlain;      // adjoint with one stencil field
+    constexpr int NF = (ADJ && !ONE) || MED ? 2 : 1;   // stencil fields A (and U, or B)
     __shared__ float sF[NF][LH * LW];
     __shared__ float sS[NF][TY * kTileX];           // injected signal per tile point
 
@@ -318,7 +319,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
     // entry ranges of the tile (uniform); the forward correction pass injects
     // nothing, the adjoint one its receivers, and it images without a source term
     constexpr bool INJ = MODE != kCorrect || ADJ;
-    constexpr bool IMG = ADJ && MODE != kCorrect && MODE != kImageV;
+    constexpr bool IMG = ADJ && MODE != kCorrect && !ONE;
     int eb0 = 0, ne0 = 0;
     if constexpr (INJ) {
         eb0 = p.inj.ptr[tile];
@@ -355,7 +356,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
     }
     int po[RY];
-    float bb[RY], kk[RY], gg[RY], uu[RY], mgy[RY], mgx[RY], mat[RY], vv[RY];
+    float bb[RY], kk[RY], gg[RY], uu[RY], mgy[RY], mgx[RY], mat[RY], vv[RY], v2[RY];
     {
         const auto rb = plane_rsrc(p.B, fbytes);
         const auto rk = plane_rsrc(p.K, fbytes);
@@ -376,7 +377,7 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
                 mat[j] = bload(plane_rsrc(p.att, fbytes), bo);
             }
         }
-        if constexpr (ADJ) {
+        if constexpr (ADJ && MODE != kAdjPlain) {
             const auto rg = plane_rsrc(p.G, fbytes);
 #pragma unroll
             for (int j = 0; j < RY; ++j)
@@ -384,9 +385,12 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         }
         if constexpr (MODE == kImageV) {
             const auto rv = plane_rsrc(p.V, fbytes);
+            const auto r2 = plane_rsrc(p.V2 ? p.V2 : p.V, p.V2 ? fbytes : 0);
 #pragma unroll
-            for (int j = 0; j < RY; ++j)
+            for (int j = 0; j < RY; ++j) {
                 vv[j] = bload(rv, po[j] >= 0 ? po[j] * 4 : -1);
+                v2[j] = bload(r2, po[j] >= 0 ? po[j] * 4 : -1);
+            }
         }
     }
 
@@ -494,8 +498,9 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
         if constexpr (MODE == kStepV)   // read once, by the adjoint much later
             __builtin_nontemporal_store(lap, p.V + po[j]);
         if constexpr (MODE == kImageV) {
-            p.G[po[j]] = fmaf(ctr, vv[j], gg[j]);
-        } else if constexpr (ADJ) {
+            // with V2 absent its loads read 0 (empty descriptor): fma(B, 0, G) = G
+            p.G[po[j]] = fmaf(ctr, vv[j], fmaf(bb[j], v2[j], gg[j]));
+        } else if constexpr (ADJ && MODE != kAdjPlain) {
             const float* SU = &sF[NF - 1][(ly + R) * LW + lx + R];
             float lu = lap2d<R, LW>(SU, cf);
             if (img_any)
@@ -532,7 +537,8 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     constexpr int HY = (NYH + NT - 1) / NT;
     constexpr int HX = (NXH + NT - 1) / NT;
     constexpr bool MED = MODE == kMedium;
-    constexpr int NF = (ADJ && MODE != kImageV) || MED ? 2 : 1;   // stencil fields: A (and U, or B)
+    constexpr bool ONE = MODE == kImageV || MODE == kAdjPlain;      // adjoint with one stencil field
+    constexpr int NF = (ADJ && !ONE) || MED ? 2 : 1;   // stencil fields: A (and U, or B)
     constexpr int PLANE = LH * LW;
     constexpr int PL = TY * kTileX;                 // block-local points per plane
     __shared__ float sF[2][NF][PLANE];
@@ -630,7 +636,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         }
 
     float pl[NF][RY], phy[NF][HY], phx[NF][HX];
-    float pb[RY], pk[RY], pg[RY], pu[RY], pm[4][RY], pv[RY];
+    float pb[RY], pk[RY], pg[RY], pu[RY], pm[4][RY], pv[RY], pv2[RY];
     auto prefetch = [&](int z) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
@@ -669,7 +675,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             for (int j = 0; j < RY; ++j)
                 pu[j] = bload_stream(ru, rbo[j]);
         }
-        if constexpr (ADJ) {
+        if constexpr (ADJ && MODE != kAdjPlain) {
             const auto rg = rsrc(p.G, z);
 #pragma unroll
             for (int j = 0; j < RY; ++j)
@@ -677,9 +683,13 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
         }
         if constexpr (MODE == kImageV) {
             const auto rv = rsrc(p.V, z);
+            // with V2 absent the descriptor is empty and its loads read 0
+            const auto r2 = p.V2 ? rsrc(p.V2, z) : plane_rsrc(p.V, 0);
 #pragma unroll
-            for (int j = 0; j < RY; ++j)
+            for (int j = 0; j < RY; ++j) {
                 pv[j] = bload_stream(rv, rbo[j]);
+                pv2[j] = bload_stream(r2, rbo[j]);
+            }
         }
     };
 
@@ -690,7 +700,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     // (and clears) it after the barrier.  Blocks with more than NT entries
     // read the rest at every plane.
     constexpr bool INJ = MODE != kCorrect || ADJ;
-    constexpr bool IMG = ADJ && MODE != kCorrect && MODE != kImageV;
+    constexpr bool IMG = ADJ && MODE != kCorrect && !ONE;
     int eb0 = 0, ne0 = 0;
     if constexpr (INJ) {
         eb0 = p.inj.ptr[lb];
@@ -761,7 +771,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             const int z = zb + u;
             if (z >= z1)
                 return false;
-            float bb[RY], kk[RY], gg[RY], uu[RY], mm[4][RY], vw[RY];
+            float bb[RY], kk[RY], gg[RY], uu[RY], mm[4][RY], vw[RY], vw2[RY];
             float* S = &sF[buf][0][0];
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
@@ -784,12 +794,13 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             for (int j = 0; j < RY; ++j) {
                 bb[j] = MODE != kPrep && !MED ? pb[j] : 0.f;
                 kk[j] = pk[j];
-                gg[j] = ADJ ? pg[j] : 0.f;
+                gg[j] = ADJ && MODE != kAdjPlain ? pg[j] : 0.f;
                 uu[j] = MODE == kCorrect ? pu[j] : 0.f;
 #pragma unroll
                 for (int m = 0; m < 4; ++m)
                     mm[m][j] = MED ? pm[m][j] : 0.f;
                 vw[j] = MODE == kImageV ? pv[j] : 0.f;
+                vw2[j] = MODE == kImageV ? pv2[j] : 0.f;
             }
             if (z + 1 < z1)
                 prefetch(z + 1);
@@ -813,7 +824,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             __syncthreads();
 
             float* Cz = p.C + (long long)z * s0;
-            float* Gz = ADJ ? p.G + (long long)z * s0 : nullptr;
+            float* Gz = ADJ && MODE != kAdjPlain ? p.G + (long long)z * s0 : nullptr;
             float* Vz = MODE == kStepV ? p.V + (long long)z * s0 : nullptr;
             const int dzd = layer_depth(z, n0, d.nb);
             const float ez = sp.e[0] * (float)(dzd * dzd);
@@ -866,8 +877,8 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                 if constexpr (MODE == kStepV)
                     __builtin_nontemporal_store(lap, Vz + roff[j]);
                 if constexpr (MODE == kImageV) {
-                    __builtin_nontemporal_store(fmaf(ctr, vw[j], gg[j]), Gz + roff[j]);
-                } else if constexpr (ADJ) {
+                    __builtin_nontemporal_store(fmaf(ctr, vw[j], fmaf(bb[j], vw2[j], gg[j])), Gz + roff[j]);
+                } else if constexpr (ADJ && MODE != kAdjPlain) {
                     const float* SU = S + (NF - 1) * PLANE;
                     const float uc0 = q[NF - 1][j][slot_c];
                     float uz = 0.f, uy = 0.f, ux = 0.f;
@@ -923,7 +934,8 @@ __global__ __launch_bounds__(64 * WAVES) void step2d_batched(Dims d, StencilCoef
 template <bool ADJ, int RY, int WAVES, int MODE>
 constexpr int min_waves_3d()
 {
-    return (MODE == kStep || MODE == kStepV || MODE == kImageV) && (RY <= 2 || (!ADJ && WAVES == 8))
+    return (MODE == kStep || MODE == kStepV || MODE == kImageV || MODE == kAdjPlain) &&
+                   (RY <= 2 || (!ADJ && WAVES == 8))
                ? 4
                : 1;
 }
@@ -1398,6 +1410,9 @@ void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const Stenci
     if (adjoint && mode == kImageV)
         R == 4 ? launch_step_t<4, true, kImageV>(d, cf, sp, ls, p, s)
                : launch_step_t<5, true, kImageV>(d, cf, sp, ls, p, s);
+    else if (adjoint && mode == kAdjPlain)
+        R == 4 ? launch_step_t<4, true, kAdjPlain>(d, cf, sp, ls, p, s)
+               : launch_step_t<5, true, kAdjPlain>(d, cf, sp, ls, p, s);
     else if (adjoint)   // the adjoint of the fourth-order step runs kCorrect
         R == 4 ? launch_step_t<4, true, kCorrect>(d, cf, sp, ls, p, s)
                : launch_step_t<5, true, kCorrect>(d, cf, sp, ls, p, s);
