@@ -634,8 +634,88 @@ struct Runner {
     Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
         : P(p), W(w), s(st), wavelet(wav), cursor(p.nt, w.snaps, (int)w.pool.size())
     {
-        vpath = P.torder == 2 && cursor.forward_steps() <= P.nt - 1 &&
-                (long long)W.pool.size() >= P.nt;
+        const bool full = cursor.forward_steps() <= P.nt - 1 && (long long)W.pool.size() >= P.nt;
+        vpath = P.torder == 2 && full;
+        ppath = P.torder == 4 && full;
+    }
+
+    // Full history, fourth order: the forward's first launch writes p^n =
+    // k (L u^n + St^n) into history field n (where the checkpointed path
+    // writes scratch), u rotates in the adjoint fields, and the adjoint takes
+    // p^m from the history instead of recomputing it: two launches per adjoint
+    // step instead of three, the same bits.
+    bool ppath = false;
+
+    const float* forward_p(float* traces)
+    {
+        float* u[2] = {W.w[0], W.w[1]};
+        launch_fill(u[0], P.dims.total, 0.f, s);
+        launch_fill(u[1], P.dims.total, 0.f, s);
+        int cur = 0;
+        for (int n = 0; n < P.nt - 1; ++n) {
+            StepParams p = base_params(P);
+            p.A = u[cur];
+            p.C = W.pool[n];
+            p.K = W.k;
+            p.step = n;
+            p.inj_sig = wavelet;
+            if (traces)
+                p.smp = rec_samples(P, traces);
+            launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
+            StepParams q = base_params(P);
+            q.A = W.pool[n];
+            q.D = u[cur];
+            q.B = u[1 - cur];
+            q.C = u[1 - cur];
+            q.K = W.k;
+            q.step = n;
+            launch_step_mode(P.dims, P.R, false, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
+            cur = 1 - cur;
+        }
+        // p^{nt-1} is never formed; the adjoint step at nt-1 multiplies it by
+        // w^{nt} = 0 (and q = k L w^{nt} = 0), so it is held at zero
+        launch_fill(W.pool[P.nt - 1], P.dims.total, 0.f, s);
+        steps += P.nt - 1;
+        launches += 2LL * (P.nt - 1);
+        return u[cur];
+    }
+
+    void backward_p(const float* grad_traces, float* dwavelet)
+    {
+        int wa = 0;
+        for (int m = P.nt - 1; m >= 0; --m) {
+            StepParams q = base_params(P);
+            q.A = W.w[wa];
+            q.C = W.q;
+            q.K = W.k;
+            q.step = m;
+            q.inj = P.no_inj;
+            if (dwavelet)
+                q.smp = src_samples(P, dwavelet);
+            launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, q, s);
+            StepParams c = base_params(P);
+            c.A = W.q;
+            c.U = W.pool[m];
+            c.D = W.w[wa];
+            c.B = W.w[1 - wa];
+            c.C = W.w[1 - wa];
+            c.K = W.k;
+            c.G = W.G;
+            c.step = m;
+            c.inj = P.rec_inj;
+            c.inj_sig = grad_traces;
+            c.inj_stride = P.nt;
+            c.img = P.no_inj;
+            if (dwavelet) {
+                c.smp = src_samples(P, dwavelet);
+                c.smp.scale = 1.f / 12.f;
+                c.smp.accumulate = 1;
+            }
+            launch_step_mode(P.dims, P.R, true, kCorrect, P.cf, P.sp, P.ls_adj, c, s);
+            ++adj_steps;
+            adj_launches += 2;
+            wa = 1 - wa;
+        }
     }
 
     // Forward sweep of the full-history path; returns the field of u^{nt-1}.
@@ -1001,8 +1081,8 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     Runner run(P, W, s, wavelet);
     const float* last;
     int tid = g_timer.begin(s);
-    if (run.vpath) {
-        last = run.forward_v(tr);
+    if (run.vpath || run.ppath) {
+        last = run.vpath ? run.forward_v(tr) : run.forward_p(tr);
         g_timer.end(tid, s, 0, run.steps, run.launches);
     } else {
         launch_fill(W.pool[0], P.dims.total, 0.f, s);
@@ -1034,7 +1114,7 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     if (rc)
         return rc;
     Runner run(P, W, s, wavelet);
-    if (!run.vpath)
+    if (!run.vpath && !run.ppath)
         run.forward_phase(false, nullptr);
     launch_fill(W.G, P.dims.total, 0.f, s);
     launch_fill(W.w[0], P.dims.total, 0.f, s);
@@ -1042,6 +1122,8 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     int tid = g_timer.begin(s);
     if (run.vpath)
         run.backward_v(grad_traces, dwavelet);
+    else if (run.ppath)
+        run.backward_p(grad_traces, dwavelet);
     else
         run.backward_phase(grad_traces, dwavelet);
     g_timer.end(tid, s, 1, run.adj_steps, run.adj_launches);
