@@ -163,3 +163,22 @@ def test_schedule_large_and_monotone():
     assert steps < 2.0 * 3000
     with pytest.raises(S.StrideError):
         S.stride_schedule_info(3000, 3)
+
+
+def test_new_entry_points_check_arguments_before_any_launch():
+    """stride_lowpass, stride_descent_step and stride_plan_forward_medium refuse
+    bad arguments on the host (no device memory is touched)."""
+    L = S.lib()
+    E = _abi.STRIDE_E_INVALID_ARG
+    # NULL rows, a cutoff at or above Nyquist, an over-long row
+    assert L.stride_lowpass(None, None, 1, 100, 1e-7, 1e6, None) == E
+    assert L.stride_lowpass(None, None, 0, 100, 1e-7, 5e6, None) == E
+    assert L.stride_lowpass(None, None, 0, 100, 1e-7, 0.0, None) == E
+    assert L.stride_lowpass(None, None, 0, 20000, 1e-7, 1e6, None) == E
+    assert L.stride_lowpass(None, None, 0, 100, 1e-7, 1e6, None) == _abi.STRIDE_OK
+    # NULL fields, negative step, inverted bounds
+    assert L.stride_descent_step(None, None, None, 10, 1.0, 0.0, 1.0, None, None) == E
+    assert L.stride_descent_step(None, None, None, 0, -1.0, 0.0, 1.0, None, None) == E
+    assert L.stride_descent_step(None, None, None, 0, 1.0, 2.0, 1.0, None, None) == E
+    assert L.stride_descent_step(None, None, None, 0, 1.0, 0.0, 1.0, None, None) == _abi.STRIDE_OK
+    assert L.stride_plan_forward_medium(None, None, None, None, 0, None, None, None, 0, None) == E
