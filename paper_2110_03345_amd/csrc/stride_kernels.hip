@@ -751,14 +751,34 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
             if (il1 >= 0 && il1 < PL)
                 sS[0][1][il1] = iv1;
     }
-    // entries beyond the first NT of the block: written at their plane
-    auto overflow = [&](auto filt, const InjTable& T, int eb, int ne, const float* sig, int stride,
-                        int pz, float* dst) {
-        for (int e = tid + NT; e < ne; e += NT) {
-            const TileEntry en = T.ent[eb + e];
-            if (en.run > 0 && en.local / PL == pz)
-                dst[en.local - pz * PL] =
-                    tile_point_signal<decltype(filt)::value>(T.ent + eb + e, en, sig, stride, p.step);
+    // Entries beyond the first NT of the block, written at their plane.  A
+    // block's entries are sorted by point, so their planes never decrease.
+    // The adjoint (receiver sets of up to 512 taps a point fill some blocks
+    // with thousands of entries) keeps a cursor per thread over its entries
+    // (tid + NT, tid + 2 NT, ...) and at plane pz takes them until the first
+    // of a later plane: every entry is read once per chunk, plus one
+    // look-ahead per plane.  The forward step, whose source entries rarely
+    // overflow, scans them at every plane and keeps its registers.
+    int oc0 = tid + NT, oc1 = tid + NT;
+    auto overflow = [&](auto filt, const InjTable& T, int eb, int ne, int& oc, const float* sig,
+                        int stride, int pz, float* dst) {
+        if constexpr (ADJ) {
+            for (; oc < ne; oc += NT) {
+                const TileEntry en = T.ent[eb + oc];
+                const int ez = en.local / PL;
+                if (ez > pz)
+                    break;
+                if (en.run > 0 && ez == pz)
+                    dst[en.local - pz * PL] = tile_point_signal<decltype(filt)::value>(
+                        T.ent + eb + oc, en, sig, stride, p.step);
+            }
+        } else {
+            for (int e = tid + NT; e < ne; e += NT) {
+                const TileEntry en = T.ent[eb + e];
+                if (en.run > 0 && en.local / PL == pz)
+                    dst[en.local - pz * PL] = tile_point_signal<decltype(filt)::value>(
+                        T.ent + eb + e, en, sig, stride, p.step);
+            }
         }
     };
 
@@ -815,11 +835,11 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                 }
             }
             if (ne0 > NT)
-                overflow(std::integral_constant<bool, MODE == kPrep>{}, p.inj, eb0, ne0, p.inj_sig,
-                         p.inj_stride, pz, &sS[buf][0][0]);
+                overflow(std::integral_constant<bool, MODE == kPrep>{}, p.inj, eb0, ne0, oc0,
+                         p.inj_sig, p.inj_stride, pz, &sS[buf][0][0]);
             if constexpr (IMG)
                 if (ne1 > NT)
-                    overflow(std::false_type{}, p.img, eb1, ne1, p.img_sig, p.img_stride, pz,
+                    overflow(std::false_type{}, p.img, eb1, ne1, oc1, p.img_sig, p.img_stride, pz,
                              &sS[buf][NF - 1][0]);
             __syncthreads();
 

@@ -52,6 +52,31 @@ def test_sinc_forward_and_gradient_match_oracle(name, make):
     assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
 
 
+def test_sinc_dense_points_3d_match_oracle():
+    """Sources and receivers packed within a few cells of the centre: with
+    512 taps a point, the step-kernel blocks around them hold thousands of
+    injection entries, so every thread of such a block takes many entries
+    beyond the block's first ones, spread over several planes of its chunk
+    (forward: the source entries; adjoint: the receiver entries)."""
+    w = W.tiny_3d(nsrc=12, nrec=48, nt=50)
+    rng = np.random.default_rng(31)
+    c = np.array([(s // 2) * w.spacing for s in w.shape])
+    w.src_xyz = c + rng.uniform(-2.0, 2.0, size=(12, 3)) * w.spacing
+    w.rec_xyz = c + rng.uniform(-3.0, 3.0, size=(48, 3)) * w.spacing
+    print(f"dense sinc points {w.shape}: 12 sources, 48 receivers", flush=True)
+    g = oracle.Grid(**w.grid_kwargs(), interp=1)
+    ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
+    plan = S.Plan.from_workload(w, interp=1)
+    tr = plan.forward(dev(w.vp), dev(w.wavelet)).cpu().numpy()
+    assert rel(tr, ref) < 1e-4, rel(tr, ref)
+    # residual of the size of the traces (see the dense-geometry parity test)
+    obs = (0.5 * ref + np.std(ref) * rng.standard_normal(ref.shape)).astype(np.float32)
+    _, J, dvp_ref = oracle.gradient(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz, obs)
+    misfit, dvp = plan.gradient(dev(w.vp), dev(w.wavelet), dev(obs))
+    assert abs(misfit.item() - J) <= 1e-4 * abs(J)
+    assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
+
+
 @pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
 def test_sinc_backward_vjp_matches_oracle(maker):
     w = maker()
