@@ -36,12 +36,12 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     # config 2 keeps every state: the adjoint alternates mode 6 (no imaging) and
     # mode 5 (two imaging terms); per-dispatch figures averaged over the pair
-    "config2": {"sha256": "1d7f956b1c489a7fb043552ebcc6b89c139c8dee4a787c137ff7f27979093176",
-                "fetch_kib": 11025.32, "write_kib": 7153.78,
-                "copy_fetch_kib": 524308.63, "copy_write_kib": 1048576.0},
+    "config2": {"sha256": "bb0de64b1359e09888b5b6d0c99f20c9bc2ace4d211b12bbed461d09d735f779",
+                "fetch_kib": 11025.57, "write_kib": 7153.94,
+                "copy_fetch_kib": 524308.44, "copy_write_kib": 1048576.0},
     # config 4 checkpoints: the fused adjoint (mode 0), counters from a checkpointed run
-    "config4": {"sha256": "1d7f956b1c489a7fb043552ebcc6b89c139c8dee4a787c137ff7f27979093176",
-                "fetch_kib": 498090.95, "write_kib": 249640.00,
+    "config4": {"sha256": "bb0de64b1359e09888b5b6d0c99f20c9bc2ace4d211b12bbed461d09d735f779",
+                "fetch_kib": 484300.79, "write_kib": 249640.00,
                 "copy_fetch_kib": 524315.75, "copy_write_kib": 1048576.0},
 }
 
