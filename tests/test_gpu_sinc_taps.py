@@ -52,7 +52,7 @@ def test_sinc_forward_and_gradient_match_oracle(name, make):
     assert rel(dvp.cpu().numpy(), dvp_ref) < 1e-4, rel(dvp.cpu().numpy(), dvp_ref)
 
 
-def test_sinc_dense_points_3d_match_oracle():
+def _dense_sinc_3d():
     """Sources and receivers packed within a few cells of the centre: with
     512 taps a point, the step-kernel blocks around them hold thousands of
     injection entries, so every thread of such a block takes many entries
@@ -63,6 +63,11 @@ def test_sinc_dense_points_3d_match_oracle():
     c = np.array([(s // 2) * w.spacing for s in w.shape])
     w.src_xyz = c + rng.uniform(-2.0, 2.0, size=(12, 3)) * w.spacing
     w.rec_xyz = c + rng.uniform(-3.0, 3.0, size=(48, 3)) * w.spacing
+    return w, rng
+
+
+def test_sinc_dense_points_3d_match_oracle():
+    w, rng = _dense_sinc_3d()
     print(f"dense sinc points {w.shape}: 12 sources, 48 receivers", flush=True)
     g = oracle.Grid(**w.grid_kwargs(), interp=1)
     ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
@@ -130,6 +135,43 @@ def test_engine_runs_sinc_tap_shots_bitwise_as_single_solves():
         _abi.stride_engine_detach(eng, slot)
         stream.synchronize()
         assert torch.equal(tr, plan.forward(vp, wav))
+    finally:
+        _abi.stride_engine_destroy(eng)
+
+
+def test_engine_dense_sinc_gradient_bitwise_as_single_solve():
+    """A gradient slot with the packed 3D sinc geometry through the batching
+    engine (its batched step kernels take the same overflow entries): traces,
+    misfit and dvp bitwise equal to the plan's own gradient."""
+    w, rng = _dense_sinc_3d()
+    plan = S.Plan.from_workload(w, interp=1)
+    grid = S.make_grid(**w.grid_kwargs(), interp=1)
+    eng = _abi.stride_engine_create(grid, 2, plan.nrec, 8, True)
+    stream = torch.cuda.Stream()
+    try:
+        vp, wav = dev(w.vp), dev(w.wavelet)
+        obs = dev(1e-3 * rng.standard_normal((plan.nrec, w.nt)))
+        tr = torch.empty((plan.nrec, w.nt), dtype=torch.float32, device="cuda")
+        mis = torch.zeros(1, dtype=torch.float64, device="cuda")
+        dvp = torch.empty_like(vp)
+        ws = plan.workspace(S.STRIDE_MODE_GRADIENT)
+        torch.cuda.synchronize()
+        slot = _abi.stride_engine_attach(eng, plan.handle, S.STRIDE_MODE_GRADIENT, vp,
+                                         float(w.vp.max()), wav, obs, tr, mis, dvp, ws, stream)
+        done = False
+        for _ in range(64):            # forward and adjoint: about 100 ticks, 8 per run
+            _, fin = _abi.stride_engine_run(eng, 8, 4, stream)
+            if slot in fin:
+                done = True
+                break
+        assert done
+        _abi.stride_engine_detach(eng, slot)
+        stream.synchronize()
+        tr2 = torch.empty_like(tr)
+        m, d = plan.gradient(vp, wav, obs, traces=tr2)
+        assert torch.equal(tr, tr2)
+        assert torch.equal(m, mis)
+        assert torch.equal(d, dvp)
     finally:
         _abi.stride_engine_destroy(eng)
 
