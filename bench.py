@@ -267,16 +267,20 @@ def serving_bench(args):
           f"mean one-at-a-time service {mean_service * 1e3:.1f} ms, rate {rate:.2f}/s",
           file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    def progress(tag):
+        return lambda n, total: print(f"[bench] {tag}: {n}/{total} requests done", file=sys.stderr,
+                                      flush=True)
+
     srv = Server(use_graphs=not args.no_graphs, max_slots=args.max_slots, max_chunk=args.max_chunk)
     try:
-        served = srv.run(specs, realtime=True)
+        served = srv.run(specs, realtime=True, progress=progress("served"))
     finally:
         srv.close()
     print(f"[bench] served: {served['solves_per_s']:.1f} shot solves/s, p50 {served['p50_s']:.3f} s, "
           f"p99 {served['p99_s']:.3f} s", file=sys.stderr, flush=True)
     if args.no_baseline:
         return
-    base = serve_one_at_a_time(specs, realtime=True)
+    base = serve_one_at_a_time(specs, realtime=True, progress=progress("one at a time"))
     print(f"[bench] one at a time: {base['solves_per_s']:.1f} shot solves/s, p50 {base['p50_s']:.3f} s, "
           f"p99 {base['p99_s']:.3f} s", file=sys.stderr, flush=True)
     # equal accuracy: every served request equals its one-at-a-time result

@@ -266,9 +266,11 @@ class Server:
         self.io_used -= req.bytes + sum(sh.bytes - sh.ws_bytes for sh in req.shots)
 
     # ------------------------------------------------------------ main loop
-    def run(self, specs, realtime: bool = True) -> dict:
+    def run(self, specs, realtime: bool = True, progress=None) -> dict:
         """Serve the request stream (arrival times honoured when realtime,
-        else every request is present at t = 0); returns results and timing."""
+        else every request is present at t = 0); returns results and timing.
+        progress(done, total), if given, is called after every 25th completed
+        request and after the last."""
         order = sorted(specs, key=lambda r: r.arrival)
         arrival = {r.rid: (r.arrival if realtime else 0.0) for r in order}
         pending = collections.deque(order)
@@ -331,6 +333,8 @@ class Server:
                 if ev.query():
                     self._complete(r, now)
                     n_done += 1
+                    if progress and (n_done % 25 == 0 or n_done == len(order)):
+                        progress(n_done, len(order))
                 else:
                     still.append((ev, r))
             finals = still
@@ -396,9 +400,10 @@ def solve_one(spec, device=None, grad_cap: int = 24 << 30, stream=None):
     return res
 
 
-def serve_one_at_a_time(specs, realtime: bool = True, device=None, grad_cap: int = 24 << 30) -> dict:
+def serve_one_at_a_time(specs, realtime: bool = True, device=None, grad_cap: int = 24 << 30,
+                        progress=None) -> dict:
     """FIFO baseline: each request in arrival order, its shots one after the
-    other through the plain entry points."""
+    other through the plain entry points (progress as in Server.run)."""
     order = sorted(specs, key=lambda r: r.arrival)
     t0 = time.perf_counter()
     lat = []
@@ -410,6 +415,8 @@ def serve_one_at_a_time(specs, realtime: bool = True, device=None, grad_cap: int
             time.sleep(wait)
         results.append(solve_one(spec, device, grad_cap))
         lat.append(time.perf_counter() - t0 - arr)
+        if progress and (len(lat) % 25 == 0 or len(lat) == len(order)):
+            progress(len(lat), len(order))
     t_end = time.perf_counter() - t0
     shots = sum(r.nshots for r in specs)
     lat = np.array(lat)
