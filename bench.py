@@ -256,13 +256,17 @@ def serving_bench(args):
         kw = dict(nt_range=(500, 3000), classes_2d=(256, 512, 1024), classes_3d=(128, 192, 256))
     else:
         kw = dict(nt_range=(500, 1500), classes_2d=(256, 512, 1024), classes_3d=(128,))
-    # calibration: one-at-a-time service time of a small sample sets the arrival rate
-    probe = [materialise(r) for r in request_stream(6, 99, 1.0, **kw)]
+    # calibration: the one-at-a-time service time of the stream's first requests
+    # sets the arrival rate (a request's content does not depend on the rate:
+    # the generator draws the same numbers for it at any rate, only the
+    # arrival times scale)
+    seed = 2024
+    probe = [materialise(r) for r in request_stream(min(24, args.requests), seed, 1.0, **kw)]
     serve_one_at_a_time(probe[:1], realtime=False)
     cal = serve_one_at_a_time(probe, realtime=False)
     mean_service = cal["makespan_s"] / len(probe)
     rate = args.load / mean_service
-    specs = [materialise(r) for r in request_stream(args.requests, 2024, rate, **kw)]
+    specs = [materialise(r) for r in request_stream(args.requests, seed, rate, **kw)]
     print(f"[bench] serving: {len(specs)} requests, {sum(r.nshots for r in specs)} shots, "
           f"mean one-at-a-time service {mean_service * 1e3:.1f} ms, rate {rate:.2f}/s",
           file=sys.stderr, flush=True)

@@ -186,8 +186,9 @@ class Server:
         req.bytes = req.vp.numel() * 4 + req.wavelet.numel() * 4
         self.io_used += req.bytes
 
-    def _try_admit(self, req: _Req, bucket: _Bucket) -> bool:
-        """Attach the request's next shot if a slot and the budget allow."""
+    def _try_admit(self, req: _Req, bucket: _Bucket, force_io: bool = False) -> bool:
+        """Attach the request's next shot if a slot and the budget allow
+        (force_io: the I/O limit may be exceeded by this shot)."""
         s = req.spec
         i = req.next_shot
         if bucket.free_slots() == 0:
@@ -198,7 +199,7 @@ class Server:
         nb = _ws_bytes(req.grid, nrec, s.kind, self.grad_cap)
         io = nrec * s.nt * 4 * (2 if s.kind == "gradient" else 1) + \
             (req.vp.numel() * 4 if s.kind == "gradient" else 0)
-        if self.io_used + io > self.io_limit:
+        if self.io_used + io > self.io_limit and not force_io:
             return False
         ws_off, ws = self.arena.alloc(nb)
         if ws is None:
@@ -287,7 +288,13 @@ class Server:
                 r = _Req(pending.popleft())
                 reqs.append(r)
                 waiting.append(r)
-            # admission: first come, first served within each grid
+            # admission: first come, first served within each grid.  The I/O
+            # limit is soft: finished shots keep their outputs counted until
+            # their request completes, and staged requests their inputs, which
+            # can fill it while no shot runs; then the oldest waiting request
+            # that fits the arena takes one shot beyond it, so the stream
+            # always moves.
+            idle = not any(b.owner for b in self.buckets.values())
             blocked = set()
             for r in list(waiting):
                 b = self._bucket(r.spec)
@@ -295,8 +302,8 @@ class Server:
                     continue
                 if r.vp is None:
                     self._stage(r)
-                while r.next_shot < r.spec.nshots and self._try_admit(r, b):
-                    pass
+                while r.next_shot < r.spec.nshots and self._try_admit(r, b, force_io=idle):
+                    idle = False
                 if r.next_shot < r.spec.nshots:
                     blocked.add(id(b))
                 else:
