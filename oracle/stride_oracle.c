@@ -215,42 +215,100 @@ int oracle_eta(const oracle_grid_t *g, double *eta)
     return 0;
 }
 
-/* Zeroth-order modified Bessel function of the first kind, by its power
- * series sum_k ((z/2)^k / k!)^2 (all terms positive; converges for all z). */
-static double bessel_i0(double z)
+/* ---------------------------------------------------------------- off-grid points
+ * Sec. 2.4: sources and receivers off the grid are spread over / sampled from
+ * nearby nodes, by linear interpolation or by Hicks' Kaiser-windowed sinc.
+ * The weights below are evaluated from their definitions, node by node:
+ *   linear: hat(x) = max(0, 1 - |x|) per axis, x the node's offset from the
+ *           point in cells (so a point on a node gives that node weight 1);
+ *   sinc:   sinc(x) * I0(b sqrt(1 - (x/r)^2)) / I0(b) for |x| < r, else 0,
+ *           with sinc exactly 0 at nonzero integers;
+ * and a tap's weight is the product of its per-axis weights. */
+
+static const double ORACLE_PI = 3.14159265358979323846;
+
+/* I0(z) = (1/2pi) * integral over one period of exp(z cos t) dt.  The integrand
+ * is smooth and periodic, so the equally spaced rule over the whole period is
+ * exact up to aliasing terms 2 I_{kM}(z), k >= 1; with M = 64 nodes and the
+ * arguments used here (|z| < 7) these are below 1e-40 of the result. */
+static double i0_integral(double z)
 {
-    double term = 1.0, sum = 1.0, q = 0.25 * z * z;
-    for (int k = 1; k < 200 && term > 1e-17 * sum; k++) {
-        term *= q / ((double)k * (double)k);
-        sum += term;
-    }
-    return sum;
+    const int M = 64;
+    double acc = 0.0;
+    for (int m = 0; m < M; m++)
+        acc += exp(z * cos(2.0 * ORACLE_PI * (double)m / (double)M));
+    return acc / (double)M;
 }
 
-/* Kaiser-windowed sinc weight of a node at offset x (in cells) from the point
- * (Hicks 2002): sinc(x) I0(b sqrt(1 - (x/r)^2)) / I0(b) for |x| <= r. */
-static double windowed_sinc(double x)
+static double hat_weight(double x)
+{
+    double d = fabs(x);
+    return d < 1.0 ? 1.0 - d : 0.0;
+}
+
+static double kaiser_sinc_weight(double x)
 {
     const double r = ORACLE_SINC_HALF_WIDTH, b = ORACLE_SINC_KAISER_B;
-    if (fabs(x) > r)
+    if (!(fabs(x) < r))
         return 0.0;
-    const double pi = 3.14159265358979323846;
-    double s = x == 0.0 ? 1.0 : sin(pi * x) / (pi * x);
+    double s;
+    if (x == floor(x))                 /* integer offset: sinc is 1 at 0, 0 elsewhere */
+        s = x == 0.0 ? 1.0 : 0.0;
+    else
+        s = sin(ORACLE_PI * x) / (ORACLE_PI * x);
     double q = x / r;
-    return s * bessel_i0(b * sqrt(1.0 - q * q)) / bessel_i0(b);
+    return s * i0_integral(b * sqrt(1.0 - q * q)) / i0_integral(b);
 }
 
 int oracle_taps_per_point(const oracle_grid_t *g)
 {
-    if (!g || (g->ndim != 2 && g->ndim != 3))
+    if (!g || (g->ndim != 2 && g->ndim != 3) || (g->interp != 0 && g->interp != 1))
         return -1;
-    if (g->interp == 1) {
-        int n = 1;
-        for (int a = 0; a < g->ndim; a++)
-            n *= 2 * ORACLE_SINC_HALF_WIDTH;
-        return n;
+    int per_axis = g->interp == 1 ? 2 * ORACLE_SINC_HALF_WIDTH : 2;
+    return g->ndim == 3 ? per_axis * per_axis * per_axis : per_axis * per_axis;
+}
+
+/* Per-axis node list of one point: every padded node closer than the reach
+ * (1 cell linear, r cells sinc) with its weight; the list is then filled up to
+ * `slots` entries with weight-0 copies of its first node. */
+static int axis_nodes(const geo_t *G, const oracle_grid_t *g, int a, double x, int slots,
+                      long *node, double *wt)
+{
+    double dx = g->spacing[a];
+    double span = (double)(G->n[a] - 1) * dx;
+    if (x < -1e-9 * dx || x > span + 1e-9 * dx || x != x)
+        return -3;                               /* outside the physical grid */
+    double pos = x / dx + (double)g->nb;        /* in padded node units */
+    double near = floor(pos + 0.5);
+    if (fabs(pos - near) < 1e-9)                 /* on a node, up to rounding */
+        pos = near;
+    int sinc = g->interp == 1;
+    double reach = sinc ? (double)ORACLE_SINC_HALF_WIDTH : 1.0;
+    if (sinc) {
+        /* the point's window of 2r nodes must lie in the padded array */
+        double lo = floor(pos) - (ORACLE_SINC_HALF_WIDTH - 1);
+        double hi = floor(pos) + ORACLE_SINC_HALF_WIDTH;
+        if (lo < 0.0 || hi > (double)(G->np[a] - 1))
+            return -3;
     }
-    return g->interp == 0 ? 1 << g->ndim : -1;
+    int count = 0;
+    for (long j = 0; j < G->np[a]; j++) {
+        double off = (double)j - pos;
+        if (!(fabs(off) < reach))
+            continue;
+        if (count == slots)
+            return -1;                           /* cannot happen for these reaches */
+        node[count] = j;
+        wt[count] = sinc ? kaiser_sinc_weight(off) : hat_weight(off);
+        count++;
+    }
+    if (count == 0)
+        return -1;
+    for (int s = count; s < slots; s++) {
+        node[s] = node[0];
+        wt[s] = 0.0;
+    }
+    return 0;
 }
 
 int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, double *w)
@@ -261,57 +319,32 @@ int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, 
     const int T = oracle_taps_per_point(g);
     if (T < 0)
         return -1;
-    const int sinc = g->interp == 1;
-    const int m = sinc ? 2 * ORACLE_SINC_HALF_WIDTH : 2;    /* nodes per axis */
+    const int slots = g->interp == 1 ? 2 * ORACLE_SINC_HALF_WIDTH : 2;
+    long node[3][2 * ORACLE_SINC_HALF_WIDTH];
+    double wt[3][2 * ORACLE_SINC_HALF_WIDTH];
     for (int p = 0; p < npts; p++) {
-        long first[3] = {0, 0, 0};
-        double w1[3][2 * ORACLE_SINC_HALF_WIDTH];
         for (int a = 0; a < G.nd; a++) {
-            double x = xyz[(long)p * G.nd + a];
-            double xmax = (double)(G.n[a] - 1) * g->spacing[a];
-            double tol = 1e-9 * g->spacing[a];
-            if (!(x >= -tol && x <= xmax + tol))
-                return -3;
-            double gx = x / g->spacing[a] + (double)g->nb;
-            long i = (long)floor(gx);
-            i = clampl(i, 0, G.np[a] - 2);
-            double f = gx - (double)i;
-            if (fabs(f) < 1e-9)
-                f = 0.0;
-            if (fabs(1.0 - f) < 1e-9)
-                f = 1.0;
-            if (!sinc) {
-                first[a] = i;
-                w1[a][0] = 1.0 - f;
-                w1[a][1] = f;
-                continue;
-            }
-            /* nodes i - r + 1 .. i + r; the point sits at i + f */
-            if (f == 1.0) {
-                i += 1;
-                f = 0.0;
-            }
-            first[a] = i - ORACLE_SINC_HALF_WIDTH + 1;
-            if (first[a] < 0 || first[a] + m - 1 > G.np[a] - 1)
-                return -3;    /* taps beyond the padded array */
-            for (int j = 0; j < m; j++) {
-                long node = first[a] + j;
-                w1[a][j] = f == 0.0 ? (node == i ? 1.0 : 0.0)
-                                    : windowed_sinc((double)node - ((double)i + f));
-            }
+            int rc = axis_nodes(&G, g, a, xyz[(long)p * G.nd + a], slots, node[a], wt[a]);
+            if (rc != 0)
+                return rc;
         }
-        for (int t = 0; t < T; t++) {
-            long lin = 0;
-            double wt = 1.0;
-            int rem = t;
-            for (int a = 0; a < G.nd; a++) {
-                int j = rem % m;
-                rem /= m;
-                lin += (first[a] + j) * G.st[a];
-                wt *= w1[a][j];
-            }
-            idx[(long)p * T + t] = lin;
-            w[(long)p * T + t] = wt;
+        /* taps in C order over the per-axis lists (last axis fastest) */
+        long *pi = idx + (long)p * T;
+        double *pw = w + (long)p * T;
+        int t = 0;
+        if (G.nd == 2) {
+            for (int j0 = 0; j0 < slots; j0++)
+                for (int j1 = 0; j1 < slots; j1++, t++) {
+                    pi[t] = pidx(&G, node[0][j0], node[1][j1], 0);
+                    pw[t] = wt[0][j0] * wt[1][j1];
+                }
+        } else {
+            for (int j0 = 0; j0 < slots; j0++)
+                for (int j1 = 0; j1 < slots; j1++)
+                    for (int j2 = 0; j2 < slots; j2++, t++) {
+                        pi[t] = pidx(&G, node[0][j0], node[1][j1], node[2][j2]);
+                        pw[t] = wt[0][j0] * wt[1][j1] * wt[2][j2];
+                    }
         }
     }
     return 0;

@@ -82,8 +82,12 @@ int oracle_pad_transpose(const oracle_grid_t *g, const double *pad, double *phys
 /* Damping rate eta on the padded grid (1/s). */
 int oracle_eta(const oracle_grid_t *g, double *eta);
 
-/* Linear-interpolation taps of npts points: idx[p*8+t] padded linear index,
- * w[p*8+t] weight; 2^ndim taps used, the rest are set to (0, 0.0). */
+/* Taps of npts points (linear or windowed sinc, per g->interp): T entries per
+ * point (T = oracle_taps_per_point), idx[p*T+t] the padded linear index and
+ * w[p*T+t] the weight, in C order over the per-axis node lists.  Each axis
+ * lists the nodes closer than the reach (1 cell linear, 4 cells sinc), filled
+ * up with weight-0 entries.  Returns -3 for a point outside the physical grid
+ * or (sinc) whose window of 8 nodes per axis leaves the padded array. */
 int oracle_taps(const oracle_grid_t *g, int npts, const double *xyz, long *idx, double *w);
 /* Taps per point: 2^ndim (linear) or (2 r)^ndim (sinc); idx and w of
  * oracle_taps hold that many entries per point. */

@@ -701,6 +701,24 @@ def test_sinc_taps_on_grid_nodes_and_partition(ndim):
     np.testing.assert_allclose(half, half[::-1, ...], rtol=0, atol=1e-15)
 
 
+def test_sinc_tap_weights_match_the_kaiser_window_from_scipy():
+    """The per-axis sinc weights, with I0 from scipy instead of the oracle's own
+    evaluation: a point on a node along axis 1 leaves the axis-0 weights alone,
+    sinc(x) I0(b sqrt(1 - (x/4)^2)) / I0(b) at the 8 offsets x around it."""
+    from scipy.special import i0
+    g = oracle.Grid(shape=(40, 40), spacing=1.0, space_order=8, nb=4, vref=0.0, dt=1.0, nt=2, interp=1)
+    b = 6.31
+    for frac in (0.5, 0.137, 0.91):
+        x0 = 17.0 + frac
+        idx, w = oracle.taps(g, np.array([[x0, 20.0]]))
+        keep = w[0] != 0
+        nodes = idx[0][keep] // g.padded_shape[1] - 4
+        offs = nodes - x0
+        want = np.sinc(offs) * i0(b * np.sqrt(1 - (offs / 4) ** 2)) / i0(b)
+        assert len(offs) == 8 and np.all(np.diff(nodes) == 1)
+        np.testing.assert_allclose(w[0][keep], want, rtol=1e-13, atol=1e-16)
+
+
 def test_sinc_taps_interpolate_band_limited_fields():
     """Kaiser-windowed sinc interpolates a field at 1/4 and 1/2 of the Nyquist
     wavenumber to about 1e-3, where bilinear taps err by 0.09 and 0.28."""
