@@ -2,19 +2,30 @@
 """Throughput of the acoustic FWI hot path on one MI355X.
 
 A step is one shot gradient: forward solve with source injection and receiver
-sampling, every forward state kept (or checkpointed), residual and misfit,
-adjoint solve fused with the imaging condition, and the gradient finalise:
-the whole hot path once over one shot of the workload.
+sampling, forward states checkpointed (binomial schedule within the HBM
+budget) or all kept when they fit, residual and misfit, adjoint solve fused
+with the imaging condition, and the gradient finalise: the whole hot path once
+over one shot of the workload.  The default workload is the 3D head (256^3 at
+0.5 mm + 30-cell sponge = 316^3 padded, 10th order, 3000 steps, 1024
+receivers): the largest single-GPU configuration, whose fields exceed the
+Infinity Cache, so that the HBM fraction measures HBM.
 
 value = grid-point updates per second of forward + adjoint propagation,
 2 * N_padded * (nt - 1) per step (recomputation by checkpointing is not
-counted as work).  A forward-only solve of the same workload is timed too.
+counted as work; its factor is reported).
 
-roofline: the dominant kernel is the fused adjoint + imaging step (28
-algorithmic bytes per grid-point update: reads u^m, w^{m+1}, w^{m+2}, k, G;
-writes w^m, G).  Its time comes from HIP events the library records on the
-solve stream around the adjoint time loop during the timed steps, with the
-step and launch counts.
+roofline: the dominant kernel is the fused adjoint + imaging step, priced at
+28 algorithmic bytes per grid-point update (reads u^m, w^{m+1}, w^{m+2}, k,
+G; writes w^m, G).  Beside it, the forward step at 16 bytes (reads u^n,
+u^{n-1}, k; writes u^{n+1}).  Kernel times come from HIP events the library
+records on the solve stream around its time loops during the timed steps,
+with the step and launch counts.  A 2D workload that keeps every state runs
+the paired adjoint instead (24 bytes per step on average); its line reports
+that figure and the 28-byte one.
+
+Extra keys: the config-2 2D shot gradient and forward (same steps), and a
+bounded serving run (served shot solves/s and p50/p99 against one request at
+a time).  --fourth-order, --sinc and --medium add those solver variants.
 """
 import argparse
 import json
@@ -107,21 +118,26 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="config2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="config4", choices=sorted(WORKLOADS))
     ap.add_argument("--budget-gb", type=float, default=200.0,
-                    help="HBM budget of the gradient workspace (checkpointing beyond it)")
+                    help="HBM budget of the gradient workspace in GiB (checkpointing beyond it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forward", action="store_true")
-    ap.add_argument("--no-fourth-order", action="store_true",
-                    help="skip the forward and gradient solves with the fourth-order-in-time scheme")
-    ap.add_argument("--no-sinc", action="store_true",
-                    help="skip the shot gradient with windowed-sinc sources and receivers")
-    ap.add_argument("--no-medium", action="store_true",
-                    help="skip the forward solves in a heterogeneous medium (density, attenuation)")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the extra config-2 (2D breast) shot gradient and forward")
+    ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
+    ap.add_argument("--fourth-order", action="store_true",
+                    help="also time the forward and gradient solves with fourth-order time")
+    ap.add_argument("--sinc", action="store_true",
+                    help="also time the shot gradient with windowed-sinc sources and receivers")
+    ap.add_argument("--medium", action="store_true",
+                    help="also time forward solves in a heterogeneous medium (density, attenuation)")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
+    ap.add_argument("--leg-requests", type=int, default=32,
+                    help="serving leg of the default run: number of requests")
     ap.add_argument("--full-mix", action="store_true",
                     help="serving: all six grid classes and nt 500-3000 (default: 2D classes and "
                          "128^3, nt 500-1500)")
@@ -177,9 +193,21 @@ def cpu_baseline(w, vp_model, obs_np, seconds):
         "unit": "grid-point updates/s (fwd+adj)",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"{w.name} grid, first {nt_s} of {w.nt} steps, one shot gradient "
-                  f"(FP64 C, OpenMP), {el:.1f} s",
+        "sample": f"{w.name} grid ({'x'.join(map(str, w.padded_shape))} padded), first {nt_s} of "
+                  f"{w.nt} steps, one shot gradient (FP64 C, OpenMP), {el:.1f} s",
+        "cpu_model": cpu_model(),
     }
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def fwi_bench(args):
@@ -243,10 +271,10 @@ def fwi_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def serving_bench(args):
+def serving_run(args, nreq):
     """Served shot solves per second and p50/p99 latency against one request at
-    a time, on the same seeded request stream."""
-    import numpy as np
+    a time, on the same seeded request stream of nreq requests; every served
+    result is compared bit for bit with its one-at-a-time result."""
     import torch
 
     from paper_2110_03345_amd.serving import Server, serve_one_at_a_time
@@ -261,16 +289,17 @@ def serving_bench(args):
     # the generator draws the same numbers for it at any rate, only the
     # arrival times scale)
     seed = 2024
-    probe = [materialise(r) for r in request_stream(min(24, args.requests), seed, 1.0, **kw)]
+    probe = [materialise(r) for r in request_stream(min(24, nreq), seed, 1.0, **kw)]
     serve_one_at_a_time(probe[:1], realtime=False)
     cal = serve_one_at_a_time(probe, realtime=False)
     mean_service = cal["makespan_s"] / len(probe)
     rate = args.load / mean_service
-    specs = [materialise(r) for r in request_stream(args.requests, seed, rate, **kw)]
+    specs = [materialise(r) for r in request_stream(nreq, seed, rate, **kw)]
     print(f"[bench] serving: {len(specs)} requests, {sum(r.nshots for r in specs)} shots, "
           f"mean one-at-a-time service {mean_service * 1e3:.1f} ms, rate {rate:.2f}/s",
           file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+
     def progress(tag):
         return lambda n, total: print(f"[bench] {tag}: {n}/{total} requests done", file=sys.stderr,
                                       flush=True)
@@ -282,8 +311,24 @@ def serving_bench(args):
         srv.close()
     print(f"[bench] served: {served['solves_per_s']:.1f} shot solves/s, p50 {served['p50_s']:.3f} s, "
           f"p99 {served['p99_s']:.3f} s", file=sys.stderr, flush=True)
+    out = {
+        "requests": len(specs),
+        "shots": served["shot_solves"],
+        "grid_classes": {"2d": list(kw["classes_2d"]), "3d": list(kw["classes_3d"])},
+        "nt_range": list(kw["nt_range"]),
+        "arrival_rate_per_s": rate,
+        "load": args.load,
+        "max_slots": args.max_slots,
+        "max_chunk": args.max_chunk,
+        "solves_per_s": served["solves_per_s"],
+        "requests_per_s": served["requests_per_s"],
+        "p50_s": served["p50_s"],
+        "p99_s": served["p99_s"],
+        "makespan_s": served["makespan_s"],
+        "peak_hbm_gb": served["peak_hbm_gb"],
+    }
     if args.no_baseline:
-        return
+        return out
     base = serve_one_at_a_time(specs, realtime=True, progress=progress("one at a time"))
     print(f"[bench] one at a time: {base['solves_per_s']:.1f} shot solves/s, p50 {base['p50_s']:.3f} s, "
           f"p99 {base['p99_s']:.3f} s", file=sys.stderr, flush=True)
@@ -294,74 +339,72 @@ def serving_bench(args):
         if r.spec.kind == "gradient":
             ok = ok and torch.equal(r.result["dvp"], b["dvp"])
         same += int(ok)
+    out["one_at_a_time"] = {k: base[k] for k in ("solves_per_s", "requests_per_s", "p50_s", "p99_s",
+                                                 "makespan_s")}
+    out["speedup_solves_per_s"] = served["solves_per_s"] / base["solves_per_s"]
+    out["identical_results"] = f"{same}/{len(specs)}"
+    return out
+
+
+def serving_bench(args):
+    res = serving_run(args, args.requests)
     line = {
         "metric": "grid-point updates/s (fwd, fwd+adj), % HBM peak; served solves/s + p50/p99",
-        "value": served["solves_per_s"],
+        "value": res["solves_per_s"],
         "unit": "shot solves/s (served)",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 0,
-        "ms_per_step": served["makespan_s"] * 1e3,
+        "ms_per_step": res["makespan_s"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded request stream, phantoms and geometries)",
-        "config": {
-            "workload": f"serving: {WORKLOADS['serving']}",
-            "requests": len(specs),
-            "shots": served["shot_solves"],
-            "grid_classes": {"2d": list(kw["classes_2d"]), "3d": list(kw["classes_3d"])},
-            "nt_range": list(kw["nt_range"]),
-            "arrival_rate_per_s": rate,
-            "load": args.load,
-            "max_slots": args.max_slots,
-            "max_chunk": args.max_chunk,
-        },
-        "p50_s": served["p50_s"],
-        "p99_s": served["p99_s"],
-        "requests_per_s": served["requests_per_s"],
-        "peak_hbm_gb": served["peak_hbm_gb"],
-        "one_at_a_time": {k: base[k] for k in ("solves_per_s", "requests_per_s", "p50_s", "p99_s",
-                                               "makespan_s")},
-        "speedup_solves_per_s": served["solves_per_s"] / base["solves_per_s"],
-        "identical_results": f"{same}/{len(specs)}",
+        "config": {"workload": f"serving: {WORKLOADS['serving']}",
+                   **{k: res[k] for k in ("requests", "shots", "grid_classes", "nt_range",
+                                          "arrival_rate_per_s", "load", "max_slots", "max_chunk")}},
+        **{k: v for k, v in res.items() if k in ("p50_s", "p99_s", "requests_per_s", "peak_hbm_gb",
+                                                  "one_at_a_time", "speedup_solves_per_s",
+                                                  "identical_results")},
         "roofline": None,
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(the shot-parallel multi-GPU design is described, not built)", file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
+def _timed(fn, steps, label=None):
+    """Runs fn(i) for i < steps between two device synchronisations with the
+    library's HIP-event timing on; returns (seconds, timing counters)."""
+    import torch
+
+    import paper_2110_03345_amd as S
+    torch.cuda.synchronize()
+    S.stride_timing_read()
+    S.stride_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn(i)
+        if label:
+            print(f"[bench] {label} {i + 1}/{steps} enqueued", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    S.stride_timing_enable(False)
+    return t1 - t0, S.stride_timing_read()
+
+
+def measure(name, args, dev, headline):
+    """Shot gradient and forward solve of one workload: timing of the whole
+    step, and per-kernel figures from the library's HIP events."""
     import torch
 
     import paper_2110_03345_amd as S
 
-    if args.workload == "serving":
-        torch.cuda.set_device(0)
-        return serving_bench(args)
-    if args.workload == "fwi":
-        torch.cuda.set_device(0)
-        return fwi_bench(args)
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-    w, vp_true, vp_model = build_workload(args.workload, args.nt)
+    w, vp_true, vp_model = build_workload(name, args.nt)
     npad = w.padded_points
-    print(f"[bench] {args.workload}: padded {w.padded_shape} = {npad} points, nt={w.nt}",
+    print(f"[bench] {name}: padded {w.padded_shape} = {npad} points, nt={w.nt}",
           file=sys.stderr, flush=True)
-
     plan = S.Plan.from_workload(w)
     vp_t = torch.from_numpy(vp_true).to(dev)
     vp_m = torch.from_numpy(vp_model).to(dev)
@@ -377,254 +420,288 @@ def main():
     misfit = torch.zeros(1, dtype=torch.float64, device=dev)
     dvp = torch.empty_like(vp_m)
 
-    def grad_step():
+    def grad_step(_):
         S.stride_plan_gradient(plan.handle, vp_m, wav, obs, traces, misfit, dvp, ws)
 
-    for _ in range(args.warmup):
-        grad_step()
-    torch.cuda.synchronize()
-    S.stride_timing_read()
-    S.stride_timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        grad_step()
-        print(f"[bench] gradient step {i + 1}/{args.steps} enqueued", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    S.stride_timing_enable(False)
-    f_ms, f_n, f_l, a_ms, a_n, a_l = S.stride_timing_read()
-    elapsed = t1 - t0
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = 2.0 * npad * (w.nt - 1) * args.steps / elapsed
-    # per time step and per kernel launch (a 2D launch advances two steps)
+    steps = args.steps if headline else max(1, min(args.steps, 10))
+    warm = args.warmup if headline else 1
+    for _ in range(warm):
+        grad_step(0)
+    elapsed, (f_ms, f_n, f_l, a_ms, a_n, a_l) = _timed(
+        grad_step, steps, f"{name} gradient step" if headline else None)
+    ms_per_step = 1e3 * elapsed / steps
+    value = 2.0 * npad * (w.nt - 1) * steps / elapsed
     adj_step_s = a_ms * 1e-3 / max(a_n, 1)
     adj_launch_s = a_ms * 1e-3 / max(a_l, 1)
     adj_spl = a_n / max(a_l, 1)
     fwd_step_s = f_ms * 1e-3 / max(f_n, 1)
     # with every state kept the forward also stores v = L u + S (4 B more) and
-    # the adjoint images from it two terms at a time (modes 6 and 5 in turn);
-    # otherwise the fused adjoint (mode 0)
-    full_history = f_n <= args.steps * (w.nt - 1)
+    # the adjoint images from it two terms at a time (modes 6 and 5 in turn:
+    # 24 B per step on average); otherwise the fused adjoint (mode 0, 28 B)
+    full_history = f_n <= steps * (w.nt - 1)
     adj_bytes = ADJ_BYTES_PAIRED if full_history else ADJ_BYTES
     adj_gbs = adj_bytes * npad / adj_step_s / 1e9
-    fwd_in_grad_gbs = (FWD_BYTES + (4 if full_history else 0)) * npad / fwd_step_s / 1e9
-    recompute = f_n / max(1, args.steps * (w.nt - 1))
-    print(f"[bench] gradient: {ms_per_step:.2f} ms/step, adjoint {adj_step_s * 1e6:.2f} us/step "
-          f"({adj_gbs:.0f} GB/s, {adj_spl:.2f} steps/launch), forward {fwd_step_s * 1e6:.2f} us/step, "
-          f"forward steps per step {f_n / args.steps:.0f}", file=sys.stderr, flush=True)
-
-    fwd = {}
+    fwd_in_grad_bytes = FWD_BYTES + (4 if full_history else 0)
+    print(f"[bench] {name} gradient: {ms_per_step:.2f} ms/step, adjoint {adj_step_s * 1e6:.2f} us/step "
+          f"({adj_gbs:.0f} GB/s), forward {fwd_step_s * 1e6:.2f} us/step, forward steps per "
+          f"gradient {f_n / steps:.0f}", file=sys.stderr, flush=True)
+    out = {
+        "w": w, "plan": plan, "vp_true": vp_true, "vp_model": vp_model, "obs": obs,
+        "npad": npad, "value": value, "ms_per_step": ms_per_step, "steps": steps,
+        "ws_bytes": ws_bytes, "forward_steps_per_gradient": f_n / steps,
+        "recompute_factor": f_n / max(1, steps * (w.nt - 1)), "full_history": full_history,
+        "adjoint": {
+            "kernel": ("adjoint leapfrog steps, imaging from the stored v two terms per even step "
+                       "(step%dd_kernel<R, true, ., ., 6> and <..., 5> in turn; per-launch figures "
+                       "average the pair)" % w.ndim) if full_history else
+                      "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., 0>)" % w.ndim,
+            "bytes_per_point": adj_bytes,
+            "achieved": adj_gbs,
+            "frac": adj_gbs / HBM_PEAK_GBS,
+            "frac_at_28B": ADJ_BYTES * npad / adj_step_s / 1e9 / HBM_PEAK_GBS,
+            "us_per_launch": adj_launch_s * 1e6,
+            "us_per_step": adj_step_s * 1e6,
+            "steps_per_launch": adj_spl,
+        },
+        "forward_in_gradient": {
+            "bytes_per_point": fwd_in_grad_bytes,
+            "us_per_step": fwd_step_s * 1e6,
+            "achieved": fwd_in_grad_bytes * npad / fwd_step_s / 1e9,
+        },
+    }
     if not args.no_forward:
+        del ws
         fws = plan.workspace(S.STRIDE_MODE_FORWARD, device=dev)
         plan.forward(vp_m, wav, traces=traces, ws=fws)
-        torch.cuda.synchronize()
-        S.stride_timing_enable(True)
-        tf0 = time.perf_counter()
-        for _ in range(args.steps):
-            plan.forward(vp_m, wav, traces=traces, ws=fws)
-        torch.cuda.synchronize()
-        tf1 = time.perf_counter()
-        S.stride_timing_enable(False)
-        ff_ms, ff_n, ff_l, _, _, _ = S.stride_timing_read()
+        el_f, (ff_ms, ff_n, ff_l, _, _, _) = _timed(
+            lambda _: plan.forward(vp_m, wav, traces=traces, ws=fws), steps)
         f_step = ff_ms * 1e-3 / max(ff_n, 1)
-        fwd = {
-            "fwd_updates_per_s": npad * (w.nt - 1) * args.steps / (tf1 - tf0),
-            "fwd_ms_per_solve": 1e3 * (tf1 - tf0) / args.steps,
-            "fwd_us_per_step": f_step * 1e6,
-            "fwd_steps_per_launch": ff_n / max(ff_l, 1),
-            "fwd_kernel_gbs": FWD_BYTES * npad / f_step / 1e9,
+        out["forward"] = {
+            "kernel": "forward leapfrog step (step%dd_kernel<R, false, ., ., 0>)" % w.ndim,
+            "updates_per_s": npad * (w.nt - 1) * steps / el_f,
+            "ms_per_solve": 1e3 * el_f / steps,
+            "bytes_per_point": FWD_BYTES,
+            "achieved": FWD_BYTES * npad / f_step / 1e9,
+            "frac": FWD_BYTES * npad / f_step / 1e9 / HBM_PEAK_GBS,
+            "us_per_launch": ff_ms * 1e3 / max(ff_l, 1),
+            "us_per_step": f_step * 1e6,
         }
-        print(f"[bench] forward: {fwd['fwd_ms_per_solve']:.2f} ms/solve, {fwd['fwd_us_per_step']:.2f} us/step "
-              f"({fwd['fwd_kernel_gbs']:.0f} GB/s, {fwd['fwd_steps_per_launch']:.2f} steps/launch)",
+        del fws
+        print(f"[bench] {name} forward: {out['forward']['ms_per_solve']:.2f} ms/solve, "
+              f"{out['forward']['us_per_step']:.2f} us/step ({out['forward']['achieved']:.0f} GB/s)",
               file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return out
 
-    if not args.no_forward and not args.no_fourth_order:
-        # the same forward and gradient solves with the fourth-order-in-time
-        # scheme (same dt, same checkpoint budget)
+
+def variants(m, args, dev):
+    """The headline workload's solves with fourth-order time, windowed-sinc
+    points or a heterogeneous medium (each behind its flag)."""
+    import torch
+
+    import paper_2110_03345_amd as S
+    w, plan, obs, npad = m["w"], m["plan"], m["obs"], m["npad"]
+    vp_m = torch.from_numpy(m["vp_model"]).to(dev)
+    vp_t = torch.from_numpy(m["vp_true"]).to(dev)
+    wav = torch.from_numpy(w.wavelet).to(dev)
+    traces = torch.empty((plan.nrec, plan.nt), dtype=torch.float32, device=dev)
+    misfit = torch.zeros(1, dtype=torch.float64, device=dev)
+    dvp = torch.empty_like(vp_m)
+    budget = int(args.budget_gb * 2**30)
+    steps = args.steps
+    out = {}
+
+    def grad_ws(p):
+        full_b = p.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+        return torch.empty(p.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full_b, budget)),
+                           dtype=torch.uint8, device=dev)
+
+    if args.fourth_order:
         plan4 = S.Plan.from_workload(w, time_order=4)
         fws4 = plan4.workspace(S.STRIDE_MODE_FORWARD, device=dev)
         plan4.forward(vp_m, wav, traces=traces, ws=fws4)
-        torch.cuda.synchronize()
-        S.stride_timing_read()
-        S.stride_timing_enable(True)
-        t40 = time.perf_counter()
-        for _ in range(args.steps):
-            plan4.forward(vp_m, wav, traces=traces, ws=fws4)
-        torch.cuda.synchronize()
-        t41 = time.perf_counter()
-        S.stride_timing_enable(False)
-        f4_ms, f4_n, f4_l, _, _, _ = S.stride_timing_read()
+        el, (f4_ms, f4_n, f4_l, _, _, _) = _timed(
+            lambda _: plan4.forward(vp_m, wav, traces=traces, ws=fws4), steps)
         f4_step = f4_ms * 1e-3 / max(f4_n, 1)
         del fws4
         four = {
             "scheme": "leapfrog + modified-equation correction (fourth order in time); forward: two "
                       "launches per step, adjoint: three (two when every state is kept)",
-            "forward": {
-                "updates_per_s": npad * (w.nt - 1) * args.steps / (t41 - t40),
-                "ms_per_solve": 1e3 * (t41 - t40) / args.steps,
-                "us_per_step": f4_step * 1e6,
-                "launches_per_step": f4_l / max(f4_n, 1),
-                "bytes_per_point": FWD4_BYTES,
-                "gbs": FWD4_BYTES * npad / f4_step / 1e9,
-            },
+            "forward": {"updates_per_s": npad * (w.nt - 1) * steps / el,
+                        "ms_per_solve": 1e3 * el / steps, "us_per_step": f4_step * 1e6,
+                        "launches_per_step": f4_l / max(f4_n, 1), "bytes_per_point": FWD4_BYTES,
+                        "gbs": FWD4_BYTES * npad / f4_step / 1e9},
         }
-        print(f"[bench] forward, fourth order: {four['forward']['ms_per_solve']:.2f} ms/solve, "
-              f"{four['forward']['us_per_step']:.2f} us/step ({four['forward']['gbs']:.0f} GB/s)",
-              file=sys.stderr, flush=True)
-        full4 = plan4.workspace_bytes(S.STRIDE_MODE_GRADIENT)
-        ws4_bytes = plan4.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full4, budget))
-        del ws
-        ws4 = torch.empty(ws4_bytes, dtype=torch.uint8, device=dev)
+        ws4 = grad_ws(plan4)
         S.stride_plan_gradient(plan4.handle, vp_m, wav, obs, traces, misfit, dvp, ws4)
-        torch.cuda.synchronize()
-        S.stride_timing_read()
-        S.stride_timing_enable(True)
-        t40 = time.perf_counter()
-        for _ in range(args.steps):
-            S.stride_plan_gradient(plan4.handle, vp_m, wav, obs, traces, misfit, dvp, ws4)
-        torch.cuda.synchronize()
-        t41 = time.perf_counter()
-        S.stride_timing_enable(False)
-        g4 = S.stride_timing_read()
+        el, g4 = _timed(lambda _: S.stride_plan_gradient(plan4.handle, vp_m, wav, obs, traces,
+                                                         misfit, dvp, ws4), steps)
         a4_step = g4[3] * 1e-3 / max(g4[4], 1)
-        a4_bytes = ADJ4_BYTES_FULL if g4[1] <= args.steps * (w.nt - 1) else ADJ4_BYTES
-        four["gradient"] = {
-            "updates_per_s": 2.0 * npad * (w.nt - 1) * args.steps / (t41 - t40),
-            "ms_per_solve": 1e3 * (t41 - t40) / args.steps,
-            "workspace_gb": ws4_bytes / 2**30,
-            "forward_steps_per_gradient": g4[1] / args.steps,
-            "adjoint_us_per_step": a4_step * 1e6,
-            "adjoint_launches_per_step": g4[5] / max(g4[4], 1),
-            "adjoint_bytes_per_point": a4_bytes,
-            "adjoint_gbs": a4_bytes * npad / a4_step / 1e9,
-        }
+        a4_bytes = ADJ4_BYTES_FULL if g4[1] <= steps * (w.nt - 1) else ADJ4_BYTES
+        four["gradient"] = {"updates_per_s": 2.0 * npad * (w.nt - 1) * steps / el,
+                            "ms_per_solve": 1e3 * el / steps,
+                            "forward_steps_per_gradient": g4[1] / steps,
+                            "adjoint_us_per_step": a4_step * 1e6,
+                            "adjoint_launches_per_step": g4[5] / max(g4[4], 1),
+                            "adjoint_bytes_per_point": a4_bytes,
+                            "adjoint_gbs": a4_bytes * npad / a4_step / 1e9}
         del ws4, plan4
-        fwd["fourth_order"] = four
-        print(f"[bench] gradient, fourth order: {four['gradient']['ms_per_solve']:.2f} ms/solve, "
-              f"adjoint {four['gradient']['adjoint_us_per_step']:.2f} us/step "
-              f"({four['gradient']['adjoint_gbs']:.0f} GB/s)", file=sys.stderr, flush=True)
+        out["fourth_order"] = four
+        print(f"[bench] fourth order: forward {four['forward']['ms_per_solve']:.2f} ms/solve, gradient "
+              f"{four['gradient']['ms_per_solve']:.2f} ms/solve", file=sys.stderr, flush=True)
 
-    if not args.no_sinc:
-        # the same shot gradient with Kaiser-windowed sinc sources and receivers
-        ws = None                     # release the first gradient's workspace
+    if args.sinc:
         plan_s = S.Plan.from_workload(w, interp=1)
-        full_s = plan_s.workspace_bytes(S.STRIDE_MODE_GRADIENT)
-        ws_s = torch.empty(plan_s.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full_s, budget)),
-                           dtype=torch.uint8, device=dev)
+        ws_s = grad_ws(plan_s)
         S.stride_plan_gradient(plan_s.handle, vp_m, wav, obs, traces, misfit, dvp, ws_s)
-        torch.cuda.synchronize()
-        S.stride_timing_read()
-        S.stride_timing_enable(True)
-        ts0 = time.perf_counter()
-        for _ in range(args.steps):
-            S.stride_plan_gradient(plan_s.handle, vp_m, wav, obs, traces, misfit, dvp, ws_s)
-        torch.cuda.synchronize()
-        ts1 = time.perf_counter()
-        S.stride_timing_enable(False)
-        gs = S.stride_timing_read()
-        fwd["sinc_taps"] = {
-            "taps_per_point": 8 ** w.ndim,
-            "gradient_ms_per_solve": 1e3 * (ts1 - ts0) / args.steps,
-            "updates_per_s": 2.0 * npad * (w.nt - 1) * args.steps / (ts1 - ts0),
-            "forward_us_per_step": gs[0] * 1e3 / max(gs[1], 1),
-            "adjoint_us_per_step": gs[3] * 1e3 / max(gs[4], 1),
-        }
+        el, gs = _timed(lambda _: S.stride_plan_gradient(plan_s.handle, vp_m, wav, obs, traces,
+                                                         misfit, dvp, ws_s), steps)
+        out["sinc_taps"] = {"taps_per_point": 8 ** w.ndim,
+                            "gradient_ms_per_solve": 1e3 * el / steps,
+                            "updates_per_s": 2.0 * npad * (w.nt - 1) * steps / el,
+                            "forward_us_per_step": gs[0] * 1e3 / max(gs[1], 1),
+                            "adjoint_us_per_step": gs[3] * 1e3 / max(gs[4], 1)}
         del ws_s, plan_s
-        print(f"[bench] gradient, windowed-sinc taps: {fwd['sinc_taps']['gradient_ms_per_solve']:.2f} "
-              f"ms/solve, forward {fwd['sinc_taps']['forward_us_per_step']:.2f} us/step, adjoint "
-              f"{fwd['sinc_taps']['adjoint_us_per_step']:.2f} us/step", file=sys.stderr, flush=True)
+        print(f"[bench] windowed-sinc taps: gradient {out['sinc_taps']['gradient_ms_per_solve']:.2f} "
+              f"ms/solve", file=sys.stderr, flush=True)
 
-    if not args.no_forward and not args.no_medium:
-        # forward solves on the phantom with its density and attenuation (y = 0 and 2)
+    if args.medium:
         import workloads as W
         mws = plan.workspace(S.STRIDE_MODE_FORWARD_MEDIUM, device=dev)
         med = {"bytes_per_point": medium_bytes(w.ndim)}
         for y in (0, 2):
             # y = 2 at 500 kHz: bone at 10 Np/m keeps the explicit viscous term
             # within the stability limit at the workload's dt (40 Np/m would not)
-            rho, alpha0 = W.medium(vp_true, w.spacing, 11, att_power=y,
+            rho, alpha0 = W.medium(m["vp_true"], w.spacing, 11, att_power=y,
                                    alpha_bone=40.0 if y == 0 else 10.0)
             rho_t, al_t = torch.from_numpy(rho).to(dev), torch.from_numpy(alpha0).to(dev)
-            plan.forward_medium(vp_t, wav, rho=rho_t, alpha0=al_t, att_power=y, traces=traces, ws=mws)
-            torch.cuda.synchronize()
-            S.stride_timing_read()
-            S.stride_timing_enable(True)
-            tm0 = time.perf_counter()
-            for _ in range(args.steps):
+
+            def run(_):
                 plan.forward_medium(vp_t, wav, rho=rho_t, alpha0=al_t, att_power=y, traces=traces,
                                     ws=mws)
-            torch.cuda.synchronize()
-            tm1 = time.perf_counter()
-            S.stride_timing_enable(False)
-            m_ms, m_n, m_l, _, _, _ = S.stride_timing_read()
+            run(0)
+            el, (m_ms, m_n, _, _, _, _) = _timed(run, steps)
             m_step = m_ms * 1e-3 / max(m_n, 1)
-            med[f"y{y}"] = {
-                "updates_per_s": npad * (w.nt - 1) * args.steps / (tm1 - tm0),
-                "ms_per_solve": 1e3 * (tm1 - tm0) / args.steps,
-                "us_per_step": m_step * 1e6,
-                "gbs": medium_bytes(w.ndim) * npad / m_step / 1e9,
-            }
-            print(f"[bench] forward, medium y={y}: {med[f'y{y}']['ms_per_solve']:.2f} ms/solve, "
-                  f"{med[f'y{y}']['us_per_step']:.2f} us/step ({med[f'y{y}']['gbs']:.0f} GB/s)",
+            med[f"y{y}"] = {"updates_per_s": npad * (w.nt - 1) * steps / el,
+                            "ms_per_solve": 1e3 * el / steps, "us_per_step": m_step * 1e6,
+                            "gbs": medium_bytes(w.ndim) * npad / m_step / 1e9}
+            print(f"[bench] medium y={y}: {med[f'y{y}']['ms_per_solve']:.2f} ms/solve",
                   file=sys.stderr, flush=True)
             del rho_t, al_t
         del mws
-        fwd["medium"] = med
+        out["medium"] = med
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(the shot-parallel multi-GPU design is described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    if args.workload == "serving":
+        torch.cuda.set_device(0)
+        return serving_bench(args)
+    if args.workload == "fwi":
+        torch.cuda.set_device(0)
+        return fwi_bench(args)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    if args.calibrate_copy:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    m = measure(args.workload, args, dev, headline=True)
+    w, npad = m["w"], m["npad"]
+    extra = variants(m, args, dev)
+    obs_np = m["obs"].cpu().numpy()
+    for k in ("plan", "obs"):
+        m.pop(k)
+    torch.cuda.empty_cache()
+
+    adj = m["adjoint"]
+    traffic = measured_traffic(args.workload)
+    roofline = {
+        "bound": "hbm",
+        "kernel": adj["kernel"],
+        "achieved": adj["achieved"],
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": adj["frac"],
+        "traffic": traffic,
+        "traffic_unit": "HBM bytes per launch",
+        "traffic_over_algorithmic": (traffic / (adj["bytes_per_point"] * npad * adj["steps_per_launch"]))
+                                    if traffic else None,
+        "bytes_per_point": adj["bytes_per_point"],
+        "algorithmic_bytes_per_launch": adj["bytes_per_point"] * npad * adj["steps_per_launch"],
+        "steps_per_launch": adj["steps_per_launch"],
+        "us_per_launch": adj["us_per_launch"],
+        "us_per_step": adj["us_per_step"],
+        "frac_at_28B": adj["frac_at_28B"],
+        "forward_in_gradient": m["forward_in_gradient"],
+    }
+    if "forward" in m:
+        ftraffic = measured_traffic(args.workload + "_forward")
+        roofline["forward"] = {
+            **m["forward"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": ftraffic,
+            "traffic_over_algorithmic": (ftraffic / (FWD_BYTES * npad)) if ftraffic else None,
+        }
+
+    legs = {}
+    if not args.no_config2 and args.workload != "config2":
+        c2 = measure("config2", args, dev, headline=False)
+        legs["config2"] = {
+            "workload": f"config2: {WORKLOADS['config2']}",
+            "updates_per_s": c2["value"], "ms_per_step": c2["ms_per_step"], "steps": c2["steps"],
+            "full_history": c2["full_history"], "adjoint": c2["adjoint"],
+            "forward_in_gradient": c2["forward_in_gradient"], "forward": c2.get("forward"),
+        }
+        del c2
+        torch.cuda.empty_cache()
+    if not args.no_serving:
+        legs["serving"] = serving_run(args, args.leg_requests)
+        torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        obs_np = obs.cpu().numpy()
-        cpu = cpu_baseline(w, vp_model, obs_np, args.cpu_seconds)
+        cpu = cpu_baseline(w, m["vp_model"], obs_np, args.cpu_seconds)
         print(f"[bench] cpu baseline: {cpu['value']:.3e} updates/s on {cpu['cores']} threads",
               file=sys.stderr, flush=True)
 
-    traffic = measured_traffic(args.workload)
     line = {
         "metric": "grid-point updates/s (fwd, fwd+adj), % HBM peak; served solves/s + p50/p99",
-        "value": value,
+        "value": m["value"],
         "unit": "grid-point updates/s (fwd+adj)",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": m["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded phantom and ring geometry; observed data from a forward solve "
-                "on the phantom)",
+        "data": "synthetic (seeded phantom and transducer geometry; observed data from a forward "
+                "solve on the phantom)",
         "config": {
             "workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+            "padded_shape": list(w.padded_shape),
             "padded_points": npad,
             "nt": w.nt,
-            "nrec": plan.nrec,
+            "nrec": int(w.rec_xyz.shape[0]),
             "step": "one shot gradient (forward + residual/misfit + adjoint/imaging + finalise)",
-            "workspace_gb": ws_bytes / 2**30,
-            "forward_steps_per_gradient": f_n / args.steps,
-            "recompute_factor": recompute,
+            "workspace_gb": m["ws_bytes"] / 2**30,
+            "forward_steps_per_gradient": m["forward_steps_per_gradient"],
+            "recompute_factor": m["recompute_factor"],
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": ("adjoint leapfrog steps, imaging from the stored v two terms per even step "
-                       "(step%dd_kernel<R, true, ., ., 6> and <..., 5> in turn; per-launch figures "
-                       "average the pair)" % w.ndim) if full_history else
-                      "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., 0>)" % w.ndim,
-            "achieved": adj_gbs,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": adj_gbs / HBM_PEAK_GBS,
-            "traffic": traffic,
-            "traffic_unit": "HBM bytes per launch",
-            "traffic_over_algorithmic": (traffic / (adj_bytes * npad * adj_spl)) if traffic else None,
-            "bytes_per_point": adj_bytes,
-            "algorithmic_bytes_per_launch": adj_bytes * npad * adj_spl,
-            "steps_per_launch": adj_spl,
-            "us_per_launch": adj_launch_s * 1e6,
-            "us_per_step": adj_step_s * 1e6,
-            "forward_kernel_in_gradient_gbs": fwd_in_grad_gbs,
-        },
-        **fwd,
+        "roofline": roofline,
+        "fwd_updates_per_s": m["forward"]["updates_per_s"] if "forward" in m else None,
+        **legs,
+        **extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
