@@ -13,6 +13,15 @@ constexpr int kThreads = 256;   // 4 wave64 per block
 constexpr int kTileX = 64;      // contiguous axis: one wave64 spans a tile row
 constexpr int kSincHalfWidth = 4;   // windowed-sinc taps: 2 r nodes per axis
 
+// Launch shapes of the step kernels: rows per thread x wave64s per block (the
+// tile is 64 x rows * waves) and, in 3D, planes per block.  The fastest
+// measured on 1104^2 and 316^3.  The 3D adjoint shape also serves every step
+// with two stencil fields (adjoint, fourth-order adjoint correction, medium).
+constexpr int kRy2d = 4, kWaves2d = 4;
+constexpr int kRy3dFwd = 4, kWaves3dFwd = 8, kZc3dFwd = 32;
+constexpr int kRy3dAdj = 2, kWaves3dAdj = 4, kZc3dAdj = 16;
+constexpr int kPitchAlign = 16;     // row pitch of the fields, in floats (64 B)
+
 // Padded grid as laid out in the workspace.  Axis nd-1 is contiguous.
 // 2D: axis 0 = rows, axis 1 = columns.  3D: axis 0 is the marching axis.
 struct Dims {

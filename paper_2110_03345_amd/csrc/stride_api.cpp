@@ -37,11 +37,13 @@ namespace {
 
 long long round_up(long long v, long long a) { return (v + a - 1) / a * a; }
 
+#ifdef STRIDE_TILE_SWEEP
 int env_int(const char* name, int dflt)
 {
     const char* s = getenv(name);
     return s && *s ? atoi(s) : dflt;
 }
+#endif
 
 // Central second-derivative weights of the (2r+1)-point stencil, as exact
 // rationals (unique solution of the Taylor moment conditions).
@@ -104,13 +106,26 @@ LaunchShape make_shape(const Dims& d, int zc, int ry, int waves)
 // Planes per 3D block.  Short chunks give many independent blocks (the march
 // is latency-bound, so parallelism wins over the 2R lead-in planes each chunk
 // re-reads, which mostly hit L2).  On 316^3: 32 for the 64 x 32 forward tile,
-// 16 for the 64 x 8 adjoint tile.
-int default_zc(const Dims& d, int ty)
+// 16 for the 64 x 8 adjoint tile.  (STRIDE_TILE_SWEEP builds read STRIDE_ZC.)
+int default_zc(const Dims& d, bool adjoint)
 {
     if (d.nd != 3)
         return 1;
+#ifdef STRIDE_TILE_SWEEP
     int want = env_int("STRIDE_ZC", 0);
-    return want > 0 ? want : (ty >= 32 ? 32 : 16);
+    if (want > 0)
+        return want;
+#endif
+    return adjoint ? kZc3dAdj : kZc3dFwd;
+}
+
+int pitch_align()
+{
+#ifdef STRIDE_TILE_SWEEP
+    return std::max(1, env_int("STRIDE_PITCH_ALIGN", kPitchAlign));
+#else
+    return kPitchAlign;
+#endif
 }
 
 // Taps of a set of points: T per point, flat.
@@ -1192,7 +1207,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         d.phys[a] = a < P->nd ? (int)grid->shape[a] : 1;
     }
     d.nb = P->nb;
-    int align = std::max(1, env_int("STRIDE_PITCH_ALIGN", 16));
+    int align = pitch_align();
     long long pitch = round_up(d.n[P->nd - 1], align);
     if (P->nd == 2) {
         d.st[1] = 1;
@@ -1249,8 +1264,8 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     int ryf, wf, rya, wa;
     tile_shape(P->nd, false, &ryf, &wf);
     tile_shape(P->nd, true, &rya, &wa);
-    P->ls_fwd = make_shape(d, default_zc(d, ryf * wf), ryf, wf);
-    P->ls_adj = make_shape(d, default_zc(d, rya * wa), rya, wa);
+    P->ls_fwd = make_shape(d, default_zc(d, false), ryf, wf);
+    P->ls_adj = make_shape(d, default_zc(d, true), rya, wa);
 
 
     TapSet st, rt;
@@ -1495,7 +1510,7 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
     d.nd = P.nd;
     for (int a = 0; a < 3; ++a)
         d.n[a] = a < P.nd ? (int)(grid->shape[a] + 2LL * P.nb) : 1;
-    int align = std::max(1, env_int("STRIDE_PITCH_ALIGN", 16));
+    int align = pitch_align();
     long long pitch = round_up(d.n[P.nd - 1], align);
     d.total = P.nd == 2 ? (long long)d.n[0] * pitch : (long long)d.n[0] * d.n[1] * pitch;
     return stride_workspace_bytes(&P, mode, budget_bytes, out_bytes);

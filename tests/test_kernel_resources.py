@@ -39,4 +39,4 @@ def test_single_shot_3d_steps_meet_their_occupancy_target():
         if mode == 0 and (ry <= 2 or (not adj and waves == 8)):
             seen += 1
             assert r["vgpr"] <= 128, (name, r)
-    assert seen >= 8, seen
+    assert seen >= 4, seen
