@@ -132,6 +132,31 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
 int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float* wavelet,
                         float* traces, void* ws, size_t ws_bytes, void* stream);
 
+/* Size of the static workspace of stride_plan_forward_static (64 MiB).  Each
+ * device the library runs on holds one such block of device memory from the
+ * loading of the library until the process ends. */
+#define STRIDE_STATIC_WORKSPACE_BYTES (64u << 20)
+
+/* stride_plan_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same solve, with the same results bit for bit, whose
+ * workspace (scratch scalars, k and the two wavefields, and p with
+ * time_order 4) is the library's static workspace on the current device
+ * instead of a caller buffer.  It calls no hipMalloc, hipFree or other
+ * allocating routine; the caller passes vp, wavelet and traces as for
+ * stride_plan_forward.  Limit: stride_workspace_bytes(plan, FORWARD) must not
+ * exceed STRIDE_STATIC_WORKSPACE_BYTES (about 5.5 M padded points with
+ * second-order time, 4.1 M with fourth-order), else WORKSPACE and nothing is
+ * enqueued.  Every call on one device shares that device's workspace and
+ * rewrites all of it that the solve reads (fields are cleared by a fill
+ * kernel, not a memset), so calls in sequence on one stream are independent;
+ * calls that overlap on one device (several streams or threads) race and must
+ * not be issued.  The current device must be the plan's.  Like
+ * stride_plan_forward it reads max(vp) back for the CFL check (one stream
+ * synchronisation).  Errors: INVALID_ARG, CFL, WORKSPACE, HIP. */
+int stride_plan_forward_static(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                               float* traces, void* stream);
+
 /* Forward solve in a heterogeneous medium (Sec. 2.4 acoustic equation with
  * variable density and power-law attenuation, y = att_power in {0, 2}):
  *   (1/vp^2) p_tt = rho div(rho^{-1} grad p) + eta d/dt (-lap)^{y/2} p + s,

@@ -28,7 +28,8 @@ STRIDE_MODE_FORWARD_MEDIUM = 2
 
 EXPORTS = (
     "stride_plan_create", "stride_plan_destroy", "stride_plan_padded_shape",
-    "stride_workspace_bytes", "stride_plan_forward", "stride_plan_forward_medium", "stride_lowpass",
+    "stride_workspace_bytes", "stride_plan_forward", "stride_plan_forward_static",
+    "stride_plan_forward_medium", "stride_lowpass",
     "stride_descent_step",
     "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
@@ -80,6 +81,7 @@ def lib():
         L.stride_plan_padded_shape.argtypes = [vp_, ctypes.POINTER(ctypes.c_int64)]
         L.stride_workspace_bytes.argtypes = [vp_, i32, sz, ctypes.POINTER(sz)]
         L.stride_plan_forward.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
+        L.stride_plan_forward_static.argtypes = [vp_, vp_, vp_, vp_, vp_]
         L.stride_plan_forward_medium.argtypes = [vp_, vp_, vp_, vp_, i32, vp_, vp_, vp_, sz, vp_]
         L.stride_lowpass.argtypes = [vp_, vp_, i32, i32, ctypes.c_double, ctypes.c_double, vp_]
         L.stride_descent_step.argtypes = [vp_, vp_, vp_, ctypes.c_int64, ctypes.c_float,
@@ -227,6 +229,16 @@ def stride_timing_read():
 def stride_plan_forward(plan, vp, wavelet, traces, ws, stream=None):
     _check(lib().stride_plan_forward(plan, _dev(vp), _dev(wavelet), _dev(traces), _dev(ws),
                                      ws.numel(), _stream(stream)))
+
+
+def stride_plan_forward_static(plan, vp, wavelet, traces, stream=None):
+    """stride_plan_forward on the library's static device workspace (no
+    allocation; STRIDE_STATIC_WORKSPACE_BYTES at most)."""
+    _check(lib().stride_plan_forward_static(plan, _dev(vp), _dev(wavelet), _dev(traces),
+                                            _stream(stream)))
+
+
+STRIDE_STATIC_WORKSPACE_BYTES = 64 << 20
 
 
 def stride_plan_forward_medium(plan, vp, rho, alpha0, att_power, wavelet, traces, ws, stream=None):

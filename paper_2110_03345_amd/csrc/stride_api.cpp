@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -1154,6 +1155,43 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// ------------------------------------------------------------ allocation-free forward
+//
+// Workspace of stride_plan_forward_static: a file-scope device array that each
+// device holds for the life of the process.  On the host, `scratch` names only
+// a stand-in for the device copy; every host use goes through the device
+// address hipGetSymbolAddress returns, looked up once per device (with that
+// device current) and kept.
+constexpr int kMaxStaticDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxStaticDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[STRIDE_STATIC_WORKSPACE_BYTES];
+
+namespace {
+
+// Device address of `scratch` on the current device.
+int static_workspace(void** out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxStaticDevices)
+        return fail(STRIDE_E_INVALID_ARG, "device %d is beyond the %d devices the static workspace serves",
+                    dev, kMaxStaticDevices);
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || (uintptr_t)ptr % 256)
+            return fail(STRIDE_E_HIP, "static workspace address %p is not 256-byte aligned", ptr);
+        g_static_ptr[dev] = ptr;
+    }
+    *out = g_static_ptr[dev];
+    return STRIDE_OK;
+}
+
 }  // namespace
 
 // ============================================================== C ABI
@@ -1402,6 +1440,31 @@ int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float*
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
     return forward_solve(*plan, vp, wavelet, traces, ws, ws_bytes, as_stream(stream));
+}
+
+int stride_plan_forward_static(const stride_plan_t* plan, const float* vp, const float* wavelet,
+                               float* traces, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    const size_t need = layout_of(*plan).fixed_fwd;
+    if (need > (size_t)STRIDE_STATIC_WORKSPACE_BYTES)
+        return fail(STRIDE_E_WORKSPACE,
+                    "the forward solve needs %zu bytes of workspace, beyond the static workspace "
+                    "of %zu bytes (use stride_plan_forward with a caller workspace)",
+                    need, (size_t)STRIDE_STATIC_WORKSPACE_BYTES);
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != plan->device)
+        return fail(STRIDE_E_INVALID_ARG, "the plan belongs to device %d, the current device is %d",
+                    plan->device, dev);
+    void* ws = nullptr;
+    int rc = static_workspace(&ws);
+    if (rc)
+        return rc;
+    return forward_solve(*plan, vp, wavelet, traces, ws, (size_t)STRIDE_STATIC_WORKSPACE_BYTES,
+                         as_stream(stream));
 }
 
 int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const float* rho,
