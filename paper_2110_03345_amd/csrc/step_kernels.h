@@ -74,6 +74,13 @@ __device__ __forceinline__ void bstore(__amdgpu_buffer_rsrc_t r, int byte_off, f
     __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, 0, 0);
 }
 
+// Store with the non-temporal policy (results are read back only in a later
+// launch): a 32-bit offset into a per-plane descriptor, no 64-bit address.
+__device__ __forceinline__ void bstore_nt(__amdgpu_buffer_rsrc_t r, int byte_off, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, byte_off, 0, 2);
+}
+
 // The builtin returns the raw 32 bits; reinterpret them (no numeric conversion).
 __device__ __forceinline__ float bload(__amdgpu_buffer_rsrc_t r, int byte_off)
 {
@@ -132,12 +139,15 @@ __device__ __forceinline__ void sample_block(const SampleSet& smp, const float* 
 
 constexpr float kTwelfth = 1.f / 12.f;
 
+// Leapfrog update with the sponge's damping: a = 1 / (1 + eta dt/2) by the
+// hardware reciprocal (within 1 ulp; an IEEE division would cost about ten
+// instructions per point, and most waves of a 3D grid touch the sponge).
 __device__ __forceinline__ float leapfrog(float ctr, float prev, float kk, float rhs, float eta,
                                           float half_dt)
 {
     if (eta == 0.f)
         return fmaf(kk, rhs, fmaf(2.f, ctr, -prev));
-    const float a = 1.f / fmaf(eta, half_dt, 1.f);
+    const float a = __builtin_amdgcn_rcpf(fmaf(eta, half_dt, 1.f));
     const float b = fmaf(-eta, half_dt, 1.f) * a;
     return fmaf(a, fmaf(kk, rhs, 2.f * ctr), -(b * prev));
 }
@@ -541,7 +551,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
 
     // plane-independent geometry: byte offsets within a plane (-1 = outside)
     const int plane_bytes = (int)(s0 * 4);
-    int rbo[RY], roff[RY];
+    int rbo[RY];
     bool rin[RY];
     float ey[RY];
     const int dxd = layer_depth(gx, n2, d.nb);
@@ -550,8 +560,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
     for (int j = 0; j < RY; ++j) {
         const int gy = y0 + wy * RY + j;
         rin[j] = xin && gy < n1;
-        roff[j] = gy * s1 + gx;
-        rbo[j] = rin[j] ? roff[j] * 4 : -1;
+        rbo[j] = rin[j] ? (gy * s1 + gx) * 4 : -1;
         const int dyd = layer_depth(gy, n1, d.nb);
         ey[j] = fmaf(sp.e[1], (float)(dyd * dyd), ex);
     }
@@ -814,9 +823,9 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                              &sS[buf][NF - 1][0]);
             __syncthreads();
 
-            float* Cz = p.C + (long long)z * s0;
-            float* Gz = ADJ && MODE != kAdjPlain ? p.G + (long long)z * s0 : nullptr;
-            float* Vz = MODE == kStepV ? p.V + (long long)z * s0 : nullptr;
+            const auto rC = rsrc(p.C, z);
+            const auto rG = rsrc(ADJ && MODE != kAdjPlain ? p.G : p.C, z);
+            const auto rV = rsrc(MODE == kStepV ? p.V : p.C, z);
             const int dzd = layer_depth(z, n0, d.nb);
             const float ez = sp.e[0] * (float)(dzd * dzd);
 #pragma unroll
@@ -858,17 +867,16 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     const float prev = q[1][j][slot_c];
                     const float lapb = fmaf(cf.c0, prev, bz + by + bx);
                     const float dens = fmaf(mm[0][j], dz, fmaf(mm[1][j], dy, mm[2][j] * dx));
-                    __builtin_nontemporal_store(medium_out(ctr, lap, dens, inj, lapb, prev, kk[j], mm[3][j],
-                                                           p.att_power, eta, sp.half_dt),
-                                                Cz + roff[j]);
+                    bstore_nt(rC, rbo[j], medium_out(ctr, lap, dens, inj, lapb, prev, kk[j], mm[3][j],
+                                                     p.att_power, eta, sp.half_dt));
                     continue;
                 }
                 const float out = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
-                __builtin_nontemporal_store(out, Cz + roff[j]);
+                bstore_nt(rC, rbo[j], out);
                 if constexpr (MODE == kStepV)
-                    __builtin_nontemporal_store(lap, Vz + roff[j]);
+                    bstore_nt(rV, rbo[j], lap);
                 if constexpr (MODE == kImageV) {
-                    __builtin_nontemporal_store(fmaf(ctr, vw[j], fmaf(bb[j], vw2[j], gg[j])), Gz + roff[j]);
+                    bstore_nt(rG, rbo[j], fmaf(ctr, vw[j], fmaf(bb[j], vw2[j], gg[j])));
                 } else if constexpr (ADJ && MODE != kAdjPlain) {
                     const float* SU = S + (NF - 1) * PLANE;
                     const float uc0 = q[NF - 1][j][slot_c];
@@ -884,8 +892,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                         lu += sS[buf][NF - 1][ly * kTileX + lx];
                         sS[buf][NF - 1][ly * kTileX + lx] = 0.f;
                     }
-                    __builtin_nontemporal_store(image_out<MODE>(ctr, uc0, lu, uu[j], kk[j], gg[j]),
-                                                Gz + roff[j]);
+                    bstore_nt(rG, rbo[j], image_out<MODE>(ctr, uc0, lu, uu[j], kk[j], gg[j]));
                 }
             }
             buf ^= 1;
@@ -984,10 +991,13 @@ __global__ __launch_bounds__(64 * WAVES) void step3d_batched(Dims d, StencilCoef
 #define STRIDE_DISPATCH2D(L) L(kRy2d, kWaves2d)
 #define STRIDE_DISPATCH3D(L)                                                                      \
     do {                                                                                          \
-        if (ls.ry == kRy3dFwd && ls.waves == kWaves3dFwd)                                         \
-            L(kRy3dFwd, kWaves3dFwd);                                                             \
-        else                                                                                      \
-            L(kRy3dAdj, kWaves3dAdj);                                                             \
+        if constexpr (!ADJ) {                                                                     \
+            if (ls.ry == kRy3dFwd && ls.waves == kWaves3dFwd) {                                   \
+                L(kRy3dFwd, kWaves3dFwd);                                                         \
+                break;                                                                            \
+            }                                                                                     \
+        }                                                                                         \
+        L(kRy3dAdj, kWaves3dAdj);                                                                 \
     } while (0)
 #endif
 
