@@ -37,9 +37,12 @@
  *     sized with stride_workspace_bytes().  Calls that run solves allocate
  *     nothing; stride_plan_create allocates the plan's small tap tables.
  *   - stream is a hipStream_t passed as void*; NULL is the default stream.
- *     Solve calls only enqueue work (no host synchronisation) except the
- *     one-shot stride_forward / stride_gradient, which create and destroy a
- *     plan and therefore return after the work has finished.
+ *     A solve call reads max(vp) back for its stability check (one stream
+ *     synchronisation before its time loop) and, while the non-finite check
+ *     is on (stride_check_finite, the default), scans its outputs and waits
+ *     for the result, so it returns after its work has finished; with the
+ *     check off it returns once the time loop is enqueued.  The one-shot
+ *     stride_forward / stride_gradient always return after the work.
  *   - Every entry point returns STRIDE_OK or a negative error code; nothing is
  *     enqueued when validation fails.  stride_last_error() returns a message
  *     for the calling thread's last error.
@@ -63,7 +66,7 @@ enum {
     STRIDE_E_GEOMETRY = -3,    /* a source or receiver lies outside the physical grid */
     STRIDE_E_WORKSPACE = -4,   /* ws_bytes below what the call needs */
     STRIDE_E_HIP = -5,         /* a HIP runtime call failed */
-    STRIDE_E_NONFINITE = -6    /* non-finite values detected */
+    STRIDE_E_NONFINITE = -6    /* NaN or infinity in a solve's outputs (stride_check_finite) */
 };
 
 /* Workspace modes: FORWARD (stride_plan_forward), GRADIENT (gradients,
@@ -289,6 +292,16 @@ int stride_engine_slot_ticks(const stride_engine_t* engine, int32_t slot, int64_
 
 /* dst[i] += src[i] on the device (shot-gradient summation in a fixed order). */
 int stride_accumulate(float* dst, const float* src, int64_t n, void* stream);
+
+/* Non-finite outputs.  While on for the calling thread (the default), every
+ * solve entry point (stride_plan_forward[_static], stride_plan_forward_medium,
+ * stride_forward_save, stride_backward, stride_plan_gradient and the one-shot
+ * forms) scans what it wrote -- traces, misfit, dvp, dwavelet -- on its stream
+ * with a small kernel, waits for the result, and returns STRIDE_E_NONFINITE,
+ * naming the outputs, if any value is NaN or infinite (for example from a
+ * wavelet or observed data holding one).  The outputs are left as computed.
+ * on = 0 turns the scan and its wait off.  Always returns STRIDE_OK. */
+int stride_check_finite(int32_t on);
 
 /* Tracing of the time loops.  While enabled on the calling thread, every solve
  * records HIP event pairs on its stream around its forward time loop, its

@@ -19,6 +19,7 @@ from ._abi import (  # noqa: F401
     lib,
     make_grid,
     stride_backward,
+    stride_check_finite,
     stride_descent_step,
     stride_forward,
     stride_forward_save,

@@ -34,7 +34,7 @@ EXPORTS = (
     "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
     "stride_schedule_info", "stride_last_error", "stride_error_string",
-    "stride_timing_enable", "stride_timing_read",
+    "stride_timing_enable", "stride_timing_read", "stride_check_finite",
     "stride_engine_create", "stride_engine_destroy", "stride_engine_attach", "stride_engine_run",
     "stride_engine_detach", "stride_engine_slot_ticks", "stride_accumulate",
 )
@@ -95,6 +95,7 @@ def lib():
         L.stride_schedule_info.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(i32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
         L.stride_timing_enable.argtypes = [i32]
+        L.stride_check_finite.argtypes = [i32]
         L.stride_timing_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                          dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
         L.stride_engine_create.argtypes = [gp, i32, i32, i32, i32, ctypes.POINTER(vp_)]
@@ -214,6 +215,11 @@ def stride_schedule_info(nt: int, fields: int):
 
 def stride_timing_enable(on: bool) -> None:
     _check(lib().stride_timing_enable(1 if on else 0))
+
+
+def stride_check_finite(on: bool) -> None:
+    """Scan solve outputs for NaN/Inf (STRIDE_E_NONFINITE) on this thread."""
+    _check(lib().stride_check_finite(1 if on else 0))
 
 
 def stride_timing_read():

@@ -203,6 +203,9 @@ void launch_residual_misfit(const float* traces, const float* observed, float* r
 void launch_finalize_dvp(const Dims& d, const float* H, const float* kdiv, const float* vp,
                          float* dvp, float* tmp0, float* tmp1, hipStream_t s);
 void launch_copy(float* dst, const float* src, long long n, hipStream_t s);
+// *flag |= bit if any of the n values is NaN or infinite (flag cleared by the caller).
+void launch_finite_scan(const float* p, long long n, unsigned* flag, unsigned bit, hipStream_t s);
+void launch_finite_scan(const double* p, long long n, unsigned* flag, unsigned bit, hipStream_t s);
 // flags[0] = bits of max(vp) (vp > 0), flags[1] = 1 if any vp <= 0 or non-finite.
 void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s);
 

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -622,6 +623,60 @@ struct PhaseTimer {
 
 thread_local PhaseTimer g_timer;
 
+// ------------------------------------------------------------ output checks
+
+// Non-finite outputs (STRIDE_E_NONFINITE): while enabled on the calling thread
+// (the default), a solve entry point scans what it wrote, each array into one
+// bit of a flag word in the workspace's scratch, and waits for the word.
+thread_local bool g_check_finite = true;
+
+struct OutArray {
+    const float* f;
+    const double* d;
+    long long n;
+    const char* what;
+};
+
+int check_finite(unsigned* flag, hipStream_t s, std::initializer_list<OutArray> outs)
+{
+    if (!g_check_finite)
+        return STRIDE_OK;
+    launch_fill(reinterpret_cast<float*>(flag), 1, 0.f, s);
+    unsigned bit = 1;
+    for (const OutArray& o : outs) {
+        if (o.n > 0 && o.f)
+            launch_finite_scan(o.f, o.n, flag, bit, s);
+        else if (o.n > 0 && o.d)
+            launch_finite_scan(o.d, o.n, flag, bit, s);
+        bit <<= 1;
+    }
+    unsigned host = 0;
+    HIP_TRY(hipMemcpyAsync(&host, flag, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (!host)
+        return STRIDE_OK;
+    std::string names;
+    bit = 1;
+    for (const OutArray& o : outs) {
+        if (host & bit)
+            names += names.empty() ? o.what : std::string(", ") + o.what;
+        bit <<= 1;
+    }
+    return fail(STRIDE_E_NONFINITE, "non-finite values in the output: %s", names.c_str());
+}
+
+// Flag word of the non-finite check: word 4 of a workspace's scratch
+// (words 0-3 hold the vp and medium checks).
+unsigned* finite_flag(void* ws) { return reinterpret_cast<unsigned*>(ws) + 4; }
+
+long long phys_points(const stride_plan& P)
+{
+    long long n = 1;
+    for (int a = 0; a < P.nd; ++a)
+        n *= P.g.shape[a];
+    return n;
+}
+
 // ------------------------------------------------------------ executors
 
 // Runs a checkpointed gradient on one stream.  forward_phase launches the
@@ -975,7 +1030,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
         g_timer.end(tid, s, 0, P.nt - 1, 2LL * (P.nt - 1));
         launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
         HIP_TRY(hipGetLastError());
-        return STRIDE_OK;
+        return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
     }
     for (int n = 0; n < P.nt - 1; ++n) {
         StepParams p = base_params(P);
@@ -992,7 +1047,7 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
     g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
     launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
-    return STRIDE_OK;
+    return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
 }
 
 // Forward solve in a heterogeneous medium: three rotating wavefields (the
@@ -1078,7 +1133,7 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
     g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
     launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
-    return STRIDE_OK;
+    return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
 }
 
 int forward_save(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
@@ -1520,7 +1575,12 @@ int stride_forward_save(const stride_plan_t* plan, const float* vp, const float*
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
     GradWs W;
-    return forward_save(*plan, vp, wavelet, traces, ws, ws_bytes, as_stream(stream), W);
+    hipStream_t s = as_stream(stream);
+    int rc = forward_save(*plan, vp, wavelet, traces, ws, ws_bytes, s, W);
+    if (rc)
+        return rc;
+    return check_finite(finite_flag(ws), s,
+                        {{traces ? traces : W.traces, nullptr, (long long)plan->nrec * plan->nt, "traces"}});
 }
 
 int stride_backward(const stride_plan_t* plan, const float* vp, const float* wavelet,
@@ -1530,7 +1590,13 @@ int stride_backward(const stride_plan_t* plan, const float* vp, const float* wav
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
-    return backward(*plan, vp, wavelet, grad_traces, dvp, dwavelet, ws, ws_bytes, as_stream(stream));
+    hipStream_t s = as_stream(stream);
+    int rc = backward(*plan, vp, wavelet, grad_traces, dvp, dwavelet, ws, ws_bytes, s);
+    if (rc)
+        return rc;
+    return check_finite(finite_flag(ws), s,
+                        {{dvp, nullptr, phys_points(*plan), "dvp"},
+                         {dwavelet, nullptr, dwavelet ? (long long)plan->nsrc * plan->nt : 0, "dwavelet"}});
 }
 
 int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float* wavelet,
@@ -1549,7 +1615,13 @@ int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float
         return rc;
     launch_residual_misfit(W.traces, observed, W.residual, (long long)plan->nrec * plan->nt, misfit,
                            W.partial, s);
-    return backward(*plan, vp, wavelet, W.residual, dvp, nullptr, ws, ws_bytes, s);
+    rc = backward(*plan, vp, wavelet, W.residual, dvp, nullptr, ws, ws_bytes, s);
+    if (rc)
+        return rc;
+    return check_finite(finite_flag(ws), s,
+                        {{W.traces, nullptr, (long long)plan->nrec * plan->nt, "traces"},
+                         {nullptr, misfit, 1, "misfit"},
+                         {dvp, nullptr, phys_points(*plan), "dvp"}});
 }
 
 int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec, int32_t mode,
@@ -1614,6 +1686,12 @@ int stride_gradient(const stride_grid_t* grid, const float* vp, const float* wav
     if (!rc && e != hipSuccess)
         rc = fail(STRIDE_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
     return rc;
+}
+
+int stride_check_finite(int32_t on)
+{
+    g_check_finite = on != 0;
+    return STRIDE_OK;
 }
 
 int stride_timing_enable(int32_t on)

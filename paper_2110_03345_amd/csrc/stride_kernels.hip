@@ -21,6 +21,7 @@
 // live in step_kernels.h and compile in their own translation units.
 #include "step_kernels.h"
 
+#include <algorithm>
 #include <cstdlib>
 
 namespace stride {
@@ -514,6 +515,31 @@ void launch_fill(float* p, long long n, float v, hipStream_t s)
 void launch_copy(float* dst, const float* src, long long n, hipStream_t s)
 {
     hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, dst, src, n);
+}
+
+// flag |= bit when any of the n values is NaN or infinite.
+template <class T>
+__global__ void finite_scan_kernel(const T* p, long long n, unsigned* flag, unsigned bit)
+{
+    bool bad = false;
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (; i < n; i += stride)
+        bad |= !isfinite(p[i]);
+    if (bad)
+        atomicOr(flag, bit);
+}
+
+void launch_finite_scan(const float* p, long long n, unsigned* flag, unsigned bit, hipStream_t s)
+{
+    hipLaunchKernelGGL(finite_scan_kernel<float>, dim3(std::min(grid_for(n, 256), 2048)), dim3(256),
+                       0, s, p, n, flag, bit);
+}
+
+void launch_finite_scan(const double* p, long long n, unsigned* flag, unsigned bit, hipStream_t s)
+{
+    hipLaunchKernelGGL(finite_scan_kernel<double>, dim3(std::min(grid_for(n, 256), 2048)), dim3(256),
+                       0, s, p, n, flag, bit);
 }
 
 void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s)
