@@ -9,12 +9,17 @@ configuration bench.py times (default tile shapes and chunk lengths).
 - 3D head-like grid, 316^3 padded, 10th order: traces of a 150-step forward
   against the oracle, and the gradient bitwise unchanged by the checkpointing
   budget at this size.
+(The full 3000-step 3D forward and a checkpointed 3D gradient at this size are
+compared in test_gpu_fullsize.py.)  Besides the relative L2 over each output,
+every trace and the interior and edge strip of each gradient are bounded on
+their own (tests/parity.py).
 """
 import numpy as np
 import pytest
 
 import oracle
 import workloads as W
+from parity import check_field, check_traces
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -22,12 +27,6 @@ pytestmark = pytest.mark.gpu
 if torch.cuda.is_available():
     import paper_2110_03345_amd as S
     from paper_2110_03345_amd.autograd import wave_traces
-
-
-def rel(a, b):
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
 def dev(x):
@@ -40,9 +39,7 @@ def test_config2_forward_full_size_matches_oracle():
     g = oracle.Grid(**w.grid_kwargs())
     tr = S.Plan.from_workload(w).forward(dev(w.vp), dev(w.wavelet)).cpu().numpy()
     ref = oracle.forward(g, w.vp, w.src_xyz, w.wavelet, w.rec_xyz)
-    err = rel(tr, ref)
-    print(f"config2 traces rel L2 {err:.2e}", flush=True)
-    assert err < 1e-3
+    print(f"config2 traces {check_traces(tr, ref, 1e-3)}", flush=True)
 
 
 def test_config3_autograd_gradient_matches_oracle():
@@ -66,10 +63,9 @@ def test_config3_autograd_gradient_matches_oracle():
         J_ref += J
         dvp_ref += d
     loss.backward()
-    err = rel(vp.grad.cpu().numpy(), dvp_ref)
-    print(f"config3 misfit {loss.item():.6e} vs {J_ref:.6e}, dvp rel L2 {err:.2e}", flush=True)
+    st = check_field(vp.grad.cpu().numpy(), dvp_ref, 1e-3)
+    print(f"config3 misfit {loss.item():.6e} vs {J_ref:.6e}, dvp {st}", flush=True)
     assert abs(loss.item() - J_ref) <= 1e-3 * J_ref
-    assert err < 1e-3
 
 
 def test_config4_full_grid_forward_and_checkpointing():
@@ -80,9 +76,7 @@ def test_config4_full_grid_forward_and_checkpointing():
     tr = plan.forward(vp, wav).cpu().numpy()
     g = oracle.Grid(**w.grid_kwargs())
     ref = oracle.forward(g, w.vp_start, w.src_xyz, w.wavelet, w.rec_xyz)
-    err = rel(tr, ref)
-    print(f"config4 traces rel L2 {err:.2e}", flush=True)
-    assert err < 1e-4
+    print(f"config4 traces {check_traces(tr, ref, 1e-4)}", flush=True)
     obs = plan.forward(dev(w.vp_true), wav)      # data for the misfit (any values will do)
     m0, g0 = plan.gradient(vp, wav, obs)
     full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
