@@ -115,6 +115,7 @@ def lib():
         L.oracle_medium_operator.argtypes = [gp, dp, dp, dp]
         L.oracle_forward_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
                                             ctypes.c_int, dp, dp]
+        L.oracle_forward_pml.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp]
         _LIB = L
     return _LIB
 
@@ -280,6 +281,21 @@ def forward_medium(grid: Grid, vp, src_xyz, wavelet, rec_xyz, rho=None, alpha0=N
                                      src.shape[0], _d(src), _d(wav), rec.shape[0], _d(rec),
                                      _d(traces))
     _check(rc, "forward_medium")
+    return traces
+
+
+def forward_pml(grid: Grid, vp, src_xyz, wavelet, rec_xyz):
+    """Receiver traces [nrec][nt] with a perfectly matched layer in the
+    grid's nb padded cells instead of the sponge (zeta from grid.vref)."""
+    vp = _f64(vp, grid.shape)
+    src = _f64(src_xyz).reshape(-1, grid.ndim)
+    rec = _f64(rec_xyz).reshape(-1, grid.ndim)
+    wav = _f64(wavelet).reshape(src.shape[0], grid.nt)
+    traces = np.zeros((rec.shape[0], grid.nt))
+    g = grid.c()
+    rc = lib().oracle_forward_pml(ctypes.byref(g), _d(vp), src.shape[0], _d(src), _d(wav),
+                                  rec.shape[0], _d(rec), _d(traces))
+    _check(rc, "forward_pml")
     return traces
 
 

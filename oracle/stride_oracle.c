@@ -982,6 +982,125 @@ int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double
 }
 
 /* ------------------------------------------------------------------------
+ * Perfectly matched layer (see the header).  Per axis a, in the layer of that
+ * axis, the stretched derivatives (1/s_a) d_a with s_a = 1 + zeta_a / (i w)
+ * become d_a - (memory term): the first derivative loses psi_a and the second
+ * chi_a, where psi_a and chi_a follow d_a u and d_a(d_a u - psi_a) through a
+ * relaxation of rate zeta_a.  Outside every layer psi = chi = 0 and the step is
+ * the plain leapfrog. */
+
+/* Second derivative along axis a (one axis of the Laplacian) at point p. */
+static double d2_axis(const geo_t *G, const double *u, const long *ii, long p, int a)
+{
+    double s = G->c[0] * u[p];
+    for (int j = 1; j <= G->r; j++) {
+        double up = (ii[a] + j < G->np[a]) ? u[p + j * G->st[a]] : 0.0;
+        double um = (ii[a] - j >= 0) ? u[p - j * G->st[a]] : 0.0;
+        s += G->c[j] * (up + um);
+    }
+    return s * G->inv_dx2[a];
+}
+
+/* Centred first derivative along axis a at point p (zero beyond the array). */
+static double d1_axis(const geo_t *G, const double *d, double inv_dx, const double *u,
+                      const long *ii, long p, int a)
+{
+    double s = 0.0;
+    for (int j = 1; j <= G->r; j++) {
+        double up = (ii[a] + j < G->np[a]) ? u[p + j * G->st[a]] : 0.0;
+        double um = (ii[a] - j >= 0) ? u[p - j * G->st[a]] : 0.0;
+        s += d[j] * (up - um);
+    }
+    return s * inv_dx;
+}
+
+int oracle_forward_pml(const oracle_grid_t *g, const double *vp, int nsrc, const double *src_xyz,
+                       const double *wavelet, int nrec, const double *rec_xyz, double *traces)
+{
+    if (!g || time_order_of(g) != 2)
+        return -1;
+    solve_t S;
+    int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
+    if (rc != 0)
+        return rc;
+    const geo_t *G = &S.G;
+    const long N = G->N;
+    const int nd = G->nd, nt = g->nt;
+    const double dt = g->dt;
+    double d[6];
+    oracle_fd1_weights(g->space_order, d);
+    double zmax[3] = {0, 0, 0}, inv_dx[3] = {0, 0, 0};
+    for (int a = 0; a < nd; a++) {
+        inv_dx[a] = 1.0 / g->spacing[a];
+        if (g->nb > 0 && g->vref > 0)
+            zmax[a] = 3.0 * g->vref * log(1.0 / ORACLE_PML_R0) / (2.0 * g->nb * g->spacing[a]);
+    }
+    double *up = calloc(N, sizeof(double)), *uc = calloc(N, sizeof(double));
+    double *un = calloc(N, sizeof(double)), *src = calloc(N, sizeof(double));
+    double *psi[3] = {NULL, NULL, NULL}, *psin[3] = {NULL, NULL, NULL}, *chi[3] = {NULL, NULL, NULL};
+    int ok = up && uc && un && src;
+    for (int a = 0; a < nd; a++) {
+        psi[a] = calloc(N, sizeof(double));
+        psin[a] = calloc(N, sizeof(double));
+        chi[a] = calloc(N, sizeof(double));
+        ok = ok && psi[a] && psin[a] && chi[a];
+    }
+    if (!ok) {
+        rc = -7;
+        goto done;
+    }
+    for (int n = 0; n < nt; n++) {
+        for (int r = 0; r < nrec; r++)
+            traces[(long)r * nt + n] = sample(&S, S.ridx, S.rw, r, uc);
+        if (n == nt - 1)
+            break;
+        source_term(&S, wavelet, nt, n, src);
+#pragma omp parallel for
+        for (long i0 = 0; i0 < G->np[0]; i0++)
+            for (long i1 = 0; i1 < G->np[1]; i1++)
+                for (long i2 = 0; i2 < G->np[2]; i2++) {
+                    long ii[3] = {i0, i1, i2};
+                    long p = pidx(G, i0, i1, i2);
+                    double rhs = src[p];
+                    for (int a = 0; a < nd; a++) {
+                        double lu = d2_axis(G, uc, ii, p, a);
+                        double depth = (double)layer_depth(ii[a], G->n[a], g->nb) / (double)(g->nb > 0 ? g->nb : 1);
+                        double zeta = zmax[a] * depth * depth;
+                        if (zeta == 0.0) {
+                            rhs += lu;
+                            psin[a][p] = 0.0;
+                            continue;
+                        }
+                        double E = exp(-zeta * dt);
+                        double dpsi = d1_axis(G, d, inv_dx[a], psi[a], ii, p, a);
+                        chi[a][p] = E * chi[a][p] + (1.0 - E) * (lu - dpsi);
+                        psin[a][p] = E * psi[a][p] + (1.0 - E) * d1_axis(G, d, inv_dx[a], uc, ii, p, a);
+                        rhs += lu - dpsi - chi[a][p];
+                    }
+                    un[p] = 2.0 * uc[p] - up[p] + S.k[p] * rhs;
+                }
+        double *tmp = up;
+        up = uc;
+        uc = un;
+        un = tmp;
+        for (int a = 0; a < nd; a++) {
+            tmp = psi[a];
+            psi[a] = psin[a];
+            psin[a] = tmp;
+        }
+    }
+done:
+    free(up); free(uc); free(un); free(src);
+    for (int a = 0; a < 3; a++) {
+        free(psi[a]);
+        free(psin[a]);
+        free(chi[a]);
+    }
+    solve_free(&S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------
  * Zero-phase FIR low-pass (see the header). */
 int oracle_lowpass(const double *in, double *out, int count, int nt, double dt, double f_max)
 {

@@ -170,6 +170,32 @@ int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double
                           int nsrc, const double *src_xyz, const double *wavelet,
                           int nrec, const double *rec_xyz, double *traces);
 
+/* Forward solve with a perfectly matched layer instead of the sponge (Sec. 2.4
+ * offers a PML beside the sponge; the paper cites an unsplit formulation
+ * without printing it).  Reading: complex coordinate stretching of each axis,
+ * d_a -> (1/s_a) d_a with s_a = 1 + zeta_a/(i omega), in the second-order
+ * equation written per axis,
+ *   (1/vp^2) u_tt = sum_a (1/s_a) d_a ((1/s_a) d_a u) + s,
+ * with memory variables for the two stretched derivatives:
+ *   (1/s_a) d_a u = d_a u - psi_a,        psi_a' = zeta_a (d_a u - psi_a),
+ *   (1/s_a) d_a q = d_a q - chi_a,        chi_a' = zeta_a (d_a q - chi_a),
+ *   q = d_a u - psi_a, so d_a q = d_aa u - d_a psi_a.
+ * Discretisation: d_aa = the axis-a part of the 2r-order Laplacian, d_a = the
+ * centred first derivative of the same order (zero beyond the padded array);
+ * the relaxations are integrated exactly over a step with their drive held
+ * (E = exp(-zeta dt)):
+ *   chi_a^n     = E chi_a^{n-1} + (1 - E) (d_aa u^n - d_a psi_a^n),
+ *   psi_a^{n+1} = E psi_a^n     + (1 - E) d_a u^n,
+ *   u^{n+1}     = 2 u^n - u^{n-1} + k (sum_a (d_aa u^n - d_a psi_a^n - chi_a^n) + S^n),
+ * zeta_a = zeta_max,a (d/nb)^2 in the nb-cell layer of axis a (d = cells into
+ * it), zeta_max,a = 3 vref ln(1/R0) / (2 nb dx_a), R0 = ORACLE_PML_R0 (the
+ * continuous layer's round-trip reflection at normal incidence).  Sources are
+ * not stretched (they lie in the physical grid).  Second-order time, forward
+ * only; vref = 0 or nb = 0 gives the plain leapfrog without damping. */
+#define ORACLE_PML_R0 1e-3
+int oracle_forward_pml(const oracle_grid_t *g, const double *vp, int nsrc, const double *src_xyz,
+                       const double *wavelet, int nrec, const double *rec_xyz, double *traces);
+
 /* Zero-phase low-pass of [count][nt] signals sampled at dt (the band-limiting
  * of wavelets and traces per frequency block, Sec. 3.2): out = h * in with
  * zeros outside the record, where h is a Hann-windowed sinc of cutoff f_max,

@@ -818,3 +818,72 @@ def test_lowpass_impulse_response_is_symmetric_and_linear():
     np.testing.assert_allclose(y[0, 300 - 80:300], y[0, 301:301 + 80][::-1], rtol=0, atol=1e-15)
     z = oracle.lowpass((2 * x[0] - 3 * x[1])[None], 8e-8, 3e5)[0]
     np.testing.assert_allclose(z, 2 * y[0] - 3 * y[1], rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------- perfectly matched layer
+
+def _pml_case(n, nb, pml, nt, recs, src, ndim=2, vref=1500.0):
+    dx = 0.2e-3 if ndim == 2 else 0.5e-3
+    c = 1500.0
+    dt = (0.4 if ndim == 2 else 0.35) * dx / c
+    g = oracle.Grid(shape=(n,) * ndim, spacing=dx, space_order=8 if ndim == 2 else 10, nb=nb,
+                    vref=vref, dt=dt, nt=nt)
+    wav = W.tone_burst(nt, dt, f0=500e3, dtype=np.float64)
+    f = oracle.forward_pml if pml else oracle.forward
+    return f(g, np.full((n,) * ndim, c), np.asarray(src) * dx, wav, np.asarray(recs) * dx)
+
+
+def test_pml_without_damping_is_the_plain_leapfrog():
+    """vref = 0 makes zeta vanish: psi = chi = 0 and the step is the
+    undamped leapfrog of the sponge scheme with vref = 0."""
+    recs = [[30, 5], [5, 5], [30, 30]]
+    a = _pml_case(60, 10, False, 150, recs, [[30, 30]], vref=0.0)
+    b = _pml_case(60, 10, True, 150, recs, [[30, 30]], vref=0.0)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+@pytest.mark.slow
+def test_pml_reflects_far_less_than_the_sponge_2d():
+    """Receivers 8 cells inside the physical edge of a 160^2 grid with 20-cell
+    layers, against the same receivers in a 560^2 grid whose boundaries are
+    out of reach: the PML's reflection is below 0.5 % of the direct wave and
+    below a sixth of the sponge's (measured 0.09-0.31 % against 2.7-10.5 %)."""
+    recs = np.array([[80, 8], [8, 8], [80, 40]])
+    src = np.array([[80, 80]])
+    off = 200
+    ref = _pml_case(560, 20, False, 700, recs + off, src + off)
+    R = {}
+    for pml in (False, True):
+        tr = _pml_case(160, 20, pml, 700, recs, src)
+        R[pml] = np.abs(tr - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert np.all(R[True] < 5e-3), R
+    assert np.all(R[True] < R[False] / 6), R
+
+
+@pytest.mark.slow
+def test_pml_reflects_less_than_the_sponge_3d():
+    """3D, 40^3 with 10-cell layers (order 10) against a 100^3 reference:
+    below 0.5 % and below a third of the sponge (measured 0.19-0.32 % against
+    1.3-1.8 %)."""
+    recs = np.array([[20, 20, 5], [5, 5, 20]])
+    src = np.array([[20, 20, 20]])
+    off = 30
+    ref = _pml_case(100, 10, False, 260, recs + off, src + off, ndim=3)
+    R = {}
+    for pml in (False, True):
+        tr = _pml_case(40, 10, pml, 260, recs, src, ndim=3)
+        R[pml] = np.abs(tr - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert np.all(R[True] < 5e-3), R
+    assert np.all(R[True] < R[False] / 3), R
+
+
+@pytest.mark.slow
+def test_pml_field_decays_without_late_growth():
+    """After the burst has left a 100^2 grid through 20-cell PML layers, the
+    largest sample of each later 1000-step window keeps falling (no late-time
+    instability) and ends below 1e-5 of the peak."""
+    tr = _pml_case(100, 20, True, 5000, [[50, 50], [50, 2], [2, 2]], [[50, 50]])
+    peak = np.abs(tr).max()
+    win = [np.abs(tr[:, lo:lo + 1000]).max() / peak for lo in range(1000, 5000, 1000)]
+    assert all(b < a for a, b in zip(win, win[1:])), win
+    assert win[-1] < 1e-5, win
