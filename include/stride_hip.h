@@ -100,6 +100,23 @@ typedef struct stride_grid {
                              point on a node gets that node alone).  Sinc taps must lie
                              in the padded grid: points within 4 cells of its edge (with
                              sponge_cells < 4) return GEOMETRY. */
+    int32_t boundary;     /* absorbing layer in the sponge_cells padded cells (Sec. 2.4
+                             offers a sponge and a PML): 0 the sponge above, 1 a
+                             perfectly matched layer: complex coordinate stretching
+                             d_a -> (1/s_a) d_a, s_a = 1 + zeta_a/(i omega), of each
+                             axis, with memory variables psi_a (first derivative) and
+                             chi_a (second) relaxed at rate zeta_a over the step
+                             (E = exp(-zeta_a dt)):
+                               chi_a^n     = E chi_a^{n-1} + (1-E) (D2_a u^n - D_a psi_a^n),
+                               psi_a^{n+1} = E psi_a^n + (1-E) D_a u^n,
+                               u^{n+1} = 2 u^n - u^{n-1}
+                                         + k (sum_a (D2_a u^n - D_a psi_a^n - chi_a^n) + S^n),
+                             D2_a the axis-a part of L, D_a the centred first
+                             derivative of the same order, zeta_a = zeta_max (d/nb)^2
+                             in the layer of axis a (d cells into it), zeta_max =
+                             3 sponge_vref ln(1000) / (2 nb dx_a).  Forward solves
+                             (stride_plan_forward[_static]) only; other solves
+                             return INVALID_ARG for it. */
 } stride_grid_t;
 
 /* A plan: the validated grid plus the source/receiver tap tables of one shot

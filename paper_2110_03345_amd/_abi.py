@@ -58,6 +58,7 @@ class stride_grid_t(ctypes.Structure):
         ("dt", ctypes.c_double),
         ("time_order", ctypes.c_int32),
         ("interp", ctypes.c_int32),
+        ("boundary", ctypes.c_int32),
     ]
 
 
@@ -120,7 +121,7 @@ def _check(rc: int):
 
 
 def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: float, dt: float,
-              nt: int, time_order: int = 2, interp: int = 0) -> stride_grid_t:
+              nt: int, time_order: int = 2, interp: int = 0, boundary: int = 0) -> stride_grid_t:
     g = stride_grid_t()
     nd = len(shape)
     sp = (float(spacing),) * nd if np.isscalar(spacing) else tuple(float(s) for s in spacing)
@@ -135,6 +136,7 @@ def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: fl
     g.dt = float(dt)
     g.time_order = int(time_order)
     g.interp = int(interp)
+    g.boundary = int(boundary)
     return g
 
 
@@ -359,10 +361,12 @@ class Plan:
     """A validated grid + shot geometry with its tap tables on the current device."""
 
     def __init__(self, shape, spacing, space_order, nb, vref, dt, nt, src_xyz, rec_xyz,
-                 time_order: int = 2, interp: int = 0):
-        self.grid = make_grid(shape, spacing, space_order, nb, vref, dt, nt, time_order, interp)
+                 time_order: int = 2, interp: int = 0, boundary: int = 0):
+        self.grid = make_grid(shape, spacing, space_order, nb, vref, dt, nt, time_order, interp,
+                              boundary)
         self.time_order = int(time_order)
         self.interp = int(interp)
+        self.boundary = int(boundary)
         self.shape = tuple(int(s) for s in shape)
         self.ndim = len(self.shape)
         self.nt = int(nt)
@@ -374,11 +378,11 @@ class Plan:
 
     @classmethod
     def from_workload(cls, w, src_xyz=None, rec_xyz=None, nt=None, time_order: int = 2,
-                      interp: int = 0):
+                      interp: int = 0, boundary: int = 0):
         return cls(w.shape, w.spacing, w.space_order, w.nb, w.vref, w.dt,
                    w.nt if nt is None else nt,
                    w.src_xyz if src_xyz is None else src_xyz,
-                   w.rec_xyz if rec_xyz is None else rec_xyz, time_order, interp)
+                   w.rec_xyz if rec_xyz is None else rec_xyz, time_order, interp, boundary)
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -150,6 +150,21 @@ enum StepMode {
     kAdjPlain = 6 // adjoint kStep without imaging (the step before a kImageV with V2)
 };
 
+// Perfectly matched layer: the memory-variable correction of one step, for
+// the points of the padded layer (the plain leapfrog without damping has
+// already written u^{n+1}; see stride_grid_t.boundary).
+struct PmlParams {
+    const float* u;          // u^n
+    float* un;               // u^{n+1}: += k (sum_a (-D_a psi_a^n - chi_a^n))
+    const float* k;
+    const float* psi[3];     // psi_a^n
+    float* psin[3];          // psi_a^{n+1}
+    float* chi[3];           // chi_a^{n-1} -> chi_a^n (in place)
+    float c0[3];             // second-derivative centre weight / dx_a^2 per axis
+    float zmax[3];           // zeta_max per axis (1/s)
+    float dt;
+};
+
 // Kernel launchers (stride_kernels.hip).
 // max_sample_threads: the largest count * sample_lanes(ntap) over the slots.
 void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
@@ -163,6 +178,8 @@ void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, cons
 void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                       const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s);
 
+void launch_pml_correction(const Dims& d, int R, const StencilCoef& cf, const PmlParams& pp,
+                           hipStream_t s);
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 // In place, per [nt] row: h[j] = (h[j-1] + 10 h[j] + h[j+1]) / 12 (zero outside),

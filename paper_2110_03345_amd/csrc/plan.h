@@ -15,6 +15,9 @@ struct stride_plan {
     stride_grid_t g;
     int nd, R, nb, nt;
     int torder;          // 2 or 4
+    int boundary;        // 0 sponge, 1 perfectly matched layer (forward solves)
+    float pml_c0[3];     // PML: second-derivative centre weight / dx_a^2 per axis
+    float pml_zmax[3];   // PML: zeta_max per axis
     stride::Dims dims;
     stride::StencilCoef cf;
     stride::Fd1 fd1;     // first-derivative weights in FP64 (medium preparation)
@@ -77,12 +80,15 @@ struct GradWs {
 
 int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W);
 
-// Views of a forward workspace: [scratch | k | u0 | u1 (| p, fourth order)].
+// Views of a forward workspace: [scratch | k | u0 | u1 (| p, fourth order)
+// (| psi_a x 2, chi_a per axis, PML)].
 struct FwdWs {
     unsigned* flags;
     float* k;
     float* u[2];
     float* p;
+    float* psi[2][3];
+    float* chi[3];
 };
 
 int fwd_ws(const stride_plan& P, void* ws, size_t bytes, FwdWs& F);

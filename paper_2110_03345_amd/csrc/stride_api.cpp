@@ -318,6 +318,11 @@ int validate_grid(const stride_grid_t* g)
     if (g->interp != 0 && g->interp != 1)
         return fail(STRIDE_E_INVALID_ARG, "interp must be 0 (linear) or 1 (windowed sinc), got %d",
                     g->interp);
+    if (g->boundary != 0 && g->boundary != 1)
+        return fail(STRIDE_E_INVALID_ARG, "boundary must be 0 (sponge) or 1 (PML), got %d",
+                    g->boundary);
+    if (g->boundary == 1 && g->time_order == 4)
+        return fail(STRIDE_E_INVALID_ARG, "the PML is offered with second-order time only");
     if (!(g->dt > 0) || !std::isfinite(g->dt))
         return fail(STRIDE_E_INVALID_ARG, "dt must be positive");
     if (!(g->sponge_vref >= 0) || !std::isfinite(g->sponge_vref))
@@ -348,7 +353,8 @@ Layout stride::layout_of(const stride_plan& P)
     L.field = (size_t)round_up(P.dims.total * 4, 256);
     L.scratch = 256 + kMisfitParts * sizeof(double);   // flags | misfit partial sums
     L.traces = (size_t)round_up((long long)P.nrec * P.nt * 4, 256);
-    L.fixed_fwd = L.scratch + (P.torder == 4 ? 4 : 3) * L.field;   // k, u, u (, p)
+    // k, u, u (, p) (, two psi_a and one chi_a per axis with the PML)
+    L.fixed_fwd = L.scratch + ((P.torder == 4 ? 4 : 3) + (P.boundary == 1 ? 3 * P.nd : 0)) * L.field;
     // k, G, w, w, traces, residual (, p and q of the fourth-order adjoint)
     L.fixed_grad = L.scratch + (P.torder == 4 ? 6 : 4) * L.field + 2 * L.traces;
     L.medium = L.scratch + (size_t)(4 + P.nd + 1) * L.field;
@@ -357,6 +363,8 @@ Layout stride::layout_of(const stride_plan& P)
 
 int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
 {
+    if (P.boundary == 1)
+        return fail(STRIDE_E_INVALID_ARG, "the PML is offered for forward solves only");
     Layout L = layout_of(P);
     if (!ws)
         return fail(STRIDE_E_INVALID_ARG, "workspace is NULL");
@@ -416,6 +424,17 @@ int stride::fwd_ws(const stride_plan& P, void* ws, size_t bytes, FwdWs& F)
     F.u[0] = (float*)(b + L.scratch + L.field);
     F.u[1] = (float*)(b + L.scratch + 2 * L.field);
     F.p = P.torder == 4 ? (float*)(b + L.scratch + 3 * L.field) : nullptr;
+    for (int a = 0; a < 3; ++a)
+        F.psi[0][a] = F.psi[1][a] = F.chi[a] = nullptr;
+    if (P.boundary == 1) {
+        char* q = b + L.scratch + 3 * L.field;
+        for (int a = 0; a < P.nd; ++a) {
+            F.psi[0][a] = (float*)q;
+            F.psi[1][a] = (float*)(q + L.field);
+            F.chi[a] = (float*)(q + 2 * L.field);
+            q += 3 * L.field;
+        }
+    }
     return STRIDE_OK;
 }
 
@@ -1032,6 +1051,20 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
         HIP_TRY(hipGetLastError());
         return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
     }
+    PmlParams pm{};
+    int ps = 0;
+    if (P.boundary == 1) {
+        for (int a = 0; a < P.nd; ++a) {
+            launch_fill(F.psi[0][a], P.dims.total, 0.f, s);
+            launch_fill(F.psi[1][a], P.dims.total, 0.f, s);
+            launch_fill(F.chi[a], P.dims.total, 0.f, s);
+            pm.chi[a] = F.chi[a];
+            pm.c0[a] = P.pml_c0[a];
+            pm.zmax[a] = P.pml_zmax[a];
+        }
+        pm.k = k;
+        pm.dt = (float)P.g.dt;
+    }
     for (int n = 0; n < P.nt - 1; ++n) {
         StepParams p = base_params(P);
         p.A = u[cur];
@@ -1042,9 +1075,20 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
         p.inj_sig = wavelet;
         p.smp = rec_samples(P, traces);
         launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
+        if (P.boundary == 1) {
+            // the step above wrote the undamped leapfrog; u^n is still intact
+            pm.u = u[cur];
+            pm.un = u[1 - cur];
+            for (int a = 0; a < P.nd; ++a) {
+                pm.psi[a] = F.psi[ps][a];
+                pm.psin[a] = F.psi[1 - ps][a];
+            }
+            launch_pml_correction(P.dims, P.R, P.cf, pm, s);
+            ps = 1 - ps;
+        }
         cur = 1 - cur;
     }
-    g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
+    g_timer.end(tid, s, 0, P.nt - 1, (P.boundary == 1 ? 2LL : 1LL) * (P.nt - 1));
     launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
     HIP_TRY(hipGetLastError());
     return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
@@ -1062,6 +1106,8 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
         return fail(STRIDE_E_INVALID_ARG, "vp, wavelet and traces must be device pointers");
     if (P.torder != 2)
         return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
+    if (P.boundary == 1)
+        return fail(STRIDE_E_INVALID_ARG, "medium forward solves use the sponge, not the PML");
     if (att_power != 0 && att_power != 2)
         return fail(STRIDE_E_INVALID_ARG, "att_power must be 0 or 2 (got %d)", att_power);
     Layout L = layout_of(P);
@@ -1353,6 +1399,21 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
             P->sp.e[a] = (float)(emax / ((double)P->nb * P->nb));
         }
     P->sp.half_dt = (float)(0.5 * grid->dt);
+    P->boundary = grid->boundary;
+    std::memset(P->pml_c0, 0, sizeof(P->pml_c0));
+    std::memset(P->pml_zmax, 0, sizeof(P->pml_zmax));
+    if (P->boundary == 1) {
+        // the layer holds the PML instead of the sponge: the step runs undamped
+        // and the layer correction adds the stretched-coordinate terms
+        for (int a = 0; a < 3; ++a)
+            P->sp.e[a] = 0.f;
+        for (int a = 0; a < P->nd; ++a) {
+            P->pml_c0[a] = (float)(c[0] / (grid->spacing[a] * grid->spacing[a]));
+            if (P->nb > 0 && grid->sponge_vref > 0)
+                P->pml_zmax[a] = (float)(3.0 * grid->sponge_vref * std::log(1000.0) /
+                                         (2.0 * (double)P->nb * grid->spacing[a]));
+        }
+    }
 
     int ryf, wf, rya, wa;
     tile_shape(P->nd, false, &ryf, &wf);
@@ -1463,11 +1524,15 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
     if (mode == STRIDE_MODE_FORWARD_MEDIUM) {
         if (plan->torder != 2)
             return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
+        if (plan->boundary == 1)
+            return fail(STRIDE_E_INVALID_ARG, "medium forward solves use the sponge, not the PML");
         *out_bytes = L.medium;
         return STRIDE_OK;
     }
     if (mode != STRIDE_MODE_GRADIENT)
         return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD, GRADIENT or FORWARD_MEDIUM");
+    if (plan->boundary == 1)
+        return fail(STRIDE_E_INVALID_ARG, "the PML is offered for forward solves only");
     long long nfields;
     if (budget_bytes == 0) {
         nfields = cached_schedule(plan->nt, plan->nt)->stats.peak_fields;
@@ -1639,6 +1704,7 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
     P.nd = grid->ndim;
     P.nt = grid->nt;
     P.torder = grid->time_order == 4 ? 4 : 2;
+    P.boundary = grid->boundary;
     P.nrec = nrec;
     P.nb = grid->sponge_cells;
     Dims& d = P.dims;

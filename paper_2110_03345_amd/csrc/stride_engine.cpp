@@ -284,6 +284,8 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         return fail(STRIDE_E_INVALID_ARG, "plan grid does not match the engine grid");
     if (plan->torder != 2)
         return fail(STRIDE_E_INVALID_ARG, "the engine runs time_order 2 solves only");
+    if (plan->boundary != 0)
+        return fail(STRIDE_E_INVALID_ARG, "the engine runs solves with the sponge only");
     if (plan->nrec > E->max_samples)
         return fail(STRIDE_E_INVALID_ARG, "plan has %d receivers; the engine samples at most %d",
                     plan->nrec, E->max_samples);

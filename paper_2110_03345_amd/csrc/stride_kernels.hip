@@ -542,6 +542,108 @@ void launch_finite_scan(const double* p, long long n, unsigned* flag, unsigned b
                        0, s, p, n, flag, bit);
 }
 
+// Perfectly matched layer: one thread per point of the padded layer, the
+// layer enumerated as three slabs of the 3D-ised grid (axis 0 of a 2D grid is
+// axis 1 here): planes of axis 0 in its layer; then, in the physical planes,
+// rows of axis 1 in its layer; then, in the physical rows, the points of
+// axis 2 in its layer.  Per axis a whose layer holds the point (zeta_a > 0):
+//   chi_a = E chi_a + (1 - E) (D2_a u - D_a psi_a),  psi_a' = E psi_a + (1 - E) D_a u,
+// and u^{n+1} += k sum_a (-D_a psi_a - chi_a).  Neighbours beyond the padded
+// array read 0.
+__global__ __launch_bounds__(256) void pml_correct_kernel(Dims d, StencilCoef cf, PmlParams pp,
+                                                          long long count, int R)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count)
+        return;
+    const bool three = d.nd == 3;
+    // 3D-ised extents, physical extents and layer widths
+    const int N0 = three ? d.n[0] : 1, N1 = three ? d.n[1] : d.n[0], N2 = three ? d.n[2] : d.n[1];
+    const int p0 = three ? d.phys[0] : 1, p1 = three ? d.phys[1] : d.phys[0];
+    const int p2 = three ? d.phys[2] : d.phys[1];
+    const int b0 = three ? d.nb : 0, b = d.nb;
+    const long long segA = 2LL * b0 * N1 * N2;
+    const long long segB = (long long)p0 * 2 * b * N2;
+    int i0, i1, i2;
+    long long r = t;
+    if (r < segA) {
+        const long long plane = (long long)N1 * N2;
+        const int zz = (int)(r / plane);
+        i0 = zz < b0 ? zz : b0 + p0 + (zz - b0);
+        r -= (long long)zz * plane;
+        i1 = (int)(r / N2);
+        i2 = (int)(r - (long long)i1 * N2);
+    } else if ((r -= segA) < segB) {
+        const long long per = 2LL * b * N2;
+        const int zi = (int)(r / per);
+        i0 = b0 + zi;
+        r -= (long long)zi * per;
+        const int yy = (int)(r / N2);
+        i1 = yy < b ? yy : b + p1 + (yy - b);
+        i2 = (int)(r - (long long)yy * N2);
+    } else {
+        r -= segB;
+        const long long per = (long long)p1 * 2 * b;
+        const int zi = (int)(r / per);
+        i0 = b0 + zi;
+        r -= (long long)zi * per;
+        const int yi = (int)(r / (2 * b));
+        i1 = b + yi;
+        const int xx = (int)(r - (long long)yi * 2 * b);
+        i2 = xx < b ? xx : b + p2 + (xx - b);
+    }
+    const int ii[3] = {i0, i1, i2};
+    const int nn[3] = {N0, N1, N2};
+    const long long st[3] = {three ? d.st[0] : 0, three ? d.st[1] : d.st[0], 1};
+    const int pl[3] = {p0, p1, p2};
+    const long long p = (long long)i0 * st[0] + (long long)i1 * st[1] + i2;
+    const float inv_b = b > 0 ? 1.f / (float)b : 0.f;
+    float corr = 0.f;
+    for (int ax = three ? 0 : 1; ax < 3; ++ax) {
+        const int a = three ? ax : ax - 1;          // axis of the solver's Dims / coefficients
+        const int i = ii[ax];
+        const int hi = b + pl[ax] - 1;
+        const int depth = i < b ? b - i : (i > hi ? i - hi : 0);
+        if (depth == 0)
+            continue;
+        const float frac = (float)depth * inv_b;
+        const float zeta = pp.zmax[a] * frac * frac;
+        const float E = expf(-zeta * pp.dt);
+        const float* u = pp.u;
+        const float* psi = pp.psi[a];
+        float d2 = pp.c0[a] * u[p], d1u = 0.f, d1p = 0.f;
+        for (int j = 1; j <= R; ++j) {
+            const bool in_p = i + j < nn[ax], in_m = i - j >= 0;
+            const float up = in_p ? u[p + j * st[ax]] : 0.f;
+            const float um = in_m ? u[p - j * st[ax]] : 0.f;
+            const float qp = in_p ? psi[p + j * st[ax]] : 0.f;
+            const float qm = in_m ? psi[p - j * st[ax]] : 0.f;
+            d2 = fmaf(cf.c[a][j], up + um, d2);
+            d1u = fmaf(cf.d[a][j], up - um, d1u);
+            d1p = fmaf(cf.d[a][j], qp - qm, d1p);
+        }
+        const float chi = fmaf(E, pp.chi[a][p], (1.f - E) * (d2 - d1p));
+        pp.chi[a][p] = chi;
+        pp.psin[a][p] = fmaf(E, psi[p], (1.f - E) * d1u);
+        corr -= d1p + chi;
+    }
+    pp.un[p] = fmaf(pp.k[p], corr, pp.un[p]);
+}
+
+void launch_pml_correction(const Dims& d, int R, const StencilCoef& cf, const PmlParams& pp,
+                           hipStream_t s)
+{
+    const bool three = d.nd == 3;
+    const long long N1 = three ? d.n[1] : d.n[0], N2 = three ? d.n[2] : d.n[1];
+    const long long p0 = three ? d.phys[0] : 1, p1 = three ? d.phys[1] : d.phys[0];
+    const long long b0 = three ? d.nb : 0;
+    const long long count = 2 * b0 * N1 * N2 + p0 * 2 * d.nb * N2 + p0 * p1 * 2 * d.nb;
+    if (count <= 0)
+        return;
+    hipLaunchKernelGGL(pml_correct_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, d,
+                       cf, pp, count, R);
+}
+
 void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s)
 {
     launch_fill(reinterpret_cast<float*>(flags), 2, 0.f, s);

@@ -81,6 +81,26 @@ def test_workspace_sizes():
     assert e.value.code == _abi.STRIDE_E_WORKSPACE
 
 
+def test_pml_workspace_and_refusals():
+    """The PML keeps two psi and one chi field per axis beside the forward's
+    k and two wavefields; it is offered for second-order forward solves only."""
+    g = _grid(nt=50, boundary=1)
+    field = -(-(52 * 64 * 4) // 256) * 256
+    scratch = 256 + 256 * 8
+    assert S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_FORWARD) == scratch + (3 + 6) * field
+    g3 = _grid(shape=(20, 22, 24), spacing=0.5e-3, nb=4, dt=0.3 * 0.5e-3 / 1500, boundary=1)
+    field3 = -(-(28 * 30 * 32 * 4) // 256) * 256      # 28 x 30 x 32 padded, pitch 32
+    assert S.stride_workspace_query(g3, 1, 3, S.STRIDE_MODE_FORWARD) == scratch + (3 + 9) * field3
+    for mode in (S.STRIDE_MODE_GRADIENT, S.STRIDE_MODE_FORWARD_MEDIUM):
+        with pytest.raises(S.StrideError) as e:
+            S.stride_workspace_query(g, 1, 3, mode)
+        assert e.value.code == _abi.STRIDE_E_INVALID_ARG and "PML" in str(e.value)
+    for bad in (dict(boundary=2), dict(boundary=1, time_order=4)):
+        with pytest.raises(S.StrideError) as e:
+            S.stride_workspace_query(_grid(**bad), 1, 3, S.STRIDE_MODE_FORWARD)
+        assert e.value.code == _abi.STRIDE_E_INVALID_ARG
+
+
 @pytest.mark.parametrize("nt", [2, 3, 4])
 def test_gradient_workspace_query_meets_the_solve_minimum(nt):
     """Very short schedules peak below the 4-field pool a gradient solve
