@@ -116,6 +116,10 @@ def lib():
         L.oracle_forward_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
                                             ctypes.c_int, dp, dp]
         L.oracle_forward_pml.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp]
+        L.oracle_adjoint_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
+                                            ctypes.c_int, dp, dp, dp, dp, ctypes.c_int]
+        L.oracle_gradient_medium.argtypes = [gp, dp, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp,
+                                             ctypes.c_int, dp, dp, dp, dp, dp, ctypes.c_int]
         _LIB = L
     return _LIB
 
@@ -282,6 +286,47 @@ def forward_medium(grid: Grid, vp, src_xyz, wavelet, rec_xyz, rho=None, alpha0=N
                                      _d(traces))
     _check(rc, "forward_medium")
     return traces
+
+
+def adjoint_medium(grid: Grid, vp, src_xyz, wavelet, rec_xyz, grad_traces, rho=None, alpha0=None,
+                   att_power: int = 0, seg: int = 0):
+    """(dvp, dwavelet): transpose of the medium forward's Jacobian applied to grad_traces."""
+    vp = _f64(vp, grid.shape)
+    rho = None if rho is None else _f64(rho, grid.shape)
+    alpha0 = None if alpha0 is None else _f64(alpha0, grid.shape)
+    src = _f64(src_xyz).reshape(-1, grid.ndim)
+    rec = _f64(rec_xyz).reshape(-1, grid.ndim)
+    wav = _f64(wavelet).reshape(src.shape[0], grid.nt)
+    gtr = _f64(grad_traces).reshape(rec.shape[0], grid.nt)
+    dvp = np.zeros(grid.shape)
+    dwav = np.zeros((src.shape[0], grid.nt))
+    g = grid.c()
+    rc = lib().oracle_adjoint_medium(ctypes.byref(g), _d(vp), _d(rho), _d(alpha0), int(att_power),
+                                     src.shape[0], _d(src), _d(wav), rec.shape[0], _d(rec), _d(gtr),
+                                     _d(dvp), _d(dwav), seg)
+    _check(rc, "adjoint_medium")
+    return dvp, dwav
+
+
+def gradient_medium(grid: Grid, vp, src_xyz, wavelet, rec_xyz, observed, rho=None, alpha0=None,
+                    att_power: int = 0, seg: int = 0):
+    """(traces, misfit, dvp) of J = 1/2 sum (traces - observed)^2 in the medium."""
+    vp = _f64(vp, grid.shape)
+    rho = None if rho is None else _f64(rho, grid.shape)
+    alpha0 = None if alpha0 is None else _f64(alpha0, grid.shape)
+    src = _f64(src_xyz).reshape(-1, grid.ndim)
+    rec = _f64(rec_xyz).reshape(-1, grid.ndim)
+    wav = _f64(wavelet).reshape(src.shape[0], grid.nt)
+    obs = _f64(observed).reshape(rec.shape[0], grid.nt)
+    traces = np.zeros((rec.shape[0], grid.nt))
+    dvp = np.zeros(grid.shape)
+    J = ctypes.c_double(0.0)
+    g = grid.c()
+    rc = lib().oracle_gradient_medium(ctypes.byref(g), _d(vp), _d(rho), _d(alpha0), int(att_power),
+                                      src.shape[0], _d(src), _d(wav), rec.shape[0], _d(rec), _d(obs),
+                                      _d(traces), ctypes.byref(J), _d(dvp), seg)
+    _check(rc, "gradient_medium")
+    return traces, float(J.value), dvp
 
 
 def forward_pml(grid: Grid, vp, src_xyz, wavelet, rec_xyz):

@@ -981,6 +981,235 @@ int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double
     return rc;
 }
 
+/* Adjoint of the heterogeneous-medium forward (see the header).  State
+ * recurrence u^{n+1} = a (2 u^n + k v^n) - b u^{n-1} with
+ *   v^n = A u^n + S^n + beta (L u^n - L u^{n-1}),  A = L + sum_a gamma_a D_a;
+ * stationarity of the Lagrangian and w = a k lambda give
+ *   w^m = a (2 w^{m+1} + k (A^T w^{m+1} + L(beta (w^{m+1} - w^{m+2})) + R^T g^m)) - b w^{m+2},
+ *   A^T w = L w - sum_a D_a (gamma_a w)    (D_a^T = -D_a with the zero extension),
+ * and, differentiating F^n = a (2 u^n + k v^n) - b u^{n-1} in vp at each point
+ * (k = dt^2 vp^2; y = 0: a, b through eta + 2 alpha0 vp; y = 2: beta = 2 alpha0 vp / dt),
+ *   dJ/dvp_pad = sum_n w^{n+1} [ (2/vp) v^n
+ *                               + (y = 2) (2 alpha0 / dt) (L u^n - L u^{n-1})
+ *                               + (y = 0) (dt alpha0 a / k) (2 u^{n-1} - 2 u^n - k v^n) ],
+ * then the padding transpose.  dJ/ds_s^n = W_s w^{n+1} / cell volume. */
+
+/* v^n at every point from u^n, u^{n-1} and the dense source (lu: L u^n out). */
+static void medium_rhs(const geo_t *G, const medium_t *M, const double *beta, const double *uc,
+                       const double *up, const double *src, double *lu, double *v)
+{
+#pragma omp parallel for
+    for (long i0 = 0; i0 < G->np[0]; i0++)
+        for (long i1 = 0; i1 < G->np[1]; i1++)
+            for (long i2 = 0; i2 < G->np[2]; i2++) {
+                long p = pidx(G, i0, i1, i2);
+                double l = lap_at(G, uc, i0, i1, i2);
+                lu[p] = l;
+                double x = l + density_term_at(G, M, uc, i0, i1, i2) + src[p];
+                if (beta[p] != 0.0)
+                    x += beta[p] * (l - lap_at(G, up, i0, i1, i2));
+                v[p] = x;
+            }
+}
+
+int oracle_adjoint_medium(const oracle_grid_t *g, const double *vp, const double *rho,
+                          const double *alpha0, int att_power, int nsrc, const double *src_xyz,
+                          const double *wavelet, int nrec, const double *rec_xyz,
+                          const double *grad_traces, double *dvp, double *dwavelet, int seg)
+{
+    if (!g || time_order_of(g) != 2 || (att_power != 0 && att_power != 2))
+        return -1;
+    solve_t S;
+    int rc = solve_init(&S, g, vp, nsrc, src_xyz, nrec, rec_xyz);
+    if (rc != 0)
+        return rc;
+    const geo_t *G = &S.G;
+    const long N = G->N;
+    const int nt = g->nt, nd = G->nd;
+    const double dt = g->dt;
+    medium_t M;
+    if ((rc = medium_init(&M, g, G, rho)) != 0) {
+        solve_free(&S);
+        return rc;
+    }
+    if (seg <= 0)
+        seg = (int)ceil(sqrt((double)nt));
+    if (seg > nt)
+        seg = nt;
+    const int nseg = (nt + seg - 1) / seg;
+    double *al = calloc(N, sizeof(double)), *beta = calloc(N, sizeof(double));
+    double *ck = malloc(sizeof(double) * 2 * N * (size_t)nseg);
+    double *useg = malloc(sizeof(double) * N * (size_t)(seg + 1));
+    double *up = calloc(N, sizeof(double)), *uc = calloc(N, sizeof(double)), *un = calloc(N, sizeof(double));
+    double *src = calloc(N, sizeof(double)), *lu = calloc(N, sizeof(double)), *v = calloc(N, sizeof(double));
+    double *w0 = calloc(N, sizeof(double)), *w1 = calloc(N, sizeof(double)), *w2 = calloc(N, sizeof(double));
+    double *y = calloc(N, sizeof(double)), *q = calloc(N, sizeof(double)), *Gacc = calloc(N, sizeof(double));
+    double *z[3] = {NULL, NULL, NULL};
+    int ok = al && beta && ck && useg && up && uc && un && src && lu && v && w0 && w1 && w2 && y && q && Gacc;
+    for (int a = 0; a < nd; a++)
+        ok = ok && (z[a] = calloc(N, sizeof(double))) != NULL;
+    if (!ok) {
+        rc = -7;
+        goto done;
+    }
+    if (alpha0) {
+        long nphys = G->n[0] * G->n[1] * G->n[2];
+        for (long i = 0; i < nphys; i++)
+            if (!(alpha0[i] >= 0.0) || !isfinite(alpha0[i])) {
+                rc = -1;
+                goto done;
+            }
+        oracle_pad(g, alpha0, al);
+        double *eta = v; /* scratch */
+        oracle_eta(g, eta);
+        for (long p = 0; p < N; p++) {
+            if (att_power == 0) {
+                double e = eta[p] + 2.0 * al[p] * S.vpp[p];
+                S.a[p] = 1.0 / (1.0 + e * dt / 2.0);
+                S.b[p] = (1.0 - e * dt / 2.0) * S.a[p];
+            } else {
+                beta[p] = 2.0 * al[p] * S.vpp[p] / dt;
+            }
+        }
+    }
+    /* forward sweep, keeping (u^n, u^{n-1}) at the segment starts */
+    for (int n = 0; n < nt; n++) {
+        if (n % seg == 0) {
+            memcpy(ck + (size_t)(n / seg) * 2 * N, uc, sizeof(double) * N);
+            memcpy(ck + (size_t)(n / seg) * 2 * N + N, up, sizeof(double) * N);
+        }
+        if (n == nt - 1)
+            break;
+        source_term(&S, wavelet, nt, n, src);
+        medium_rhs(G, &M, beta, uc, up, src, lu, v);
+        for (long p = 0; p < N; p++)
+            un[p] = S.a[p] * (2.0 * uc[p] + S.k[p] * v[p]) - S.b[p] * up[p];
+        double *tmp = up;
+        up = uc;
+        uc = un;
+        un = tmp;
+    }
+    if (dwavelet)
+        memset(dwavelet, 0, sizeof(double) * (size_t)nsrc * nt);
+    /* reverse sweep: w1 = w^{m+1}, w2 = w^{m+2}; useg[0] = u^{start-1}, useg[1 + i] = u^{start+i} */
+    for (int j = nseg - 1; j >= 0; j--) {
+        int start = j * seg;
+        int end = start + seg < nt ? start + seg : nt;
+        memcpy(uc, ck + (size_t)j * 2 * N, sizeof(double) * N);
+        memcpy(up, ck + (size_t)j * 2 * N + N, sizeof(double) * N);
+        memcpy(useg, up, sizeof(double) * N);
+        for (int n = start; n < end; n++) {
+            memcpy(useg + (size_t)(n - start + 1) * N, uc, sizeof(double) * N);
+            if (n == end - 1)
+                break;
+            source_term(&S, wavelet, nt, n, src);
+            medium_rhs(G, &M, beta, uc, up, src, lu, v);
+            for (long p = 0; p < N; p++)
+                un[p] = S.a[p] * (2.0 * uc[p] + S.k[p] * v[p]) - S.b[p] * up[p];
+            double *tmp = up;
+            up = uc;
+            uc = un;
+            un = tmp;
+        }
+        for (int m = end - 1; m >= start; m--) {
+            const double *um = useg + (size_t)(m - start + 1) * N;
+            const double *umm = useg + (size_t)(m - start) * N;
+            /* imaging of step m (u^m -> u^{m+1}) with lambda^{m+1} = w^{m+1} / (a k) */
+            source_term(&S, wavelet, nt, m, src);
+            medium_rhs(G, &M, beta, um, umm, src, lu, v);
+            if (att_power == 2)
+                oracle_laplacian(g, umm, q);   /* L u^{m-1} */
+#pragma omp parallel for
+            for (long p = 0; p < N; p++) {
+                double d = 2.0 * v[p] / S.vpp[p];
+                if (alpha0 && att_power == 2)
+                    d += 2.0 * al[p] / dt * (lu[p] - q[p]);
+                if (alpha0 && att_power == 0)
+                    d += dt * al[p] * S.a[p] / S.k[p] * (2.0 * umm[p] - 2.0 * um[p] - S.k[p] * v[p]);
+                Gacc[p] += w1[p] * d;
+            }
+            if (dwavelet)
+                for (int s2 = 0; s2 < nsrc; s2++)
+                    dwavelet[(long)s2 * nt + m] = sample(&S, S.sidx, S.sw, s2, w1) / G->cellvol;
+            if (m == 0)
+                break;
+            /* adjoint step */
+            for (long p = 0; p < N; p++)
+                y[p] = (1.0 + beta[p]) * w1[p] - beta[p] * w2[p];
+            for (int a = 0; a < nd; a++)
+                for (long p = 0; p < N; p++)
+                    z[a][p] = M.gam[a][p] * w1[p];
+            receiver_transpose(&S, grad_traces, nt, m, q);
+#pragma omp parallel for
+            for (long i0 = 0; i0 < G->np[0]; i0++)
+                for (long i1 = 0; i1 < G->np[1]; i1++)
+                    for (long i2 = 0; i2 < G->np[2]; i2++) {
+                        long ii[3] = {i0, i1, i2};
+                        long p = pidx(G, i0, i1, i2);
+                        double rhs = lap_at(G, y, i0, i1, i2) + q[p];
+                        for (int a = 0; a < nd; a++) {
+                            double sd = 0.0;
+                            for (int jj = 1; jj <= G->r; jj++) {
+                                double zp = (ii[a] + jj < G->np[a]) ? z[a][p + jj * G->st[a]] : 0.0;
+                                double zm = (ii[a] - jj >= 0) ? z[a][p - jj * G->st[a]] : 0.0;
+                                sd += M.d[jj] * (zp - zm);
+                            }
+                            rhs -= sd * M.inv_dx[a];
+                        }
+                        w0[p] = S.a[p] * (2.0 * w1[p] + S.k[p] * rhs) - S.b[p] * w2[p];
+                    }
+            double *tmp = w2;
+            w2 = w1;
+            w1 = w0;
+            w0 = tmp;
+        }
+    }
+    if (dvp)
+        oracle_pad_transpose(g, Gacc, dvp);
+done:
+    free(al); free(beta); free(ck); free(useg); free(up); free(uc); free(un); free(src);
+    free(lu); free(v); free(w0); free(w1); free(w2); free(y); free(q); free(Gacc);
+    for (int a = 0; a < 3; a++)
+        free(z[a]);
+    medium_free(&M);
+    solve_free(&S);
+    return rc;
+}
+
+int oracle_gradient_medium(const oracle_grid_t *g, const double *vp, const double *rho,
+                           const double *alpha0, int att_power, int nsrc, const double *src_xyz,
+                           const double *wavelet, int nrec, const double *rec_xyz,
+                           const double *observed, double *traces_out, double *misfit, double *dvp,
+                           int seg)
+{
+    if (!g || g->nt < 1 || nrec < 0)
+        return -1;
+    size_t ntr = (size_t)nrec * g->nt;
+    double *tr = malloc(sizeof(double) * (ntr + 1)), *res = malloc(sizeof(double) * (ntr + 1));
+    if (!tr || !res) {
+        free(tr); free(res);
+        return -7;
+    }
+    int rc = oracle_forward_medium(g, vp, rho, alpha0, att_power, nsrc, src_xyz, wavelet, nrec,
+                                   rec_xyz, tr);
+    if (rc == 0) {
+        double J = 0.0;
+        for (size_t i = 0; i < ntr; i++) {
+            res[i] = tr[i] - observed[i];
+            J += 0.5 * res[i] * res[i];
+        }
+        if (misfit)
+            *misfit = J;
+        if (traces_out)
+            memcpy(traces_out, tr, sizeof(double) * ntr);
+        rc = oracle_adjoint_medium(g, vp, rho, alpha0, att_power, nsrc, src_xyz, wavelet, nrec,
+                                   rec_xyz, res, dvp, NULL, seg);
+    }
+    free(tr);
+    free(res);
+    return rc;
+}
+
 /* ------------------------------------------------------------------------
  * Perfectly matched layer (see the header).  Per axis a, in the layer of that
  * axis, the stretched derivatives (1/s_a) d_a with s_a = 1 + zeta_a / (i w)

@@ -196,6 +196,25 @@ int oracle_forward_medium(const oracle_grid_t *g, const double *vp, const double
 int oracle_forward_pml(const oracle_grid_t *g, const double *vp, int nsrc, const double *src_xyz,
                        const double *wavelet, int nrec, const double *rec_xyz, double *traces);
 
+/* Adjoint and shot gradient of oracle_forward_medium (rho and alpha0 fixed):
+ * the exact discrete transpose of the medium step, with w = a k lambda,
+ *   w^m = a (2 w^{m+1} + k (L y - sum_a D_a (gamma_a w^{m+1}) + R^T g^m)) - b w^{m+2},
+ *   y = (1 + beta) w^{m+1} - beta w^{m+2}  (beta = 0 for y = 0),
+ * dvp = P^T sum_n w^{n+1} [ (2/vp) v^n + (y = 2) (2 alpha0/dt) (L u^n - L u^{n-1})
+ *                         + (y = 0) (dt alpha0 a / k) (2 u^{n-1} - 2 u^n - k v^n) ],
+ * v^n the step's right-hand side (L u^n + sum_a gamma_a D_a u^n + S^n + beta (L u^n -
+ * L u^{n-1})); dwavelet[s][n] = W_s w^{n+1} / cell volume.  Two-level
+ * checkpointing with segments of seg steps (seg <= 0: sqrt(nt)). */
+int oracle_adjoint_medium(const oracle_grid_t *g, const double *vp, const double *rho,
+                          const double *alpha0, int att_power, int nsrc, const double *src_xyz,
+                          const double *wavelet, int nrec, const double *rec_xyz,
+                          const double *grad_traces, double *dvp, double *dwavelet, int seg);
+int oracle_gradient_medium(const oracle_grid_t *g, const double *vp, const double *rho,
+                           const double *alpha0, int att_power, int nsrc, const double *src_xyz,
+                           const double *wavelet, int nrec, const double *rec_xyz,
+                           const double *observed, double *traces_out, double *misfit, double *dvp,
+                           int seg);
+
 /* Zero-phase low-pass of [count][nt] signals sampled at dt (the band-limiting
  * of wavelets and traces per frequency block, Sec. 3.2): out = h * in with
  * zeros outside the record, where h is a Hann-windowed sinc of cutoff f_max,
