@@ -70,8 +70,14 @@ enum {
 };
 
 /* Workspace modes: FORWARD (stride_plan_forward), GRADIENT (gradients,
- * forward_save/backward, the engine), FORWARD_MEDIUM (stride_plan_forward_medium). */
-enum { STRIDE_MODE_FORWARD = 0, STRIDE_MODE_GRADIENT = 1, STRIDE_MODE_FORWARD_MEDIUM = 2 };
+ * forward_save/backward, the engine), FORWARD_MEDIUM (stride_plan_forward_medium),
+ * GRADIENT_MEDIUM (stride_plan_gradient_medium). */
+enum {
+    STRIDE_MODE_FORWARD = 0,
+    STRIDE_MODE_GRADIENT = 1,
+    STRIDE_MODE_FORWARD_MEDIUM = 2,
+    STRIDE_MODE_GRADIENT_MEDIUM = 3
+};
 
 /* Physical grid, stencil, sponge and time axis of a solve. */
 typedef struct stride_grid {
@@ -199,6 +205,25 @@ int stride_plan_forward_static(const stride_plan_t* plan, const float* vp, const
 int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const float* rho,
                                const float* alpha0, int32_t att_power, const float* wavelet,
                                float* traces, void* ws, size_t ws_bytes, void* stream);
+
+/* Shot gradient in a heterogeneous medium (the medium of
+ * stride_plan_forward_medium, rho and alpha0 fixed): traces (optional), misfit
+ * J = 1/2 sum (traces - observed)^2 (FP64 device scalar) and dvp = dJ/dvp, by
+ * the exact discrete adjoint of the medium step (Sec. 2.2 adjoint-state
+ * method).  With w = a k lambda the adjoint step is
+ *   w^m = a (2 w^{m+1} + k (L y - sum_a D_a (gamma_a w^{m+1}) + R^T r^m)) - b w^{m+2},
+ *   y = (1 + beta) w^{m+1} - beta w^{m+2}   (beta = 0 for y = 0),
+ * (D_a is antisymmetric, so the density term transposes to -D_a (gamma_a .)),
+ * and dvp = P^T (2/vp) sum_n w^{n+1} h^n with h^n the step's right-hand side v^n
+ * plus the attenuation's vp dependence: y = 2, + (beta/2) (L u^n - L u^{n-1});
+ * y = 0, + (att a dt/4) ((2 u^{n-1} - 2 u^n)/k - v^n), att = 2 alpha0 vp.  Every
+ * step's h is kept (no checkpointing): ws is GRADIENT_MEDIUM bytes, about
+ * nt fields.  Second-order time, sponge boundary.  Errors: INVALID_ARG, CFL,
+ * WORKSPACE, HIP, NONFINITE. */
+int stride_plan_gradient_medium(const stride_plan_t* plan, const float* vp, const float* rho,
+                                const float* alpha0, int32_t att_power, const float* wavelet,
+                                const float* observed, float* traces, double* misfit, float* dvp,
+                                void* ws, size_t ws_bytes, void* stream);
 
 /* One gradient-descent step of an inversion loop (Sec. 2.2 local optimiser):
  *   vp[i] = clamp(vp[i] - step_size m[i] g[i] / max_j |m[j] g[j]|, vmin, vmax),

@@ -14,6 +14,7 @@ from ._abi import (  # noqa: F401
     STRIDE_MODE_FORWARD,
     STRIDE_MODE_FORWARD_MEDIUM,
     STRIDE_MODE_GRADIENT,
+    STRIDE_MODE_GRADIENT_MEDIUM,
     Plan,
     StrideError,
     lib,
@@ -30,6 +31,7 @@ from ._abi import (  # noqa: F401
     stride_plan_forward,
     stride_plan_forward_medium,
     stride_plan_gradient,
+    stride_plan_gradient_medium,
     stride_plan_padded_shape,
     stride_schedule_info,
     stride_timing_enable,

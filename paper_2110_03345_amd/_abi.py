@@ -25,11 +25,12 @@ STRIDE_E_NONFINITE = -6
 STRIDE_MODE_FORWARD = 0
 STRIDE_MODE_GRADIENT = 1
 STRIDE_MODE_FORWARD_MEDIUM = 2
+STRIDE_MODE_GRADIENT_MEDIUM = 3
 
 EXPORTS = (
     "stride_plan_create", "stride_plan_destroy", "stride_plan_padded_shape",
     "stride_workspace_bytes", "stride_plan_forward", "stride_plan_forward_static",
-    "stride_plan_forward_medium", "stride_lowpass",
+    "stride_plan_forward_medium", "stride_plan_gradient_medium", "stride_lowpass",
     "stride_descent_step",
     "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
@@ -84,6 +85,8 @@ def lib():
         L.stride_plan_forward.argtypes = [vp_, vp_, vp_, vp_, vp_, sz, vp_]
         L.stride_plan_forward_static.argtypes = [vp_, vp_, vp_, vp_, vp_]
         L.stride_plan_forward_medium.argtypes = [vp_, vp_, vp_, vp_, i32, vp_, vp_, vp_, sz, vp_]
+        L.stride_plan_gradient_medium.argtypes = [vp_, vp_, vp_, vp_, i32, vp_, vp_, vp_, vp_, vp_,
+                                                  vp_, sz, vp_]
         L.stride_lowpass.argtypes = [vp_, vp_, i32, i32, ctypes.c_double, ctypes.c_double, vp_]
         L.stride_descent_step.argtypes = [vp_, vp_, vp_, ctypes.c_int64, ctypes.c_float,
                                           ctypes.c_float, ctypes.c_float, vp_, vp_]
@@ -253,6 +256,14 @@ def stride_plan_forward_medium(plan, vp, rho, alpha0, att_power, wavelet, traces
     _check(lib().stride_plan_forward_medium(plan, _dev(vp), _dev(rho), _dev(alpha0), int(att_power),
                                             _dev(wavelet), _dev(traces), _dev(ws), ws.numel(),
                                             _stream(stream)))
+
+
+def stride_plan_gradient_medium(plan, vp, rho, alpha0, att_power, wavelet, observed, traces, misfit,
+                                dvp, ws, stream=None):
+    _check(lib().stride_plan_gradient_medium(plan, _dev(vp), _dev(rho), _dev(alpha0), int(att_power),
+                                             _dev(wavelet), _dev(observed), _dev(traces),
+                                             _dev(misfit), _dev(dvp), _dev(ws), ws.numel(),
+                                             _stream(stream)))
 
 
 def stride_lowpass(x, dt: float, f_max: float, out=None, stream=None):
@@ -450,6 +461,27 @@ class Plan:
         stride_plan_forward_medium(self.handle, vp, rho, alpha0, att_power, wavelet, traces, ws,
                                    stream)
         return traces
+
+    def gradient_medium(self, vp, wavelet, observed, rho=None, alpha0=None, att_power: int = 0,
+                        traces=None, ws=None, stream=None):
+        """(misfit, dvp) of the shot gradient in the medium (rho, alpha0 fixed);
+        every step's imaging factor is kept (GRADIENT_MEDIUM workspace)."""
+        import torch
+        self._vp(vp)
+        self._wavelet(wavelet)
+        for a, name in ((rho, "rho"), (alpha0, "alpha0")):
+            if a is not None:
+                _dev(a, self.shape, torch.float32, name)
+        self._traces_like(observed, "observed")
+        if traces is not None:
+            self._traces_like(traces, "traces")
+        if ws is None:
+            ws = self.workspace(STRIDE_MODE_GRADIENT_MEDIUM, device=vp.device)
+        misfit = torch.zeros(1, dtype=torch.float64, device=vp.device)
+        dvp = torch.empty_like(vp)
+        stride_plan_gradient_medium(self.handle, vp, rho, alpha0, att_power, wavelet, observed,
+                                    traces, misfit, dvp, ws, stream)
+        return misfit, dvp
 
     def gradient(self, vp, wavelet, observed, ws=None, budget_bytes: int = 0, traces=None,
                  stream=None):

@@ -142,7 +142,8 @@ enum StepMode {
                   // D = w^{m+1}, and G += U (D + A/12) + (k/12) D L U with U = p
     kMedium = 3,  // forward step in a heterogeneous medium, B a stencil field too:
                   // C = a (2 A + k (L A + sum_a gam_a D_a A + S [+ att (L A - L B)])) - b B,
-                  // with att added to the damping instead when att_power is 0
+                  // with att added to the damping instead when att_power is 0; with V
+                  // given it also stores the imaging factor of the vp gradient there
     kStepV = 4,   // forward kStep that also stores V = L A + S (full-history gradients)
     kImageV = 5,  // adjoint kStep whose imaging reads V = L u^m + S^m instead of the
                   // stencil of u^m: G += A V, and with V2 the previous step's term as
@@ -165,6 +166,23 @@ struct PmlParams {
     float dt;
 };
 
+// One adjoint step of the heterogeneous-medium gradient (the exact transpose
+// of kMedium): w^m = a (2 w^{m+1} + k (L y - sum_a D_a (gam_a w^{m+1}))) - b w^{m+2},
+// y = (1 + beta) w^{m+1} - beta w^{m+2} (beta = att when att_power is 2, else 0;
+// with att_power 0 att joins the damping), and G += w^{m+1} H.  The receiver
+// residual is added afterwards by launch_inject_table.
+struct MediumAdjParams {
+    const float* w1;         // w^{m+1}
+    const float* w2;         // w^{m+2}
+    float* w0;               // w^m
+    const float* k;
+    const float* gam[3];
+    const float* att;        // 2 alpha0 vp (att_power 0) or beta (2); NULL: none
+    int att_power;
+    const float* H;          // imaging factor of step m; NULL: no imaging
+    float* G;
+};
+
 // Kernel launchers (stride_kernels.hip).
 // max_sample_threads: the largest count * sample_lanes(ntap) over the slots.
 void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
@@ -180,6 +198,14 @@ void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const Stenci
 
 void launch_pml_correction(const Dims& d, int R, const StencilCoef& cf, const PmlParams& pp,
                            hipStream_t s);
+void launch_medium_adjoint(const Dims& d, int R, const StencilCoef& cf, const SpongeCoef& sp,
+                           const MediumAdjParams& mp, hipStream_t s);
+// out[p] += a(p) k(p) (sum of the signals injected at p), for every point of an
+// injection table built for the launch shape ls; a(p) the damping factor of
+// the sponge and (att_power 0) the attenuation field att.
+void launch_inject_table(const Dims& d, const LaunchShape& ls, const InjTable& T, const float* sig,
+                         int stride, int step, const float* k, const float* att, int att_power,
+                         const SpongeCoef& sp, float* out, hipStream_t s);
 void launch_sample(const SampleSet& smp, const float* field, int step, hipStream_t s);
 void launch_fill(float* p, long long n, float v, hipStream_t s);
 // In place, per [nt] row: h[j] = (h[j-1] + 10 h[j] + h[j+1]) / 12 (zero outside),

@@ -58,6 +58,7 @@ struct Layout {
     size_t fixed_fwd;  // scratch + k + 2 fields
     size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual (+ p, q)
     size_t medium;     // scratch + k + 3 wavefields + ndim gamma fields + attenuation
+    size_t grad_medium;// medium + G + traces + residual + nt - 1 imaging factors
 };
 
 Layout layout_of(const stride_plan& P);

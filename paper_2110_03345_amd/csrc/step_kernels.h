@@ -247,6 +247,27 @@ __device__ __forceinline__ float medium_out(float ctr, float lap, float dens, fl
     return leapfrog(ctr, prev, kk, rhs, eta, half_dt);
 }
 
+// Imaging factor of a medium step for the gradient with respect to vp,
+// dJ/dvp = (2/vp) sum_n w^{n+1} h^n (stored by the forward when V is given):
+//   y = 2:  h = v + (att/2) (L u - L u^{n-1})                (att = beta = 2 alpha0 vp / dt),
+//   y = 0:  h = v + (att a dt/4) ((2 u^{n-1} - 2 u) / k - v)  (att = 2 alpha0 vp, a the
+//           step's damping factor with the attenuation),
+// v the step's right-hand side L u + sum_a gamma_a D_a u + S (+ beta (L u - L u^{n-1})).
+__device__ __forceinline__ float medium_h(float ctr, float lap, float dens, float inj, float lapb,
+                                          float prev, float kk, float at, int att_power, float eta,
+                                          float half_dt)
+{
+    float v = lap + dens + inj;
+    if (att_power == 2) {
+        const float dl = lap - lapb;
+        v = fmaf(at, dl, v);
+        return fmaf(0.5f * at, dl, v);
+    }
+    const float a = __builtin_amdgcn_rcpf(fmaf(eta + at, half_dt, 1.f));
+    const float du = 2.f * (prev - ctr) / kk;
+    return fmaf(at * a * (0.5f * half_dt), du - v, v);
+}
+
 // Imaging accumulator update of an adjoint launch.  Second order:
 // G += w^{m+1} (L u^m + S^m) with ctr = w^{m+1}, lu = L u^m + S^m.  Fourth
 // order accumulates k G, the gradient with respect to k times k:
@@ -471,8 +492,13 @@ __device__ __forceinline__ void step2d_body(const Dims& d, const StencilCoef& cf
             }
             const float* SB = &sF[1][(ly + R) * LW + lx + R];
             const float lapb = lap2d<R, LW>(SB, cf);
-            p.C[po[j]] = medium_out(ctr, lap, fmaf(mgy[j], dy, mgx[j] * dx), inj, lapb, SB[0], kk[j],
-                                    mat[j], p.att_power, eta, sp.half_dt);
+            const float dens = fmaf(mgy[j], dy, mgx[j] * dx);
+            p.C[po[j]] = medium_out(ctr, lap, dens, inj, lapb, SB[0], kk[j], mat[j], p.att_power, eta,
+                                    sp.half_dt);
+            if (p.V)   // gradient forward: the imaging factor, read once by the adjoint
+                __builtin_nontemporal_store(medium_h(ctr, lap, dens, inj, lapb, SB[0], kk[j], mat[j],
+                                                     p.att_power, eta, sp.half_dt),
+                                            p.V + po[j]);
             continue;
         }
         p.C[po[j]] = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);
@@ -825,7 +851,7 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
 
             const auto rC = rsrc(p.C, z);
             const auto rG = rsrc(ADJ && MODE != kAdjPlain ? p.G : p.C, z);
-            const auto rV = rsrc(MODE == kStepV ? p.V : p.C, z);
+            const auto rV = rsrc((MODE == kStepV || MED) && p.V ? p.V : p.C, z);
             const int dzd = layer_depth(z, n0, d.nb);
             const float ez = sp.e[0] * (float)(dzd * dzd);
 #pragma unroll
@@ -869,6 +895,9 @@ __device__ __forceinline__ void step3d_body(const Dims& d, const StencilCoef& cf
                     const float dens = fmaf(mm[0][j], dz, fmaf(mm[1][j], dy, mm[2][j] * dx));
                     bstore_nt(rC, rbo[j], medium_out(ctr, lap, dens, inj, lapb, prev, kk[j], mm[3][j],
                                                      p.att_power, eta, sp.half_dt));
+                    if (p.V)   // gradient forward: the imaging factor
+                        bstore_nt(rV, rbo[j], medium_h(ctr, lap, dens, inj, lapb, prev, kk[j], mm[3][j],
+                                                       p.att_power, eta, sp.half_dt));
                     continue;
                 }
                 const float out = step_out<ADJ, MODE>(ctr, lap, inj, uu[j], bb[j], kk[j], eta, sp.half_dt);

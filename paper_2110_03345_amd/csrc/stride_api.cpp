@@ -358,6 +358,8 @@ Layout stride::layout_of(const stride_plan& P)
     // k, G, w, w, traces, residual (, p and q of the fourth-order adjoint)
     L.fixed_grad = L.scratch + (P.torder == 4 ? 6 : 4) * L.field + 2 * L.traces;
     L.medium = L.scratch + (size_t)(4 + P.nd + 1) * L.field;
+    // the medium gradient keeps every step's imaging factor: G and nt - 1 fields more
+    L.grad_medium = L.medium + (size_t)P.nt * L.field + 2 * L.traces;
     return L;
 }
 
@@ -1098,44 +1100,57 @@ int forward_solve(const stride_plan& P, const float* vp, const float* wavelet, f
 // step reads u^{n-1} as a stencil field, so u^{n+1} cannot overwrite it), the
 // medium fields prepared once, one kMedium launch per step on the two-field
 // launch shape (whose source table is src_img).
-int forward_medium(const stride_plan& P, const float* vp, const float* rho, const float* alpha0,
-                   int att_power, const float* wavelet, float* traces, void* ws, size_t bytes,
-                   hipStream_t s)
+// Views of a medium workspace: [scratch | k | u0 | u1 | u2 | gamma_a x nd | att]
+// (the gradient adds [G | traces | residual | H x (nt - 1)]).
+struct MediumWs {
+    unsigned* flags;
+    float* k;
+    float* u[3];
+    float* gam[3];
+    float* att;
+    char* tail;
+};
+
+void medium_views(const stride_plan& P, const Layout& L, void* ws, MediumWs& M)
 {
-    if (!vp || (!wavelet && P.nsrc > 0) || (!traces && P.nrec > 0))
-        return fail(STRIDE_E_INVALID_ARG, "vp, wavelet and traces must be device pointers");
+    char* b = (char*)ws;
+    M.flags = (unsigned*)b;
+    b += L.scratch;
+    M.k = (float*)b;
+    b += L.field;
+    for (int i = 0; i < 3; ++i, b += L.field)
+        M.u[i] = (float*)b;
+    for (int a = 0; a < 3; ++a)
+        M.gam[a] = nullptr;
+    for (int a = 0; a < P.nd; ++a, b += L.field)
+        M.gam[a] = (float*)b;
+    M.att = (float*)b;
+    M.tail = b + L.field;
+}
+
+int medium_args(const stride_plan& P, const float* vp, const float* wavelet, int att_power)
+{
+    if (!vp || (!wavelet && P.nsrc > 0))
+        return fail(STRIDE_E_INVALID_ARG, "vp and wavelet must be device pointers");
     if (P.torder != 2)
-        return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
+        return fail(STRIDE_E_INVALID_ARG, "medium solves need time_order 2");
     if (P.boundary == 1)
-        return fail(STRIDE_E_INVALID_ARG, "medium forward solves use the sponge, not the PML");
+        return fail(STRIDE_E_INVALID_ARG, "medium solves use the sponge, not the PML");
     if (att_power != 0 && att_power != 2)
         return fail(STRIDE_E_INVALID_ARG, "att_power must be 0 or 2 (got %d)", att_power);
-    Layout L = layout_of(P);
-    if (!ws || (uintptr_t)ws % 256)
-        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
-    if (bytes < L.medium)
-        return fail(STRIDE_E_WORKSPACE, "medium forward workspace needs %zu bytes (got %zu)",
-                    L.medium, bytes);
-    char* b = (char*)ws;
-    unsigned* flags = (unsigned*)b;
-    b += L.scratch;
-    float* k = (float*)b;
-    b += L.field;
-    float* u[3];
-    for (int i = 0; i < 3; ++i, b += L.field)
-        u[i] = (float*)b;
-    float* gam[3] = {nullptr, nullptr, nullptr};
-    for (int a = 0; a < P.nd; ++a, b += L.field)
-        gam[a] = (float*)b;
-    float* att = (float*)b;
+    return STRIDE_OK;
+}
 
-    long long nphys = 1;
-    for (int a = 0; a < P.nd; ++a)
-        nphys *= P.g.shape[a];
-    launch_vp_check(vp, nphys, flags, s);
-    launch_medium_check(vp, rho, alpha0, nphys, att_power, P.g.dt, flags, s);
+// Value and stability checks of a medium solve (one stream sync), then k and
+// the medium fields on the padded grid.
+int prepare_medium(const stride_plan& P, const float* vp, const float* rho, const float* alpha0,
+                   int att_power, const MediumWs& M, hipStream_t s)
+{
+    const long long nphys = phys_points(P);
+    launch_vp_check(vp, nphys, M.flags, s);
+    launch_medium_check(vp, rho, alpha0, nphys, att_power, P.g.dt, M.flags, s);
     unsigned host[4] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(host, flags, sizeof(host), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(host, M.flags, sizeof(host), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (host[1])
         return fail(STRIDE_E_INVALID_ARG, "vp contains non-positive or non-finite values");
@@ -1149,27 +1164,38 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
     int rc = check_cfl(P, std::max((double)vmax, std::sqrt((double)veff2)));
     if (rc)
         return rc;
+    float* gam[3] = {M.gam[0], M.gam[1], M.gam[2]};
+    launch_prep_k(P.dims, vp, P.g.dt, M.k, s);
+    launch_prep_medium(P.dims, P.fd1, vp, rho, alpha0, att_power, P.g.dt, gam, M.att, s);
+    return STRIDE_OK;
+}
 
-    launch_prep_k(P.dims, vp, P.g.dt, k, s);
-    launch_prep_medium(P.dims, P.fd1, vp, rho, alpha0, att_power, P.g.dt, gam, att, s);
-    launch_fill(u[0], P.dims.total, 0.f, s);
-    launch_fill(u[1], P.dims.total, 0.f, s);
+// Medium forward sweep: three rotating wavefields (the step reads u^{n-1} as a
+// stencil field, so u^{n+1} cannot overwrite it), one kMedium launch per step
+// on the two-field launch shape (whose source table is src_img); with H the
+// step n also stores its imaging factor into H[n].  Returns the field of u^{nt-1}.
+const float* medium_sweep(const stride_plan& P, const MediumWs& M, const float* wavelet,
+                          int att_power, float* traces, float* const* H, hipStream_t s)
+{
+    launch_fill(M.u[0], P.dims.total, 0.f, s);
+    launch_fill(M.u[1], P.dims.total, 0.f, s);
     int tid = g_timer.begin(s);
     int cur = 0, prev = 1, next = 2;
     for (int n = 0; n < P.nt - 1; ++n) {
         StepParams p = base_params(P);
-        p.A = u[cur];
-        p.B = u[prev];
-        p.C = u[next];
-        p.K = k;
+        p.A = M.u[cur];
+        p.B = M.u[prev];
+        p.C = M.u[next];
+        p.K = M.k;
         p.step = n;
         p.inj = P.src_img;
         p.inj_sig = wavelet;
         p.smp = rec_samples(P, traces);
         for (int a = 0; a < 3; ++a)
-            p.gam[a] = gam[a] ? gam[a] : gam[0];
-        p.att = att;
+            p.gam[a] = M.gam[a] ? M.gam[a] : M.gam[0];
+        p.att = M.att;
         p.att_power = att_power;
+        p.V = H ? H[n] : nullptr;
         launch_step_mode(P.dims, P.R, false, kMedium, P.cf, P.sp, P.ls_adj, p, s);
         const int t = prev;
         prev = cur;
@@ -1177,9 +1203,109 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
         next = t;
     }
     g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
-    launch_sample(rec_samples(P, traces), u[cur], P.nt - 1, s);
+    launch_sample(rec_samples(P, traces), M.u[cur], P.nt - 1, s);
+    return M.u[cur];
+}
+
+int forward_medium(const stride_plan& P, const float* vp, const float* rho, const float* alpha0,
+                   int att_power, const float* wavelet, float* traces, void* ws, size_t bytes,
+                   hipStream_t s)
+{
+    int rc = medium_args(P, vp, wavelet, att_power);
+    if (rc)
+        return rc;
+    if (!traces && P.nrec > 0)
+        return fail(STRIDE_E_INVALID_ARG, "traces must be a device pointer");
+    Layout L = layout_of(P);
+    if (!ws || (uintptr_t)ws % 256)
+        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.medium)
+        return fail(STRIDE_E_WORKSPACE, "medium forward workspace needs %zu bytes (got %zu)",
+                    L.medium, bytes);
+    MediumWs M;
+    medium_views(P, L, ws, M);
+    if ((rc = prepare_medium(P, vp, rho, alpha0, att_power, M, s)))
+        return rc;
+    medium_sweep(P, M, wavelet, att_power, traces, nullptr, s);
     HIP_TRY(hipGetLastError());
     return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
+}
+
+// Shot gradient in the medium, every step's imaging factor kept (no
+// checkpointing): the medium sweep storing H, residual and misfit, then per
+// adjoint step the direct medium adjoint kernel (w rotates through the three
+// wavefields) and the receiver residual injected through the plan's table.
+int gradient_medium(const stride_plan& P, const float* vp, const float* rho, const float* alpha0,
+                    int att_power, const float* wavelet, const float* observed, float* traces,
+                    double* misfit, float* dvp, void* ws, size_t bytes, hipStream_t s)
+{
+    int rc = medium_args(P, vp, wavelet, att_power);
+    if (rc)
+        return rc;
+    if ((!observed && P.nrec > 0) || !misfit || !dvp)
+        return fail(STRIDE_E_INVALID_ARG, "observed, misfit and dvp must be device pointers");
+    Layout L = layout_of(P);
+    if (!ws || (uintptr_t)ws % 256)
+        return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
+    if (bytes < L.grad_medium)
+        return fail(STRIDE_E_WORKSPACE,
+                    "medium gradient workspace needs %zu bytes (got %zu): every step's imaging "
+                    "factor is kept", L.grad_medium, bytes);
+    MediumWs M;
+    medium_views(P, L, ws, M);
+    char* b = M.tail;
+    float* G = (float*)b;
+    b += L.field;
+    float* tr_ws = (float*)b;
+    b += L.traces;
+    float* residual = (float*)b;
+    b += L.traces;
+    std::vector<float*> H((size_t)std::max(P.nt - 1, 1));
+    for (int n = 0; n < P.nt - 1; ++n, b += L.field)
+        H[n] = (float*)b;
+    if ((rc = prepare_medium(P, vp, rho, alpha0, att_power, M, s)))
+        return rc;
+    float* tr = traces ? traces : tr_ws;
+    medium_sweep(P, M, wavelet, att_power, tr, H.data(), s);
+    const long long ntr = (long long)P.nrec * P.nt;
+    launch_residual_misfit(tr, observed, residual, ntr, misfit, (double*)(M.flags + 64), s);
+
+    // adjoint: w^{m+1} and w^{m+2} start at zero; step m images with H[m]
+    float* w[3] = {M.u[0], M.u[1], M.u[2]};
+    for (int i = 0; i < 3; ++i)
+        launch_fill(w[i], P.dims.total, 0.f, s);
+    launch_fill(G, P.dims.total, 0.f, s);
+    int i0 = 0, i1 = 1, i2 = 2;   // w^m, w^{m+1}, w^{m+2}
+    int tid = g_timer.begin(s);
+    for (int m = P.nt - 1; m >= 0; --m) {
+        MediumAdjParams mp{};
+        mp.w1 = w[i1];
+        mp.w2 = w[i2];
+        mp.w0 = w[i0];
+        mp.k = M.k;
+        for (int a = 0; a < 3; ++a)
+            mp.gam[a] = M.gam[a] ? M.gam[a] : M.gam[0];
+        mp.att = M.att;
+        mp.att_power = att_power;
+        mp.H = m <= P.nt - 2 ? H[m] : nullptr;   // w^{nt} = 0: step nt-1 images nothing
+        mp.G = G;
+        launch_medium_adjoint(P.dims, P.R, P.cf, P.sp, mp, s);
+        if (m == 0)
+            break;   // w^0 is not needed; the launch above added the last imaging term
+        launch_inject_table(P.dims, P.ls_adj, P.rec_inj, residual, P.nt, m, M.k, M.att, att_power,
+                            P.sp, w[i0], s);
+        const int t = i2;
+        i2 = i1;
+        i1 = i0;
+        i0 = t;
+    }
+    g_timer.end(tid, s, 1, P.nt, 2LL * P.nt - 1);
+    // dvp = P^T (2 G / vp_pad); two wavefields serve as the finalise's scratch
+    launch_finalize_dvp(P.dims, G, nullptr, vp, dvp, w[i1], w[i2], s);
+    HIP_TRY(hipGetLastError());
+    return check_finite(finite_flag(ws), s,
+                        {{tr, nullptr, ntr, "traces"}, {nullptr, misfit, 1, "misfit"},
+                         {dvp, nullptr, phys_points(P), "dvp"}});
 }
 
 int forward_save(const stride_plan& P, const float* vp, const float* wavelet, float* traces,
@@ -1521,16 +1647,17 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
         *out_bytes = L.fixed_fwd;
         return STRIDE_OK;
     }
-    if (mode == STRIDE_MODE_FORWARD_MEDIUM) {
+    if (mode == STRIDE_MODE_FORWARD_MEDIUM || mode == STRIDE_MODE_GRADIENT_MEDIUM) {
         if (plan->torder != 2)
             return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
         if (plan->boundary == 1)
             return fail(STRIDE_E_INVALID_ARG, "medium forward solves use the sponge, not the PML");
-        *out_bytes = L.medium;
+        *out_bytes = mode == STRIDE_MODE_GRADIENT_MEDIUM ? L.grad_medium : L.medium;
         return STRIDE_OK;
     }
     if (mode != STRIDE_MODE_GRADIENT)
-        return fail(STRIDE_E_INVALID_ARG, "mode must be FORWARD, GRADIENT or FORWARD_MEDIUM");
+        return fail(STRIDE_E_INVALID_ARG,
+                    "mode must be FORWARD, GRADIENT, FORWARD_MEDIUM or GRADIENT_MEDIUM");
     if (plan->boundary == 1)
         return fail(STRIDE_E_INVALID_ARG, "the PML is offered for forward solves only");
     long long nfields;
@@ -1596,6 +1723,18 @@ int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
     return forward_medium(*plan, vp, rho, alpha0, att_power, wavelet, traces, ws, ws_bytes,
                           as_stream(stream));
+}
+
+int stride_plan_gradient_medium(const stride_plan_t* plan, const float* vp, const float* rho,
+                                const float* alpha0, int32_t att_power, const float* wavelet,
+                                const float* observed, float* traces, double* misfit, float* dvp,
+                                void* ws, size_t ws_bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan)
+        return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
+    return gradient_medium(*plan, vp, rho, alpha0, att_power, wavelet, observed, traces, misfit, dvp,
+                           ws, ws_bytes, as_stream(stream));
 }
 
 int stride_descent_step(float* vp, const float* grad, const float* mask, int64_t n, float step_size,

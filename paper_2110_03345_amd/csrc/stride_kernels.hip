@@ -644,6 +644,135 @@ void launch_pml_correction(const Dims& d, int R, const StencilCoef& cf, const Pm
                        cf, pp, count, R);
 }
 
+// Padded coordinates of linear index t over the padded grid (no pitch) and the
+// sponge rate there.
+__device__ __forceinline__ void padded_coords(const Dims& d, long long t, int c[3])
+{
+    c[2] = 0;
+    if (d.nd == 3) {
+        const long long plane = (long long)d.n[1] * d.n[2];
+        c[0] = (int)(t / plane);
+        const long long r = t - (long long)c[0] * plane;
+        c[1] = (int)(r / d.n[2]);
+        c[2] = (int)(r - (long long)c[1] * d.n[2]);
+    } else {
+        c[0] = (int)(t / d.n[1]);
+        c[1] = (int)(t - (long long)c[0] * d.n[1]);
+    }
+}
+
+__device__ __forceinline__ float sponge_eta(const Dims& d, const SpongeCoef& sp, const int c[3])
+{
+    float eta = 0.f;
+    for (int a = 0; a < d.nd; ++a) {
+        const int dep = layer_depth(c[a], d.n[a], d.nb);
+        eta = fmaf(sp.e[a], (float)(dep * dep), eta);
+    }
+    return eta;
+}
+
+// One thread per padded point; neighbours beyond the padded array read 0.
+__global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
+                                                             MediumAdjParams mp, int R)
+{
+    const long long count = (long long)d.n[0] * d.n[1] * (d.nd == 3 ? d.n[2] : 1);
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count)
+        return;
+    int c[3];
+    padded_coords(d, t, c);
+    const long long p = d.nd == 3 ? c[0] * d.st[0] + c[1] * d.st[1] + c[2] : c[0] * d.st[0] + c[1];
+    const bool y2 = mp.att && mp.att_power == 2;
+    auto yv = [&](long long q) {
+        const float b = y2 ? mp.att[q] : 0.f;
+        return fmaf(b, mp.w1[q] - mp.w2[q], mp.w1[q]);
+    };
+    const float w1 = mp.w1[p];
+    float lap_y = cf.c0 * yv(p);
+    float dens = 0.f;
+    for (int a = 0; a < d.nd; ++a) {
+        const long long st = d.st[a];
+        float sy = 0.f, sz = 0.f;
+        for (int j = 1; j <= R; ++j) {
+            const bool in_p = c[a] + j < d.n[a], in_m = c[a] - j >= 0;
+            const long long qp = p + j * st, qm = p - j * st;
+            const float yp = in_p ? yv(qp) : 0.f, ym = in_m ? yv(qm) : 0.f;
+            const float zp = in_p ? mp.gam[a][qp] * mp.w1[qp] : 0.f;
+            const float zm = in_m ? mp.gam[a][qm] * mp.w1[qm] : 0.f;
+            sy = fmaf(cf.c[a][j], yp + ym, sy);
+            sz = fmaf(cf.d[a][j], zp - zm, sz);
+        }
+        lap_y += sy;
+        dens += sz;
+    }
+    float eta = sponge_eta(d, sp, c);
+    if (mp.att && mp.att_power == 0)
+        eta += mp.att[p];
+    mp.w0[p] = leapfrog(w1, mp.w2[p], mp.k[p], lap_y - dens, eta, sp.half_dt);
+    if (mp.H)
+        mp.G[p] = fmaf(w1, mp.H[p], mp.G[p]);
+}
+
+void launch_medium_adjoint(const Dims& d, int R, const StencilCoef& cf, const SpongeCoef& sp,
+                           const MediumAdjParams& mp, hipStream_t s)
+{
+    const long long count = (long long)d.n[0] * d.n[1] * (d.nd == 3 ? d.n[2] : 1);
+    hipLaunchKernelGGL(medium_adjoint_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
+                       d, cf, sp, mp, R);
+}
+
+// One block per step-kernel block of the table's launch shape; each thread
+// takes the table's entries tid, tid + 256, ...; the first entry of a point
+// sums the point's run in entry order (so every point is written by one
+// thread, and always in the same order).
+__global__ __launch_bounds__(256) void inject_table_kernel(Dims d, LaunchShape ls, InjTable T,
+                                                           const float* sig, int stride, int step,
+                                                           const float* k, const float* att,
+                                                           int att_power, SpongeCoef sp, float* out)
+{
+    const int b = blockIdx.x;
+    const int e0 = T.ptr[b], e1 = T.ptr[b + 1];
+    const int zci = b / ls.tiles_xy;
+    const int tile = b - zci * ls.tiles_xy;
+    const int y0 = (tile / ls.tiles_x) * ls.ty;
+    const int x0 = (tile % ls.tiles_x) * kTileX;
+    const int plane = ls.ty * kTileX;
+    for (int e = e0 + (int)threadIdx.x; e < e1; e += blockDim.x) {
+        const TileEntry head = T.ent[e];
+        if (head.run <= 0)
+            continue;
+        const float v = tile_point_signal(T.ent + e, head, sig, stride, step);
+        const int pz = head.local / plane;
+        const int rem = head.local - pz * plane;
+        int c[3];
+        if (d.nd == 3) {
+            c[0] = zci * ls.zc + pz;
+            c[1] = y0 + rem / kTileX;
+            c[2] = x0 + rem % kTileX;
+        } else {
+            c[0] = y0 + rem / kTileX;
+            c[1] = x0 + rem % kTileX;
+            c[2] = 0;
+        }
+        const long long p = d.nd == 3 ? c[0] * d.st[0] + c[1] * d.st[1] + c[2] : c[0] * d.st[0] + c[1];
+        float eta = sponge_eta(d, sp, c);
+        if (att && att_power == 0)
+            eta += att[p];
+        const float a = eta == 0.f ? 1.f : __builtin_amdgcn_rcpf(fmaf(eta, sp.half_dt, 1.f));
+        out[p] = fmaf(a * k[p], v, out[p]);
+    }
+}
+
+void launch_inject_table(const Dims& d, const LaunchShape& ls, const InjTable& T, const float* sig,
+                         int stride, int step, const float* k, const float* att, int att_power,
+                         const SpongeCoef& sp, float* out, hipStream_t s)
+{
+    if (ls.tile_blocks <= 0)
+        return;
+    hipLaunchKernelGGL(inject_table_kernel, dim3(ls.tile_blocks), dim3(256), 0, s, d, ls, T, sig,
+                       stride, step, k, att, att_power, sp, out);
+}
+
 void launch_vp_check(const float* vp, long long n, unsigned* flags, hipStream_t s)
 {
     launch_fill(reinterpret_cast<float*>(flags), 2, 0.f, s);

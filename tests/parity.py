@@ -11,7 +11,8 @@ the strongest signals dominate:
 - fields on the physical grid (dvp): the interior (cells at least `inner` from
   every face) and the edge strip (cells within `edge` of a face, where the
   padding transpose adds the absorbing layer into the edge cells) are each
-  within `per` x tol of their own norm.
+  within `per` x tol of their own norm, or of `floor` x the whole field's norm
+  when the region holds less (a strip the wave has barely reached).
 
 The FP32 kernels and the FP64 oracle differ by rounding only, and rounding
 errors are relative to the local signal, so per-trace and per-region errors
@@ -52,14 +53,19 @@ def regions(shape, inner=4, edge=2):
     return dist >= inner, dist < edge
 
 
-def check_field(d, ref, tol, per=3.0, inner=4, edge=2, what="dvp"):
+def check_field(d, ref, tol, per=3.0, inner=4, edge=2, floor=1e-2, what="dvp"):
     d = np.asarray(d, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     glob = rel(d, ref)
     assert glob < tol, f"{what}: relative L2 {glob:.3e} >= {tol:.1e}"
     ins, strip = regions(ref.shape, inner, edge)
-    e_in = rel(d[ins], ref[ins])
-    e_edge = rel(d[strip], ref[strip])
+    total = np.linalg.norm(ref)
+
+    def region(m):
+        return float(np.linalg.norm(d[m] - ref[m]) / max(np.linalg.norm(ref[m]), floor * total))
+
+    e_in = region(ins)
+    e_edge = region(strip)
     assert e_in < per * tol, f"{what}: interior relative L2 {e_in:.3e} >= {per * tol:.1e}"
     assert e_edge < per * tol, f"{what}: edge strip relative L2 {e_edge:.3e} >= {per * tol:.1e}"
     return {"global": glob, "interior": e_in, "edge": e_edge}
