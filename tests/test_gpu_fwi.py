@@ -46,6 +46,17 @@ def test_descent_step_matches_its_definition():
     np.testing.assert_allclose(v.cpu().numpy(), want, rtol=0, atol=2e-3)
 
 
+def _batches(nshots, per_iter, iters, rng):
+    """The mini-batch rule of the loop, written here on its own: shots in the
+    reverse order of a permutation drawn with rng, a new permutation appended
+    whenever the block needs more shots (each shot once before any reuse),
+    split into iters sorted batches of per_iter."""
+    order = []
+    while len(order) < per_iter * iters:
+        order.extend(rng.permutation(nshots).tolist()[::-1])
+    return [sorted(order[i * per_iter:(i + 1) * per_iter]) for i in range(iters)]
+
+
 def _oracle_loop(sv, observed, freqs, iters, per_iter, step, seed):
     g = oracle.Grid(**sv.grid_kwargs())
     rng = np.random.default_rng(seed)
@@ -55,7 +66,7 @@ def _oracle_loop(sv, observed, freqs, iters, per_iter, step, seed):
     for f_max in freqs:
         wf = oracle.lowpass(wav[None], sv.dt, f_max)
         of = [oracle.lowpass(o, sv.dt, f_max) for o in observed]
-        for batch in fwi.shot_batches(len(observed), per_iter, iters, rng):
+        for batch in _batches(len(observed), per_iter, iters, rng):
             G = np.zeros(sv.shape)
             for i in batch:
                 G += oracle.gradient(g, vp, sv.positions[i:i + 1], wf, sv.positions, of[i])[2]
