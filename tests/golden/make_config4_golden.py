@@ -10,9 +10,11 @@ element 0 of the 1024-element hemisphere) into tests/golden/:
   config4_gradient.npz  shot gradient at the skull-only starting model, first
                         1000 steps, observed data zero (J = 1/2 sum traces^2):
       misfit      J
-      plane_a0, plane_a1, plane_a2   dvp on the central plane of each axis (128)
-      face_a0_lo, face_a2_hi         dvp on the physical faces i0 = 0 and i2 = 255,
-                                     where the padding transpose sums the layer
+      slice_axes, slice_index        the planes stored: per axis the plane of
+                                     largest norm (through the source), and the
+                                     physical face of axis 0 of larger norm (the
+                                     padding transpose sums the layer into it)
+      slice_0 .. slice_3             dvp on those planes, float32
       norms_a0, norms_a1, norms_a2   L2 norm of dvp over each plane of each axis
       norm_all, norm_interior, norm_edge   L2 norms over all cells, cells at least
                                      4 from every face, cells within 2 of a face
@@ -61,15 +63,17 @@ def main(which):
         t0 = time.time()
         _, J, dvp = oracle.gradient(g, w.vp_start, w.src_xyz, w.wavelet, w.rec_xyz, obs)
         print(f"gradient {w.padded_shape} nt={w.nt}: {time.time() - t0:.0f} s, J = {J:.6e}", flush=True)
-        c = w.shape[0] // 2
         inner, edge = edge_masks(w.shape)
+        norms = [np.linalg.norm(dvp, axis=tuple(b for b in range(3) if b != a)) for a in range(3)]
+        axes = [0, 1, 2, 0]
+        index = [int(np.argmax(n)) for n in norms]
+        index.append(0 if norms[0][0] > norms[0][-1] else w.shape[0] - 1)
+        slices = {f"slice_{i}": np.take(dvp, k, axis=a).astype(np.float32)
+                  for i, (a, k) in enumerate(zip(axes, index))}
         np.savez_compressed(
-            os.path.join(HERE, "config4_gradient.npz"), misfit=J,
-            plane_a0=dvp[c].astype(np.float32), plane_a1=dvp[:, c].astype(np.float32),
-            plane_a2=dvp[:, :, c].astype(np.float32),
-            face_a0_lo=dvp[0].astype(np.float32), face_a2_hi=dvp[:, :, -1].astype(np.float32),
-            norms_a0=np.linalg.norm(dvp, axis=(1, 2)), norms_a1=np.linalg.norm(dvp, axis=(0, 2)),
-            norms_a2=np.linalg.norm(dvp, axis=(0, 1)), norm_all=np.linalg.norm(dvp),
+            os.path.join(HERE, "config4_gradient.npz"), misfit=J, slice_axes=np.array(axes),
+            slice_index=np.array(index), **slices, norms_a0=norms[0], norms_a1=norms[1],
+            norms_a2=norms[2], norm_all=np.linalg.norm(dvp),
             norm_interior=np.linalg.norm(dvp[inner]), norm_edge=np.linalg.norm(dvp[edge]))
 
 
