@@ -97,8 +97,7 @@ typedef struct stride_grid {
                                u^{n+1} = a (2 u^n + p + (k/12) L p) - b u^{n-1};
                              stable up to sqrt(3) times the leapfrog CFL limit.
                              Forward solves, gradients and stride_backward (dvp, and
-                             dwavelet for nt <= 15360); the batching engine returns
-                             INVALID_ARG for it */
+                             dwavelet for nt <= 15360), in the batching engine too */
     int32_t interp;       /* off-grid sources and receivers (Sec. 2.4): 0 bi/tri-linear
                              (2 nodes per axis), 1 Kaiser-windowed sinc after Hicks
                              (8 nodes per axis: weight sinc(x) I0(b sqrt(1 - (x/4)^2)) /
@@ -286,12 +285,18 @@ int stride_schedule_info(int32_t nt, int64_t fields, int32_t* snaps, int64_t* fo
 /* ---------------------------------------------------------------- batching
  * An engine advances many shots on one padded grid together (shot
  * parallelism, Sec. 2.5, on one device): each slot holds one forward solve or
- * one checkpointed shot gradient with its own model, geometry, nt, dt and
- * sponge speed; a tick advances every active slot by one forward or adjoint
- * step in one batched launch per direction.  Slots attach and detach between
+ * one shot gradient with its own model, geometry, nt, dt, sponge speed and
+ * time order; a tick advances every active slot by one forward or adjoint
+ * step, the slots that run the same step kind sharing one batched launch
+ * (forward, forward keeping v, fourth-order p / q, adjoint with imaging,
+ * adjoint imaging from v, adjoint without imaging, and the two fourth-order
+ * corrections).  A gradient whose workspace holds every state takes the
+ * full-history path of stride_plan_gradient (second order: the forward keeps
+ * v^n = L u^n + S^n and the adjoint images from it; fourth order: the forward
+ * keeps p^n), else the checkpointed one.  Slots attach and detach between
  * stride_engine_run calls (continuous batching).  A slot computes exactly the
  * bits the one-shot entry points compute.  All calls on one engine must use
- * the same stream and come from one thread. */
+ * the same stream and come from one thread.  Sponge boundaries only. */
 typedef struct stride_engine stride_engine_t;
 
 /* grid fixes shape, spacing, space_order and sponge_cells (nt, dt and

@@ -185,7 +185,7 @@ struct MediumAdjParams {
 
 // Kernel launchers (stride_kernels.hip).
 // max_sample_threads: the largest count * sample_lanes(ntap) over the slots.
-void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
+void launch_step_batched(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                          const LaunchShape& ls, const SlotStep* table, int nslots,
                          int max_sample_threads, hipStream_t s);
 void launch_accumulate(float* dst, const float* src, long long n, hipStream_t s);

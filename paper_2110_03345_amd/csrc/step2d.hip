@@ -14,16 +14,16 @@ void launch_family_2d(bool adjoint, int R, int mode, const Dims& d, const Stenci
                : launch_mode_r<false, false, 5>(mode, d, cf, sp, ls, p, s);
 }
 
-void launch_batched_2d(bool adjoint, int R, const Dims& d, const StencilCoef& cf,
+void launch_batched_2d(bool adjoint, int R, int mode, const Dims& d, const StencilCoef& cf,
                        const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
                        hipStream_t s)
 {
     if (adjoint)
-        R == 4 ? batched2d_t<4, true>(d, cf, ls, table, nslots, max_samples, s)
-               : batched2d_t<5, true>(d, cf, ls, table, nslots, max_samples, s);
+        R == 4 ? batched_mode_r<false, true, 4>(mode, d, cf, ls, table, nslots, max_samples, s)
+               : batched_mode_r<false, true, 5>(mode, d, cf, ls, table, nslots, max_samples, s);
     else
-        R == 4 ? batched2d_t<4, false>(d, cf, ls, table, nslots, max_samples, s)
-               : batched2d_t<5, false>(d, cf, ls, table, nslots, max_samples, s);
+        R == 4 ? batched_mode_r<false, false, 4>(mode, d, cf, ls, table, nslots, max_samples, s)
+               : batched_mode_r<false, false, 5>(mode, d, cf, ls, table, nslots, max_samples, s);
 }
 
 }  // namespace stride

@@ -10,11 +10,12 @@ void launch_family_3d_adj(int R, int mode, const Dims& d, const StencilCoef& cf,
            : launch_mode_r<true, true, 5>(mode, d, cf, sp, ls, p, s);
 }
 
-void launch_batched_3d_adj(int R, const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
-                           const SlotStep* table, int nslots, int max_samples, hipStream_t s)
+void launch_batched_3d_adj(int R, int mode, const Dims& d, const StencilCoef& cf,
+                           const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
+                           hipStream_t s)
 {
-    R == 4 ? batched3d_t<4, true>(d, cf, ls, table, nslots, max_samples, s)
-           : batched3d_t<5, true>(d, cf, ls, table, nslots, max_samples, s);
+    R == 4 ? batched_mode_r<true, true, 4>(mode, d, cf, ls, table, nslots, max_samples, s)
+           : batched_mode_r<true, true, 5>(mode, d, cf, ls, table, nslots, max_samples, s);
 }
 
 }  // namespace stride

@@ -944,14 +944,14 @@ __global__ __launch_bounds__(64 * WAVES) void step2d_kernel(Dims d, StencilCoef 
     step2d_body<R, ADJ, RY, WAVES, MODE>(d, cf, sp, p, ls, blockIdx.x);
 }
 
-template <int R, bool ADJ, int RY, int WAVES>
+template <int R, bool ADJ, int RY, int WAVES, int MODE>
 __global__ __launch_bounds__(64 * WAVES) void step2d_batched(Dims d, StencilCoef cf, LaunchShape ls,
                                                              const SlotStep* table)
 {
     const SlotStep st = table[blockIdx.y];
     if (!st.active)
         return;
-    step2d_body<R, ADJ, RY, WAVES>(d, cf, st.sp, st.p, ls, blockIdx.x);
+    step2d_body<R, ADJ, RY, WAVES, MODE>(d, cf, st.sp, st.p, ls, blockIdx.x);
 }
 
 // Occupancy target of a single-shot 3D kernel: 4 waves per SIMD (at most 128
@@ -975,14 +975,14 @@ void step3d_kernel(Dims d, StencilCoef cf, SpongeCoef sp, StepParams p, LaunchSh
     step3d_body<R, ADJ, RY, WAVES, MODE>(d, cf, sp, p, ls, blockIdx.x);
 }
 
-template <int R, bool ADJ, int RY, int WAVES>
+template <int R, bool ADJ, int RY, int WAVES, int MODE>
 __global__ __launch_bounds__(64 * WAVES) void step3d_batched(Dims d, StencilCoef cf, LaunchShape ls,
                                                              const SlotStep* table)
 {
     const SlotStep st = table[blockIdx.y];
     if (!st.active)
         return;
-    step3d_body<R, ADJ, RY, WAVES>(d, cf, st.sp, st.p, ls, blockIdx.x);
+    step3d_body<R, ADJ, RY, WAVES, MODE>(d, cf, st.sp, st.p, ls, blockIdx.x);
 }
 
 // Tile shapes with compiled kernels (rows per thread, waves); tile_shape()
@@ -1059,7 +1059,7 @@ void launch3d_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp, cons
 #undef STRIDE_LAUNCH3D
 }
 
-template <int R, bool ADJ>
+template <int R, bool ADJ, int MODE>
 void batched2d_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls, const SlotStep* table,
                  int nslots, int max_sample_threads, hipStream_t s)
 {
@@ -1067,12 +1067,13 @@ void batched2d_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls, co
     int smp_blocks = (max_sample_threads + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks, nslots);
 #define STRIDE_LAUNCH2DB(RY_, W_)                                                                  \
-    hipLaunchKernelGGL((step2d_batched<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, ls, table)
+    hipLaunchKernelGGL((step2d_batched<R, ADJ, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, ls, \
+                       table)
     STRIDE_DISPATCH2D(STRIDE_LAUNCH2DB);
 #undef STRIDE_LAUNCH2DB
 }
 
-template <int R, bool ADJ>
+template <int R, bool ADJ, int MODE>
 void batched3d_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls, const SlotStep* table,
                  int nslots, int max_sample_threads, hipStream_t s)
 {
@@ -1080,7 +1081,8 @@ void batched3d_t(const Dims& d, const StencilCoef& cf, const LaunchShape& ls, co
     int smp_blocks = (max_sample_threads + nt - 1) / nt;
     dim3 grid(ls.tile_blocks_pad + smp_blocks, nslots);
 #define STRIDE_LAUNCH3DB(RY_, W_)                                                                  \
-    hipLaunchKernelGGL((step3d_batched<R, ADJ, RY_, W_>), grid, dim3(64 * (W_)), 0, s, d, cf, ls, table)
+    hipLaunchKernelGGL((step3d_batched<R, ADJ, RY_, W_, MODE>), grid, dim3(64 * (W_)), 0, s, d, cf, ls, \
+                       table)
     STRIDE_DISPATCH3D(STRIDE_LAUNCH3DB);
 #undef STRIDE_LAUNCH3DB
 }
@@ -1120,6 +1122,42 @@ void launch_mode_r(int mode, const Dims& d, const StencilCoef& cf, const SpongeC
         }
     }
 #undef STRIDE_MODE_CASE
+}
+
+// Runtime mode to template arguments for the batched launches of one
+// family.  Forward modes: kStep, kStepV, kPrep, kCorrect; adjoint modes:
+// kStep, kImageV, kAdjPlain, kCorrect.
+template <bool THREE_D, bool ADJ, int R>
+void batched_mode_r(int mode, const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
+                    const SlotStep* table, int nslots, int max_sample_threads, hipStream_t s)
+{
+#define STRIDE_BMODE_CASE(M_)                                                                     \
+    case M_:                                                                                      \
+        if constexpr (THREE_D)                                                                    \
+            batched3d_t<R, ADJ, M_>(d, cf, ls, table, nslots, max_sample_threads, s);             \
+        else                                                                                      \
+            batched2d_t<R, ADJ, M_>(d, cf, ls, table, nslots, max_sample_threads, s);             \
+        return;
+    if constexpr (ADJ) {
+        switch (mode) {
+            STRIDE_BMODE_CASE(kStep)
+            STRIDE_BMODE_CASE(kImageV)
+            STRIDE_BMODE_CASE(kAdjPlain)
+            STRIDE_BMODE_CASE(kCorrect)
+        default:
+            return;
+        }
+    } else {
+        switch (mode) {
+            STRIDE_BMODE_CASE(kStep)
+            STRIDE_BMODE_CASE(kStepV)
+            STRIDE_BMODE_CASE(kPrep)
+            STRIDE_BMODE_CASE(kCorrect)
+        default:
+            return;
+        }
+    }
+#undef STRIDE_BMODE_CASE
 }
 
 }  // namespace

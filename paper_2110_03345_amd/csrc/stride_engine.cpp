@@ -21,6 +21,7 @@
 // gradient finalise.  A shot's arithmetic is the single-shot kernels' body,
 // so its result is the same bits alone and in any batch.
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -31,6 +32,27 @@
 using namespace stride;
 
 namespace {
+
+// Launch groups of a tick, one batched launch each (empty groups launch
+// nothing).  Stage-0 groups run first; the fourth-order corrections read the
+// p / q fields that kPrep rows of the same tick wrote.
+enum Group {
+    kGFwd = 0,       // forward leapfrog step
+    kGFwdV,          // forward step storing v = L u + S (full history, second order)
+    kGPrep,          // k (L A + St): fourth-order forward p, adjoint p and q
+    kGAdj,           // adjoint step with the fused imaging (checkpointed, second order)
+    kGAdjImage,      // adjoint step adding two imaging terms from v (full history)
+    kGAdjPlain,      // adjoint step without imaging (full history)
+    kGFwdCorrect,    // fourth-order forward correction (stage 1)
+    kGAdjCorrect,    // fourth-order adjoint correction with imaging (stage 1)
+    kGroups
+};
+constexpr bool kGroupAdjoint[kGroups] = {false, false, false, true, true, true, false, true};
+constexpr int kGroupMode[kGroups] = {kStep, kStepV, kPrep, kStep, kImageV, kAdjPlain, kCorrect, kCorrect};
+
+// A fourth-order adjoint step has two kPrep rows (p and q); every other
+// group has at most one row per slot.
+int group_rows(int g, int max_slots) { return g == kGPrep ? 2 * max_slots : max_slots; }
 
 struct SlotJob {
     bool used = false;
@@ -44,10 +66,12 @@ struct SlotJob {
     double* misfit = nullptr;
     float* dvp = nullptr;
     FwdWs F{};
-    int cur = 0, n = 0;                  // forward mode: ping-pong index and time index
+    int cur = 0, n = 0;                  // forward sweeps: ping-pong index and time index
     GradWs W;
-    std::unique_ptr<StepCursor> cursor;  // gradient mode
+    std::unique_ptr<StepCursor> cursor;  // checkpointed gradient
+    bool history = false;                // gradient keeping v^n (second order) or p^n (fourth)
     int phase = 0;                       // gradient: 0 forward sweep, 1 recompute + adjoint
+    int m = 0;                           // full-history adjoint: next step
     int wa = 0;                          // adjoint ping-pong
     long long left = 0;                  // ticks until the current phase ends
 };
@@ -74,92 +98,202 @@ struct stride_engine {
     bool graphs;
     stride_plan_t* shape_plan = nullptr;   // geometry-free plan fixing the layout
     std::vector<SlotJob> slots;
-    SlotStep* d_table = nullptr;           // [tmax][2][max_slots] on the device
+    int group_off[kGroups + 1] = {};        // row offset of each group within a tick
+    SlotStep* d_table = nullptr;           // [tmax][rows per tick] on the device
     SlotStep* h_stage[2] = {nullptr, nullptr};
     hipEvent_t stage_ev[2] = {nullptr, nullptr};
     bool stage_used[2] = {false, false};
     int stage_i = 0;
-    std::map<long long, hipGraphExec_t> execs;   // key: (ticks, rows per launch)
+    std::map<std::array<int, kGroups + 1>, hipGraphExec_t> execs;   // (ticks, launch heights)
     long long ticks_total = 0;
+
+    int tick_rows() const { return group_off[kGroups]; }
 };
 
 namespace {
 
-int fill_tick(stride_engine* E, SlotJob& J, SlotStep* fwd, SlotStep* adj)
+// Rows of one slot for one tick, appended to the groups' row lists.
+struct TickRows {
+    SlotStep* row[kGroups];
+    int count[kGroups];
+    void add(int g, const SlotStep& t) { row[g][count[g]++] = t; }
+};
+
+SlotStep make_row(const stride_plan& P, const StepParams& p)
+{
+    SlotStep t{};
+    t.p = p;
+    t.sp = P.sp;
+    t.active = 1;
+    return t;
+}
+
+// Forward step n from u^n = A to u^{n+1} = C (B = u^{n-1}, overwritten by C),
+// sampling `smp`; fourth order: p = k (L u^n + St^n) into `pbuf`, then the
+// correction.  With `keep` set (full history) the step also stores v^n (second
+// order) or writes p^n to `keep` instead of `pbuf` (fourth order).
+void forward_rows(const stride_plan& P, TickRows& R, const float* A, const float* B, float* C,
+                  const float* K, int n, const float* wavelet, SampleSet smp, float* pbuf,
+                  float* keep)
+{
+    StepParams p = base_params(P);
+    p.K = K;
+    p.step = n;
+    if (P.torder == 2) {
+        p.A = A;
+        p.B = B;
+        p.C = C;
+        p.inj_sig = wavelet;
+        p.smp = smp;
+        if (keep)
+            p.V = keep;
+        R.add(keep ? kGFwdV : kGFwd, make_row(P, p));
+        return;
+    }
+    float* pp = keep ? keep : pbuf;
+    p.A = A;
+    p.C = pp;
+    p.inj_sig = wavelet;
+    p.smp = smp;
+    R.add(kGPrep, make_row(P, p));
+    StepParams q = base_params(P);
+    q.A = pp;
+    q.D = A;
+    q.B = B;
+    q.C = C;
+    q.K = K;
+    q.step = n;
+    R.add(kGFwdCorrect, make_row(P, q));
+}
+
+int fill_tick(SlotJob& J, TickRows& R)
 {
     const stride_plan& P = *J.P;
     if (J.mode == STRIDE_MODE_FORWARD) {
-        SlotStep& t = *fwd;
-        t.p = base_params(P);
-        t.p.A = J.F.u[J.cur];
-        t.p.B = J.F.u[1 - J.cur];
-        t.p.C = J.F.u[1 - J.cur];
-        t.p.K = J.F.k;
-        t.p.step = J.n;
-        t.p.inj_sig = J.wavelet;
-        t.p.smp = rec_samples(P, J.traces);
-        t.sp = P.sp;
-        t.active = 1;
+        forward_rows(P, R, J.F.u[J.cur], J.F.u[1 - J.cur], J.F.u[1 - J.cur], J.F.k, J.n, J.wavelet,
+                     rec_samples(P, J.traces), J.F.p, nullptr);
         J.cur = 1 - J.cur;
         ++J.n;
-        return 1;
+        return STRIDE_OK;
+    }
+    if (J.history) {
+        // full history: u rotates in the adjoint fields during the forward sweep
+        if (J.phase == 0) {
+            float* u[2] = {J.W.w[0], J.W.w[1]};
+            forward_rows(P, R, u[J.cur], u[1 - J.cur], u[1 - J.cur], J.W.k, J.n, J.wavelet,
+                         rec_samples(P, J.W.traces), nullptr, J.W.pool[J.n]);
+            J.cur = 1 - J.cur;
+            ++J.n;
+            return STRIDE_OK;
+        }
+        const int m = J.m--;
+        StepParams c = base_params(P);
+        c.B = J.W.w[1 - J.wa];
+        c.C = J.W.w[1 - J.wa];
+        c.K = J.W.k;
+        c.G = J.W.G;
+        c.step = m;
+        c.inj = P.rec_inj;
+        c.inj_sig = J.W.residual;
+        c.inj_stride = P.nt;
+        c.img = P.no_inj;
+        if (P.torder == 2) {
+            // imaging terms in pairs: odd m leaves G alone, even m adds both
+            c.A = J.W.w[J.wa];
+            c.V = J.W.pool[m];
+            c.V2 = m + 1 <= P.nt - 1 ? J.W.pool[m + 1] : nullptr;
+            R.add(m % 2 == 0 ? kGAdjImage : kGAdjPlain, make_row(P, c));
+        } else {
+            StepParams q = base_params(P);
+            q.A = J.W.w[J.wa];
+            q.C = J.W.q;
+            q.K = J.W.k;
+            q.step = m;
+            q.inj = P.no_inj;
+            R.add(kGPrep, make_row(P, q));
+            c.A = J.W.q;
+            c.U = J.W.pool[m];
+            c.D = J.W.w[J.wa];
+            R.add(kGAdjCorrect, make_row(P, c));
+        }
+        J.wa = 1 - J.wa;
+        return STRIDE_OK;
     }
     StepOp op;
     if (!J.cursor->next(op))
         return fail(STRIDE_E_WORKSPACE, "checkpoint schedule ended early (pool overflow)");
     if (!op.reverse) {
-        SlotStep& t = *fwd;
-        t.p = base_params(P);
-        t.p.A = J.W.pool[op.a];
-        t.p.B = J.W.pool[op.b];
-        t.p.C = J.W.pool[op.c];
-        t.p.K = J.W.k;
-        t.p.step = op.step;
-        t.p.inj_sig = J.wavelet;
-        if (op.first_sweep)
-            t.p.smp = rec_samples(P, J.W.traces);
-        t.sp = P.sp;
-        t.active = 1;
-        return 1;
+        forward_rows(P, R, J.W.pool[op.a], J.W.pool[op.b], J.W.pool[op.c], J.W.k, op.step,
+                     J.wavelet, op.first_sweep ? rec_samples(P, J.W.traces) : SampleSet{}, J.W.p,
+                     nullptr);
+        return STRIDE_OK;
     }
-    SlotStep& t = *adj;
-    t.p = base_params(P);
-    t.p.A = J.W.w[J.wa];
-    t.p.B = J.W.w[1 - J.wa];
-    t.p.C = J.W.w[1 - J.wa];
-    t.p.K = J.W.k;
-    t.p.U = J.W.pool[op.a];
-    t.p.G = J.W.G;
-    t.p.step = op.step;
-    t.p.inj = P.rec_inj;
-    t.p.inj_sig = J.W.residual;
-    t.p.inj_stride = P.nt;
-    t.p.img = P.src_img;
-    t.p.img_sig = J.wavelet;
-    t.p.img_stride = P.nt;
-    t.sp = P.sp;
-    t.active = 1;
+    StepParams c = base_params(P);
+    c.B = J.W.w[1 - J.wa];
+    c.C = J.W.w[1 - J.wa];
+    c.K = J.W.k;
+    c.G = J.W.G;
+    c.step = op.step;
+    c.inj = P.rec_inj;
+    c.inj_sig = J.W.residual;
+    c.inj_stride = P.nt;
+    if (P.torder == 2) {
+        c.A = J.W.w[J.wa];
+        c.U = J.W.pool[op.a];
+        c.img = P.src_img;
+        c.img_sig = J.wavelet;
+        c.img_stride = P.nt;
+        R.add(kGAdj, make_row(P, c));
+    } else {
+        // p = k (L u^m + St^m), q = k L w^{m+1}, then w^m and the imaging
+        StepParams p = base_params(P);
+        p.A = J.W.pool[op.a];
+        p.C = J.W.p;
+        p.K = J.W.k;
+        p.step = op.step;
+        p.inj_sig = J.wavelet;
+        R.add(kGPrep, make_row(P, p));
+        StepParams q = base_params(P);
+        q.A = J.W.w[J.wa];
+        q.C = J.W.q;
+        q.K = J.W.k;
+        q.step = op.step;
+        q.inj = P.no_inj;
+        R.add(kGPrep, make_row(P, q));
+        c.A = J.W.q;
+        c.U = J.W.p;
+        c.D = J.W.w[J.wa];
+        c.img = P.no_inj;
+        R.add(kGAdjCorrect, make_row(P, c));
+    }
     J.wa = 1 - J.wa;
-    return 2;
+    return STRIDE_OK;
 }
 
-// gy_fwd / gy_adj: rows of the per-tick tables each launch covers (0 = no launch).
-void launch_chunk(stride_engine* E, int ticks, int gy_fwd, int gy_adj, hipStream_t s)
+// gy[g]: rows of group g each launch covers (0 = no launch).
+void launch_chunk(stride_engine* E, int ticks, const int* gy, hipStream_t s)
 {
+    const int sample_threads = E->max_samples * sample_lanes(E->ntap);
     for (int t = 0; t < ticks; ++t) {
-        const SlotStep* base = E->d_table + (size_t)t * 2 * E->max_slots;
-        if (gy_fwd)
-            launch_step_batched(E->dims, E->R, false, E->cf, E->ls_fwd, base, gy_fwd,
-                                E->max_samples * sample_lanes(E->ntap), s);
-        if (gy_adj)
-            launch_step_batched(E->dims, E->R, true, E->cf, E->ls_adj, base + E->max_slots, gy_adj, 0, s);
+        const SlotStep* base = E->d_table + (size_t)t * E->tick_rows();
+        for (int g = 0; g < kGroups; ++g) {
+            if (!gy[g])
+                continue;
+            const bool adj = kGroupAdjoint[g];
+            // traces are sampled by the forward step (fourth order: its kPrep row)
+            const bool smp = g == kGFwd || g == kGFwdV || g == kGPrep;
+            launch_step_batched(E->dims, E->R, adj, kGroupMode[g], E->cf, adj ? E->ls_adj : E->ls_fwd,
+                                base + E->group_off[g], gy[g], smp ? sample_threads : 0, s);
+        }
     }
 }
 
-int get_exec(stride_engine* E, int ticks, int gy_fwd, int gy_adj, hipStream_t s,
-             hipGraphExec_t* out)
+int get_exec(stride_engine* E, int ticks, const int* gy, hipStream_t s, hipGraphExec_t* out)
 {
-    long long key = ((long long)ticks * 8192 + gy_fwd) * 8192 + gy_adj;
+    std::array<int, kGroups + 1> key{};
+    key[0] = ticks;
+    for (int g = 0; g < kGroups; ++g)
+        key[g + 1] = gy[g];
     auto it = E->execs.find(key);
     if (it != E->execs.end()) {
         *out = it->second;
@@ -167,7 +301,7 @@ int get_exec(stride_engine* E, int ticks, int gy_fwd, int gy_adj, hipStream_t s,
     }
     hipGraph_t g = nullptr;
     STRIDE_HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-    launch_chunk(E, ticks, gy_fwd, gy_adj, s);
+    launch_chunk(E, ticks, gy, s);
     hipError_t e = hipStreamEndCapture(s, &g);
     if (e != hipSuccess)
         return fail(STRIDE_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
@@ -181,9 +315,17 @@ int get_exec(stride_engine* E, int ticks, int gy_fwd, int gy_adj, hipStream_t s,
     return STRIDE_OK;
 }
 
+// Ticks of a gradient's second phase (recomputation and adjoint).
+long long second_phase_ticks(const SlotJob& J)
+{
+    const int nt = J.P->nt;
+    return J.history ? nt : J.cursor->forward_steps() - (nt - 1) + nt;
+}
+
 // Work between phases, enqueued after the chunk that ended the phase.
 void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
 {
+    (void)E;
     const stride_plan& P = *J.P;
     if (J.mode == STRIDE_MODE_FORWARD) {
         launch_sample(rec_samples(P, J.traces), J.F.u[J.cur], P.nt - 1, s);
@@ -192,17 +334,28 @@ void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
     }
     if (J.phase == 0) {
         // the forward sweep ended in x_{nt-1}: last sample, residual, misfit
-        launch_sample(rec_samples(P, J.W.traces),
-                      J.W.pool[J.cursor->cur()], P.nt - 1, s);
+        const float* last = J.history ? J.W.w[J.cur] : J.W.pool[J.cursor->cur()];
+        launch_sample(rec_samples(P, J.W.traces), last, P.nt - 1, s);
         launch_residual_misfit(J.W.traces, J.observed, J.W.residual, (long long)P.nrec * P.nt,
                                J.misfit, J.W.partial, s);
         if (J.traces)
             launch_copy(J.traces, J.W.traces, (long long)P.nrec * P.nt, s);
+        if (J.history) {
+            // v^{nt-1} (p^{nt-1}) is never formed and meets w^{nt} = 0; the
+            // adjoint fields held u and start at zero
+            launch_fill(J.W.pool[P.nt - 1], P.dims.total, 0.f, s);
+            launch_fill(J.W.w[0], P.dims.total, 0.f, s);
+            launch_fill(J.W.w[1], P.dims.total, 0.f, s);
+            J.m = P.nt - 1;
+            J.wa = 0;
+        }
         J.phase = 1;
-        J.left = J.cursor->forward_steps() - (P.nt - 1) + P.nt;
+        J.left = second_phase_ticks(J);
         return;
     }
-    launch_finalize_dvp(P.dims, J.W.G, nullptr, J.vp, J.dvp, J.W.w[0], J.W.w[1], s);
+    // the fourth-order accumulator holds k G
+    launch_finalize_dvp(P.dims, J.W.G, P.torder == 4 ? J.W.k : nullptr, J.vp, J.dvp, J.W.w[0],
+                        J.W.w[1], s);
     J.finished = true;
 }
 
@@ -236,7 +389,9 @@ int stride_engine_create(const stride_grid_t* grid, int32_t max_slots, int32_t m
     E->tmax = t;
     E->graphs = use_graphs != 0;
     E->slots.resize(max_slots);
-    size_t bytes = sizeof(SlotStep) * (size_t)E->tmax * 2 * max_slots;
+    for (int g = 0; g < kGroups; ++g)
+        E->group_off[g + 1] = E->group_off[g] + group_rows(g, max_slots);
+    size_t bytes = sizeof(SlotStep) * (size_t)E->tmax * E->tick_rows();
     hipError_t e = hipMalloc((void**)&E->d_table, bytes);
     for (int i = 0; i < 2 && e == hipSuccess; ++i) {
         e = hipHostMalloc((void**)&E->h_stage[i], bytes, hipHostMallocDefault);
@@ -282,8 +437,6 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
     if (!same_layout(E->dims, plan->dims) || E->R != plan->R || E->ntap != plan->ntap ||
         std::memcmp(&E->cf, &plan->cf, sizeof(StencilCoef)) != 0)
         return fail(STRIDE_E_INVALID_ARG, "plan grid does not match the engine grid");
-    if (plan->torder != 2)
-        return fail(STRIDE_E_INVALID_ARG, "the engine runs time_order 2 solves only");
     if (plan->boundary != 0)
         return fail(STRIDE_E_INVALID_ARG, "the engine runs solves with the sponge only");
     if (plan->nrec > E->max_samples)
@@ -331,9 +484,19 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         if (rc)
             return rc;
         launch_prep_k(plan->dims, vp, plan->g.dt, J.W.k, s);
-        for (float* f : {J.W.pool[0], J.W.pool[1], J.W.G, J.W.w[0], J.W.w[1]})
-            launch_fill(f, plan->dims.total, 0.f, s);
         J.cursor = std::make_unique<StepCursor>(plan->nt, J.W.snaps, (int)J.W.pool.size());
+        // every state fits: the forward keeps v^n (p^n) and the adjoint images
+        // from it, the single-shot full-history path (the same bits)
+        J.history = J.cursor->forward_steps() <= plan->nt - 1 &&
+                    (long long)J.W.pool.size() >= plan->nt;
+        if (J.history) {
+            J.cursor.reset();
+            for (float* f : {J.W.G, J.W.w[0], J.W.w[1]})
+                launch_fill(f, plan->dims.total, 0.f, s);
+        } else {
+            for (float* f : {J.W.pool[0], J.W.pool[1], J.W.G, J.W.w[0], J.W.w[1]})
+                launch_fill(f, plan->dims.total, 0.f, s);
+        }
         J.phase = 0;
         J.left = plan->nt - 1;
     } else {
@@ -371,46 +534,57 @@ int stride_engine_run(stride_engine_t* E, int32_t max_ticks, void* stream, int32
     if (ticks > cap)
         ticks /= 2;
 
-    // per-tick slot tables, active entries packed from row 0, in the pinned
-    // staging buffer
+    // per-tick slot tables, each group's active rows packed from its first
+    // row, in the pinned staging buffer
     int si = E->stage_i;
     if (E->stage_used[si])
         STRIDE_HIP_TRY(hipEventSynchronize(E->stage_ev[si]));
     SlotStep* H = E->h_stage[si];
-    size_t bytes = sizeof(SlotStep) * (size_t)ticks * 2 * E->max_slots;
-    std::memset((void*)H, 0, bytes);
-    int rows_fwd = 0, rows_adj = 0;
+    const size_t per_tick = (size_t)E->tick_rows();
+    size_t bytes = sizeof(SlotStep) * (size_t)ticks * per_tick;
+    int rows[kGroups] = {};
+    std::vector<int> counts((size_t)ticks * kGroups, 0);
     std::vector<long long> used_ticks(E->max_slots, 0);
     for (int t = 0; t < ticks; ++t) {
-        SlotStep* row = H + (size_t)t * 2 * E->max_slots;
-        int nf = 0, na = 0;
+        SlotStep* tick = H + (size_t)t * per_tick;
+        TickRows R;
+        for (int g = 0; g < kGroups; ++g) {
+            R.row[g] = tick + E->group_off[g];
+            R.count[g] = 0;
+        }
         for (int j = 0; j < E->max_slots; ++j) {
             SlotJob& J = E->slots[j];
             if (!J.used || J.finished || used_ticks[j] >= J.left)
                 continue;
-            SlotStep fwd{}, adj{};
-            int kind = fill_tick(E, J, &fwd, &adj);
-            if (kind < 0)
-                return kind;
-            if (kind == 1)
-                row[nf++] = fwd;
-            else
-                row[E->max_slots + na++] = adj;
+            int rc = fill_tick(J, R);
+            if (rc)
+                return rc;
             ++used_ticks[j];
         }
-        rows_fwd = std::max(rows_fwd, nf);
-        rows_adj = std::max(rows_adj, na);
+        for (int g = 0; g < kGroups; ++g) {
+            counts[(size_t)t * kGroups + g] = R.count[g];
+            rows[g] = std::max(rows[g], R.count[g]);
+        }
     }
-    // round launch heights up to powers of two so that captured graphs repeat
-    auto pow2 = [&](int n) {
-        if (n == 0)
-            return 0;
-        int p = 1;
-        while (p < n)
-            p *= 2;
-        return std::min(p, E->max_slots);
-    };
-    const int gy_fwd = pow2(rows_fwd), gy_adj = pow2(rows_adj);
+    // round launch heights up to powers of two so that captured graphs
+    // repeat; rows past a tick's count up to the height are inactive
+    int gy[kGroups];
+    for (int g = 0; g < kGroups; ++g) {
+        int h = 0;
+        if (rows[g]) {
+            h = 1;
+            while (h < rows[g])
+                h *= 2;
+            h = std::min(h, group_rows(g, E->max_slots));
+        }
+        gy[g] = h;
+        for (int t = 0; t < ticks; ++t) {
+            SlotStep* r = H + (size_t)t * per_tick + E->group_off[g];
+            const int c = counts[(size_t)t * kGroups + g];
+            if (h > c)
+                std::memset((void*)(r + c), 0, sizeof(SlotStep) * (size_t)(h - c));
+        }
+    }
     STRIDE_HIP_TRY(hipMemcpyAsync(E->d_table, H, bytes, hipMemcpyHostToDevice, s));
     STRIDE_HIP_TRY(hipEventRecord(E->stage_ev[si], s));
     E->stage_used[si] = true;
@@ -418,12 +592,12 @@ int stride_engine_run(stride_engine_t* E, int32_t max_ticks, void* stream, int32
 
     if (E->graphs && s != nullptr) {
         hipGraphExec_t x = nullptr;
-        int rc = get_exec(E, ticks, gy_fwd, gy_adj, s, &x);
+        int rc = get_exec(E, ticks, gy, s, &x);
         if (rc)
             return rc;
         STRIDE_HIP_TRY(hipGraphLaunch(x, s));
     } else {
-        launch_chunk(E, ticks, gy_fwd, gy_adj, s);
+        launch_chunk(E, ticks, gy, s);
     }
     for (int j = 0; j < E->max_slots; ++j) {
         SlotJob& J = E->slots[j];
@@ -456,7 +630,7 @@ int stride_engine_slot_ticks(const stride_engine_t* E, int32_t slot, int64_t* ti
     const SlotJob& J = E->slots[slot];
     long long left = J.finished ? 0 : J.left;
     if (J.mode == STRIDE_MODE_GRADIENT && J.phase == 0 && !J.finished)
-        left += J.cursor->forward_steps() - (J.P->nt - 1) + J.P->nt;
+        left += second_phase_ticks(J);
     *ticks_left = left;
     return STRIDE_OK;
 }

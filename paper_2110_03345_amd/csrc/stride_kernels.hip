@@ -449,13 +449,15 @@ void launch_family_3d_fwd(int R, int mode, const Dims& d, const StencilCoef& cf,
                           const LaunchShape& ls, const StepParams& p, hipStream_t s);
 void launch_family_3d_adj(int R, int mode, const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                           const LaunchShape& ls, const StepParams& p, hipStream_t s);
-void launch_batched_2d(bool adjoint, int R, const Dims& d, const StencilCoef& cf,
+void launch_batched_2d(bool adjoint, int R, int mode, const Dims& d, const StencilCoef& cf,
                        const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
                        hipStream_t s);
-void launch_batched_3d_fwd(int R, const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
-                           const SlotStep* table, int nslots, int max_samples, hipStream_t s);
-void launch_batched_3d_adj(int R, const Dims& d, const StencilCoef& cf, const LaunchShape& ls,
-                           const SlotStep* table, int nslots, int max_samples, hipStream_t s);
+void launch_batched_3d_fwd(int R, int mode, const Dims& d, const StencilCoef& cf,
+                           const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
+                           hipStream_t s);
+void launch_batched_3d_adj(int R, int mode, const Dims& d, const StencilCoef& cf,
+                           const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
+                           hipStream_t s);
 
 void launch_step_mode(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                       const SpongeCoef& sp, const LaunchShape& ls, const StepParams& p, hipStream_t s)
@@ -474,16 +476,16 @@ void launch_step(const Dims& d, int R, bool adjoint, const StencilCoef& cf, cons
     launch_step_mode(d, R, adjoint, kStep, cf, sp, ls, p, s);
 }
 
-void launch_step_batched(const Dims& d, int R, bool adjoint, const StencilCoef& cf,
+void launch_step_batched(const Dims& d, int R, bool adjoint, int mode, const StencilCoef& cf,
                          const LaunchShape& ls, const SlotStep* table, int nslots, int max_samples,
                          hipStream_t s)
 {
     if (d.nd == 2)
-        launch_batched_2d(adjoint, R, d, cf, ls, table, nslots, max_samples, s);
+        launch_batched_2d(adjoint, R, mode, d, cf, ls, table, nslots, max_samples, s);
     else if (adjoint)
-        launch_batched_3d_adj(R, d, cf, ls, table, nslots, max_samples, s);
+        launch_batched_3d_adj(R, mode, d, cf, ls, table, nslots, max_samples, s);
     else
-        launch_batched_3d_fwd(R, d, cf, ls, table, nslots, max_samples, s);
+        launch_batched_3d_fwd(R, mode, d, cf, ls, table, nslots, max_samples, s);
 }
 
 __global__ void accumulate_kernel(float* dst, const float* src, long long n)

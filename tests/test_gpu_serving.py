@@ -33,7 +33,9 @@ def _shots(maker, n, seed=0, **kw):
     return out
 
 
-def _run_engine(shots, kinds, use_graphs, budget_frac=None, max_chunk=16):
+def _run_engine(shots, kinds, use_graphs, budget_frac=None, max_chunk=16, orders=None, fracs=None):
+    """Runs the shots through one engine of 4 slots; orders / fracs: time
+    order and gradient workspace fraction per shot (default 2 and full)."""
     dev = torch.device("cuda")
     w0 = shots[0]
     grid = S.make_grid(**w0.grid_kwargs())
@@ -47,7 +49,7 @@ def _run_engine(shots, kinds, use_graphs, budget_frac=None, max_chunk=16):
             while pending and len(attached) < 4:
                 i = pending.pop(0)
                 w, kind = shots[i], kinds[i]
-                plan = S.Plan.from_workload(w)
+                plan = S.Plan.from_workload(w, time_order=orders[i] if orders else 2)
                 vp = torch.from_numpy(w.vp).to(dev)
                 wav = torch.from_numpy(w.wavelet).to(dev)
                 tr = torch.empty((plan.nrec, w.nt), dtype=torch.float32, device=dev)
@@ -57,7 +59,8 @@ def _run_engine(shots, kinds, use_graphs, budget_frac=None, max_chunk=16):
                     obs = mis = dvp = None
                 else:
                     full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
-                    budget = int(full * budget_frac) if budget_frac else 0
+                    frac = fracs[i] if fracs else budget_frac
+                    budget = int(full * frac) if frac else 0
                     ws = plan.workspace(S.STRIDE_MODE_GRADIENT, budget)
                     rng = np.random.default_rng(i)
                     obs = torch.from_numpy(
@@ -107,6 +110,29 @@ def test_engine_checkpointed_gradients_equal_single_shot():
     for r in outs:
         m, d = r["plan"].gradient(r["vp"], r["wav"], r["obs"])
         assert torch.equal(d, r["dvp"]) and torch.equal(m, r["misfit"])
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+def test_engine_fourth_order_and_mixed_slots_equal_single_shot(maker):
+    """Fourth-order forward and gradient slots (full history and
+    checkpointed) next to second-order ones in one engine: each equals its
+    single-shot solve bit for bit."""
+    shots = _shots(maker, 7, nt=64, seed=5)
+    kinds = ["forward", "gradient", "gradient", "forward", "gradient", "gradient", "forward"]
+    orders = [4, 4, 4, 2, 2, 4, 4]
+    fracs = [None, None, 0.35, None, 0.3, 0.5, None]
+    outs = _run_engine(shots, kinds, True, max_chunk=8, orders=orders, fracs=fracs)
+    for r in outs:
+        plan, vp, wav = r["plan"], r["vp"], r["wav"]
+        print(f"shot {r['i']} {r['kind']} order {orders[r['i']]} nt={shots[r['i']].nt}", flush=True)
+        if r["kind"] == "forward":
+            assert torch.equal(plan.forward(vp, wav), r["traces"])
+        else:
+            tr = torch.empty_like(r["traces"])
+            m, d = plan.gradient(vp, wav, r["obs"], traces=tr)
+            assert torch.equal(tr, r["traces"])
+            assert torch.equal(m, r["misfit"])
+            assert torch.equal(d, r["dvp"])
 
 
 def test_engine_rejects_mismatched_grid_and_full_slots():
