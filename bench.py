@@ -24,8 +24,10 @@ the paired adjoint instead (24 bytes per step on average); its line reports
 that figure and the 28-byte one.
 
 Extra keys: the config-2 2D shot gradient and forward (same steps), and a
-bounded serving run (served shot solves/s and p50/p99 against one request at
-a time).  --fourth-order, --sinc and --medium add those solver variants.
+bounded serving run over the full six-class request mix (2D 256^2, 512^2,
+1024^2 and 3D 128^3, 192^3, 256^3, nt 500-3000; --leg-requests requests):
+served shot solves/s and p50/p99 against one request at a time.
+--fourth-order, --sinc and --medium add those solver variants.
 """
 import argparse
 import json
@@ -139,11 +141,16 @@ def parse():
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
-    ap.add_argument("--leg-requests", type=int, default=32,
-                    help="serving leg of the default run: number of requests")
+    ap.add_argument("--leg-requests", type=int, default=40,
+                    help="serving leg of the default run: number of requests of the full six-class "
+                         "mix")
     ap.add_argument("--full-mix", action="store_true",
                     help="serving: all six grid classes and nt 500-3000 (default: 2D classes and "
                          "128^3, nt 500-1500)")
+    ap.add_argument("--classes-2d", default=None,
+                    help="serving: comma-separated 2D grid classes (overrides the mix; '' for none)")
+    ap.add_argument("--classes-3d", default=None,
+                    help="serving: comma-separated 3D grid classes (overrides the mix; '' for none)")
     ap.add_argument("--no-graphs", action="store_true", help="serving: direct launches, no hipGraphs")
     ap.add_argument("--max-slots", type=int, default=32, help="serving: shots per engine")
     ap.add_argument("--max-chunk", type=int, default=64, help="serving: ticks per graph chunk")
@@ -274,19 +281,24 @@ def fwi_bench(args):
     print(json.dumps(line), flush=True)
 
 
-def serving_run(args, nreq):
+def serving_run(args, nreq, full_mix=None):
     """Served shot solves per second and p50/p99 latency against one request at
     a time, on the same seeded request stream of nreq requests; every served
-    result is compared bit for bit with its one-at-a-time result."""
+    result is compared bit for bit with its one-at-a-time result.  full_mix:
+    all six grid classes with nt 500-3000 (default: args.full_mix)."""
     import torch
 
     from paper_2110_03345_amd.serving import Server, serve_one_at_a_time
     from workloads.serving_mix import materialise, request_stream
 
-    if args.full_mix:
+    if args.full_mix if full_mix is None else full_mix:
         kw = dict(nt_range=(500, 3000), classes_2d=(256, 512, 1024), classes_3d=(128, 192, 256))
     else:
         kw = dict(nt_range=(500, 1500), classes_2d=(256, 512, 1024), classes_3d=(128,))
+    for dim in ("2d", "3d"):
+        sel = getattr(args, "classes_" + dim)
+        if sel is not None:
+            kw["classes_" + dim] = tuple(int(c) for c in sel.split(",") if c)
     # calibration: the one-at-a-time service time of the stream's first requests
     # sets the arrival rate (a request's content does not depend on the rate:
     # the generator draws the same numbers for it at any rate, only the
@@ -307,6 +319,7 @@ def serving_run(args, nreq):
         return lambda n, total: print(f"[bench] {tag}: {n}/{total} requests done", file=sys.stderr,
                                       flush=True)
 
+    torch.cuda.empty_cache()   # the calibration's cached blocks would shrink the server's budget
     srv = Server(use_graphs=not args.no_graphs, max_slots=args.max_slots, max_chunk=args.max_chunk)
     try:
         served = srv.run(specs, realtime=True, progress=progress("served"))
@@ -667,7 +680,7 @@ def main():
         del c2
         torch.cuda.empty_cache()
     if not args.no_serving:
-        legs["serving"] = serving_run(args, args.leg_requests)
+        legs["serving"] = serving_run(args, args.leg_requests, full_mix=True)
         torch.cuda.empty_cache()
 
     cpu = None

@@ -353,7 +353,16 @@ class Server:
                 elif pending:
                     time.sleep(max(0.0, min(0.002, arrival[pending[0].rid] - now)))
                 elif waiting and not any(b.owner for b in self.buckets.values()):
-                    raise RuntimeError(f"request {waiting[0].spec.rid} does not fit the HBM budget")
+                    r = waiting[0]
+                    nb = _ws_bytes(r.grid or _abi.make_grid(**r.spec.grid_kwargs()),
+                                   r.spec.rec_xyz.shape[0], r.spec.kind, self.grad_cap)
+                    raise RuntimeError(
+                        f"request {r.spec.rid} ({r.spec.kind}, {r.spec.ndim}D n={r.spec.n}, "
+                        f"nt={r.spec.nt}, shot {r.next_shot} of {r.spec.nshots}) does not fit the "
+                        f"HBM budget: workspace {nb} B, arena {self.arena.size} B with "
+                        f"{self.arena.used} B in use (largest free "
+                        f"{max((sz for _, sz in self.arena.free), default=0)} B), I/O "
+                        f"{self.io_used} of {self.io_limit} B")
         t_end = time.perf_counter() - t0
         lat = np.array([r.t_done - arrival[r.spec.rid] for r in reqs])
         return {
