@@ -151,6 +151,8 @@ def parse():
                     help="serving: comma-separated 2D grid classes (overrides the mix; '' for none)")
     ap.add_argument("--classes-3d", default=None,
                     help="serving: comma-separated 3D grid classes (overrides the mix; '' for none)")
+    ap.add_argument("--frac-gradient", type=float, default=0.3,
+                    help="serving: fraction of gradient requests (the rest are forward solves)")
     ap.add_argument("--no-graphs", action="store_true", help="serving: direct launches, no hipGraphs")
     ap.add_argument("--max-slots", type=int, default=32, help="serving: shots per engine")
     ap.add_argument("--max-chunk", type=int, default=64, help="serving: ticks per graph chunk")
@@ -299,6 +301,7 @@ def serving_run(args, nreq, full_mix=None):
         sel = getattr(args, "classes_" + dim)
         if sel is not None:
             kw["classes_" + dim] = tuple(int(c) for c in sel.split(",") if c)
+    kw["frac_gradient"] = args.frac_gradient
     # calibration: the one-at-a-time service time of the stream's first requests
     # sets the arrival rate (a request's content does not depend on the rate:
     # the generator draws the same numbers for it at any rate, only the
@@ -331,6 +334,7 @@ def serving_run(args, nreq, full_mix=None):
         "requests": len(specs),
         "shots": served["shot_solves"],
         "grid_classes": {"2d": list(kw["classes_2d"]), "3d": list(kw["classes_3d"])},
+        "frac_gradient": kw["frac_gradient"],
         "nt_range": list(kw["nt_range"]),
         "arrival_rate_per_s": rate,
         "load": args.load,
@@ -358,6 +362,9 @@ def serving_run(args, nreq, full_mix=None):
     out["one_at_a_time"] = {k: base[k] for k in ("solves_per_s", "requests_per_s", "p50_s", "p99_s",
                                                  "makespan_s")}
     out["speedup_solves_per_s"] = served["solves_per_s"] / base["solves_per_s"]
+    # the load as measured: arrivals per second over the requests per second one
+    # at a time completes on this stream (above 1: the baseline is saturated)
+    out["arrival_over_one_at_a_time_rate"] = rate / base["requests_per_s"]
     out["identical_results"] = f"{same}/{len(specs)}"
     return out
 
@@ -379,10 +386,12 @@ def serving_bench(args):
         "data": "synthetic (seeded request stream, phantoms and geometries)",
         "config": {"workload": f"serving: {WORKLOADS['serving']}",
                    **{k: res[k] for k in ("requests", "shots", "grid_classes", "nt_range",
-                                          "arrival_rate_per_s", "load", "max_slots", "max_chunk")}},
+                                          "arrival_rate_per_s", "load", "max_slots", "max_chunk",
+                                          "frac_gradient")}},
         **{k: v for k, v in res.items() if k in ("p50_s", "p99_s", "requests_per_s", "peak_hbm_gb",
                                                   "one_at_a_time", "speedup_solves_per_s",
-                                                  "identical_results")},
+                                                  "identical_results",
+                                                  "arrival_over_one_at_a_time_rate")},
         "roofline": None,
         "cpu_baseline": None,
     }

@@ -147,7 +147,12 @@ class Server:
 
     def __init__(self, hbm_budget: Optional[int] = None, max_slots: int = 32, max_chunk: int = 64,
                  use_graphs: bool = True, grad_cap: int = 24 << 30, max_inflight: int = 3,
-                 max_receivers: int = 1024, device=None):
+                 max_receivers: int = 1024, io_limit: Optional[int] = None, device=None):
+        """hbm_budget: bytes of the workspace arena (default 80 % of free HBM).
+        io_limit: bytes of the I/O buffers (models, wavelets, observed data,
+        traces, gradients), which sit outside hbm_budget; default max(1 GiB,
+        5 % of free HBM).  The limit is soft: when no shot runs anywhere, the
+        oldest waiting request may take one shot beyond it."""
         self.device = torch.device(device or "cuda")
         free, _ = torch.cuda.mem_get_info(self.device)
         self.budget = int(hbm_budget if hbm_budget is not None else 0.80 * free)
@@ -162,9 +167,11 @@ class Server:
         # workspaces come from the arena; models, traces and gradients (small
         # next to the workspaces) are ordinary tensors counted in io_used
         self.arena = _Arena(self.budget, self.device)
-        self.io_limit = max(1 << 30, int(0.05 * free))
+        self.io_limit = int(io_limit) if io_limit is not None else max(1 << 30, int(0.05 * free))
         self.io_used = 0
+        self.io_peak = 0
         self.peak_used = 0
+        self.max_attached = 0
         self.buckets: Dict[tuple, _Bucket] = {}
         self.upload = torch.cuda.Stream()
 
@@ -231,7 +238,9 @@ class Server:
         req.shots.append(shot)
         req.next_shot += 1
         self.io_used += io
+        self.io_peak = max(self.io_peak, self.io_used)
         self.peak_used = max(self.peak_used, self.arena.used + self.io_used)
+        self.max_attached = max(self.max_attached, sum(len(b.owner) for b in self.buckets.values()))
         return True
 
     def _shot_done(self, sh: _Shot):
@@ -375,6 +384,8 @@ class Server:
             "p99_s": float(np.percentile(lat, 99)),
             "ticks": ticks,
             "peak_hbm_gb": self.peak_used / 2**30,
+            "io_peak_bytes": self.io_peak,
+            "max_attached_shots": self.max_attached,
             "workspace_peak_bytes": self.arena.peak,
             "workspace_budget_bytes": self.arena.size,
         }

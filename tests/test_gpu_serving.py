@@ -196,6 +196,36 @@ def test_server_results_equal_solo_solves(realtime):
     assert out["p99_s"] >= out["p50_s"] > 0
 
 
+def test_server_io_limit_overrun_path():
+    """An I/O limit too small for any shot: a shot is admitted only when no
+    shot runs anywhere (one beyond the limit at a time), every request still
+    completes, and each result equals its one-at-a-time solve."""
+    specs = _small_mix(8, seed=21)
+    srv = Server(max_slots=6, max_chunk=16, use_graphs=True, io_limit=1)
+    try:
+        out = srv.run(specs, realtime=False)
+    finally:
+        srv.close()
+    assert len(out["requests"]) == len(specs)
+    assert out["max_attached_shots"] == 1     # one shot beyond the limit at a time
+
+    def shot_io(sp):
+        grad = sp.kind == "gradient"
+        return sp.rec_xyz.shape[0] * sp.nt * 4 * (2 if grad else 1) + (sp.vp.nbytes if grad else 0)
+
+    # the overrun: staged inputs, plus the outputs of the request being admitted
+    # and of the one before it, whose shots stay counted until it completes
+    staged = sum(r.spec.vp.nbytes + r.spec.wavelet.nbytes for r in out["requests"])
+    per_req = sorted((shot_io(r.spec) * r.spec.nshots for r in out["requests"]), reverse=True)
+    assert 1 < out["io_peak_bytes"] <= 1 + staged + per_req[0] + per_req[1]
+    for r in out["requests"]:
+        solo = solve_one(r.spec)
+        for a, b in zip(r.result["traces"], solo["traces"]):
+            assert torch.equal(a, b)
+        if r.spec.kind == "gradient":
+            assert torch.equal(r.result["dvp"], solo["dvp"])
+
+
 def test_served_requests_match_the_oracle():
     """Sampled requests of a served mix (one forward, one gradient, each of
     several shots) against the FP64 oracle."""
