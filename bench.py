@@ -200,14 +200,22 @@ def cpu_baseline(w, vp_model, obs_np, seconds):
     per_step = max(run(12) - run(4), 1e-9) / 8
     nt_s = int(max(8, min(w.nt, seconds / per_step)))
     el = run(nt_s)
+    cores = oracle.num_threads()
+    # one thread: the per-step cost from 3 and 1 steps (about the same set-up)
+    oracle.set_num_threads(1)
+    try:
+        per_step_1 = max(run(3) - run(1), 1e-9) / 2
+    finally:
+        oracle.set_num_threads(cores)
     return {
         "value": 2.0 * npad * (nt_s - 1) / el,
         "unit": "grid-point updates/s (fwd+adj)",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{w.name} grid ({'x'.join(map(str, w.padded_shape))} padded), first {nt_s} of "
                   f"{w.nt} steps, one shot gradient (FP64 C, OpenMP), {el:.1f} s",
         "cpu_model": cpu_model(),
+        "one_thread_value": 2.0 * npad / per_step_1,
     }
 
 

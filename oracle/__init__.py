@@ -107,6 +107,7 @@ def lib():
         L.oracle_gradient.argtypes = [gp, dp, ctypes.c_int, dp, dp, ctypes.c_int, dp, dp,
                                       dp, dp, dp, ctypes.c_int]
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
         L.oracle_fd1_weights.argtypes = [ctypes.c_int, dp]
         L.oracle_taps_per_point.argtypes = [gp]
         L.oracle_lowpass.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
@@ -144,6 +145,11 @@ def _check(rc: int, what: str):
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the following oracle calls (timing only; results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def fd_weights(space_order: int) -> np.ndarray:

@@ -50,6 +50,16 @@ int oracle_num_threads(void)
 #endif
 }
 
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Central second-derivative weights: the unique weights of the (2r+1)-point
  * symmetric stencil exact on polynomials of degree <= 2r+1 (Taylor moment
  * conditions); written as the exact rationals. */

@@ -137,7 +137,6 @@ int oracle_gradient(const oracle_grid_t *g, const double *vp,
                     int nrec, const double *rec_xyz, const double *observed,
                     double *traces_out, double *misfit, double *dvp, int seg);
 
-/* Number of OpenMP threads the oracle will use. */
 /* Centred first-derivative weights d[1..r] of the (2r+1)-point antisymmetric
  * stencil exact on polynomials of degree <= 2r: du/dx ~ sum_j d_j (u_{+j} - u_{-j}) / dx. */
 int oracle_fd1_weights(int space_order, double *d);
@@ -223,7 +222,10 @@ int oracle_gradient_medium(const oracle_grid_t *g, const double *vp, const doubl
  * scaled so that sum_k h_k = 1.  Returns the number of taps K, or -1. */
 int oracle_lowpass(const double *in, double *out, int count, int nt, double dt, double f_max);
 
+/* Number of OpenMP threads the oracle will use, and a way to change it (for
+ * timing; the results do not depend on it). */
 int oracle_num_threads(void);
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }
