@@ -27,7 +27,7 @@ Extra keys: the config-2 2D shot gradient and forward (same steps), and a
 bounded serving run over the full six-class request mix (2D 256^2, 512^2,
 1024^2 and 3D 128^3, 192^3, 256^3, nt 500-3000; --leg-requests requests):
 served shot solves/s and p50/p99 against one request at a time.
---fourth-order, --sinc and --medium add those solver variants.
+--fourth-order, --sinc, --medium and --pml add those solver variants.
 """
 import argparse
 import json
@@ -53,12 +53,12 @@ MEASURED_TRAFFIC = {
                 "fetch_kib": 11025.57, "write_kib": 7153.94,
                 "copy_fetch_kib": 524308.44, "copy_write_kib": 1048576.0},
     # config 4 checkpoints: the fused adjoint (mode 0), counters from a checkpointed run
-    "config4": {"sha256": "590d35b8673a84224404ae02760b45c062b8cd8d5b38862c9763b4ce3bb42c1d",
-                "fetch_kib": 477361.18, "write_kib": 249640.00,
-                "copy_fetch_kib": 524309.56, "copy_write_kib": 1048576.0},
-    "config4_forward": {"sha256": "590d35b8673a84224404ae02760b45c062b8cd8d5b38862c9763b4ce3bb42c1d",
-                        "fetch_kib": 240988.94, "write_kib": 124846.85,
-                        "copy_fetch_kib": 524309.56, "copy_write_kib": 1048576.0},
+    "config4": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
+                "fetch_kib": 477528.27, "write_kib": 249640.00,
+                "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
+    "config4_forward": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
+                        "fetch_kib": 240887.80, "write_kib": 124846.85,
+                        "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
 }
 
 
@@ -137,7 +137,10 @@ def parse():
     ap.add_argument("--sinc", action="store_true",
                     help="also time the shot gradient with windowed-sinc sources and receivers")
     ap.add_argument("--medium", action="store_true",
-                    help="also time forward solves in a heterogeneous medium (density, attenuation)")
+                    help="also time forward solves in a heterogeneous medium (density, attenuation) "
+                         "and the medium shot gradient on the 2D breast grid")
+    ap.add_argument("--pml", action="store_true",
+                    help="also time the forward solve with the perfectly matched layer")
     ap.add_argument("--nt", type=int, default=0,
                     help="override the number of time steps (profiling runs only)")
     ap.add_argument("--requests", type=int, default=60, help="serving: number of requests")
@@ -622,7 +625,49 @@ def variants(m, args, dev):
                   file=sys.stderr, flush=True)
             del rho_t, al_t
         del mws
+        # the medium shot gradient keeps every step's imaging factor, so it is
+        # timed on the 2D breast grid (1104^2, 2500 steps: 12.5 GB), at the
+        # 1500 m/s model against data from the phantom in its medium, y = 0
+        w2 = W.config2()
+        vt2 = torch.from_numpy(w2.vp).to(dev)
+        v02 = torch.full_like(vt2, 1500.0)
+        wav2 = torch.from_numpy(w2.wavelet).to(dev)
+        rho, alpha0 = W.medium(w2.vp, w2.spacing, 11, att_power=0)
+        rho_t, al_t = torch.from_numpy(rho).to(dev), torch.from_numpy(alpha0).to(dev)
+        plan2 = S.Plan.from_workload(w2)
+        mws2 = plan2.workspace(S.STRIDE_MODE_FORWARD_MEDIUM, device=dev)
+        obs2 = plan2.forward_medium(vt2, wav2, rho=rho_t, alpha0=al_t, att_power=0, ws=mws2)
+        del mws2
+        gws2 = plan2.workspace(S.STRIDE_MODE_GRADIENT_MEDIUM, device=dev)
+
+        def grad(_):
+            plan2.gradient_medium(v02, wav2, obs2, rho=rho_t, alpha0=al_t, att_power=0, ws=gws2)
+        grad(0)
+        el, _ = _timed(grad, steps)
+        npad2 = w2.padded_points
+        med["gradient_config2_y0"] = {"ms_per_gradient": 1e3 * el / steps,
+                                      "updates_per_s": 2.0 * npad2 * (w2.nt - 1) * steps / el,
+                                      "workspace_gb": gws2.numel() / 1e9}
+        print(f"[bench] medium gradient (config2, y=0): {1e3 * el / steps:.2f} ms/gradient",
+              file=sys.stderr, flush=True)
+        del gws2, plan2, rho_t, al_t
         out["medium"] = med
+
+    if args.pml:
+        # forward solves with the perfectly matched layer in the padded cells
+        plan_p = S.Plan.from_workload(w, boundary=1)
+        fws_p = plan_p.workspace(S.STRIDE_MODE_FORWARD, device=dev)
+        plan_p.forward(vp_m, wav, traces=traces, ws=fws_p)
+        el, (p_ms, p_n, p_l, _, _, _) = _timed(
+            lambda _: plan_p.forward(vp_m, wav, traces=traces, ws=fws_p), steps)
+        p_step = p_ms * 1e-3 / max(p_n, 1)
+        out["pml"] = {"boundary": "perfectly matched layer (leapfrog launch + layer correction)",
+                      "updates_per_s": npad * (w.nt - 1) * steps / el,
+                      "ms_per_solve": 1e3 * el / steps, "us_per_step": p_step * 1e6,
+                      "launches_per_step": p_l / max(p_n, 1)}
+        print(f"[bench] pml forward: {out['pml']['ms_per_solve']:.2f} ms/solve, "
+              f"{out['pml']['us_per_step']:.2f} us/step", file=sys.stderr, flush=True)
+        del fws_p, plan_p
     return out
 
 
