@@ -544,106 +544,158 @@ void launch_finite_scan(const double* p, long long n, unsigned* flag, unsigned b
                        0, s, p, n, flag, bit);
 }
 
-// Perfectly matched layer: one thread per point of the padded layer, the
-// layer enumerated as three slabs of the 3D-ised grid (axis 0 of a 2D grid is
-// axis 1 here): planes of axis 0 in its layer; then, in the physical planes,
-// rows of axis 1 in its layer; then, in the physical rows, the points of
-// axis 2 in its layer.  Per axis a whose layer holds the point (zeta_a > 0):
+// Perfectly matched layer.  Per axis a whose layer holds a point (zeta_a > 0):
 //   chi_a = E chi_a + (1 - E) (D2_a u - D_a psi_a),  psi_a' = E psi_a + (1 - E) D_a u,
-// and u^{n+1} += k sum_a (-D_a psi_a - chi_a).  Neighbours beyond the padded
-// array read 0.
-__global__ __launch_bounds__(256) void pml_correct_kernel(Dims d, StencilCoef cf, PmlParams pp,
-                                                          long long count, int R)
+// and u^{n+1} += k sum_a (-D_a psi_a - chi_a), the axes taken in order 0, 1, 2.
+// Neighbours beyond the padded array read 0.  One thread per point of the
+// layer, over three launches of 64-lane rows (no index division): the planes
+// of axis 0 in its layer (3D), then within the physical planes the rows of
+// axis 1 in its layer, then within the physical rows the points of axis 2 in
+// its layer.  Blocks are 4 rows; in the first launch the rows of a block are 4
+// consecutive planes and consecutive blocks continue along axis 0, so the 2R
+// axis-0 neighbours a point reads come from the same or a neighbouring block
+// (L2) rather than from a plane's distance away in the launch.
+struct PmlGeom {
+    int nn[3];        // 3D-ised padded extents (axis 0 of a 2D grid has extent 1)
+    int st[3];        // strides in floats (pitched rows)
+    int pl[3];        // physical extents
+    int b;            // layer width of axes 1 and 2 (and of axis 0 in 3D)
+    int b0;           // layer width of axis 0 (0 in 2D)
+    int three;
+};
+
+template <int R>
+__device__ __forceinline__ void pml_axis_term(const StencilCoef& cf, const PmlParams& pp,
+                                              const PmlGeom& g, long long p, const int* ii, int ax,
+                                              float& corr)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count)
+    const int a = g.three ? ax : ax - 1;        // axis of the solver's Dims / coefficients
+    const int i = ii[ax];
+    const int b = ax == 0 ? g.b0 : g.b;
+    const int hi = b + g.pl[ax] - 1;
+    const int depth = i < b ? b - i : (i > hi ? i - hi : 0);
+    if (depth == 0)
         return;
-    const bool three = d.nd == 3;
-    // 3D-ised extents, physical extents and layer widths
-    const int N0 = three ? d.n[0] : 1, N1 = three ? d.n[1] : d.n[0], N2 = three ? d.n[2] : d.n[1];
-    const int p0 = three ? d.phys[0] : 1, p1 = three ? d.phys[1] : d.phys[0];
-    const int p2 = three ? d.phys[2] : d.phys[1];
-    const int b0 = three ? d.nb : 0, b = d.nb;
-    const long long segA = 2LL * b0 * N1 * N2;
-    const long long segB = (long long)p0 * 2 * b * N2;
-    int i0, i1, i2;
-    long long r = t;
-    if (r < segA) {
-        const long long plane = (long long)N1 * N2;
-        const int zz = (int)(r / plane);
-        i0 = zz < b0 ? zz : b0 + p0 + (zz - b0);
-        r -= (long long)zz * plane;
-        i1 = (int)(r / N2);
-        i2 = (int)(r - (long long)i1 * N2);
-    } else if ((r -= segA) < segB) {
-        const long long per = 2LL * b * N2;
-        const int zi = (int)(r / per);
-        i0 = b0 + zi;
-        r -= (long long)zi * per;
-        const int yy = (int)(r / N2);
-        i1 = yy < b ? yy : b + p1 + (yy - b);
-        i2 = (int)(r - (long long)yy * N2);
-    } else {
-        r -= segB;
-        const long long per = (long long)p1 * 2 * b;
-        const int zi = (int)(r / per);
-        i0 = b0 + zi;
-        r -= (long long)zi * per;
-        const int yi = (int)(r / (2 * b));
-        i1 = b + yi;
-        const int xx = (int)(r - (long long)yi * 2 * b);
-        i2 = xx < b ? xx : b + p2 + (xx - b);
+    const float frac = (float)depth / (float)b;
+    const float zeta = pp.zmax[a] * frac * frac;
+    const float E = __expf(-zeta * pp.dt);   // hardware exp2: a few ulp, far inside the tolerance
+    const float* u = pp.u + p;
+    const float* psi = pp.psi[a] + p;
+    const int s = g.st[ax];
+    float d2 = pp.c0[a] * u[0], d1u = 0.f, d1p = 0.f;
+#pragma unroll
+    for (int j = 1; j <= R; ++j) {
+        const bool in_p = i + j < g.nn[ax], in_m = i - j >= 0;
+        const float up = in_p ? u[j * s] : 0.f;
+        const float um = in_m ? u[-j * s] : 0.f;
+        const float qp = in_p ? psi[j * s] : 0.f;
+        const float qm = in_m ? psi[-j * s] : 0.f;
+        d2 = fmaf(cf.c[a][j], up + um, d2);
+        d1u = fmaf(cf.d[a][j], up - um, d1u);
+        d1p = fmaf(cf.d[a][j], qp - qm, d1p);
     }
+    const float chi = fmaf(E, pp.chi[a][p], (1.f - E) * (d2 - d1p));
+    pp.chi[a][p] = chi;
+    pp.psin[a][p] = fmaf(E, psi[0], (1.f - E) * d1u);
+    corr -= d1p + chi;
+}
+
+template <int R>
+__device__ __forceinline__ void pml_point(const StencilCoef& cf, const PmlParams& pp, const PmlGeom& g,
+                                          int i0, int i1, int i2)
+{
     const int ii[3] = {i0, i1, i2};
-    const int nn[3] = {N0, N1, N2};
-    const long long st[3] = {three ? d.st[0] : 0, three ? d.st[1] : d.st[0], 1};
-    const int pl[3] = {p0, p1, p2};
-    const long long p = (long long)i0 * st[0] + (long long)i1 * st[1] + i2;
-    const float inv_b = b > 0 ? 1.f / (float)b : 0.f;
+    const long long p = (long long)i0 * g.st[0] + (long long)i1 * g.st[1] + i2;
     float corr = 0.f;
-    for (int ax = three ? 0 : 1; ax < 3; ++ax) {
-        const int a = three ? ax : ax - 1;          // axis of the solver's Dims / coefficients
-        const int i = ii[ax];
-        const int hi = b + pl[ax] - 1;
-        const int depth = i < b ? b - i : (i > hi ? i - hi : 0);
-        if (depth == 0)
-            continue;
-        const float frac = (float)depth * inv_b;
-        const float zeta = pp.zmax[a] * frac * frac;
-        const float E = expf(-zeta * pp.dt);
-        const float* u = pp.u;
-        const float* psi = pp.psi[a];
-        float d2 = pp.c0[a] * u[p], d1u = 0.f, d1p = 0.f;
-        for (int j = 1; j <= R; ++j) {
-            const bool in_p = i + j < nn[ax], in_m = i - j >= 0;
-            const float up = in_p ? u[p + j * st[ax]] : 0.f;
-            const float um = in_m ? u[p - j * st[ax]] : 0.f;
-            const float qp = in_p ? psi[p + j * st[ax]] : 0.f;
-            const float qm = in_m ? psi[p - j * st[ax]] : 0.f;
-            d2 = fmaf(cf.c[a][j], up + um, d2);
-            d1u = fmaf(cf.d[a][j], up - um, d1u);
-            d1p = fmaf(cf.d[a][j], qp - qm, d1p);
-        }
-        const float chi = fmaf(E, pp.chi[a][p], (1.f - E) * (d2 - d1p));
-        pp.chi[a][p] = chi;
-        pp.psin[a][p] = fmaf(E, psi[p], (1.f - E) * d1u);
-        corr -= d1p + chi;
-    }
+    for (int ax = g.three ? 0 : 1; ax < 3; ++ax)
+        pml_axis_term<R>(cf, pp, g, p, ii, ax, corr);
     pp.un[p] = fmaf(pp.k[p], corr, pp.un[p]);
+}
+
+// Planes of axis 0 in its layer: grid (2 ceil(b0/4), column chunks, rows);
+// blockIdx.x = side x plane group (fastest), wave = plane within the group.
+template <int R>
+__global__ __launch_bounds__(256) void pml_layer0_kernel(Dims d, StencilCoef cf, PmlParams pp,
+                                                         PmlGeom g)
+{
+    const int groups = (g.b0 + 3) / 4;
+    const int side = (int)blockIdx.x >= groups;
+    const int zl = ((int)blockIdx.x - side * groups) * 4 + ((int)threadIdx.x >> 6);
+    const int i2 = (int)blockIdx.y * 64 + ((int)threadIdx.x & 63);
+    if (zl >= g.b0 || i2 >= g.nn[2])
+        return;
+    const int i0 = side == 0 ? zl : g.b0 + g.pl[0] + zl;
+    pml_point<R>(cf, pp, g, i0, (int)blockIdx.z, i2);
+}
+
+// Rows of axis 1 in its layer, in the physical planes: grid (column chunks,
+// ceil(2b/4), physical planes).
+template <int R>
+__global__ __launch_bounds__(256) void pml_layer1_kernel(Dims d, StencilCoef cf, PmlParams pp,
+                                                         PmlGeom g)
+{
+    const int rl = (int)blockIdx.y * 4 + ((int)threadIdx.x >> 6);
+    const int i2 = (int)blockIdx.x * 64 + ((int)threadIdx.x & 63);
+    if (rl >= 2 * g.b || i2 >= g.nn[2])
+        return;
+    const int i1 = rl < g.b ? rl : g.b + g.pl[1] + (rl - g.b);
+    pml_point<R>(cf, pp, g, g.b0 + (int)blockIdx.z, i1, i2);
+}
+
+// Points of axis 2 in its layer, in the physical rows of the physical planes:
+// one 64-lane row per (plane, row) with lanes 0 .. 2b-1 on the layer's points
+// (b <= 32; wider layers take several lane groups); grid (lane groups x
+// ceil(rows/4), physical planes).
+template <int R>
+__global__ __launch_bounds__(256) void pml_layer2_kernel(Dims d, StencilCoef cf, PmlParams pp,
+                                                         PmlGeom g)
+{
+    const int lanes = (2 * g.b + 63) / 64;      // 64-lane groups per row
+    const int rg = (int)blockIdx.x / lanes;
+    const int lg = (int)blockIdx.x - rg * lanes;
+    const int yi = rg * 4 + ((int)threadIdx.x >> 6);
+    const int xl = lg * 64 + ((int)threadIdx.x & 63);
+    if (yi >= g.pl[1] || xl >= 2 * g.b)
+        return;
+    const int i2 = xl < g.b ? xl : g.b + g.pl[2] + (xl - g.b);
+    pml_point<R>(cf, pp, g, g.b0 + (int)blockIdx.y, g.b + yi, i2);
 }
 
 void launch_pml_correction(const Dims& d, int R, const StencilCoef& cf, const PmlParams& pp,
                            hipStream_t s)
 {
     const bool three = d.nd == 3;
-    const long long N1 = three ? d.n[1] : d.n[0], N2 = three ? d.n[2] : d.n[1];
-    const long long p0 = three ? d.phys[0] : 1, p1 = three ? d.phys[1] : d.phys[0];
-    const long long b0 = three ? d.nb : 0;
-    const long long count = 2 * b0 * N1 * N2 + p0 * 2 * d.nb * N2 + p0 * p1 * 2 * d.nb;
-    if (count <= 0)
+    PmlGeom g{};
+    g.three = three ? 1 : 0;
+    g.nn[0] = three ? d.n[0] : 1;
+    g.nn[1] = three ? d.n[1] : d.n[0];
+    g.nn[2] = three ? d.n[2] : d.n[1];
+    g.st[0] = three ? (int)d.st[0] : 0;
+    g.st[1] = three ? (int)d.st[1] : (int)d.st[0];
+    g.st[2] = 1;
+    g.pl[0] = three ? d.phys[0] : 1;
+    g.pl[1] = three ? d.phys[1] : d.phys[0];
+    g.pl[2] = three ? d.phys[2] : d.phys[1];
+    g.b = d.nb;
+    g.b0 = three ? d.nb : 0;
+    if (g.b <= 0)
         return;
-    hipLaunchKernelGGL(pml_correct_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, d,
-                       cf, pp, count, R);
+    const unsigned cch = (unsigned)((g.nn[2] + 63) / 64);
+    const unsigned lanes = (unsigned)((2 * g.b + 63) / 64);
+    const dim3 g0(2 * ((g.b0 + 3) / 4), cch, g.nn[1]);
+    const dim3 g1(cch, (2 * g.b + 3) / 4, g.pl[0]);
+    const dim3 g2(lanes * ((g.pl[1] + 3) / 4), g.pl[0]);
+    if (R == 4) {
+        if (g.b0 > 0)
+            hipLaunchKernelGGL(pml_layer0_kernel<4>, g0, dim3(256), 0, s, d, cf, pp, g);
+        hipLaunchKernelGGL(pml_layer1_kernel<4>, g1, dim3(256), 0, s, d, cf, pp, g);
+        hipLaunchKernelGGL(pml_layer2_kernel<4>, g2, dim3(256), 0, s, d, cf, pp, g);
+    } else {
+        if (g.b0 > 0)
+            hipLaunchKernelGGL(pml_layer0_kernel<5>, g0, dim3(256), 0, s, d, cf, pp, g);
+        hipLaunchKernelGGL(pml_layer1_kernel<5>, g1, dim3(256), 0, s, d, cf, pp, g);
+        hipLaunchKernelGGL(pml_layer2_kernel<5>, g2, dim3(256), 0, s, d, cf, pp, g);
+    }
 }
 
 // Padded coordinates of linear index t over the padded grid (no pitch) and the
