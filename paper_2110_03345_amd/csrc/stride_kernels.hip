@@ -725,9 +725,11 @@ __device__ __forceinline__ float sponge_eta(const Dims& d, const SpongeCoef& sp,
     return eta;
 }
 
-// One thread per padded point; neighbours beyond the padded array read 0.
+// One thread per padded point; neighbours beyond the padded array read 0.  The
+// radius is a template argument, so the loads of all 2R taps issue together.
+template <int R>
 __global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
-                                                             MediumAdjParams mp, int R)
+                                                             MediumAdjParams mp)
 {
     const long long count = (long long)d.n[0] * d.n[1] * (d.nd == 3 ? d.n[2] : 1);
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -747,6 +749,7 @@ __global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef
     for (int a = 0; a < d.nd; ++a) {
         const long long st = d.st[a];
         float sy = 0.f, sz = 0.f;
+#pragma unroll
         for (int j = 1; j <= R; ++j) {
             const bool in_p = c[a] + j < d.n[a], in_m = c[a] - j >= 0;
             const long long qp = p + j * st, qm = p - j * st;
@@ -771,8 +774,11 @@ void launch_medium_adjoint(const Dims& d, int R, const StencilCoef& cf, const Sp
                            const MediumAdjParams& mp, hipStream_t s)
 {
     const long long count = (long long)d.n[0] * d.n[1] * (d.nd == 3 ? d.n[2] : 1);
-    hipLaunchKernelGGL(medium_adjoint_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s,
-                       d, cf, sp, mp, R);
+    const dim3 g((unsigned)((count + 255) / 256));
+    if (R == 4)
+        hipLaunchKernelGGL(medium_adjoint_kernel<4>, g, dim3(256), 0, s, d, cf, sp, mp);
+    else
+        hipLaunchKernelGGL(medium_adjoint_kernel<5>, g, dim3(256), 0, s, d, cf, sp, mp);
 }
 
 // One block per step-kernel block of the table's launch shape; each thread
