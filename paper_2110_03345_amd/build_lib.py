@@ -22,6 +22,8 @@ LIB = os.path.join(HERE, "libstride_hip.so")
 SOURCES = ["csrc/step3d_adj.hip", "csrc/step3d_fwd.hip", "csrc/step2d.hip", "csrc/stride_kernels.hip",
            "csrc/stride_api.cpp", "csrc/stride_engine.cpp", "csrc/revolve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# roctx trace ranges around the entry points (recorded only under a tool)
+LINK_LIBS = ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 ARCH = os.environ.get("STRIDE_ARCH", "gfx950")
 
 # Packed-FP32 instructions stay disabled: the kernels are plain scalar FP32.
@@ -83,7 +85,7 @@ def build(verbose: bool = False) -> str:
     with open(RESOURCES, "w") as f:
         json.dump(resources, f, indent=0, sort_keys=True)
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + LINK_LIBS + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -7,6 +7,8 @@
 #include <unordered_map>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/stride_hip.h"
 #include "common.h"
 #include "revolve.h"
@@ -40,6 +42,15 @@ struct stride_plan {
 };
 
 namespace stride {
+
+// Host-side trace range (rocprofv3 --marker-trace shows it around the work the
+// call enqueues); nothing is recorded without a tool attached.
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
+};
 
 // Records the calling thread's last error message and returns `code`.
 int fail(int code, const char* fmt, ...);

@@ -1321,6 +1321,7 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
         return rc;
     float* tr = traces ? traces : W.traces;
     launch_prep_k(P.dims, vp, P.g.dt, W.k, s);
+    TraceRange range_("forward sweep");
     Runner run(P, W, s, wavelet);
     const float* last;
     int tid = g_timer.begin(s);
@@ -1362,6 +1363,7 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     launch_fill(W.G, P.dims.total, 0.f, s);
     launch_fill(W.w[0], P.dims.total, 0.f, s);
     launch_fill(W.w[1], P.dims.total, 0.f, s);
+    TraceRange range_("adjoint sweep");
     int tid = g_timer.begin(s);
     if (run.vpath)
         run.backward_v(grad_traces, dwavelet);
@@ -1683,6 +1685,7 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
 int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float* wavelet,
                         float* traces, void* ws, size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_plan_forward");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1692,6 +1695,7 @@ int stride_plan_forward(const stride_plan_t* plan, const float* vp, const float*
 int stride_plan_forward_static(const stride_plan_t* plan, const float* vp, const float* wavelet,
                                float* traces, void* stream)
 {
+    TraceRange range_("stride_plan_forward_static");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1718,6 +1722,7 @@ int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const
                                const float* alpha0, int32_t att_power, const float* wavelet,
                                float* traces, void* ws, size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_plan_forward_medium");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1730,6 +1735,7 @@ int stride_plan_gradient_medium(const stride_plan_t* plan, const float* vp, cons
                                 const float* observed, float* traces, double* misfit, float* dvp,
                                 void* ws, size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_plan_gradient_medium");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1775,6 +1781,7 @@ int stride_lowpass(const float* in, float* out, int32_t count, int32_t nt, doubl
 int stride_forward_save(const stride_plan_t* plan, const float* vp, const float* wavelet,
                         float* traces, void* ws, size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_forward_save");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1791,6 +1798,7 @@ int stride_backward(const stride_plan_t* plan, const float* vp, const float* wav
                     const float* grad_traces, float* dvp, float* dwavelet, void* ws,
                     size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_backward");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1807,6 +1815,7 @@ int stride_plan_gradient(const stride_plan_t* plan, const float* vp, const float
                          const float* observed, float* traces, double* misfit, float* dvp,
                          void* ws, size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_plan_gradient");
     g_err.clear();
     if (!plan)
         return fail(STRIDE_E_INVALID_ARG, "plan is NULL");
@@ -1860,6 +1869,7 @@ int stride_forward(const stride_grid_t* grid, const float* vp, const float* wave
                    const double* src_xyz, int32_t nrec, const double* rec_xyz, float* traces,
                    void* ws, size_t ws_bytes, void* stream)
 {
+    TraceRange range_("stride_forward");
     stride_plan_t* plan = nullptr;
     int rc = stride_plan_create(grid, nsrc, src_xyz, nrec, rec_xyz, &plan);
     if (rc)
@@ -1879,6 +1889,7 @@ int stride_gradient(const stride_grid_t* grid, const float* vp, const float* wav
                     const float* observed, double* misfit, float* dvp, void* ws, size_t ws_bytes,
                     void* stream)
 {
+    TraceRange range_("stride_gradient");
     stride_plan_t* plan = nullptr;
     int rc = stride_plan_create(grid, nsrc, src_xyz, nrec, rec_xyz, &plan);
     if (rc)

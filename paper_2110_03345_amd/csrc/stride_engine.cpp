@@ -432,6 +432,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
                          float* traces, double* misfit, float* dvp, void* ws, size_t ws_bytes,
                          void* stream, int32_t* slot)
 {
+    TraceRange range_("stride_engine_attach");
     if (!E || !plan || !slot)
         return fail(STRIDE_E_INVALID_ARG, "NULL engine, plan or slot");
     if (!same_layout(E->dims, plan->dims) || E->R != plan->R || E->ntap != plan->ntap ||
@@ -512,6 +513,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
 int stride_engine_run(stride_engine_t* E, int32_t max_ticks, void* stream, int32_t* ticks_run,
                       int32_t* finished)
 {
+    TraceRange range_("stride_engine_run");
     if (!E || !ticks_run)
         return fail(STRIDE_E_INVALID_ARG, "NULL engine or ticks_run");
     hipStream_t s = (hipStream_t)stream;

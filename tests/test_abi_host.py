@@ -30,6 +30,17 @@ def test_library_exports_every_header_function():
     assert set(names) == set(_abi.EXPORTS)
 
 
+def test_library_marks_its_entry_points_with_trace_ranges():
+    """The solves push and pop roctx ranges (seen by rocprofv3 --marker-trace)."""
+    import shutil
+    import subprocess
+    if not shutil.which("nm"):
+        pytest.skip("no nm")
+    out = subprocess.run(["nm", "-D", "--undefined-only", S.lib()._name], capture_output=True,
+                         text=True, check=True).stdout
+    assert "roctxRangePushA" in out and "roctxRangePop" in out
+
+
 def _grid(**kw):
     base = dict(shape=(40, 50), spacing=0.2e-3, space_order=8, nb=6, vref=1500.0,
                 dt=0.4 * 0.2e-3 / 1500, nt=20)

@@ -62,7 +62,9 @@ def test_host_library_under_sanitizers():
         assert all(p.wait() == 0 for p in procs)
         lib = os.path.join(tmp, "libstride_san.so")
         subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950",
-                        "-Xarch_host", "-fsanitize=" + SAN] + objs + kernels + ["-o", lib],
+                        "-Xarch_host", "-fsanitize=" + SAN] + objs + kernels +
+                       ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
+                        "-o", lib],
                        check=True, stderr=subprocess.DEVNULL)
         env = dict(os.environ, LD_PRELOAD=runtime,
                    ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
