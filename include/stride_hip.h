@@ -146,7 +146,9 @@ int stride_plan_padded_shape(const stride_plan_t* plan, int64_t out[3]);
  * size that keeps every state (no recomputation).  The snapshot count a solve
  * uses is derived from the ws_bytes it is given.  Errors: INVALID_ARG,
  * WORKSPACE (budget below the minimum of 8 wavefields plus traces; 10 with
- * time_order 4).  FORWARD_MEDIUM ignores budget_bytes and needs time_order 2. */
+ * time_order 4).  FORWARD_MEDIUM ignores budget_bytes and needs time_order 2;
+ * GRADIENT_MEDIUM takes a budget as GRADIENT does (0 or a budget at least the
+ * full size keeps every imaging factor). */
 int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budget_bytes,
                            size_t* out_bytes);
 
@@ -215,10 +217,14 @@ int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const
  * (D_a is antisymmetric, so the density term transposes to -D_a (gamma_a .)),
  * and dvp = P^T (2/vp) sum_n w^{n+1} h^n with h^n the step's right-hand side v^n
  * plus the attenuation's vp dependence: y = 2, + (beta/2) (L u^n - L u^{n-1});
- * y = 0, + (att a dt/4) ((2 u^{n-1} - 2 u^n)/k - v^n), att = 2 alpha0 vp.  Every
- * step's h is kept (no checkpointing): ws is GRADIENT_MEDIUM bytes, about
- * nt fields.  Second-order time, sponge boundary.  Errors: INVALID_ARG, CFL,
- * WORKSPACE, HIP, NONFINITE. */
+ * y = 0, + (att a dt/4) ((2 u^{n-1} - 2 u^n)/k - v^n), att = 2 alpha0 vp.  With
+ * ws_bytes >= the GRADIENT_MEDIUM size for budget 0 (about nt fields) every
+ * step's h is kept; a smaller workspace (stride_workspace_bytes with a budget)
+ * keeps forward states by binomial checkpointing and recomputes h^m from the
+ * stored (u^m, u^{m-1}) before adjoint step m, with the same result bit for bit.
+ * Second-order time, sponge boundary.  Errors: INVALID_ARG, CFL, WORKSPACE (below
+ * the checkpointed minimum of 13 + ndim wavefields plus traces), HIP,
+ * NONFINITE. */
 int stride_plan_gradient_medium(const stride_plan_t* plan, const float* vp, const float* rho,
                                 const float* alpha0, int32_t att_power, const float* wavelet,
                                 const float* observed, float* traces, double* misfit, float* dvp,

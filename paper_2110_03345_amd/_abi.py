@@ -463,9 +463,11 @@ class Plan:
         return traces
 
     def gradient_medium(self, vp, wavelet, observed, rho=None, alpha0=None, att_power: int = 0,
-                        traces=None, ws=None, stream=None):
-        """(misfit, dvp) of the shot gradient in the medium (rho, alpha0 fixed);
-        every step's imaging factor is kept (GRADIENT_MEDIUM workspace)."""
+                        traces=None, ws=None, budget_bytes: int = 0, stream=None):
+        """(misfit, dvp) of the shot gradient in the medium (rho, alpha0 fixed).
+        The GRADIENT_MEDIUM workspace keeps every step's imaging factor; a
+        smaller one (budget_bytes) checkpoints the forward states and
+        recomputes the factors during the adjoint sweep."""
         import torch
         self._vp(vp)
         self._wavelet(wavelet)
@@ -476,7 +478,7 @@ class Plan:
         if traces is not None:
             self._traces_like(traces, "traces")
         if ws is None:
-            ws = self.workspace(STRIDE_MODE_GRADIENT_MEDIUM, device=vp.device)
+            ws = self.workspace(STRIDE_MODE_GRADIENT_MEDIUM, budget_bytes, device=vp.device)
         misfit = torch.zeros(1, dtype=torch.float64, device=vp.device)
         dvp = torch.empty_like(vp)
         stride_plan_gradient_medium(self.handle, vp, rho, alpha0, att_power, wavelet, observed,

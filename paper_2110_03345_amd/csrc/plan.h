@@ -70,6 +70,7 @@ struct Layout {
     size_t fixed_grad; // scratch + k + G + 2 adjoint fields + traces + residual (+ p, q)
     size_t medium;     // scratch + k + 3 wavefields + ndim gamma fields + attenuation
     size_t grad_medium;// medium + G + traces + residual + nt - 1 imaging factors
+    size_t grad_medium_fixed; // checkpointed: medium + G + traces + residual + h + scratch u^{m+1}
 };
 
 Layout layout_of(const stride_plan& P);
@@ -125,7 +126,7 @@ inline SampleSet src_samples(const stride_plan& P, float* out)
 
 // One step of a checkpointed gradient solve.
 struct StepOp {
-    bool reverse;      // adjoint step at `step` (field a = u^step); else forward step
+    bool reverse;      // adjoint step at `step` (a = u^step, b = u^{step-1}); else forward step
     int step;          // forward: n (u^n -> u^{n+1}); adjoint: m
     int a, b, c;       // pool fields: forward A = u^n, B = u^{n-1}, C = u^{n+1}
     bool first_sweep;  // forward step before the first adjoint step (records traces)
@@ -135,10 +136,13 @@ struct StepOp {
 // wavefields, one forward or adjoint step at a time.  Store / Free / Restore
 // are pure bookkeeping (no copies): a stored state keeps its two fields
 // pinned; a step writes in place when its u^{n-1} field is pinned by nothing
-// else, and into a free field otherwise.  Fields 0 and 1 hold x_0 = (0, 0).
+// else, and into a free field otherwise (always into a free field with
+// in_place false, for steps that read u^{n-1} as a stencil field: the pool
+// then needs one field more than the schedule's peak).  Fields 0 and 1 hold
+// x_0 = (0, 0).
 class StepCursor {
   public:
-    StepCursor(int nt, int snaps, int pool_fields);
+    StepCursor(int nt, int snaps, int pool_fields, bool in_place = true);
     bool next(StepOp& op);           // false when the schedule is finished
     void unget(const StepOp& op);    // push back one op (to stop before it)
     bool overflow() const { return overflow_; }
@@ -159,6 +163,7 @@ class StepCursor {
     bool reversed_ = false;
     bool overflow_ = false;
     bool have_back_ = false;
+    bool in_place_ = true;
     StepOp back_{};
 };
 

@@ -358,8 +358,10 @@ Layout stride::layout_of(const stride_plan& P)
     // k, G, w, w, traces, residual (, p and q of the fourth-order adjoint)
     L.fixed_grad = L.scratch + (P.torder == 4 ? 6 : 4) * L.field + 2 * L.traces;
     L.medium = L.scratch + (size_t)(4 + P.nd + 1) * L.field;
-    // the medium gradient keeps every step's imaging factor: G and nt - 1 fields more
+    // the medium gradient keeps every step's imaging factor: G and nt - 1 fields more;
+    // checkpointed, G, h^m and a discarded u^{m+1} plus the state pool
     L.grad_medium = L.medium + (size_t)P.nt * L.field + 2 * L.traces;
+    L.grad_medium_fixed = L.medium + 3 * L.field + 2 * L.traces;
     return L;
 }
 
@@ -485,7 +487,8 @@ StepParams stride::base_params(const stride_plan& P)
 
 // ------------------------------------------------------------ step cursor
 
-StepCursor::StepCursor(int nt, int snaps, int pool_fields) : cs_(cached_schedule(nt, snaps))
+StepCursor::StepCursor(int nt, int snaps, int pool_fields, bool in_place)
+    : cs_(cached_schedule(nt, snaps)), in_place_(in_place)
 {
     ref_.assign(pool_fields, 0);
     for (int f = pool_fields - 1; f >= 2; --f)
@@ -529,7 +532,7 @@ bool StepCursor::next(StepOp& op)
         if (target_ >= 0 && idx_ < target_) {
             // one forward step of the current Advance
             int old_prev = prev_;
-            int out = ref_[prev_] == 1 ? prev_ : alloc();
+            int out = in_place_ && ref_[prev_] == 1 ? prev_ : alloc();
             if (out < 0)
                 return false;
             op = StepOp{false, idx_, cur_, old_prev, out, !reversed_};
@@ -582,7 +585,7 @@ bool StepCursor::next(StepOp& op)
             continue;
         }
         case Act::Reverse:
-            op = StepOp{true, a.step, cur_, -1, -1, false};
+            op = StepOp{true, a.step, cur_, prev_, -1, false};
             reversed_ = true;
             ++pc_;
             return true;
@@ -1231,10 +1234,11 @@ int forward_medium(const stride_plan& P, const float* vp, const float* rho, cons
     return check_finite(finite_flag(ws), s, {{traces, nullptr, (long long)P.nrec * P.nt, "traces"}});
 }
 
-// Shot gradient in the medium, every step's imaging factor kept (no
-// checkpointing): the medium sweep storing H, residual and misfit, then per
-// adjoint step the direct medium adjoint kernel (w rotates through the three
-// wavefields) and the receiver residual injected through the plan's table.
+// Shot gradient in the medium: the medium sweep storing every step's imaging
+// factor H (or, in a smaller workspace, checkpointed states from which h^m is
+// recomputed just before it is needed), residual and misfit, then per adjoint
+// step the direct medium adjoint kernel (w rotates through three wavefields)
+// and the receiver residual injected through the plan's table.
 int gradient_medium(const stride_plan& P, const float* vp, const float* rho, const float* alpha0,
                     int att_power, const float* wavelet, const float* observed, float* traces,
                     double* misfit, float* dvp, void* ws, size_t bytes, hipStream_t s)
@@ -1247,10 +1251,15 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
     Layout L = layout_of(P);
     if (!ws || (uintptr_t)ws % 256)
         return fail(STRIDE_E_INVALID_ARG, "workspace must be a 256-byte aligned device pointer");
-    if (bytes < L.grad_medium)
+    // every step's imaging factor kept, or checkpointed forward states (the
+    // medium step reads u^{n-1} as a stencil field, so steps never write in
+    // place) with h^m recomputed from x_m before adjoint step m
+    const bool full = bytes >= L.grad_medium;
+    if (!full && bytes < L.grad_medium_fixed + 5 * L.field)
         return fail(STRIDE_E_WORKSPACE,
-                    "medium gradient workspace needs %zu bytes (got %zu): every step's imaging "
-                    "factor is kept", L.grad_medium, bytes);
+                    "medium gradient workspace needs %zu bytes (every imaging factor kept) or at "
+                    "least %zu (checkpointed), got %zu", L.grad_medium,
+                    L.grad_medium_fixed + 5 * L.field, bytes);
     MediumWs M;
     medium_views(P, L, ws, M);
     char* b = M.tail;
@@ -1260,24 +1269,80 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
     b += L.traces;
     float* residual = (float*)b;
     b += L.traces;
-    std::vector<float*> H((size_t)std::max(P.nt - 1, 1));
-    for (int n = 0; n < P.nt - 1; ++n, b += L.field)
-        H[n] = (float*)b;
+    std::vector<float*> H, pool;
+    float *hbuf = nullptr, *cbuf = nullptr;
+    std::unique_ptr<StepCursor> cursor;
+    if (full) {
+        H.resize((size_t)std::max(P.nt - 1, 1));
+        for (int n = 0; n < P.nt - 1; ++n, b += L.field)
+            H[n] = (float*)b;
+    } else {
+        hbuf = (float*)b;
+        b += L.field;
+        cbuf = (float*)b;
+        b += L.field;
+        const long long nf = (long long)((bytes - L.grad_medium_fixed) / L.field);
+        for (long long f = 0; f < nf; ++f, b += L.field)
+            pool.push_back((float*)b);
+        const int snaps = snaps_for_fields(P.nt, nf - 1);
+        if (snaps < 0)
+            return fail(STRIDE_E_WORKSPACE, "medium gradient workspace too small for checkpointing");
+        cursor = std::make_unique<StepCursor>(P.nt, snaps, (int)nf, false);
+    }
     if ((rc = prepare_medium(P, vp, rho, alpha0, att_power, M, s)))
         return rc;
     float* tr = traces ? traces : tr_ws;
-    medium_sweep(P, M, wavelet, att_power, tr, H.data(), s);
+    // one medium step u^n = A, u^{n-1} = B -> C, sampling into smp, h into V
+    auto medium_step = [&](const float* A, const float* B, float* C, int n, float* smp, float* V) {
+        StepParams p = base_params(P);
+        p.A = A;
+        p.B = B;
+        p.C = C;
+        p.K = M.k;
+        p.step = n;
+        p.inj = P.src_img;
+        p.inj_sig = wavelet;
+        if (smp)
+            p.smp = rec_samples(P, smp);
+        for (int a = 0; a < 3; ++a)
+            p.gam[a] = M.gam[a] ? M.gam[a] : M.gam[0];
+        p.att = M.att;
+        p.att_power = att_power;
+        p.V = V;
+        launch_step_mode(P.dims, P.R, false, kMedium, P.cf, P.sp, P.ls_adj, p, s);
+    };
+    if (full) {
+        medium_sweep(P, M, wavelet, att_power, tr, H.data(), s);
+    } else {
+        launch_fill(pool[0], P.dims.total, 0.f, s);
+        launch_fill(pool[1], P.dims.total, 0.f, s);
+        int tid = g_timer.begin(s);
+        long long fsteps = 0;
+        StepOp op;
+        while (cursor->next(op)) {
+            if (op.reverse) {
+                cursor->unget(op);
+                break;
+            }
+            medium_step(pool[op.a], pool[op.b], pool[op.c], op.step, op.first_sweep ? tr : nullptr,
+                        nullptr);
+            ++fsteps;
+        }
+        g_timer.end(tid, s, 0, fsteps, fsteps);
+        if (cursor->overflow())
+            return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
+        launch_sample(rec_samples(P, tr), pool[cursor->cur()], P.nt - 1, s);
+    }
     const long long ntr = (long long)P.nrec * P.nt;
     launch_residual_misfit(tr, observed, residual, ntr, misfit, (double*)(M.flags + 64), s);
 
-    // adjoint: w^{m+1} and w^{m+2} start at zero; step m images with H[m]
+    // adjoint: w^{m+1} and w^{m+2} start at zero; step m images with h^m
     float* w[3] = {M.u[0], M.u[1], M.u[2]};
     for (int i = 0; i < 3; ++i)
         launch_fill(w[i], P.dims.total, 0.f, s);
     launch_fill(G, P.dims.total, 0.f, s);
     int i0 = 0, i1 = 1, i2 = 2;   // w^m, w^{m+1}, w^{m+2}
-    int tid = g_timer.begin(s);
-    for (int m = P.nt - 1; m >= 0; --m) {
+    auto adjoint_step = [&](int m, const float* Hm) {
         MediumAdjParams mp{};
         mp.w1 = w[i1];
         mp.w2 = w[i2];
@@ -1287,19 +1352,42 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
             mp.gam[a] = M.gam[a] ? M.gam[a] : M.gam[0];
         mp.att = M.att;
         mp.att_power = att_power;
-        mp.H = m <= P.nt - 2 ? H[m] : nullptr;   // w^{nt} = 0: step nt-1 images nothing
+        mp.H = Hm;    // w^{nt} = 0: step nt-1 images nothing
         mp.G = G;
         launch_medium_adjoint(P.dims, P.R, P.cf, P.sp, mp, s);
         if (m == 0)
-            break;   // w^0 is not needed; the launch above added the last imaging term
+            return;   // w^0 is not needed; the launch above added the last imaging term
         launch_inject_table(P.dims, P.ls_adj, P.rec_inj, residual, P.nt, m, M.k, M.att, att_power,
                             P.sp, w[i0], s);
         const int t = i2;
         i2 = i1;
         i1 = i0;
         i0 = t;
+    };
+    int tid = g_timer.begin(s);
+    long long alaunches = 2LL * P.nt - 1;   // adjoint step + receiver injection (none at m = 0)
+    if (full) {
+        for (int m = P.nt - 1; m >= 0; --m)
+            adjoint_step(m, m <= P.nt - 2 ? H[m] : nullptr);
+    } else {
+        StepOp op;
+        while (cursor->next(op)) {
+            ++alaunches;
+            if (!op.reverse) {
+                medium_step(pool[op.a], pool[op.b], pool[op.c], op.step, nullptr, nullptr);
+                continue;
+            }
+            const int m = op.step;
+            if (m <= P.nt - 2)   // h^m from x_m = (u^m, u^{m-1}); u^{m+1} is discarded
+                medium_step(pool[op.a], pool[op.b], cbuf, m, nullptr, hbuf);
+            else
+                --alaunches;
+            adjoint_step(m, m <= P.nt - 2 ? hbuf : nullptr);
+        }
+        if (cursor->overflow())
+            return fail(STRIDE_E_WORKSPACE, "checkpoint pool overflow");
     }
-    g_timer.end(tid, s, 1, P.nt, 2LL * P.nt - 1);
+    g_timer.end(tid, s, 1, P.nt, alaunches);
     // dvp = P^T (2 G / vp_pad); two wavefields serve as the finalise's scratch
     launch_finalize_dvp(P.dims, G, nullptr, vp, dvp, w[i1], w[i2], s);
     HIP_TRY(hipGetLastError());
@@ -1654,7 +1742,20 @@ int stride_workspace_bytes(const stride_plan_t* plan, int32_t mode, size_t budge
             return fail(STRIDE_E_INVALID_ARG, "medium forward solves need time_order 2");
         if (plan->boundary == 1)
             return fail(STRIDE_E_INVALID_ARG, "medium forward solves use the sponge, not the PML");
-        *out_bytes = mode == STRIDE_MODE_GRADIENT_MEDIUM ? L.grad_medium : L.medium;
+        if (mode == STRIDE_MODE_FORWARD_MEDIUM || budget_bytes == 0 || budget_bytes >= L.grad_medium) {
+            *out_bytes = mode == STRIDE_MODE_GRADIENT_MEDIUM ? L.grad_medium : L.medium;
+            return STRIDE_OK;
+        }
+        // checkpointed medium gradient within the budget (steps never in place)
+        if (budget_bytes < L.grad_medium_fixed + 5 * L.field)
+            return fail(STRIDE_E_WORKSPACE, "budget %zu below the medium gradient minimum %zu",
+                        budget_bytes, L.grad_medium_fixed + 5 * L.field);
+        const long long cap = (long long)((budget_bytes - L.grad_medium_fixed) / L.field);
+        const int sn = snaps_for_fields(plan->nt, cap - 1);
+        if (sn < 0)
+            return fail(STRIDE_E_WORKSPACE, "budget too small for checkpointing");
+        const long long nf = std::max<long long>(cached_schedule(plan->nt, sn)->stats.peak_fields + 1, 5);
+        *out_bytes = std::min(L.grad_medium, L.grad_medium_fixed + (size_t)nf * L.field);
         return STRIDE_OK;
     }
     if (mode != STRIDE_MODE_GRADIENT)

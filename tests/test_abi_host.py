@@ -161,6 +161,31 @@ def test_medium_workspace_size():
     assert e.value.code == _abi.STRIDE_E_INVALID_ARG
 
 
+def test_medium_gradient_workspace_budget():
+    """GRADIENT_MEDIUM: the medium fields, G, traces and residual plus nt - 1
+    imaging factors in full; under a budget, G, h, a scratch u^{m+1} and a
+    checkpoint pool one field above the schedule's peak (medium steps never
+    write in place), never more than the budget nor below 5 pool fields."""
+    nt = 60
+    g = _grid(nt=nt)
+    field = -(-(52 * 64 * 4) // 256) * 256
+    scratch = 256 + 256 * 8
+    traces = -(-(3 * nt * 4) // 256) * 256
+    medium = scratch + 7 * field
+    full = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT_MEDIUM)
+    assert full == medium + nt * field + 2 * traces
+    assert S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT_MEDIUM, full + 5) == full
+    fixed = medium + 3 * field + 2 * traces
+    for pool in (5, 6, 9, 15):
+        b = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT_MEDIUM, fixed + pool * field)
+        assert fixed + 5 * field <= b <= fixed + pool * field and (b - fixed) % field == 0
+        snaps, _, peak = S.stride_schedule_info(nt, pool - 1)
+        assert b == fixed + max(peak + 1, 5) * field
+    with pytest.raises(S.StrideError) as e:
+        S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT_MEDIUM, fixed + 4 * field)
+    assert e.value.code == _abi.STRIDE_E_WORKSPACE
+
+
 @lru_cache(None)
 def _dp(l, s):
     """Brute-force minimal forward steps to reverse l steps with s free slots."""

@@ -1,7 +1,9 @@
 """Heterogeneous medium (variable density, power-law attenuation y = 0 and 2):
 HIP forward traces against the FP64 oracle's in 2D and 3D, orders 8 and 10,
 ragged shapes, and at the benchmark grids; the constant medium against the
-plain forward; value, order and stability checks before any launch."""
+plain forward; value, order and stability checks before any launch; shot
+gradients against the oracle's, with every imaging factor kept and
+checkpointed (bitwise equal to each other)."""
 import numpy as np
 import pytest
 
@@ -187,7 +189,7 @@ def test_medium_gradient_benchmark_grid_and_bitwise_repeat():
     in the 500-step window the burst has not reached the phantom's
     inclusions, and data from the phantom would differ from the model's traces
     by less than FP32 rounding can resolve to 1e-4); two runs give the same
-    bits."""
+    bits, and so does a checkpointed run in an eighth of the workspace."""
     from parity import check_field
     w = W.config2(nt=500)
     rho, alpha0 = W.medium(w.vp, w.spacing, 11, att_power=0)
@@ -203,7 +205,53 @@ def test_medium_gradient_benchmark_grid_and_bitwise_repeat():
     m1, d1 = plan.gradient_medium(*args, **dkw)
     m2, d2 = plan.gradient_medium(*args, **dkw)
     assert torch.equal(m1, m2) and torch.equal(d1, d2)
+    budget = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT_MEDIUM) // 8     # checkpointed
+    m3, d3 = plan.gradient_medium(*args, budget_bytes=budget, **dkw)
+    assert torch.equal(m1, m3) and torch.equal(d1, d3)
     e_J = abs(m1.item() - J) / J
     sf = check_field(d1.cpu().numpy(), dvp_ref, 1e-4)
     print(f"medium gradient config2 nt=500: misfit rel {e_J:.2e}, dvp {sf}", flush=True)
     assert e_J < 1e-4
+
+
+@pytest.mark.parametrize("att_power", [0, 2])
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_medium_gradient_checkpointed_equals_full_history(name, make, att_power):
+    """A workspace below the full size checkpoints the forward states and
+    recomputes every imaging factor from them: misfit, traces and dvp equal
+    the full-history solve's bit for bit, from the smallest pool up to one
+    short of the full size, two solves in a row on one workspace."""
+    w = make()
+    rho, alpha0 = _fields(w, 5, att_power)
+    print(f"medium gradient checkpointed {name} y={att_power}: shape={w.shape} nt={w.nt}",
+          flush=True)
+    g = oracle.Grid(**w.grid_kwargs())
+    kw = dict(rho=rho, alpha0=alpha0, att_power=att_power)
+    obs = oracle.forward_medium(g, w.vp * 0.98, w.src_xyz, w.wavelet, w.rec_xyz,
+                                **kw).astype(np.float32)
+    plan = S.Plan.from_workload(w)
+    args = (dev(w.vp), dev(w.wavelet), dev(obs))
+    dkw = dict(rho=dev(rho), alpha0=dev(alpha0), att_power=att_power)
+    t0 = torch.empty((plan.nrec, plan.nt), dtype=torch.float32, device="cuda")
+    m0, d0 = plan.gradient_medium(*args, traces=t0, **dkw)
+    full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT_MEDIUM)
+    # FORWARD holds k and two wavefields, FORWARD_MEDIUM k, three and ndim + 1 medium fields
+    field = (plan.workspace_bytes(S.STRIDE_MODE_FORWARD_MEDIUM)
+             - plan.workspace_bytes(S.STRIDE_MODE_FORWARD)) // (2 + len(w.shape))
+    fixed = full - (plan.nt - 3) * field      # G, h^m and the scratch u^{m+1} kept
+    sizes = []
+    for budget in (fixed + 5 * field, fixed + 9 * field, full - field):
+        b = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT_MEDIUM, budget)
+        assert b < full
+        sizes.append(b)
+    for b in sorted(set(sizes)):
+        ws = torch.empty(b, dtype=torch.uint8, device="cuda")
+        for rep in range(2):
+            t1 = torch.empty_like(t0)
+            m1, d1 = plan.gradient_medium(*args, traces=t1, ws=ws, **dkw)
+            assert torch.equal(m0, m1) and torch.equal(t0, t1) and torch.equal(d0, d1), (b, rep)
+        del ws
+    small = plan.workspace(S.STRIDE_MODE_GRADIENT_MEDIUM, full - field)
+    with pytest.raises(S.StrideError) as e:
+        plan.gradient_medium(*args, ws=small[:fixed + 4 * field], **dkw)
+    assert e.value.code == -4    # STRIDE_E_WORKSPACE
