@@ -47,16 +47,18 @@ HBM_PEAK_GBS = 8000.0
 # kernel file and its header; any change makes `traffic` null until the
 # counters are taken again.
 MEASURED_TRAFFIC = {
-    # config 2 keeps every state: the adjoint alternates mode 6 (no imaging) and
-    # mode 5 (two imaging terms); per-dispatch figures averaged over the pair
-    "config2": {"sha256": "bb0de64b1359e09888b5b6d0c99f20c9bc2ace4d211b12bbed461d09d735f779",
-                "fetch_kib": 11025.57, "write_kib": 7153.94,
-                "copy_fetch_kib": 524308.44, "copy_write_kib": 1048576.0},
-    # config 4 checkpoints: the fused adjoint (mode 0), counters from a checkpointed run
-    "config4": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
-                "fetch_kib": 477528.27, "write_kib": 249640.00,
-                "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
-    "config4_forward": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
+    # keyed by workload and the adjoint kernel: "pair" = the adjoint imaging
+    # from the stored v (mode 6, no imaging, and mode 5, two imaging terms, in
+    # turn; per-dispatch figures averaged over the pair), "fused" = the adjoint
+    # with its own stencil of u^m (mode 0, binomial checkpointing), "forward" =
+    # the plain forward step of a forward solve
+    "config2/pair": {"sha256": "bb0de64b1359e09888b5b6d0c99f20c9bc2ace4d211b12bbed461d09d735f779",
+                     "fetch_kib": 11025.57, "write_kib": 7153.94,
+                     "copy_fetch_kib": 524308.44, "copy_write_kib": 1048576.0},
+    "config4/fused": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
+                      "fetch_kib": 477528.27, "write_kib": 249640.00,
+                      "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
+    "config4/forward": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
                         "fetch_kib": 240887.80, "write_kib": 124846.85,
                         "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
 }
@@ -71,10 +73,10 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel, or None if not measured
-    for the current kernel source."""
-    m = MEASURED_TRAFFIC.get(workload)
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel ("workload/kernel"), or None if not
+    measured for the current kernel source."""
+    m = MEASURED_TRAFFIC.get(key)
     if not m or m["sha256"] != kernel_source_sha():
         return None
     gib_kib = float(1 << 20)
@@ -105,7 +107,7 @@ WORKLOADS = {
                "starting model against data from the phantom",
     "config4": "3D head-like phantom, 256^3 at 0.5 mm + 30-cell sponge (316^3 padded), 10th order, "
                "3000 steps, 1 shot, 1024 hemisphere receivers; gradient at the skull-only starting "
-               "model, binomial checkpointing within the HBM budget",
+               "model, forward states kept within a 200 GiB HBM budget (segmented history)",
     "config3": "2D breast-like phantom, 512^2 at 0.2 mm + 40-cell sponge (592^2 padded), 8th order, "
                "1500 steps, shot 0 of the 64-shot ring survey; gradient at 1500 m/s",
     "fwi": "frequency-block inversion of the 2D breast-like phantom of config 3 (512^2 at 0.2 mm, "
@@ -471,25 +473,36 @@ def measure(name, args, dev, headline):
     adj_launch_s = a_ms * 1e-3 / max(a_l, 1)
     adj_spl = a_n / max(a_l, 1)
     fwd_step_s = f_ms * 1e-3 / max(f_n, 1)
-    # with every state kept the forward also stores v = L u + S (4 B more) and
-    # the adjoint images from it two terms at a time (modes 6 and 5 in turn:
-    # 24 B per step on average); otherwise the fused adjoint (mode 0, 28 B)
-    full_history = f_n <= steps * (w.nt - 1)
-    adj_bytes = ADJ_BYTES_PAIRED if full_history else ADJ_BYTES
+    # with every state kept (full history) or segment by segment (segmented
+    # history) the forward also stores v = L u + S (4 B more) and the adjoint
+    # images from it two terms at a time (modes 6 and 5 in turn: 24 B per step
+    # on average); with binomial checkpointing the fused adjoint (mode 0, 28 B)
+    path, path_fsteps, nseg = plan.gradient_path(ws_bytes)
+    full_history = path == S.STRIDE_PATH_FULL_HISTORY
+    from_v = path != S.STRIDE_PATH_BINOMIAL
+    adj_bytes = ADJ_BYTES_PAIRED if from_v else ADJ_BYTES
     adj_gbs = adj_bytes * npad / adj_step_s / 1e9
-    fwd_in_grad_bytes = FWD_BYTES + (4 if full_history else 0)
+    # segmented: the steps before the last segment run once without v (first
+    # sweep) and once with it (recomputation); every other step keeps v
+    v_steps = w.nt - 1 if from_v else 0
+    fwd_in_grad_bytes = (FWD_BYTES * path_fsteps + 4 * v_steps) / path_fsteps
+    path_name = {S.STRIDE_PATH_FULL_HISTORY: "full history",
+                 S.STRIDE_PATH_SEGMENTED: "segmented history, %d segments" % nseg,
+                 S.STRIDE_PATH_BINOMIAL: "binomial checkpointing"}[path]
     print(f"[bench] {name} gradient: {ms_per_step:.2f} ms/step, adjoint {adj_step_s * 1e6:.2f} us/step "
           f"({adj_gbs:.0f} GB/s), forward {fwd_step_s * 1e6:.2f} us/step, forward steps per "
-          f"gradient {f_n / steps:.0f}", file=sys.stderr, flush=True)
+          f"gradient {f_n / steps:.0f} ({path_name})", file=sys.stderr, flush=True)
     out = {
         "w": w, "plan": plan, "vp_true": vp_true, "vp_model": vp_model, "obs": obs,
         "npad": npad, "value": value, "ms_per_step": ms_per_step, "steps": steps,
         "ws_bytes": ws_bytes, "forward_steps_per_gradient": f_n / steps,
         "recompute_factor": f_n / max(1, steps * (w.nt - 1)), "full_history": full_history,
+        "gradient_path": path_name,
+        "traffic_key": f"{name}/{'pair' if from_v else 'fused'}",
         "adjoint": {
             "kernel": ("adjoint leapfrog steps, imaging from the stored v two terms per even step "
                        "(step%dd_kernel<R, true, ., ., 6> and <..., 5> in turn; per-launch figures "
-                       "average the pair)" % w.ndim) if full_history else
+                       "average the pair)" % w.ndim) if from_v else
                       "adjoint leapfrog step + imaging (step%dd_kernel<R, true, ., ., 0>)" % w.ndim,
             "bytes_per_point": adj_bytes,
             "achieved": adj_gbs,
@@ -703,7 +716,7 @@ def main():
     torch.cuda.empty_cache()
 
     adj = m["adjoint"]
-    traffic = measured_traffic(args.workload)
+    traffic = measured_traffic(m["traffic_key"])
     roofline = {
         "bound": "hbm",
         "kernel": adj["kernel"],
@@ -724,7 +737,7 @@ def main():
         "forward_in_gradient": m["forward_in_gradient"],
     }
     if "forward" in m:
-        ftraffic = measured_traffic(args.workload + "_forward")
+        ftraffic = measured_traffic(args.workload + "/forward")
         roofline["forward"] = {
             **m["forward"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "traffic": ftraffic,
             "traffic_over_algorithmic": (ftraffic / (FWD_BYTES * npad)) if ftraffic else None,

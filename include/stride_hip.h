@@ -122,6 +122,11 @@ typedef struct stride_grid {
                              3 sponge_vref ln(1000) / (2 nb dx_a).  Forward solves
                              (stride_plan_forward[_static]) only; other solves
                              return INVALID_ARG for it. */
+    int32_t checkpointing; /* gradients whose workspace cannot keep every state
+                             (stride_gradient_path): 0 the library's choice,
+                             segmented history where its cost model prefers it to
+                             binomial checkpointing; 1 binomial checkpointing
+                             always.  The results are the same bits either way. */
 } stride_grid_t;
 
 /* A plan: the validated grid plus the source/receiver tap tables of one shot
@@ -281,6 +286,27 @@ int stride_gradient(const stride_grid_t* grid, const float* vp, const float* wav
                     void* stream);
 int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec, int32_t mode,
                            size_t budget_bytes, size_t* out_bytes);
+
+/* How stride_plan_gradient / stride_forward_save + stride_backward run in a
+ * GRADIENT workspace of ws_bytes, for a plan on `grid` with nrec receivers
+ * (host only, no device needed; Sec. 2.2 adjoint-state method with
+ * the forward wavefields kept or recomputed):
+ *   path 0 (STRIDE_PATH_FULL_HISTORY): every state fits; the forward keeps
+ *     v^n = L u^n + S^n (second order; p^n with time_order 4) and the adjoint
+ *     images from it;
+ *   path 1 (STRIDE_PATH_SEGMENTED): second order, the forward keeps the states
+ *     at the starts of `segments` segments and v^n over the last one; each
+ *     other segment's v^n is recomputed once, just before its adjoint steps;
+ *   path 2 (STRIDE_PATH_BINOMIAL): binomial checkpointing (revolve) with the
+ *     adjoint recomputing L u^m itself.
+ * The library takes path 1 over path 2 when its cost model of the step
+ * kernels says it is faster; all three give the same bits.  forward_steps:
+ * forward step launches per gradient.  Errors: INVALID_ARG, WORKSPACE. */
+#define STRIDE_PATH_FULL_HISTORY 0
+#define STRIDE_PATH_SEGMENTED 1
+#define STRIDE_PATH_BINOMIAL 2
+int stride_gradient_path(const stride_grid_t* grid, int32_t nrec, size_t ws_bytes, int32_t* path,
+                         int64_t* forward_steps, int32_t* segments);
 
 /* Checkpointing schedule summary for nt steps within `fields` wavefields
  * (host only): snapshots used, total forward steps (nt - 1 means no

@@ -15,6 +15,9 @@ from ._abi import (  # noqa: F401
     STRIDE_MODE_FORWARD_MEDIUM,
     STRIDE_MODE_GRADIENT,
     STRIDE_MODE_GRADIENT_MEDIUM,
+    STRIDE_PATH_BINOMIAL,
+    STRIDE_PATH_FULL_HISTORY,
+    STRIDE_PATH_SEGMENTED,
     Plan,
     StrideError,
     lib,
@@ -25,6 +28,7 @@ from ._abi import (  # noqa: F401
     stride_forward,
     stride_forward_save,
     stride_gradient,
+    stride_gradient_path,
     stride_lowpass,
     stride_plan_create,
     stride_plan_destroy,

@@ -34,7 +34,7 @@ EXPORTS = (
     "stride_descent_step",
     "stride_forward_save", "stride_backward",
     "stride_plan_gradient", "stride_forward", "stride_gradient", "stride_workspace_query",
-    "stride_schedule_info", "stride_last_error", "stride_error_string",
+    "stride_schedule_info", "stride_gradient_path", "stride_last_error", "stride_error_string",
     "stride_timing_enable", "stride_timing_read", "stride_check_finite",
     "stride_engine_create", "stride_engine_destroy", "stride_engine_attach", "stride_engine_run",
     "stride_engine_detach", "stride_engine_slot_ticks", "stride_accumulate",
@@ -60,6 +60,7 @@ class stride_grid_t(ctypes.Structure):
         ("time_order", ctypes.c_int32),
         ("interp", ctypes.c_int32),
         ("boundary", ctypes.c_int32),
+        ("checkpointing", ctypes.c_int32),
     ]
 
 
@@ -98,6 +99,8 @@ def lib():
         L.stride_workspace_query.argtypes = [gp, i32, i32, i32, sz, ctypes.POINTER(sz)]
         L.stride_schedule_info.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(i32),
                                            ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
+        L.stride_gradient_path.argtypes = [gp, i32, sz, ctypes.POINTER(i32),
+                                           ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32)]
         L.stride_timing_enable.argtypes = [i32]
         L.stride_check_finite.argtypes = [i32]
         L.stride_timing_read.argtypes = [dp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -124,7 +127,8 @@ def _check(rc: int):
 
 
 def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: float, dt: float,
-              nt: int, time_order: int = 2, interp: int = 0, boundary: int = 0) -> stride_grid_t:
+              nt: int, time_order: int = 2, interp: int = 0, boundary: int = 0,
+              checkpointing: int = 0) -> stride_grid_t:
     g = stride_grid_t()
     nd = len(shape)
     sp = (float(spacing),) * nd if np.isscalar(spacing) else tuple(float(s) for s in spacing)
@@ -140,6 +144,7 @@ def make_grid(shape: Sequence[int], spacing, space_order: int, nb: int, vref: fl
     g.time_order = int(time_order)
     g.interp = int(interp)
     g.boundary = int(boundary)
+    g.checkpointing = int(checkpointing)
     return g
 
 
@@ -216,6 +221,23 @@ def stride_schedule_info(nt: int, fields: int):
     p = ctypes.c_int32()
     _check(lib().stride_schedule_info(nt, fields, ctypes.byref(s), ctypes.byref(f), ctypes.byref(p)))
     return int(s.value), int(f.value), int(p.value)
+
+
+STRIDE_PATH_FULL_HISTORY = 0
+STRIDE_PATH_SEGMENTED = 1
+STRIDE_PATH_BINOMIAL = 2
+
+
+def stride_gradient_path(grid, nrec: int, ws_bytes: int):
+    """(path, forward steps per gradient, segments) of a gradient in a
+    workspace of ws_bytes: path 0 full history, 1 segmented history, 2
+    binomial checkpointing."""
+    k = ctypes.c_int32()
+    f = ctypes.c_int64()
+    n = ctypes.c_int32()
+    _check(lib().stride_gradient_path(ctypes.byref(grid), nrec, ws_bytes, ctypes.byref(k),
+                                      ctypes.byref(f), ctypes.byref(n)))
+    return int(k.value), int(f.value), int(n.value)
 
 
 def stride_timing_enable(on: bool) -> None:
@@ -372,9 +394,9 @@ class Plan:
     """A validated grid + shot geometry with its tap tables on the current device."""
 
     def __init__(self, shape, spacing, space_order, nb, vref, dt, nt, src_xyz, rec_xyz,
-                 time_order: int = 2, interp: int = 0, boundary: int = 0):
+                 time_order: int = 2, interp: int = 0, boundary: int = 0, checkpointing: int = 0):
         self.grid = make_grid(shape, spacing, space_order, nb, vref, dt, nt, time_order, interp,
-                              boundary)
+                              boundary, checkpointing)
         self.time_order = int(time_order)
         self.interp = int(interp)
         self.boundary = int(boundary)
@@ -389,11 +411,12 @@ class Plan:
 
     @classmethod
     def from_workload(cls, w, src_xyz=None, rec_xyz=None, nt=None, time_order: int = 2,
-                      interp: int = 0, boundary: int = 0):
+                      interp: int = 0, boundary: int = 0, checkpointing: int = 0):
         return cls(w.shape, w.spacing, w.space_order, w.nb, w.vref, w.dt,
                    w.nt if nt is None else nt,
                    w.src_xyz if src_xyz is None else src_xyz,
-                   w.rec_xyz if rec_xyz is None else rec_xyz, time_order, interp, boundary)
+                   w.rec_xyz if rec_xyz is None else rec_xyz, time_order, interp, boundary,
+                   checkpointing)
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -410,6 +433,11 @@ class Plan:
 
     def workspace_bytes(self, mode: int, budget_bytes: int = 0) -> int:
         return stride_workspace_bytes(self.handle, mode, budget_bytes)
+
+    def gradient_path(self, ws_bytes: int):
+        """(path, forward steps, segments) of a gradient in ws_bytes
+        (STRIDE_PATH_*)."""
+        return stride_gradient_path(self.grid, self.nrec, ws_bytes)
 
     def workspace(self, mode: int, budget_bytes: int = 0, device=None):
         import torch

@@ -87,11 +87,24 @@ struct GradWs {
     float* residual;
     float* p;          // fourth order: k (L u^m + St^m), also the forward steps' p
     float* q;          // fourth order: k L w^{m+1}
-    std::vector<float*> pool;
+    std::vector<float*> pool;   // every field the workspace holds beyond the above
+    int peak;                   // fields the binomial schedule uses (pool[0, peak))
     int snaps;
 };
 
 int grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W);
+
+// How a gradient runs in a pool of `fields` wavefields (snaps: the binomial
+// schedule's snapshot count for that pool).
+struct GradPath {
+    enum Kind { kFull = 0, kSegmented = 1, kBinomial = 2 };
+    int kind = kBinomial;
+    std::vector<int> starts;      // segmented: segment starts (0 first; the last segment ends at nt)
+    int vbuf = 0;                 // segmented: v fields (the longest segment)
+    long long forward_steps = 0;  // forward step launches per gradient
+};
+
+GradPath grad_path(const stride_plan& P, long long fields, int snaps);
 
 // Views of a forward workspace: [scratch | k | u0 | u1 (| p, fourth order)
 // (| psi_a x 2, chi_a per axis, PML)].

@@ -318,6 +318,10 @@ int validate_grid(const stride_grid_t* g)
     if (g->interp != 0 && g->interp != 1)
         return fail(STRIDE_E_INVALID_ARG, "interp must be 0 (linear) or 1 (windowed sinc), got %d",
                     g->interp);
+    if (g->checkpointing != 0 && g->checkpointing != 1)
+        return fail(STRIDE_E_INVALID_ARG,
+                    "checkpointing must be 0 (library's choice) or 1 (binomial), got %d",
+                    g->checkpointing);
     if (g->boundary != 0 && g->boundary != 1)
         return fail(STRIDE_E_INVALID_ARG, "boundary must be 0 (sponge) or 1 (PML), got %d",
                     g->boundary);
@@ -405,11 +409,14 @@ int stride::grad_ws(const stride_plan& P, void* ws, size_t bytes, GradWs& W)
         W.q = (float*)b;
         b += L.field;
     }
+    // every field the workspace holds: the binomial schedule uses the first
+    // peak_fields, the segmented-history path all of them
     W.pool.clear();
-    for (int f = 0; f < st.peak_fields; ++f) {
+    for (long long f = 0; f < nfields; ++f) {
         W.pool.push_back((float*)b);
         b += L.field;
     }
+    W.peak = st.peak_fields;
     W.snaps = s;
     return STRIDE_OK;
 }
@@ -483,6 +490,58 @@ StepParams stride::base_params(const stride_plan& P)
     p.img = P.src_img;
     p.img_stride = P.nt;
     return p;
+}
+
+// Full history when every state fits; otherwise, for second-order time, the
+// segmented history when a cost model of the step kernels prefers it to the
+// binomial schedule with the fused two-stencil adjoint.  Step costs relative
+// to the plain forward step, measured on MI355X (3D 316^3 / 2D 1104^2):
+// forward keeping v 1.18 / 1.04, adjoint imaging from v in pairs 1.48 / 1.30,
+// fused adjoint 2.04 / 1.69.  The segment count is the smallest whose v buffer
+// and stored start states fit, which leaves the fewest steps to recompute.
+GradPath stride::grad_path(const stride_plan& P, long long fields, int snaps)
+{
+    GradPath g;
+    const long long nt = P.nt;
+    const long long fb = cached_schedule(P.nt, snaps)->stats.forward_steps;
+    g.forward_steps = fb * (P.torder == 4 ? 2 : 1);
+    if (fb <= nt - 1 && fields >= nt) {
+        g.kind = GradPath::kFull;
+        return g;
+    }
+    if (P.torder != 2 || P.g.checkpointing == 1)
+        return g;
+    const bool d3 = P.nd == 3;
+    const double c_fv = d3 ? 1.18 : 1.04, c_v = d3 ? 1.48 : 1.30, c_fused = d3 ? 2.04 : 1.69;
+    const double cost_b = (double)fb + c_fused * (double)nt;
+    for (long long K = 2;; ++K) {
+        const long long S = fields - 2 * (K - 1);   // v buffer beside K - 1 field pairs
+        const long long Se = S & ~1LL;
+        if (Se < 2)
+            break;
+        long long last = std::max(0LL, nt - S);
+        last += last & 1;                           // segment ends are even
+        if ((K - 1) * Se < last)
+            continue;
+        long long q = (last + K - 2) / (K - 1);
+        q += q & 1;
+        std::vector<int> st;
+        for (long long j = 0; j < last; j += q)
+            st.push_back((int)j);
+        st.push_back((int)last);
+        const long long vbuf = std::max(nt - last, q);
+        if (vbuf + 2 * ((long long)st.size() - 1) > fields)
+            break;
+        const double cost_s = (double)last + c_fv * (double)(nt - 1) + c_v * (double)nt;
+        if (cost_s < cost_b) {
+            g.kind = GradPath::kSegmented;
+            g.starts = std::move(st);
+            g.vbuf = (int)vbuf;
+            g.forward_steps = nt - 1 + last;
+        }
+        break;
+    }
+    return g;
 }
 
 // ------------------------------------------------------------ step cursor
@@ -701,6 +760,26 @@ long long phys_points(const stride_plan& P)
     return n;
 }
 
+// The fields of a plan that workspace sizes and gradient paths depend on,
+// without the device tables (host only).
+void geometry_free_plan(const stride_grid_t* grid, int nrec, stride_plan& P)
+{
+    P.g = *grid;
+    P.nd = grid->ndim;
+    P.nt = grid->nt;
+    P.torder = grid->time_order == 4 ? 4 : 2;
+    P.boundary = grid->boundary;
+    P.nrec = nrec;
+    P.nb = grid->sponge_cells;
+    Dims& d = P.dims;
+    d.nd = P.nd;
+    for (int a = 0; a < 3; ++a)
+        d.n[a] = a < P.nd ? (int)(grid->shape[a] + 2LL * P.nb) : 1;
+    int align = pitch_align();
+    long long pitch = round_up(d.n[P.nd - 1], align);
+    d.total = P.nd == 2 ? (long long)d.n[0] * pitch : (long long)d.n[0] * d.n[1] * pitch;
+}
+
 // ------------------------------------------------------------ executors
 
 // Runs a checkpointed gradient on one stream.  forward_phase launches the
@@ -726,12 +805,136 @@ struct Runner {
     // checkpointed path, so the results are the same bits.
     bool vpath = false;
 
+    // Segmented history (second order, when not every state fits and the
+    // cost model below prefers it): the forward sweep stores the states at
+    // the starts of the segments and v^n over the last segment; the adjoint
+    // takes the segments last to first, recomputing a segment's v^n from its
+    // stored start state (the first from x_0 = 0) just before its adjoint
+    // steps, and images from v as the full-history path does.  Every step
+    // before the last segment is recomputed once, more than the binomial
+    // schedule's recomputation, but each adjoint step then has one stencil
+    // field instead of two.  The same arithmetic, so the same bits.
+    bool segpath = false;
+    GradPath path;
+
     Runner(const stride_plan& p, GradWs& w, hipStream_t st, const float* wav)
-        : P(p), W(w), s(st), wavelet(wav), cursor(p.nt, w.snaps, (int)w.pool.size())
+        : P(p), W(w), s(st), wavelet(wav), cursor(p.nt, w.snaps, w.peak),
+          path(grad_path(p, (long long)w.pool.size(), w.snaps))
     {
-        const bool full = cursor.forward_steps() <= P.nt - 1 && (long long)W.pool.size() >= P.nt;
-        vpath = P.torder == 2 && full;
-        ppath = P.torder == 4 && full;
+        vpath = path.kind == GradPath::kFull && P.torder == 2;
+        ppath = path.kind == GradPath::kFull && P.torder == 4;
+        segpath = path.kind == GradPath::kSegmented;
+    }
+
+    // pool layout of the segmented path: v buffer [0, vbuf), two working
+    // fields, then the start state (u^j, u^{j-1}) of segments 1 .. K-2
+    float* seg_work(int i) const { return W.pool[path.vbuf + i]; }
+    float* seg_state(int k, int i) const { return W.pool[path.vbuf + 2 * k + i]; }
+
+    // One leapfrog step u[cur] = u^n, u[1-cur] = u^{n-1} -> u^{n+1} in place of
+    // u^{n-1}; with V it also keeps v^n there (kStepV).
+    void seg_step(float* const* u, int cur, int n, float* V, float* traces)
+    {
+        StepParams p = base_params(P);
+        p.A = u[cur];
+        p.B = u[1 - cur];
+        p.C = u[1 - cur];
+        p.K = W.k;
+        p.step = n;
+        p.inj_sig = wavelet;
+        if (traces)
+            p.smp = rec_samples(P, traces);
+        if (V) {
+            p.V = V;
+            launch_step_mode(P.dims, P.R, false, kStepV, P.cf, P.sp, P.ls_fwd, p, s);
+        } else {
+            launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
+        }
+        ++steps;
+        ++launches;
+    }
+
+    // Forward sweep of the segmented path (u rotates in the adjoint fields);
+    // returns the field of u^{nt-1}.
+    const float* forward_seg(float* traces)
+    {
+        const std::vector<int>& j = path.starts;
+        const int K = (int)j.size(), last = j[K - 1];
+        float* u[2] = {W.w[0], W.w[1]};
+        launch_fill(u[0], P.dims.total, 0.f, s);
+        launch_fill(u[1], P.dims.total, 0.f, s);
+        int cur = 0, next_state = 1;
+        for (int n = 0; n < P.nt - 1; ++n) {
+            seg_step(u, cur, n, n >= last ? W.pool[n - last] : nullptr, traces);
+            cur = 1 - cur;
+            if (next_state <= K - 2 && n + 1 == j[next_state]) {
+                launch_copy(seg_state(next_state, 0), u[cur], P.dims.total, s);
+                launch_copy(seg_state(next_state, 1), u[1 - cur], P.dims.total, s);
+                ++next_state;
+            }
+        }
+        // v^{nt-1} is held at zero, as on the full-history path
+        launch_fill(W.pool[P.nt - 1 - last], P.dims.total, 0.f, s);
+        return u[cur];
+    }
+
+    // Adjoint steps e-1 .. j with v^m in V[m - j] (imaging in pairs as in
+    // backward_v; segment ends other than nt are even, so a pair never
+    // straddles two segments).
+    void adjoint_v(int j, int e, float* const* V, int& wa, const float* grad_traces,
+                   float* dwavelet)
+    {
+        for (int m = e - 1; m >= j; --m) {
+            const bool image = (m % 2) == 0;
+            StepParams p = base_params(P);
+            p.A = W.w[wa];
+            p.B = W.w[1 - wa];
+            p.C = W.w[1 - wa];
+            p.K = W.k;
+            p.G = W.G;
+            p.V = V[m - j];
+            p.V2 = m + 1 < e ? V[m + 1 - j] : nullptr;
+            p.step = m;
+            p.inj = P.rec_inj;
+            p.inj_sig = grad_traces;
+            p.inj_stride = P.nt;
+            p.img = P.no_inj;
+            if (dwavelet)
+                p.smp = src_samples(P, dwavelet);
+            launch_step_mode(P.dims, P.R, true, image ? kImageV : kAdjPlain, P.cf, P.sp, P.ls_adj, p,
+                             s);
+            ++adj_steps;
+            ++adj_launches;
+            wa = 1 - wa;
+        }
+    }
+
+    void backward_seg(const float* grad_traces, float* dwavelet)
+    {
+        const std::vector<int>& j = path.starts;
+        const int K = (int)j.size();
+        int wa = 0;
+        for (int k = K - 1; k >= 0; --k) {
+            const int e = k + 1 < K ? j[k + 1] : P.nt;
+            if (k < K - 1) {
+                // recompute v^n, n in [j_k, e), from the segment's start state
+                float* u[2] = {k >= 1 ? seg_state(k, 0) : seg_work(0),
+                               k >= 1 ? seg_state(k, 1) : seg_work(1)};
+                if (k == 0) {
+                    launch_fill(u[0], P.dims.total, 0.f, s);
+                    launch_fill(u[1], P.dims.total, 0.f, s);
+                }
+                const int seg = g_timer.begin(s);
+                const long long s0 = steps, l0 = launches;
+                int cur = 0;
+                for (int n = j[k]; n < e; ++n) {
+                    seg_step(u, cur, n, W.pool[n - j[k]], nullptr);
+                    cur = 1 - cur;
+                }
+                g_timer.end(seg, s, 2, steps - s0, launches - l0);
+            }
+            adjoint_v(j[k], e, W.pool.data(), wa, grad_traces, dwavelet);
+        }
     }
 
     // Full history, fourth order: the forward's first launch writes p^n =
@@ -849,29 +1052,7 @@ struct Runner {
     void backward_v(const float* grad_traces, float* dwavelet)
     {
         int wa = 0;
-        for (int m = P.nt - 1; m >= 0; --m) {
-            const bool image = (m % 2) == 0;
-            StepParams p = base_params(P);
-            p.A = W.w[wa];
-            p.B = W.w[1 - wa];
-            p.C = W.w[1 - wa];
-            p.K = W.k;
-            p.G = W.G;
-            p.V = W.pool[m];
-            p.V2 = m + 1 <= P.nt - 1 ? W.pool[m + 1] : nullptr;
-            p.step = m;
-            p.inj = P.rec_inj;
-            p.inj_sig = grad_traces;
-            p.inj_stride = P.nt;
-            p.img = P.no_inj;
-            if (dwavelet)
-                p.smp = src_samples(P, dwavelet);
-            launch_step_mode(P.dims, P.R, true, image ? kImageV : kAdjPlain, P.cf, P.sp, P.ls_adj, p,
-                             s);
-            ++adj_steps;
-            ++adj_launches;
-            wa = 1 - wa;
-        }
+        adjoint_v(0, P.nt, W.pool.data(), wa, grad_traces, dwavelet);
     }
 
     void fwd_launch(const StepOp& op, float* traces)
@@ -1413,8 +1594,8 @@ int forward_save(const stride_plan& P, const float* vp, const float* wavelet, fl
     Runner run(P, W, s, wavelet);
     const float* last;
     int tid = g_timer.begin(s);
-    if (run.vpath || run.ppath) {
-        last = run.vpath ? run.forward_v(tr) : run.forward_p(tr);
+    if (run.vpath || run.ppath || run.segpath) {
+        last = run.vpath ? run.forward_v(tr) : run.ppath ? run.forward_p(tr) : run.forward_seg(tr);
         g_timer.end(tid, s, 0, run.steps, run.launches);
     } else {
         launch_fill(W.pool[0], P.dims.total, 0.f, s);
@@ -1446,7 +1627,7 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     if (rc)
         return rc;
     Runner run(P, W, s, wavelet);
-    if (!run.vpath && !run.ppath)
+    if (!run.vpath && !run.ppath && !run.segpath)
         run.forward_phase(false, nullptr);
     launch_fill(W.G, P.dims.total, 0.f, s);
     launch_fill(W.w[0], P.dims.total, 0.f, s);
@@ -1455,6 +1636,8 @@ int backward(const stride_plan& P, const float* vp, const float* wavelet, const 
     int tid = g_timer.begin(s);
     if (run.vpath)
         run.backward_v(grad_traces, dwavelet);
+    else if (run.segpath)
+        run.backward_seg(grad_traces, dwavelet);
     else if (run.ppath)
         run.backward_p(grad_traces, dwavelet);
     else
@@ -1949,20 +2132,7 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
         return fail(STRIDE_E_INVALID_ARG, "bad arguments");
     // the tables do not change the workspace: a geometry-free plan suffices
     stride_plan P{};
-    P.g = *grid;
-    P.nd = grid->ndim;
-    P.nt = grid->nt;
-    P.torder = grid->time_order == 4 ? 4 : 2;
-    P.boundary = grid->boundary;
-    P.nrec = nrec;
-    P.nb = grid->sponge_cells;
-    Dims& d = P.dims;
-    d.nd = P.nd;
-    for (int a = 0; a < 3; ++a)
-        d.n[a] = a < P.nd ? (int)(grid->shape[a] + 2LL * P.nb) : 1;
-    int align = pitch_align();
-    long long pitch = round_up(d.n[P.nd - 1], align);
-    d.total = P.nd == 2 ? (long long)d.n[0] * pitch : (long long)d.n[0] * d.n[1] * pitch;
+    geometry_free_plan(grid, nrec, P);
     return stride_workspace_bytes(&P, mode, budget_bytes, out_bytes);
 }
 
@@ -2047,6 +2217,37 @@ int stride_timing_read(double* fwd_ms, int64_t* fwd_steps, int64_t* fwd_launches
         *adj_steps = n[1];
     if (adj_launches)
         *adj_launches = l[1];
+    return STRIDE_OK;
+}
+
+int stride_gradient_path(const stride_grid_t* grid, int32_t nrec, size_t ws_bytes, int32_t* path,
+                         int64_t* forward_steps, int32_t* segments)
+{
+    g_err.clear();
+    int rc = validate_grid(grid);
+    if (rc)
+        return rc;
+    if (nrec < 0)
+        return fail(STRIDE_E_INVALID_ARG, "nrec must be >= 0");
+    if (grid->boundary == 1)
+        return fail(STRIDE_E_INVALID_ARG, "the PML is offered for forward solves only");
+    stride_plan P{};
+    geometry_free_plan(grid, nrec, P);
+    Layout L = layout_of(P);
+    if (ws_bytes < L.fixed_grad + 4 * L.field)
+        return fail(STRIDE_E_WORKSPACE, "gradient workspace needs at least %zu bytes (got %zu)",
+                    L.fixed_grad + 4 * L.field, ws_bytes);
+    const long long nfields = (long long)((ws_bytes - L.fixed_grad) / L.field);
+    const int sn = snaps_for_fields(P.nt, nfields);
+    if (sn < 0)
+        return fail(STRIDE_E_WORKSPACE, "workspace too small for checkpointing");
+    GradPath g = grad_path(P, nfields, sn);
+    if (path)
+        *path = g.kind;
+    if (forward_steps)
+        *forward_steps = g.forward_steps;
+    if (segments)
+        *segments = g.kind == GradPath::kSegmented ? (int32_t)g.starts.size() : 0;
     return STRIDE_OK;
 }
 

@@ -485,7 +485,7 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         if (rc)
             return rc;
         launch_prep_k(plan->dims, vp, plan->g.dt, J.W.k, s);
-        J.cursor = std::make_unique<StepCursor>(plan->nt, J.W.snaps, (int)J.W.pool.size());
+        J.cursor = std::make_unique<StepCursor>(plan->nt, J.W.snaps, J.W.peak);
         // every state fits: the forward keeps v^n (p^n) and the adjoint images
         // from it, the single-shot full-history path (the same bits)
         J.history = J.cursor->forward_steps() <= plan->nt - 1 &&

@@ -186,6 +186,39 @@ def test_medium_gradient_workspace_budget():
     assert e.value.code == _abi.STRIDE_E_WORKSPACE
 
 
+def test_gradient_path_choice():
+    """Full history when every state fits; for second order below that the
+    segmented history (each step before the last segment recomputed once) while
+    it is cheaper than the binomial schedule, binomial for very small pools,
+    fourth order, or when asked for; a larger workspace never needs more
+    forward steps."""
+    g = _grid(shape=(60, 70, 80), spacing=0.5e-3, nb=6, dt=0.3 * 0.5e-3 / 1500, nt=400)
+    full = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT)
+    assert S.stride_gradient_path(g, 3, full) == (S.STRIDE_PATH_FULL_HISTORY, 399, 0)
+    prev = None
+    for frac in (0.9, 0.6, 0.3):
+        b = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT, int(full * frac))
+        path, fsteps, nseg = S.stride_gradient_path(g, 3, b)
+        assert path == S.STRIDE_PATH_SEGMENTED and nseg >= 2, frac
+        assert 399 < fsteps < 2 * 399
+        assert prev is None or fsteps >= prev
+        prev = fsteps
+        gb = _grid(shape=(60, 70, 80), spacing=0.5e-3, nb=6, dt=0.3 * 0.5e-3 / 1500, nt=400,
+                   checkpointing=1)
+        pb, fb, nb_ = S.stride_gradient_path(gb, 3, b)
+        assert pb == S.STRIDE_PATH_BINOMIAL and nb_ == 0 and 399 < fb
+    small = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT, int(full * 0.02))
+    assert S.stride_gradient_path(g, 3, small)[0] == S.STRIDE_PATH_BINOMIAL
+    g4 = _grid(shape=(60, 70, 80), spacing=0.5e-3, nb=6, dt=0.3 * 0.5e-3 / 1500, nt=400,
+               time_order=4)
+    b4 = S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT,
+                                  S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT) // 3)
+    assert S.stride_gradient_path(g4, 3, b4)[0] == S.STRIDE_PATH_BINOMIAL
+    with pytest.raises(S.StrideError) as e:
+        S.stride_gradient_path(_grid(checkpointing=2), 3, full)
+    assert e.value.code == _abi.STRIDE_E_INVALID_ARG
+
+
 @lru_cache(None)
 def _dp(l, s):
     """Brute-force minimal forward steps to reverse l steps with s free slots."""

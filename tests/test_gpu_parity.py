@@ -131,6 +131,47 @@ def test_checkpointing_is_bitwise_invisible(maker, kw):
         assert torch.equal(m0, m2)
 
 
+@pytest.mark.parametrize("maker,kw", [(W.tiny_2d, dict(nt=90)), (W.tiny_2d, dict(nt=91)),
+                                      (W.tiny_3d, dict(nt=50)), (W.tiny_3d, dict(nt=51))])
+def test_gradient_paths_give_the_same_bits(maker, kw):
+    """Full history, segmented history and binomial checkpointing (the same
+    workspace, checkpointing = 1 forcing the last) give the same bits: the
+    gradient with its misfit, and the split forward / backward with the
+    wavelet cotangent; both parities of nt, several segment counts."""
+    w = maker(**kw)
+    plan = S.Plan.from_workload(w)
+    plan_b = S.Plan.from_workload(w, checkpointing=1)
+    rng = np.random.default_rng(7)
+    obs = dev(rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32) * 1e-3)
+    gtr = dev(rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32))
+    vp, wav = dev(w.vp), dev(w.wavelet)
+
+    def vjp(p, ws):
+        tr = torch.empty((p.nrec, p.nt), dtype=torch.float32, device="cuda")
+        S.stride_forward_save(p.handle, vp, wav, tr, ws)
+        dvp, dw = torch.empty_like(vp), torch.zeros_like(wav)
+        S.stride_backward(p.handle, vp, wav, gtr, dvp, dw, ws)
+        return tr, dvp, dw
+
+    full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
+    ws_full = plan.workspace(S.STRIDE_MODE_GRADIENT)
+    m0, g0 = plan.gradient(vp, wav, obs, ws=ws_full)
+    v0 = vjp(plan, ws_full)
+    seen = set()
+    for frac in (0.7, 0.45, 0.25):
+        ws = plan.workspace(S.STRIDE_MODE_GRADIENT, int(full * frac))
+        path = plan.gradient_path(ws.numel())
+        seen.add(path[0])
+        print(f"{w.shape} nt={w.nt} frac={frac}: path {path}", flush=True)
+        for p in (plan, plan_b):
+            m1, g1 = p.gradient(vp, wav, obs, ws=ws)
+            assert torch.equal(m0, m1) and torch.equal(g0, g1), (frac, p.grid.checkpointing)
+            v1 = vjp(p, ws)
+            assert all(torch.equal(a, b) for a, b in zip(v0, v1)), (frac, p.grid.checkpointing)
+        del ws
+    assert S.STRIDE_PATH_SEGMENTED in seen
+
+
 def _dense_geometry(w, nsrc, nrec, seed):
     """Sources and receivers packed into a few cells around one point: one
     step-kernel block gets more injection entries than it has threads, some
