@@ -58,6 +58,9 @@ MEASURED_TRAFFIC = {
     "config4/fused": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
                       "fetch_kib": 477528.27, "write_kib": 249640.00,
                       "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
+    "config4/pair": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
+                     "fetch_kib": 323894.58, "write_kib": 187230.00,
+                     "copy_fetch_kib": 524315.12, "copy_write_kib": 1048576.0},
     "config4/forward": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
                         "fetch_kib": 240887.80, "write_kib": 124846.85,
                         "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
@@ -131,6 +134,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-forward", action="store_true")
+    ap.add_argument("--binomial", action="store_true",
+                    help="headline gradient with binomial checkpointing (checkpointing = 1)")
+    ap.add_argument("--no-binomial", action="store_true",
+                    help="skip the binomial-checkpointing leg beside a checkpointed headline")
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the extra config-2 (2D breast) shot gradient and forward")
     ap.add_argument("--no-serving", action="store_true", help="skip the bounded serving leg")
@@ -432,18 +439,20 @@ def _timed(fn, steps, label=None):
     return t1 - t0, S.stride_timing_read()
 
 
-def measure(name, args, dev, headline):
+def measure(name, args, dev, headline, built=None, checkpointing=0, forward=True):
     """Shot gradient and forward solve of one workload: timing of the whole
-    step, and per-kernel figures from the library's HIP events."""
+    step, and per-kernel figures from the library's HIP events.  built: the
+    (workload, vp_true, vp_model) of an earlier call; checkpointing 1 forces
+    binomial checkpointing."""
     import torch
 
     import paper_2110_03345_amd as S
 
-    w, vp_true, vp_model = build_workload(name, args.nt)
+    w, vp_true, vp_model = built or build_workload(name, args.nt)
     npad = w.padded_points
     print(f"[bench] {name}: padded {w.padded_shape} = {npad} points, nt={w.nt}",
           file=sys.stderr, flush=True)
-    plan = S.Plan.from_workload(w)
+    plan = S.Plan.from_workload(w, checkpointing=checkpointing)
     vp_t = torch.from_numpy(vp_true).to(dev)
     vp_m = torch.from_numpy(vp_model).to(dev)
     wav = torch.from_numpy(w.wavelet).to(dev)
@@ -518,7 +527,7 @@ def measure(name, args, dev, headline):
             "achieved": fwd_in_grad_bytes * npad / fwd_step_s / 1e9,
         },
     }
-    if not args.no_forward:
+    if forward and not args.no_forward:
         del ws
         fws = plan.workspace(S.STRIDE_MODE_FORWARD, device=dev)
         plan.forward(vp_m, wav, traces=traces, ws=fws)
@@ -707,12 +716,30 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    m = measure(args.workload, args, dev, headline=True)
+    m = measure(args.workload, args, dev, headline=True, checkpointing=1 if args.binomial else 0)
     w, npad = m["w"], m["npad"]
+    binomial = None
+    if not args.binomial and not args.no_binomial and m["gradient_path"] != "full history":
+        # the same gradient with binomial checkpointing in the same budget
+        torch.cuda.empty_cache()
+        b = measure(args.workload, args, dev, headline=False,
+                    built=(w, m["vp_true"], m["vp_model"]), checkpointing=1, forward=False)
+        btraffic = measured_traffic(b["traffic_key"])
+        binomial = {
+            "gradient_path": b["gradient_path"], "ms_per_step": b["ms_per_step"],
+            "updates_per_s": b["value"], "steps": b["steps"],
+            "forward_steps_per_gradient": b["forward_steps_per_gradient"],
+            "recompute_factor": b["recompute_factor"], "adjoint": b["adjoint"],
+            "forward_in_gradient": b["forward_in_gradient"], "traffic": btraffic,
+            "traffic_over_algorithmic": (btraffic / (b["adjoint"]["bytes_per_point"] * npad))
+                                        if btraffic else None,
+        }
+        del b
+        torch.cuda.empty_cache()
     extra = variants(m, args, dev)
     obs_np = m["obs"].cpu().numpy()
     for k in ("plan", "obs"):
-        m.pop(k)
+        m.pop(k, None)
     torch.cuda.empty_cache()
 
     adj = m["adjoint"]
@@ -791,6 +818,7 @@ def main():
         },
         "roofline": roofline,
         "fwd_updates_per_s": m["forward"]["updates_per_s"] if "forward" in m else None,
+        "binomial": binomial,
         **legs,
         **extra,
         "cpu_baseline": cpu,

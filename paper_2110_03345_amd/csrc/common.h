@@ -16,10 +16,13 @@ constexpr int kSincHalfWidth = 4;   // windowed-sinc taps: 2 r nodes per axis
 // Launch shapes of the step kernels: rows per thread x wave64s per block (the
 // tile is 64 x rows * waves) and, in 3D, planes per block.  The fastest
 // measured on 1104^2 and 316^3.  The 3D adjoint shape also serves every step
-// with two stencil fields (adjoint, fourth-order adjoint correction, medium).
+// with two stencil fields (adjoint, fourth-order adjoint correction, medium);
+// the adjoint steps that image from a stored v (one stencil field) take a
+// taller tile of their own, with the adjoint's chunk length.
 constexpr int kRy2d = 4, kWaves2d = 4;
 constexpr int kRy3dFwd = 4, kWaves3dFwd = 8, kZc3dFwd = 32;
 constexpr int kRy3dAdj = 2, kWaves3dAdj = 4, kZc3dAdj = 16;
+constexpr int kRy3dAdjV = 4, kWaves3dAdjV = 4;
 constexpr int kPitchAlign = 16;     // row pitch of the fields, in floats (64 B)
 
 // Padded grid as laid out in the workspace.  Axis nd-1 is contiguous.
@@ -130,6 +133,8 @@ struct LaunchShape {
 // Rows per thread and waves per block of the step kernels for a dimension
 // and direction (the tile is 64 x ry*waves).
 void tile_shape(int nd, bool adjoint, int* ry, int* waves);
+// Shape of the adjoint steps imaging from a stored v (kImageV, kAdjPlain).
+void tile_shape_v(int nd, int* ry, int* waves);
 
 // What a step launch computes.  Fourth-order time runs two launches per
 // forward step and three per adjoint step (kPrep on u^m and on w^{m+1}, then

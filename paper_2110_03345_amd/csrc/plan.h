@@ -25,6 +25,7 @@ struct stride_plan {
     stride::Fd1 fd1;     // first-derivative weights in FP64 (medium preparation)
     stride::SpongeCoef sp;
     stride::LaunchShape ls_fwd, ls_adj;
+    stride::LaunchShape ls_adjv;         // adjoint steps imaging from a stored v
     double nyquist;      // -(c0 + 2 sum_j cj (-1)^j): largest eigenvalue of -L per axis
     double cellvol;
     int nsrc, nrec;
@@ -34,7 +35,8 @@ struct stride_plan {
     stride::InjTable src_inj;    // sources, weights / cell volume (blocks of ls_fwd)
     stride::InjTable src_img;    // the same entries, blocks of ls_adj (imaging source term)
     stride::InjTable rec_inj;    // receivers (adjoint injection), weights (blocks of ls_adj)
-    stride::InjTable no_inj;     // no entries (blocks of either shape)
+    stride::InjTable rec_inj_v;  // the same entries, blocks of ls_adjv
+    stride::InjTable no_inj;     // no entries (blocks of any shape)
     const long long* rec_idx;
     const float* rec_w;          // receiver sampling
     const long long* src_idx;

@@ -986,8 +986,9 @@ __global__ __launch_bounds__(64 * WAVES) void step3d_batched(Dims d, StencilCoef
 }
 
 // Tile shapes with compiled kernels (rows per thread, waves); tile_shape()
-// returns one of these.  Without STRIDE_TILE_SWEEP: the 2D shape and the two
-// 3D shapes (forward, and adjoint / two-field steps) of common.h.
+// returns one of these.  Without STRIDE_TILE_SWEEP: the 2D shape and the three
+// 3D shapes (forward, adjoint / two-field steps, and adjoint steps imaging
+// from v) of common.h.
 #ifdef STRIDE_TILE_SWEEP
 #define STRIDE_DISPATCH2D(L)                                                                      \
     do {                                                                                          \
@@ -1023,6 +1024,12 @@ __global__ __launch_bounds__(64 * WAVES) void step3d_batched(Dims d, StencilCoef
         if constexpr (!ADJ) {                                                                     \
             if (ls.ry == kRy3dFwd && ls.waves == kWaves3dFwd) {                                   \
                 L(kRy3dFwd, kWaves3dFwd);                                                         \
+                break;                                                                            \
+            }                                                                                     \
+        }                                                                                         \
+        if constexpr (ADJ && (MODE == kImageV || MODE == kAdjPlain)) {                            \
+            if (ls.ry == kRy3dAdjV && ls.waves == kWaves3dAdjV) {                                 \
+                L(kRy3dAdjV, kWaves3dAdjV);                                                       \
                 break;                                                                            \
             }                                                                                     \
         }                                                                                         \

@@ -895,13 +895,13 @@ struct Runner {
             p.V = V[m - j];
             p.V2 = m + 1 < e ? V[m + 1 - j] : nullptr;
             p.step = m;
-            p.inj = P.rec_inj;
+            p.inj = P.rec_inj_v;
             p.inj_sig = grad_traces;
             p.inj_stride = P.nt;
             p.img = P.no_inj;
             if (dwavelet)
                 p.smp = src_samples(P, dwavelet);
-            launch_step_mode(P.dims, P.R, true, image ? kImageV : kAdjPlain, P.cf, P.sp, P.ls_adj, p,
+            launch_step_mode(P.dims, P.R, true, image ? kImageV : kAdjPlain, P.cf, P.sp, P.ls_adjv, p,
                              s);
             ++adj_steps;
             ++adj_launches;
@@ -1814,11 +1814,13 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
         }
     }
 
-    int ryf, wf, rya, wa;
+    int ryf, wf, rya, wa, ryv, wv;
     tile_shape(P->nd, false, &ryf, &wf);
     tile_shape(P->nd, true, &rya, &wa);
+    tile_shape_v(P->nd, &ryv, &wv);
     P->ls_fwd = make_shape(d, default_zc(d, false), ryf, wf);
     P->ls_adj = make_shape(d, default_zc(d, true), rya, wa);
+    P->ls_adjv = make_shape(d, default_zc(d, true), ryv, wv);
 
 
     TapSet st, rt;
@@ -1830,6 +1832,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     HostTiles tsf = build_tiles(*P, st, 1.0 / P->cellvol, P->ls_fwd);
     HostTiles tsa = build_tiles(*P, st, 1.0 / P->cellvol, P->ls_adj);
     HostTiles tra = build_tiles(*P, rt, 1.0, P->ls_adj);
+    HostTiles trv = build_tiles(*P, rt, 1.0, P->ls_adjv);
     std::vector<long long> ridx, sidx;
     std::vector<float> rw, sw;
     flatten_sample(rt, 1.0, ridx, rw);
@@ -1855,7 +1858,11 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     size_t o_tsa_ent = add(tsa.ent.data(), tsa.ent.size(), sizeof(TileEntry));
     size_t o_tra_ptr = add(tra.ptr.data(), tra.ptr.size(), 4);
     size_t o_tra_ent = add(tra.ent.data(), tra.ent.size(), sizeof(TileEntry));
-    std::vector<int> none((size_t)std::max(P->ls_fwd.tile_blocks, P->ls_adj.tile_blocks) + 1, 0);
+    size_t o_trv_ptr = add(trv.ptr.data(), trv.ptr.size(), 4);
+    size_t o_trv_ent = add(trv.ent.data(), trv.ent.size(), sizeof(TileEntry));
+    std::vector<int> none(
+        (size_t)std::max({P->ls_fwd.tile_blocks, P->ls_adj.tile_blocks, P->ls_adjv.tile_blocks}) + 1,
+        0);
     size_t o_none = add(none.data(), none.size(), 4);
     std::vector<char> host(off, 0);
     for (auto& pt : parts)
@@ -1876,6 +1883,7 @@ int stride_plan_create(const stride_grid_t* grid, int32_t nsrc, const double* sr
     P->src_inj = InjTable{(const int*)(B + o_tsf_ptr), (const TileEntry*)(B + o_tsf_ent)};
     P->src_img = InjTable{(const int*)(B + o_tsa_ptr), (const TileEntry*)(B + o_tsa_ent)};
     P->rec_inj = InjTable{(const int*)(B + o_tra_ptr), (const TileEntry*)(B + o_tra_ent)};
+    P->rec_inj_v = InjTable{(const int*)(B + o_trv_ptr), (const TileEntry*)(B + o_trv_ent)};
     P->no_inj = InjTable{(const int*)(B + o_none), (const TileEntry*)(B + o_tra_ent)};
 
     P->rec_idx = (const long long*)(B + o_ridx);

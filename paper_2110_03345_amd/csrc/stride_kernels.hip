@@ -73,6 +73,31 @@ void tile_shape(int nd, bool adjoint, int* ry, int* waves)
 #endif
 }
 
+void tile_shape_v(int nd, int* ry, int* waves)
+{
+    if (nd == 2) {
+        tile_shape(nd, true, ry, waves);
+        return;
+    }
+#ifdef STRIDE_TILE_SWEEP
+    const char* er = getenv("STRIDE_RY3D_ADJV");
+    const char* ew = getenv("STRIDE_WAVES3D_ADJV");
+    int r = er && *er ? atoi(er) : kRy3dAdjV;
+    int w = ew && *ew ? atoi(ew) : kWaves3dAdjV;
+    if (w != 8)
+        w = 4;
+    if (r != 1 && r != 2)
+        r = 4;
+    if (w == 4 && r == 1)
+        r = 2;
+    *ry = r;
+    *waves = w;
+#else
+    *ry = kRy3dAdjV;
+    *waves = kWaves3dAdjV;
+#endif
+}
+
 namespace {
 
 // ------------------------------------------------------------ small kernels
