@@ -52,18 +52,18 @@ MEASURED_TRAFFIC = {
     # turn; per-dispatch figures averaged over the pair), "fused" = the adjoint
     # with its own stencil of u^m (mode 0, binomial checkpointing), "forward" =
     # the plain forward step of a forward solve
-    "config2/pair": {"sha256": "bb0de64b1359e09888b5b6d0c99f20c9bc2ace4d211b12bbed461d09d735f779",
-                     "fetch_kib": 11025.57, "write_kib": 7153.94,
-                     "copy_fetch_kib": 524308.44, "copy_write_kib": 1048576.0},
-    "config4/fused": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
-                      "fetch_kib": 477528.27, "write_kib": 249640.00,
-                      "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
-    "config4/pair": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
-                     "fetch_kib": 323894.58, "write_kib": 187230.00,
-                     "copy_fetch_kib": 524315.12, "copy_write_kib": 1048576.0},
-    "config4/forward": {"sha256": "b78b5289d5ef939623548f156acd92d43fd1159330c14e288a1b5774c9f53859",
-                        "fetch_kib": 240887.80, "write_kib": 124846.85,
-                        "copy_fetch_kib": 524314.88, "copy_write_kib": 1048576.0},
+    "config2/pair": {"sha256": "a3a270b9d6f6091d300dcb38d0a3b444e81e7962e9e1de5ce89ad9c84cea5057",
+                     "fetch_kib": 10940.59, "write_kib": 7153.05,
+                     "copy_fetch_kib": 524308.00, "copy_write_kib": 1048576.0},
+    "config4/pair": {"sha256": "a3a270b9d6f6091d300dcb38d0a3b444e81e7962e9e1de5ce89ad9c84cea5057",
+                     "fetch_kib": 338138.13, "write_kib": 187230.00,
+                     "copy_fetch_kib": 524315.50, "copy_write_kib": 1048576.0},
+    "config4/fused": {"sha256": "a3a270b9d6f6091d300dcb38d0a3b444e81e7962e9e1de5ce89ad9c84cea5057",
+                      "fetch_kib": 477481.36, "write_kib": 249640.00,
+                      "copy_fetch_kib": 524308.00, "copy_write_kib": 1048576.0},
+    "config4/forward": {"sha256": "a3a270b9d6f6091d300dcb38d0a3b444e81e7962e9e1de5ce89ad9c84cea5057",
+                        "fetch_kib": 240994.32, "write_kib": 124852.00,
+                        "copy_fetch_kib": 524315.50, "copy_write_kib": 1048576.0},
 }
 
 
