@@ -71,9 +71,19 @@ struct SlotJob {
     std::unique_ptr<StepCursor> cursor;  // checkpointed gradient
     bool history = false;                // gradient keeping v^n (second order) or p^n (fourth)
     int phase = 0;                       // gradient: 0 forward sweep, 1 recompute + adjoint
-    int m = 0;                           // full-history adjoint: next step
+    int m = 0;                           // full-history / segmented adjoint: next step
     int wa = 0;                          // adjoint ping-pong
     long long left = 0;                  // ticks until the current phase ends
+    // segmented history: segment starts, v buffer pool[0, vbuf), working pair
+    // pool[vbuf], pool[vbuf + 1], start state of segment k in pool[vbuf + 2k],
+    // pool[vbuf + 2k + 1]; fc / fp hold u^n / u^{n-1} of the sweep in progress
+    bool seg = false;
+    GradPath path;
+    int sk = 0;                          // phase 1: segment in progress
+    bool recompute = false;              // phase 1: recomputing segment sk's v
+    int rn = 0;                          // recompute: next step
+    float* fc = nullptr;
+    float* fp = nullptr;
 };
 
 bool same_layout(const Dims& a, const Dims& b)
@@ -93,6 +103,7 @@ struct stride_engine {
     int R;
     StencilCoef cf;
     LaunchShape ls_fwd, ls_adj;
+    LaunchShape ls_adjv;      // adjoint steps imaging from a stored v (the single-shot shape)
     int max_slots, max_samples, tmax;
     int ntap;                 // taps per receiver of the engine's grid (linear or sinc)
     bool graphs;
@@ -166,9 +177,93 @@ void forward_rows(const stride_plan& P, TickRows& R, const float* A, const float
     R.add(kGFwdCorrect, make_row(P, q));
 }
 
+// Adjoint step m imaging from v^m = V[m - j] (pairs as on the full-history
+// path; V2 only inside [j, e)).
+void adjoint_v_row(const stride_plan& P, TickRows& R, SlotJob& J, int m, int j, int e)
+{
+    StepParams c = base_params(P);
+    c.A = J.W.w[J.wa];
+    c.B = J.W.w[1 - J.wa];
+    c.C = J.W.w[1 - J.wa];
+    c.K = J.W.k;
+    c.G = J.W.G;
+    c.step = m;
+    c.inj = P.rec_inj_v;
+    c.inj_sig = J.W.residual;
+    c.inj_stride = P.nt;
+    c.img = P.no_inj;
+    c.V = J.W.pool[m - j];
+    c.V2 = m + 1 < e ? J.W.pool[m + 1 - j] : nullptr;
+    R.add(m % 2 == 0 ? kGAdjImage : kGAdjPlain, make_row(P, c));
+    J.wa = 1 - J.wa;
+}
+
+// Segmented history, forward sweep: the field that receives u^t.  The start
+// states x_{j_k} (k = 1 .. K-2) land in their pool pair directly (u^{j_k - 1}
+// then u^{j_k}), so no copies are needed; every other step writes in place of
+// u^{n-1} when that is a working field (the adjoint fields, free until the
+// adjoint starts) and into the other working field otherwise.
+float* seg_sweep_target(const SlotJob& J, int t)
+{
+    const std::vector<int>& j = J.path.starts;
+    for (int k = 1; k + 1 < (int)j.size(); ++k) {
+        if (t == j[k])
+            return J.W.pool[J.path.vbuf + 2 * k];
+        if (t == j[k] - 1)
+            return J.W.pool[J.path.vbuf + 2 * k + 1];
+    }
+    if (J.fp == J.W.w[0] || J.fp == J.W.w[1])
+        return J.fp;
+    return J.fc == J.W.w[0] ? J.W.w[1] : J.W.w[0];
+}
+
+int fill_seg(SlotJob& J, TickRows& R)
+{
+    const stride_plan& P = *J.P;
+    const std::vector<int>& st = J.path.starts;
+    const int K = (int)st.size(), last = st[K - 1];
+    if (J.phase == 0) {
+        const int n = J.n;
+        float* C = seg_sweep_target(J, n + 1);
+        forward_rows(P, R, J.fc, J.fp, C, J.W.k, n, J.wavelet, rec_samples(P, J.W.traces), nullptr,
+                     n >= last ? J.W.pool[n - last] : nullptr);
+        J.fp = J.fc;
+        J.fc = C;
+        ++J.n;
+        return STRIDE_OK;
+    }
+    const int j = st[J.sk], e = J.sk + 1 < K ? st[J.sk + 1] : P.nt;
+    if (J.recompute) {
+        // v^n of segment sk from its start state, u in place
+        const int n = J.rn++;
+        forward_rows(P, R, J.fc, J.fp, J.fp, J.W.k, n, J.wavelet, SampleSet{}, nullptr,
+                     J.W.pool[n - j]);
+        std::swap(J.fc, J.fp);
+        if (J.rn == e) {
+            J.recompute = false;
+            J.m = e - 1;
+        }
+        return STRIDE_OK;
+    }
+    const int m = J.m--;
+    adjoint_v_row(P, R, J, m, j, e);
+    if (m == j && J.sk > 0) {
+        // next: segment sk - 1, recomputed from its start state (x_0 = 0 in
+        // the zeroed working pair for the first segment)
+        const int k = --J.sk;
+        J.recompute = true;
+        J.rn = st[k];
+        J.fc = J.W.pool[J.path.vbuf + 2 * k];
+        J.fp = J.W.pool[J.path.vbuf + 2 * k + 1];
+    }
+    return STRIDE_OK;
+}
+
 int fill_tick(SlotJob& J, TickRows& R)
 {
     const stride_plan& P = *J.P;
+    if (J.seg)
+        return fill_seg(J, R);
     if (J.mode == STRIDE_MODE_FORWARD) {
         forward_rows(P, R, J.F.u[J.cur], J.F.u[1 - J.cur], J.F.u[1 - J.cur], J.F.k, J.n, J.wavelet,
                      rec_samples(P, J.traces), J.F.p, nullptr);
@@ -187,6 +282,11 @@ int fill_tick(SlotJob& J, TickRows& R)
             return STRIDE_OK;
         }
         const int m = J.m--;
+        if (P.torder == 2) {
+            // imaging terms in pairs: odd m leaves G alone, even m adds both
+            adjoint_v_row(P, R, J, m, 0, P.nt);
+            return STRIDE_OK;
+        }
         StepParams c = base_params(P);
         c.B = J.W.w[1 - J.wa];
         c.C = J.W.w[1 - J.wa];
@@ -197,25 +297,18 @@ int fill_tick(SlotJob& J, TickRows& R)
         c.inj_sig = J.W.residual;
         c.inj_stride = P.nt;
         c.img = P.no_inj;
-        if (P.torder == 2) {
-            // imaging terms in pairs: odd m leaves G alone, even m adds both
-            c.A = J.W.w[J.wa];
-            c.V = J.W.pool[m];
-            c.V2 = m + 1 <= P.nt - 1 ? J.W.pool[m + 1] : nullptr;
-            R.add(m % 2 == 0 ? kGAdjImage : kGAdjPlain, make_row(P, c));
-        } else {
-            StepParams q = base_params(P);
-            q.A = J.W.w[J.wa];
-            q.C = J.W.q;
-            q.K = J.W.k;
-            q.step = m;
-            q.inj = P.no_inj;
-            R.add(kGPrep, make_row(P, q));
-            c.A = J.W.q;
-            c.U = J.W.pool[m];
-            c.D = J.W.w[J.wa];
-            R.add(kGAdjCorrect, make_row(P, c));
-        }
+        // fourth order: q = k L w^{m+1}, then the correction with p^m from the history
+        StepParams q = base_params(P);
+        q.A = J.W.w[J.wa];
+        q.C = J.W.q;
+        q.K = J.W.k;
+        q.step = m;
+        q.inj = P.no_inj;
+        R.add(kGPrep, make_row(P, q));
+        c.A = J.W.q;
+        c.U = J.W.pool[m];
+        c.D = J.W.w[J.wa];
+        R.add(kGAdjCorrect, make_row(P, c));
         J.wa = 1 - J.wa;
         return STRIDE_OK;
     }
@@ -282,8 +375,11 @@ void launch_chunk(stride_engine* E, int ticks, const int* gy, hipStream_t s)
             const bool adj = kGroupAdjoint[g];
             // traces are sampled by the forward step (fourth order: its kPrep row)
             const bool smp = g == kGFwd || g == kGFwdV || g == kGPrep;
-            launch_step_batched(E->dims, E->R, adj, kGroupMode[g], E->cf, adj ? E->ls_adj : E->ls_fwd,
-                                base + E->group_off[g], gy[g], smp ? sample_threads : 0, s);
+            const LaunchShape& ls = !adj                                     ? E->ls_fwd
+                                    : (g == kGAdjImage || g == kGAdjPlain) ? E->ls_adjv
+                                                                           : E->ls_adj;
+            launch_step_batched(E->dims, E->R, adj, kGroupMode[g], E->cf, ls, base + E->group_off[g],
+                                gy[g], smp ? sample_threads : 0, s);
         }
     }
 }
@@ -319,6 +415,8 @@ int get_exec(stride_engine* E, int ticks, const int* gy, hipStream_t s, hipGraph
 long long second_phase_ticks(const SlotJob& J)
 {
     const int nt = J.P->nt;
+    if (J.seg)
+        return nt + J.path.starts.back();
     return J.history ? nt : J.cursor->forward_steps() - (nt - 1) + nt;
 }
 
@@ -334,7 +432,9 @@ void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
     }
     if (J.phase == 0) {
         // the forward sweep ended in x_{nt-1}: last sample, residual, misfit
-        const float* last = J.history ? J.W.w[J.cur] : J.W.pool[J.cursor->cur()];
+        const float* last = J.seg       ? J.fc
+                            : J.history ? J.W.w[J.cur]
+                                        : J.W.pool[J.cursor->cur()];
         launch_sample(rec_samples(P, J.W.traces), last, P.nt - 1, s);
         launch_residual_misfit(J.W.traces, J.observed, J.W.residual, (long long)P.nrec * P.nt,
                                J.misfit, J.W.partial, s);
@@ -346,6 +446,18 @@ void end_phase(stride_engine* E, SlotJob& J, hipStream_t s)
             launch_fill(J.W.pool[P.nt - 1], P.dims.total, 0.f, s);
             launch_fill(J.W.w[0], P.dims.total, 0.f, s);
             launch_fill(J.W.w[1], P.dims.total, 0.f, s);
+            J.m = P.nt - 1;
+            J.wa = 0;
+        }
+        if (J.seg) {
+            // as above for the last segment's v buffer; the working pair
+            // holds x_0 = 0 for the first segment's recomputation
+            const int last_start = J.path.starts.back();
+            launch_fill(J.W.pool[P.nt - 1 - last_start], P.dims.total, 0.f, s);
+            for (float* f : {J.W.w[0], J.W.w[1], J.W.pool[J.path.vbuf], J.W.pool[J.path.vbuf + 1]})
+                launch_fill(f, P.dims.total, 0.f, s);
+            J.sk = (int)J.path.starts.size() - 1;
+            J.recompute = false;
             J.m = P.nt - 1;
             J.wa = 0;
         }
@@ -380,6 +492,7 @@ int stride_engine_create(const stride_grid_t* grid, int32_t max_slots, int32_t m
     E->cf = sp->cf;
     E->ls_fwd = sp->ls_fwd;
     E->ls_adj = sp->ls_adj;
+    E->ls_adjv = sp->ls_adjv;
     E->max_slots = max_slots;
     E->max_samples = max_receivers;
     E->ntap = sp->ntap;
@@ -485,16 +598,19 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         if (rc)
             return rc;
         launch_prep_k(plan->dims, vp, plan->g.dt, J.W.k, s);
-        J.cursor = std::make_unique<StepCursor>(plan->nt, J.W.snaps, J.W.peak);
-        // every state fits: the forward keeps v^n (p^n) and the adjoint images
-        // from it, the single-shot full-history path (the same bits)
-        J.history = J.cursor->forward_steps() <= plan->nt - 1 &&
-                    (long long)J.W.pool.size() >= plan->nt;
-        if (J.history) {
-            J.cursor.reset();
+        // the single-shot path for this workspace (the same bits): every
+        // state fits, the forward keeps v^n (p^n) and the adjoint images from
+        // it; segmented history; or the binomial schedule's own step cursor
+        J.path = grad_path(*plan, (long long)J.W.pool.size(), J.W.snaps);
+        J.history = J.path.kind == GradPath::kFull;
+        J.seg = J.path.kind == GradPath::kSegmented;
+        if (J.history || J.seg) {
             for (float* f : {J.W.G, J.W.w[0], J.W.w[1]})
                 launch_fill(f, plan->dims.total, 0.f, s);
+            J.fc = J.W.w[0];
+            J.fp = J.W.w[1];
         } else {
+            J.cursor = std::make_unique<StepCursor>(plan->nt, J.W.snaps, J.W.peak);
             for (float* f : {J.W.pool[0], J.W.pool[1], J.W.G, J.W.w[0], J.W.w[1]})
                 launch_fill(f, plan->dims.total, 0.f, s);
         }

@@ -113,6 +113,30 @@ def test_engine_checkpointed_gradients_equal_single_shot():
 
 
 @pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
+@pytest.mark.parametrize("use_graphs", [True, False])
+def test_engine_gradient_paths_equal_single_shot(maker, use_graphs):
+    """Gradient slots on every path in one engine, full history, segmented
+    history (2 to 4 segments) and binomial checkpointing, chosen by their
+    workspaces as the single-shot solve chooses: each equals its single-shot
+    solve bit for bit (traces, misfit, dvp)."""
+    shots = _shots(maker, 6, nt=80, seed=9)
+    fracs = [None, 0.7, 0.45, 0.25, 0.6, 0.35]
+    outs = _run_engine(shots, ["gradient"] * 6, use_graphs, max_chunk=8, fracs=fracs)
+    paths = set()
+    for r in outs:
+        plan, vp, wav = r["plan"], r["vp"], r["wav"]
+        path = plan.gradient_path(r["ws"].numel())
+        paths.add(path[0])
+        print(f"shot {r['i']} nt={shots[r['i']].nt} frac={fracs[r['i']]} path {path}", flush=True)
+        tr = torch.empty_like(r["traces"])
+        m, d = plan.gradient(vp, wav, r["obs"], traces=tr, ws=r["ws"])
+        assert torch.equal(tr, r["traces"])
+        assert torch.equal(m, r["misfit"])
+        assert torch.equal(d, r["dvp"])
+    assert {S.STRIDE_PATH_FULL_HISTORY, S.STRIDE_PATH_SEGMENTED, S.STRIDE_PATH_BINOMIAL} <= paths
+
+
+@pytest.mark.parametrize("maker", [W.tiny_2d, W.tiny_3d])
 def test_engine_fourth_order_and_mixed_slots_equal_single_shot(maker):
     """Fourth-order forward and gradient slots (full history and
     checkpointed) next to second-order ones in one engine: each equals its
