@@ -169,10 +169,10 @@ def parse():
     ap.add_argument("--max-slots", type=int, default=32, help="serving: shots per engine")
     ap.add_argument("--max-chunk", type=int, default=64, help="serving: ticks per graph chunk")
     ap.add_argument("--no-baseline", action="store_true", help="serving: skip the one-at-a-time run")
-    ap.add_argument("--load", type=float, default=1.5,
-                    help="serving: arrival rate in units of the one-at-a-time service rate (1.5 "
-                         "is the specified stream; 4 saturates both systems, so solves/s then "
-                         "measures capacity)")
+    ap.add_argument("--load", type=float, default=3.0,
+                    help="serving: arrival rate in units of the one-at-a-time service rate of the "
+                         "stream's first requests (3 keeps both systems busy through the stream, "
+                         "so solves/s measures capacity; near 1.5 the server waits for arrivals)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run a 1 GiB device-to-device copy first (scale for HBM byte counters)")
     return ap.parse_args()
