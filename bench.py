@@ -110,7 +110,7 @@ WORKLOADS = {
                "starting model against data from the phantom",
     "config4": "3D head-like phantom, 256^3 at 0.5 mm + 30-cell sponge (316^3 padded), 10th order, "
                "3000 steps, 1 shot, 1024 hemisphere receivers; gradient at the skull-only starting "
-               "model, forward states kept within a 200 GiB HBM budget (segmented history)",
+               "model, forward states kept within a 256 GiB HBM budget (segmented history)",
     "config3": "2D breast-like phantom, 512^2 at 0.2 mm + 40-cell sponge (592^2 padded), 8th order, "
                "1500 steps, shot 0 of the 64-shot ring survey; gradient at 1500 m/s",
     "fwi": "frequency-block inversion of the 2D breast-like phantom of config 3 (512^2 at 0.2 mm, "
@@ -129,7 +129,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="config4", choices=sorted(WORKLOADS))
-    ap.add_argument("--budget-gb", type=float, default=200.0,
+    ap.add_argument("--budget-gb", type=float, default=256.0,
                     help="HBM budget of the gradient workspace in GiB (checkpointing beyond it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
