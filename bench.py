@@ -2,31 +2,36 @@
 """Throughput of the acoustic FWI hot path on one MI355X.
 
 A step is one shot gradient: forward solve with source injection and receiver
-sampling, forward states checkpointed (binomial schedule within the HBM
-budget) or all kept when they fit, residual and misfit, adjoint solve fused
-with the imaging condition, and the gradient finalise: the whole hot path once
-over one shot of the workload.  The default workload is the 3D head (256^3 at
-0.5 mm + 30-cell sponge = 316^3 padded, 10th order, 3000 steps, 1024
-receivers): the largest single-GPU configuration, whose fields exceed the
+sampling, forward states kept within the HBM budget (every state when it fits;
+otherwise the library's choice of segmented history or binomial
+checkpointing), residual and misfit, adjoint solve with the imaging condition,
+and the gradient finalise: the whole hot path once over one shot of the
+workload.  The default workload is the 3D head (256^3 at 0.5 mm + 30-cell
+sponge = 316^3 padded, 10th order, 3000 steps, 1024 receivers, 256 GiB
+budget): the largest single-GPU configuration, whose fields exceed the
 Infinity Cache, so that the HBM fraction measures HBM.
 
 value = grid-point updates per second of forward + adjoint propagation,
-2 * N_padded * (nt - 1) per step (recomputation by checkpointing is not
-counted as work; its factor is reported).
+2 * N_padded * (nt - 1) per step (recomputation is not counted as work; its
+factor is reported).
 
-roofline: the dominant kernel is the fused adjoint + imaging step, priced at
-28 algorithmic bytes per grid-point update (reads u^m, w^{m+1}, w^{m+2}, k,
-G; writes w^m, G).  Beside it, the forward step at 16 bytes (reads u^n,
-u^{n-1}, k; writes u^{n+1}).  Kernel times come from HIP events the library
-records on the solve stream around its time loops during the timed steps,
-with the step and launch counts.  A 2D workload that keeps every state runs
-the paired adjoint instead (24 bytes per step on average); its line reports
-that figure and the 28-byte one.
+roofline: the dominant kernel is the adjoint step of the path the gradient
+takes.  Imaging from the stored v (full or segmented history) it alternates an
+adjoint step without imaging (reads w^{m+1}, w^{m+2}, k; writes w^m: 16 bytes)
+and one adding two imaging terms (also reads v^m, v^{m+1}, G and writes G: 32
+bytes), 24 bytes per grid-point update on average; the fused adjoint of
+binomial checkpointing reads u^m, w^{m+1}, w^{m+2}, k, G and writes w^m, G (28
+bytes).  The line gives both fractions.  Beside it, the forward step at 16
+bytes (reads u^n, u^{n-1}, k; writes u^{n+1}).  Kernel times come from HIP
+events the library records on the solve stream around its time loops during
+the timed steps, with the step and launch counts.  The "binomial" key times
+the same gradient with binomial checkpointing forced in the same workspace.
 
 Extra keys: the config-2 2D shot gradient and forward (same steps), and a
 bounded serving run over the full six-class request mix (2D 256^2, 512^2,
-1024^2 and 3D 128^3, 192^3, 256^3, nt 500-3000; --leg-requests requests):
-served shot solves/s and p50/p99 against one request at a time.
+1024^2 and 3D 128^3, 192^3, 256^3, nt 500-3000; --leg-requests requests,
+arriving at --load times the one-at-a-time rate): served shot solves/s and
+p50/p99 against one request at a time.
 --fourth-order, --sinc, --medium and --pml add those solver variants.
 """
 import argparse
