@@ -99,12 +99,14 @@ def test_sinc_dense_points_3d_fourth_order_match_oracle():
 
 
 def test_sinc_dense_points_3d_checkpointed_gradient():
-    """The packed geometry under workspace budgets that force checkpointing:
-    the fused adjoint step then takes two overflowing entry sets at once (the
-    receiver injection and the source imaging term); the gradient equals the
+    """The packed geometry under workspace budgets that force checkpointing,
+    by the library's choice of path and by binomial checkpointing (whose fused
+    adjoint step takes two overflowing entry sets at once: the receiver
+    injection and the source imaging term); the gradient equals the
     full-history one bitwise."""
     w, rng = _dense_sinc_3d()
     plan = S.Plan.from_workload(w, interp=1)
+    plan_b = S.Plan.from_workload(w, interp=1, checkpointing=1)
     obs = dev(1e-3 * rng.standard_normal((plan.nrec, w.nt)))
     vp, wav = dev(w.vp), dev(w.wavelet)
     m0, g0 = plan.gradient(vp, wav, obs)
@@ -115,9 +117,10 @@ def test_sinc_dense_points_3d_checkpointed_gradient():
             ws = plan.workspace(S.STRIDE_MODE_GRADIENT, int(full * frac))
         except S.StrideError:
             continue
-        m1, g1 = plan.gradient(vp, wav, obs, ws=ws)
-        assert torch.equal(g0, g1), frac
-        assert torch.equal(m0, m1), frac
+        for p in (plan, plan_b):
+            m1, g1 = p.gradient(vp, wav, obs, ws=ws)
+            assert torch.equal(g0, g1), (frac, p.grid.checkpointing)
+            assert torch.equal(m0, m1), (frac, p.grid.checkpointing)
         ran += 1
     assert ran > 0
 
