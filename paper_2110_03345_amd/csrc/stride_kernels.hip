@@ -750,39 +750,55 @@ __device__ __forceinline__ float sponge_eta(const Dims& d, const SpongeCoef& sp,
     return eta;
 }
 
-// One thread per padded point; neighbours beyond the padded array read 0.  The
-// radius is a template argument, so the loads of all 2R taps issue together.
-template <int R>
+// One thread per padded point, a wave per 64 points of a row along the
+// contiguous axis, four rows per block (grid: row chunks x row groups x
+// planes), so the point's coordinates come from the launch indices without a
+// division; neighbours beyond the padded array read 0.  The radius, the
+// dimension and whether y = 2 attenuation enters the stencil operand are
+// template arguments: the loads of all 2R taps of an axis issue together, and
+// without y = 2 the operand is w^{m+1} itself.
+template <int R, int ND, bool Y2>
 __global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
                                                              MediumAdjParams mp)
 {
-    const long long count = (long long)d.n[0] * d.n[1] * (d.nd == 3 ? d.n[2] : 1);
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count)
-        return;
+    const int ix = (int)blockIdx.x * 64 + ((int)threadIdx.x & 63);
+    const int iy = (int)blockIdx.y * 4 + ((int)threadIdx.x >> 6);
     int c[3];
-    padded_coords(d, t, c);
-    const long long p = d.nd == 3 ? c[0] * d.st[0] + c[1] * d.st[1] + c[2] : c[0] * d.st[0] + c[1];
-    const bool y2 = mp.att && mp.att_power == 2;
+    if constexpr (ND == 3) {
+        c[0] = (int)blockIdx.z;
+        c[1] = iy;
+        c[2] = ix;
+    } else {
+        c[0] = iy;
+        c[1] = ix;
+        c[2] = 0;
+    }
+    if (c[ND - 2] >= d.n[ND - 2] || c[ND - 1] >= d.n[ND - 1])
+        return;
+    const long long p = ND == 3 ? (long long)c[0] * d.st[0] + (long long)c[1] * d.st[1] + c[2]
+                                : (long long)c[0] * d.st[0] + c[1];
     auto yv = [&](long long q) {
-        const float b = y2 ? mp.att[q] : 0.f;
-        return fmaf(b, mp.w1[q] - mp.w2[q], mp.w1[q]);
+        if constexpr (Y2)
+            return fmaf(mp.att[q], mp.w1[q] - mp.w2[q], mp.w1[q]);
+        else
+            return mp.w1[q];
     };
     const float w1 = mp.w1[p];
     float lap_y = cf.c0 * yv(p);
     float dens = 0.f;
-    for (int a = 0; a < d.nd; ++a) {
+#pragma unroll
+    for (int a = 0; a < ND; ++a) {
         const long long st = d.st[a];
         float sy = 0.f, sz = 0.f;
 #pragma unroll
-        for (int j = 1; j <= R; ++j) {
-            const bool in_p = c[a] + j < d.n[a], in_m = c[a] - j >= 0;
-            const long long qp = p + j * st, qm = p - j * st;
+        for (int jj = 1; jj <= R; ++jj) {
+            const bool in_p = c[a] + jj < d.n[a], in_m = c[a] - jj >= 0;
+            const long long qp = p + jj * st, qm = p - jj * st;
             const float yp = in_p ? yv(qp) : 0.f, ym = in_m ? yv(qm) : 0.f;
             const float zp = in_p ? mp.gam[a][qp] * mp.w1[qp] : 0.f;
             const float zm = in_m ? mp.gam[a][qm] * mp.w1[qm] : 0.f;
-            sy = fmaf(cf.c[a][j], yp + ym, sy);
-            sz = fmaf(cf.d[a][j], zp - zm, sz);
+            sy = fmaf(cf.c[a][jj], yp + ym, sy);
+            sz = fmaf(cf.d[a][jj], zp - zm, sz);
         }
         lap_y += sy;
         dens += sz;
@@ -795,15 +811,27 @@ __global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef
         mp.G[p] = fmaf(w1, mp.H[p], mp.G[p]);
 }
 
+template <int R, int ND>
+void launch_medium_adjoint_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
+                             const MediumAdjParams& mp, hipStream_t s)
+{
+    const dim3 g((unsigned)((d.n[ND - 1] + 63) / 64), (unsigned)((d.n[ND - 2] + 3) / 4),
+                 ND == 3 ? (unsigned)d.n[0] : 1u);
+    if (mp.att && mp.att_power == 2)
+        hipLaunchKernelGGL((medium_adjoint_kernel<R, ND, true>), g, dim3(256), 0, s, d, cf, sp, mp);
+    else
+        hipLaunchKernelGGL((medium_adjoint_kernel<R, ND, false>), g, dim3(256), 0, s, d, cf, sp, mp);
+}
+
 void launch_medium_adjoint(const Dims& d, int R, const StencilCoef& cf, const SpongeCoef& sp,
                            const MediumAdjParams& mp, hipStream_t s)
 {
-    const long long count = (long long)d.n[0] * d.n[1] * (d.nd == 3 ? d.n[2] : 1);
-    const dim3 g((unsigned)((count + 255) / 256));
     if (R == 4)
-        hipLaunchKernelGGL(medium_adjoint_kernel<4>, g, dim3(256), 0, s, d, cf, sp, mp);
+        d.nd == 3 ? launch_medium_adjoint_t<4, 3>(d, cf, sp, mp, s)
+                  : launch_medium_adjoint_t<4, 2>(d, cf, sp, mp, s);
     else
-        hipLaunchKernelGGL(medium_adjoint_kernel<5>, g, dim3(256), 0, s, d, cf, sp, mp);
+        d.nd == 3 ? launch_medium_adjoint_t<5, 3>(d, cf, sp, mp, s)
+                  : launch_medium_adjoint_t<5, 2>(d, cf, sp, mp, s);
 }
 
 // One block per step-kernel block of the table's launch shape; each thread
