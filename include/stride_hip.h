@@ -294,9 +294,10 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
  *   path 0 (STRIDE_PATH_FULL_HISTORY): every state fits; the forward keeps
  *     v^n = L u^n + S^n (second order; p^n with time_order 4) and the adjoint
  *     images from it;
- *   path 1 (STRIDE_PATH_SEGMENTED): second order, the forward keeps the states
- *     at the starts of `segments` segments and v^n over the last one; each
- *     other segment's v^n is recomputed once, just before its adjoint steps;
+ *   path 1 (STRIDE_PATH_SEGMENTED): the forward keeps the states at the
+ *     starts of `segments` segments and v^n (p^n) over the last one; each
+ *     other segment's v^n (p^n) is recomputed once, just before its adjoint
+ *     steps (the batching engine runs fourth-order such slots by path 2);
  *   path 2 (STRIDE_PATH_BINOMIAL): binomial checkpointing (revolve) with the
  *     adjoint recomputing L u^m itself.
  * The library takes path 1 over path 2 when its cost model of the step

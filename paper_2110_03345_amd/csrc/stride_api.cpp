@@ -492,13 +492,16 @@ StepParams stride::base_params(const stride_plan& P)
     return p;
 }
 
-// Full history when every state fits; otherwise, for second-order time, the
-// segmented history when a cost model of the step kernels prefers it to the
-// binomial schedule with the fused two-stencil adjoint.  Step costs relative
-// to the plain forward step, measured on MI355X (3D 316^3 / 2D 1104^2):
-// forward keeping v 1.18 / 1.04, adjoint imaging from v in pairs 1.48 / 1.30,
-// fused adjoint 2.04 / 1.69.  The segment count is the smallest whose v buffer
-// and stored start states fit, which leaves the fewest steps to recompute.
+// Full history when every state fits; otherwise the segmented history when a
+// cost model of the step kernels prefers it to the binomial schedule (whose
+// adjoint recomputes L u^m itself).  Step costs relative to the plain
+// second-order forward step, measured on MI355X (3D 316^3 / 2D 1104^2):
+// second order, forward keeping v 1.18 / 1.04, adjoint imaging from v in
+// pairs 1.48 / 1.30, fused adjoint 2.04 / 1.69; fourth order, forward 2.0
+// (two launches, keeping p or not), adjoint from the kept p 3.13 / 2.63
+// (two launches), binomial adjoint 3.98 / 3.53 (three).  The segment count is
+// the smallest whose buffer and stored start states fit, which leaves the
+// fewest steps to recompute.
 GradPath stride::grad_path(const stride_plan& P, long long fields, int snaps)
 {
     GradPath g;
@@ -509,11 +512,20 @@ GradPath stride::grad_path(const stride_plan& P, long long fields, int snaps)
         g.kind = GradPath::kFull;
         return g;
     }
-    if (P.torder != 2 || P.g.checkpointing == 1)
+    if (P.g.checkpointing == 1)
         return g;
     const bool d3 = P.nd == 3;
-    const double c_fv = d3 ? 1.18 : 1.04, c_v = d3 ? 1.48 : 1.30, c_fused = d3 ? 2.04 : 1.69;
-    const double cost_b = (double)fb + c_fused * (double)nt;
+    // per forward step (f: plain, fv: keeping v or p) and adjoint step (a:
+    // imaging from the kept v or p, fused: the binomial path's own)
+    double c_f = 1.0, c_fv = d3 ? 1.18 : 1.04, c_a = d3 ? 1.48 : 1.30, c_fused = d3 ? 2.04 : 1.69;
+    if (P.torder == 4) {
+        // two launches per forward step either way; the adjoint keeps its
+        // correction and q launches and drops the p launch
+        c_f = c_fv = 2.0;
+        c_a = d3 ? 3.13 : 2.63;
+        c_fused = d3 ? 3.98 : 3.53;
+    }
+    const double cost_b = c_f * (double)fb + c_fused * (double)nt;
     for (long long K = 2;; ++K) {
         const long long S = fields - 2 * (K - 1);   // v buffer beside K - 1 field pairs
         const long long Se = S & ~1LL;
@@ -532,12 +544,12 @@ GradPath stride::grad_path(const stride_plan& P, long long fields, int snaps)
         const long long vbuf = std::max(nt - last, q);
         if (vbuf + 2 * ((long long)st.size() - 1) > fields)
             break;
-        const double cost_s = (double)last + c_fv * (double)(nt - 1) + c_v * (double)nt;
+        const double cost_s = c_f * (double)last + c_fv * (double)(nt - 1) + c_a * (double)nt;
         if (cost_s < cost_b) {
             g.kind = GradPath::kSegmented;
             g.starts = std::move(st);
             g.vbuf = (int)vbuf;
-            g.forward_steps = nt - 1 + last;
+            g.forward_steps = (nt - 1 + last) * (P.torder == 4 ? 2 : 1);
         }
         break;
     }
@@ -805,15 +817,16 @@ struct Runner {
     // checkpointed path, so the results are the same bits.
     bool vpath = false;
 
-    // Segmented history (second order, when not every state fits and the
-    // cost model below prefers it): the forward sweep stores the states at
-    // the starts of the segments and v^n over the last segment; the adjoint
-    // takes the segments last to first, recomputing a segment's v^n from its
-    // stored start state (the first from x_0 = 0) just before its adjoint
-    // steps, and images from v as the full-history path does.  Every step
-    // before the last segment is recomputed once, more than the binomial
-    // schedule's recomputation, but each adjoint step then has one stencil
-    // field instead of two.  The same arithmetic, so the same bits.
+    // Segmented history (when not every state fits and the cost model of
+    // grad_path prefers it): the forward sweep stores the states at the
+    // starts of the segments and v^n (fourth order: p^n) over the last
+    // segment; the adjoint takes the segments last to first, recomputing a
+    // segment's v^n (p^n) from its stored start state (the first from
+    // x_0 = 0) just before its adjoint steps, and then runs the full-history
+    // path's adjoint steps.  Every step before the last segment is recomputed
+    // once; in exchange each second-order adjoint step has one stencil field
+    // instead of two, and each fourth-order one two launches instead of
+    // three.  The same arithmetic, so the same bits.
     bool segpath = false;
     GradPath path;
 
@@ -831,26 +844,42 @@ struct Runner {
     float* seg_work(int i) const { return W.pool[path.vbuf + i]; }
     float* seg_state(int k, int i) const { return W.pool[path.vbuf + 2 * k + i]; }
 
-    // One leapfrog step u[cur] = u^n, u[1-cur] = u^{n-1} -> u^{n+1} in place of
-    // u^{n-1}; with V it also keeps v^n there (kStepV).
+    // One forward step u[cur] = u^n, u[1-cur] = u^{n-1} -> u^{n+1} in place of
+    // u^{n-1}; with V it also keeps v^n there (kStepV), or with fourth-order
+    // time writes its p^n = k (L u^n + St^n) there instead of the scratch p.
     void seg_step(float* const* u, int cur, int n, float* V, float* traces)
     {
         StepParams p = base_params(P);
         p.A = u[cur];
-        p.B = u[1 - cur];
-        p.C = u[1 - cur];
         p.K = W.k;
         p.step = n;
         p.inj_sig = wavelet;
         if (traces)
             p.smp = rec_samples(P, traces);
+        ++steps;
+        if (P.torder == 4) {
+            float* pp = V ? V : W.p;
+            p.C = pp;
+            launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
+            StepParams q = base_params(P);
+            q.A = pp;
+            q.D = u[cur];
+            q.B = u[1 - cur];
+            q.C = u[1 - cur];
+            q.K = W.k;
+            q.step = n;
+            launch_step_mode(P.dims, P.R, false, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
+            launches += 2;
+            return;
+        }
+        p.B = u[1 - cur];
+        p.C = u[1 - cur];
         if (V) {
             p.V = V;
             launch_step_mode(P.dims, P.R, false, kStepV, P.cf, P.sp, P.ls_fwd, p, s);
         } else {
             launch_step(P.dims, P.R, false, P.cf, P.sp, P.ls_fwd, p, s);
         }
-        ++steps;
         ++launches;
     }
 
@@ -884,6 +913,10 @@ struct Runner {
     void adjoint_v(int j, int e, float* const* V, int& wa, const float* grad_traces,
                    float* dwavelet)
     {
+        if (P.torder == 4) {
+            adjoint_p(j, e, V, wa, grad_traces, dwavelet);
+            return;
+        }
         for (int m = e - 1; m >= j; --m) {
             const bool image = (m % 2) == 0;
             StepParams p = base_params(P);
@@ -981,7 +1014,15 @@ struct Runner {
     void backward_p(const float* grad_traces, float* dwavelet)
     {
         int wa = 0;
-        for (int m = P.nt - 1; m >= 0; --m) {
+        adjoint_p(0, P.nt, W.pool.data(), wa, grad_traces, dwavelet);
+    }
+
+    // Fourth-order adjoint steps e-1 .. j with p^m = Pm[m - j] kept: q = k L
+    // w^{m+1}, then the correction (two launches instead of three).
+    void adjoint_p(int j, int e, float* const* Pm, int& wa, const float* grad_traces,
+                   float* dwavelet)
+    {
+        for (int m = e - 1; m >= j; --m) {
             StepParams q = base_params(P);
             q.A = W.w[wa];
             q.C = W.q;
@@ -993,7 +1034,7 @@ struct Runner {
             launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, q, s);
             StepParams c = base_params(P);
             c.A = W.q;
-            c.U = W.pool[m];
+            c.U = Pm[m - j];
             c.D = W.w[wa];
             c.B = W.w[1 - wa];
             c.C = W.w[1 - wa];

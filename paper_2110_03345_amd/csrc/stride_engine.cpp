@@ -600,10 +600,13 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         launch_prep_k(plan->dims, vp, plan->g.dt, J.W.k, s);
         // the single-shot path for this workspace (the same bits): every
         // state fits, the forward keeps v^n (p^n) and the adjoint images from
-        // it; segmented history; or the binomial schedule's own step cursor
+        // it; segmented history (second order); or the binomial schedule's
+        // own step cursor
         J.path = grad_path(*plan, (long long)J.W.pool.size(), J.W.snaps);
         J.history = J.path.kind == GradPath::kFull;
-        J.seg = J.path.kind == GradPath::kSegmented;
+        // fourth-order segmented history stays a single-shot path: such slots
+        // take the binomial schedule (the same bits)
+        J.seg = J.path.kind == GradPath::kSegmented && plan->torder == 2;
         if (J.history || J.seg) {
             for (float* f : {J.W.G, J.W.w[0], J.W.w[1]})
                 launch_fill(f, plan->dims.total, 0.f, s);

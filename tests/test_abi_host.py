@@ -187,11 +187,11 @@ def test_medium_gradient_workspace_budget():
 
 
 def test_gradient_path_choice():
-    """Full history when every state fits; for second order below that the
-    segmented history (each step before the last segment recomputed once) while
-    it is cheaper than the binomial schedule, binomial for very small pools,
-    fourth order, or when asked for; a larger workspace never needs more
-    forward steps."""
+    """Full history when every state fits; below that the segmented history
+    (each step before the last segment recomputed once) while it is cheaper
+    than the binomial schedule, binomial for very small pools or when asked
+    for; a larger workspace never needs more forward steps; fourth-order
+    forward steps count two launches."""
     g = _grid(shape=(60, 70, 80), spacing=0.5e-3, nb=6, dt=0.3 * 0.5e-3 / 1500, nt=400)
     full = S.stride_workspace_query(g, 1, 3, S.STRIDE_MODE_GRADIENT)
     assert S.stride_gradient_path(g, 3, full) == (S.STRIDE_PATH_FULL_HISTORY, 399, 0)
@@ -211,9 +211,14 @@ def test_gradient_path_choice():
     assert S.stride_gradient_path(g, 3, small)[0] == S.STRIDE_PATH_BINOMIAL
     g4 = _grid(shape=(60, 70, 80), spacing=0.5e-3, nb=6, dt=0.3 * 0.5e-3 / 1500, nt=400,
                time_order=4)
-    b4 = S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT,
-                                  S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT) // 3)
-    assert S.stride_gradient_path(g4, 3, b4)[0] == S.STRIDE_PATH_BINOMIAL
+    full4 = S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT)
+    assert S.stride_gradient_path(g4, 3, full4) == (S.STRIDE_PATH_FULL_HISTORY, 2 * 399, 0)
+    b4 = S.stride_workspace_query(g4, 1, 3, S.STRIDE_MODE_GRADIENT, full4 // 2)
+    p4, f4, n4 = S.stride_gradient_path(g4, 3, b4)
+    assert p4 == S.STRIDE_PATH_SEGMENTED and n4 >= 2 and f4 % 2 == 0 and 2 * 399 < f4 < 4 * 399
+    g4b = _grid(shape=(60, 70, 80), spacing=0.5e-3, nb=6, dt=0.3 * 0.5e-3 / 1500, nt=400,
+                time_order=4, checkpointing=1)
+    assert S.stride_gradient_path(g4b, 3, b4)[0] == S.STRIDE_PATH_BINOMIAL
     with pytest.raises(S.StrideError) as e:
         S.stride_gradient_path(_grid(checkpointing=2), 3, full)
     assert e.value.code == _abi.STRIDE_E_INVALID_ARG

@@ -131,16 +131,19 @@ def test_checkpointing_is_bitwise_invisible(maker, kw):
         assert torch.equal(m0, m2)
 
 
-@pytest.mark.parametrize("maker,kw", [(W.tiny_2d, dict(nt=90)), (W.tiny_2d, dict(nt=91)),
-                                      (W.tiny_3d, dict(nt=50)), (W.tiny_3d, dict(nt=51))])
-def test_gradient_paths_give_the_same_bits(maker, kw):
+@pytest.mark.parametrize("maker,kw,order", [
+    (W.tiny_2d, dict(nt=90), 2), (W.tiny_2d, dict(nt=91), 2),
+    (W.tiny_3d, dict(nt=50), 2), (W.tiny_3d, dict(nt=51), 2),
+    (W.tiny_2d, dict(nt=91), 4), (W.tiny_3d, dict(nt=50), 4)])
+def test_gradient_paths_give_the_same_bits(maker, kw, order):
     """Full history, segmented history and binomial checkpointing (the same
     workspace, checkpointing = 1 forcing the last) give the same bits: the
     gradient with its misfit, and the split forward / backward with the
-    wavelet cotangent; both parities of nt, several segment counts."""
+    wavelet cotangent; both parities of nt, several segment counts, second-
+    and fourth-order time."""
     w = maker(**kw)
-    plan = S.Plan.from_workload(w)
-    plan_b = S.Plan.from_workload(w, checkpointing=1)
+    plan = S.Plan.from_workload(w, time_order=order)
+    plan_b = S.Plan.from_workload(w, time_order=order, checkpointing=1)
     rng = np.random.default_rng(7)
     obs = dev(rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32) * 1e-3)
     gtr = dev(rng.standard_normal((w.rec_xyz.shape[0], w.nt)).astype(np.float32))
