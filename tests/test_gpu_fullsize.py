@@ -11,7 +11,9 @@ times (default tile shapes and chunk lengths).
   tests/golden/make_config4_golden.py: 64 sampled receivers sample by sample,
   and the norm and peak of every one of the 1024 traces.
 - 3D shot gradient (316^3, first 1000 steps, observed data zero), checkpointed
-  with the benchmark's ratio of stored wavefields to steps (1676 for 3000),
+  with the ratio of stored wavefields to steps of a 200 GiB budget (1676 for
+  3000; the library takes the segmented history there, and binomial
+  checkpointing forced in the same workspace gives the same bits),
   against tests/golden/config4_gradient.npz: misfit, dvp on the plane of
   largest norm of each axis (through the source) and on the physical face of
   axis 0 nearest the source (where the padding transpose adds the layer), and
@@ -93,6 +95,11 @@ def test_config4_checkpointed_gradient_matches_golden():
     S.stride_timing_enable(False)
     fwd_steps = S.stride_timing_read()[1]
     assert fwd_steps > w.nt - 1, "the gradient did not checkpoint"
+    # the same workspace with binomial checkpointing forced: the same bits
+    path = plan.gradient_path(ws.numel())
+    plan_b = S.Plan.from_workload(w, checkpointing=1)
+    misfit_b, dvp_b = plan_b.gradient(dev(w.vp_start), dev(w.wavelet), obs, ws=ws)
+    assert torch.equal(misfit, misfit_b) and torch.equal(dvp, dvp_b), path
     d = dvp.cpu().numpy().astype(np.float64)
     tol = 1e-4
     e_J = abs(misfit.item() - float(ref["misfit"])) / float(ref["misfit"])
