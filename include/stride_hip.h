@@ -225,8 +225,10 @@ int stride_plan_forward_medium(const stride_plan_t* plan, const float* vp, const
  * y = 0, + (att a dt/4) ((2 u^{n-1} - 2 u^n)/k - v^n), att = 2 alpha0 vp.  With
  * ws_bytes >= the GRADIENT_MEDIUM size for budget 0 (about nt fields) every
  * step's h is kept; a smaller workspace (stride_workspace_bytes with a budget)
+ * keeps start states of segments and h over the last segment, recomputing each
+ * other segment's h once (segmented history, when the segments fit), or else
  * keeps forward states by binomial checkpointing and recomputes h^m from the
- * stored (u^m, u^{m-1}) before adjoint step m, with the same result bit for bit.
+ * stored (u^m, u^{m-1}) before adjoint step m; the same result bit for bit.
  * Second-order time, sponge boundary.  Errors: INVALID_ARG, CFL, WORKSPACE (below
  * the checkpointed minimum of 13 + ndim wavefields plus traces), HIP,
  * NONFINITE. */

@@ -108,6 +108,10 @@ struct GradPath {
 
 GradPath grad_path(const stride_plan& P, long long fields, int snaps);
 
+// Segment starts (0 first) and buffer length of a segmented history for nt
+// steps in `fields` pool fields; false when no segmentation fits.
+bool make_segments(long long nt, long long fields, std::vector<int>& starts, int& vbuf);
+
 // Views of a forward workspace: [scratch | k | u0 | u1 (| p, fourth order)
 // (| psi_a x 2, chi_a per axis, PML)].
 struct FwdWs {

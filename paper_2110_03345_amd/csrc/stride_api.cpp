@@ -492,6 +492,35 @@ StepParams stride::base_params(const stride_plan& P)
     return p;
 }
 
+// Segments of the segmented history for nt steps in a pool of `fields`
+// fields: the smallest count K whose buffer (the longest segment) and K - 2
+// stored start states plus a working pair fit, which leaves the fewest steps
+// before the last segment.  Segment ends are even.  False when none fits.
+bool stride::make_segments(long long nt, long long fields, std::vector<int>& starts, int& vbuf)
+{
+    for (long long K = 2;; ++K) {
+        const long long S = fields - 2 * (K - 1);   // buffer beside K - 1 field pairs
+        const long long Se = S & ~1LL;
+        if (Se < 2)
+            return false;
+        long long last = std::max(0LL, nt - S);
+        last += last & 1;
+        if ((K - 1) * Se < last)
+            continue;
+        long long q = (last + K - 2) / (K - 1);
+        q += q & 1;
+        starts.clear();
+        for (long long j = 0; j < last; j += q)
+            starts.push_back((int)j);
+        starts.push_back((int)last);
+        const long long buf = std::max(nt - last, q);
+        if (buf + 2 * ((long long)starts.size() - 1) > fields)
+            return false;
+        vbuf = (int)buf;
+        return true;
+    }
+}
+
 // Full history when every state fits; otherwise the segmented history when a
 // cost model of the step kernels prefers it to the binomial schedule (whose
 // adjoint recomputes L u^m itself).  Step costs relative to the plain
@@ -526,32 +555,17 @@ GradPath stride::grad_path(const stride_plan& P, long long fields, int snaps)
         c_fused = d3 ? 3.98 : 3.53;
     }
     const double cost_b = c_f * (double)fb + c_fused * (double)nt;
-    for (long long K = 2;; ++K) {
-        const long long S = fields - 2 * (K - 1);   // v buffer beside K - 1 field pairs
-        const long long Se = S & ~1LL;
-        if (Se < 2)
-            break;
-        long long last = std::max(0LL, nt - S);
-        last += last & 1;                           // segment ends are even
-        if ((K - 1) * Se < last)
-            continue;
-        long long q = (last + K - 2) / (K - 1);
-        q += q & 1;
-        std::vector<int> st;
-        for (long long j = 0; j < last; j += q)
-            st.push_back((int)j);
-        st.push_back((int)last);
-        const long long vbuf = std::max(nt - last, q);
-        if (vbuf + 2 * ((long long)st.size() - 1) > fields)
-            break;
-        const double cost_s = c_f * (double)last + c_fv * (double)(nt - 1) + c_a * (double)nt;
-        if (cost_s < cost_b) {
-            g.kind = GradPath::kSegmented;
-            g.starts = std::move(st);
-            g.vbuf = (int)vbuf;
-            g.forward_steps = (nt - 1 + last) * (P.torder == 4 ? 2 : 1);
-        }
-        break;
+    std::vector<int> st;
+    int vbuf = 0;
+    if (!make_segments(nt, fields, st, vbuf))
+        return g;
+    const long long last = st.back();
+    const double cost_s = c_f * (double)last + c_fv * (double)(nt - 1) + c_a * (double)nt;
+    if (cost_s < cost_b) {
+        g.kind = GradPath::kSegmented;
+        g.starts = std::move(st);
+        g.vbuf = vbuf;
+        g.forward_steps = (nt - 1 + last) * (P.torder == 4 ? 2 : 1);
     }
     return g;
 }
@@ -1494,6 +1508,14 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
     std::vector<float*> H, pool;
     float *hbuf = nullptr, *cbuf = nullptr;
     std::unique_ptr<StepCursor> cursor;
+    // segmented history (as for the plain gradient): h^n over the last
+    // segment kept by the first sweep, each other segment's h^n recomputed
+    // once from its start state; pool = h buffer [0, hlen), working pair,
+    // start state of segment k at hlen + 2k; preferred whenever it fits, since
+    // it saves the binomial path's recomputation of h^m at every adjoint step
+    bool seg = false;
+    std::vector<int> segs;
+    int hlen = 0;
     if (full) {
         H.resize((size_t)std::max(P.nt - 1, 1));
         for (int n = 0; n < P.nt - 1; ++n, b += L.field)
@@ -1506,10 +1528,14 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
         const long long nf = (long long)((bytes - L.grad_medium_fixed) / L.field);
         for (long long f = 0; f < nf; ++f, b += L.field)
             pool.push_back((float*)b);
-        const int snaps = snaps_for_fields(P.nt, nf - 1);
-        if (snaps < 0)
-            return fail(STRIDE_E_WORKSPACE, "medium gradient workspace too small for checkpointing");
-        cursor = std::make_unique<StepCursor>(P.nt, snaps, (int)nf, false);
+        seg = make_segments(P.nt, nf, segs, hlen);
+        if (!seg) {
+            const int snaps = snaps_for_fields(P.nt, nf - 1);
+            if (snaps < 0)
+                return fail(STRIDE_E_WORKSPACE,
+                            "medium gradient workspace too small for checkpointing");
+            cursor = std::make_unique<StepCursor>(P.nt, snaps, (int)nf, false);
+        }
     }
     if ((rc = prepare_medium(P, vp, rho, alpha0, att_power, M, s)))
         return rc;
@@ -1533,8 +1559,37 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
         p.V = V;
         launch_step_mode(P.dims, P.R, false, kMedium, P.cf, P.sp, P.ls_adj, p, s);
     };
+    // the field of three that is neither a nor b
+    auto third = [](float* const* f3, const float* a, const float* b3) {
+        for (int i = 0; i < 3; ++i)
+            if (f3[i] != a && f3[i] != b3)
+                return f3[i];
+        return (float*)nullptr;
+    };
     if (full) {
         medium_sweep(P, M, wavelet, att_power, tr, H.data(), s);
+    } else if (seg) {
+        // u rotates through the three wavefields (free until the adjoint);
+        // the start states x_{j_k} (k = 1 .. K-2) are written into their pool
+        // pair by the steps that produce them
+        const int K = (int)segs.size(), last = segs.back();
+        launch_fill(M.u[0], P.dims.total, 0.f, s);
+        launch_fill(M.u[1], P.dims.total, 0.f, s);
+        float *fc = M.u[0], *fp = M.u[1];
+        int tid = g_timer.begin(s);
+        for (int n = 0; n < P.nt - 1; ++n) {
+            float* out = nullptr;
+            for (int k = 1; k + 1 < K && !out; ++k)
+                out = n + 1 == segs[k] ? pool[hlen + 2 * k]
+                      : n + 1 == segs[k] - 1 ? pool[hlen + 2 * k + 1] : nullptr;
+            if (!out)
+                out = third(M.u, fc, fp);
+            medium_step(fc, fp, out, n, tr, n >= last ? pool[n - last] : nullptr);
+            fp = fc;
+            fc = out;
+        }
+        g_timer.end(tid, s, 0, P.nt - 1, P.nt - 1);
+        launch_sample(rec_samples(P, tr), fc, P.nt - 1, s);
     } else {
         launch_fill(pool[0], P.dims.total, 0.f, s);
         launch_fill(pool[1], P.dims.total, 0.f, s);
@@ -1591,6 +1646,30 @@ int gradient_medium(const stride_plan& P, const float* vp, const float* rho, con
     if (full) {
         for (int m = P.nt - 1; m >= 0; --m)
             adjoint_step(m, m <= P.nt - 2 ? H[m] : nullptr);
+    } else if (seg) {
+        const int K = (int)segs.size();
+        for (int k = K - 1; k >= 0; --k) {
+            const int j = segs[k], e = k + 1 < K ? segs[k + 1] : P.nt;
+            if (k < K - 1) {
+                // h^n, n in [j, e), from the segment's start state (x_0 = 0 in
+                // the working pair for the first); the scratch field is the third
+                float* f3[3] = {pool[hlen + 2 * k], pool[hlen + 2 * k + 1], cbuf};
+                if (k == 0) {
+                    launch_fill(f3[0], P.dims.total, 0.f, s);
+                    launch_fill(f3[1], P.dims.total, 0.f, s);
+                }
+                float *fc = f3[0], *fp = f3[1];
+                for (int n = j; n < e; ++n) {
+                    float* out = third(f3, fc, fp);
+                    medium_step(fc, fp, out, n, nullptr, pool[n - j]);
+                    fp = fc;
+                    fc = out;
+                    ++alaunches;
+                }
+            }
+            for (int m = e - 1; m >= j; --m)
+                adjoint_step(m, m <= P.nt - 2 ? pool[m - j] : nullptr);
+        }
     } else {
         StepOp op;
         while (cursor->next(op)) {
