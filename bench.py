@@ -100,8 +100,8 @@ ADJ_BYTES_PAIRED = 24
 # fourth-order adjoint step: read u^m, k, write p; read w^{m+1}, k, write q;
 # read q, p, w^{m+1}, w^{m+2}, k, H, write w^m, H
 ADJ4_BYTES = 56
-# with every state kept the forward's p^n is kept too and the adjoint drops its
-# first launch: read w^{m+1}, k, write q; read q, p, w^{m+1}, w^{m+2}, k, H, write w^m, H
+# with p^n kept (every state, or segment by segment) the adjoint drops its first
+# launch: read w^{m+1}, k, write q; read q, p, w^{m+1}, w^{m+2}, k, H, write w^m, H
 ADJ4_BYTES_FULL = 44
 # medium forward step: read u^n, u^{n-1}, k, ndim density gradients, attenuation; write u^{n+1}
 
@@ -589,7 +589,8 @@ def variants(m, args, dev):
         del fws4
         four = {
             "scheme": "leapfrog + modified-equation correction (fourth order in time); forward: two "
-                      "launches per step, adjoint: three (two when every state is kept)",
+                      "launches per step, adjoint: three (two when p is kept: full or segmented "
+                      "history)",
             "forward": {"updates_per_s": npad * (w.nt - 1) * steps / el,
                         "ms_per_solve": 1e3 * el / steps, "us_per_step": f4_step * 1e6,
                         "launches_per_step": f4_l / max(f4_n, 1), "bytes_per_point": FWD4_BYTES,
@@ -600,7 +601,9 @@ def variants(m, args, dev):
         el, g4 = _timed(lambda _: S.stride_plan_gradient(plan4.handle, vp_m, wav, obs, traces,
                                                          misfit, dvp, ws4), steps)
         a4_step = g4[3] * 1e-3 / max(g4[4], 1)
-        a4_bytes = ADJ4_BYTES_FULL if g4[1] <= steps * (w.nt - 1) else ADJ4_BYTES
+        # p^m kept (full or segmented history): two adjoint launches, 44 B
+        kept = plan4.gradient_path(ws4.numel())[0] != S.STRIDE_PATH_BINOMIAL
+        a4_bytes = ADJ4_BYTES_FULL if kept else ADJ4_BYTES
         four["gradient"] = {"updates_per_s": 2.0 * npad * (w.nt - 1) * steps / el,
                             "ms_per_solve": 1e3 * el / steps,
                             "forward_steps_per_gradient": g4[1] / steps,
@@ -650,8 +653,31 @@ def variants(m, args, dev):
                             "gbs": medium_bytes(w.ndim) * npad / m_step / 1e9}
             print(f"[bench] medium y={y}: {med[f'y{y}']['ms_per_solve']:.2f} ms/solve",
                   file=sys.stderr, flush=True)
-            del rho_t, al_t
+            if y == 0:
+                # data for the 3D medium gradient below: the phantom in its medium
+                obs_m = plan.forward_medium(vp_t, wav, rho=rho_t, alpha0=al_t, att_power=0, ws=mws)
+                rho4, al4 = rho_t, al_t
+            else:
+                del rho_t, al_t
         del mws
+        # the 3D medium shot gradient within the budget (every imaging factor
+        # would take about 3000 fields): segmented history, one warm-up and one
+        # timed gradient at the skull-only starting model
+        torch.cuda.empty_cache()
+        full_m = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT_MEDIUM)
+        gws4 = plan.workspace(S.STRIDE_MODE_GRADIENT_MEDIUM, min(full_m, budget), device=dev)
+
+        def grad4(_):
+            plan.gradient_medium(vp_m, wav, obs_m, rho=rho4, alpha0=al4, att_power=0, ws=gws4)
+        grad4(0)
+        el, _ = _timed(grad4, 1)
+        med["gradient_config4_y0"] = {"ms_per_gradient": 1e3 * el,
+                                      "updates_per_s": 2.0 * npad * (w.nt - 1) / el,
+                                      "workspace_gb": gws4.numel() / 2**30}
+        print(f"[bench] medium gradient (config4, y=0): {1e3 * el:.2f} ms/gradient",
+              file=sys.stderr, flush=True)
+        del gws4, obs_m, rho4, al4
+        torch.cuda.empty_cache()
         # the medium shot gradient keeps every step's imaging factor, so it is
         # timed on the 2D breast grid (1104^2, 2500 steps: 12.5 GB), at the
         # 1500 m/s model against data from the phantom in its medium, y = 0
