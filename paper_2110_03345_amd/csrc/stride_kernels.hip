@@ -750,73 +750,135 @@ __device__ __forceinline__ float sponge_eta(const Dims& d, const SpongeCoef& sp,
     return eta;
 }
 
-// One thread per padded point, a wave per 64 points of a row along the
-// contiguous axis, four rows per block (grid: row chunks x row groups x
-// planes), so the point's coordinates come from the launch indices without a
-// division; neighbours beyond the padded array read 0.  The radius, the
-// dimension and whether y = 2 attenuation enters the stencil operand are
-// template arguments: the loads of all 2R taps of an axis issue together, and
-// without y = 2 the operand is w^{m+1} itself.
+// One thread per padded point of a 64 x 8 tile of the plane spanned by the
+// last two axes (the row axis ay and the contiguous axis ax), one plane per
+// block (3D: blockIdx.z), two rows per thread.  The block first stages in LDS
+// the stencil operand y over the tile and its R-wide halo, and the density
+// products gamma_ay w^{m+1} (tile and row halo) and gamma_ax w^{m+1} (tile and
+// column halo); the in-plane taps then come from LDS and, in 3D, those of
+// axis 0 from global memory (through the caches).  Neighbours beyond the
+// padded array read 0.  The sums run in the same order as the point-wise
+// definition: centre, then per axis the taps j = 1..R.
+constexpr int kMadjRows = 8;
+
 template <int R, int ND, bool Y2>
 __global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef cf, SpongeCoef sp,
                                                              MediumAdjParams mp)
 {
-    const int ix = (int)blockIdx.x * 64 + ((int)threadIdx.x & 63);
-    const int iy = (int)blockIdx.y * 4 + ((int)threadIdx.x >> 6);
-    int c[3];
-    if constexpr (ND == 3) {
-        c[0] = (int)blockIdx.z;
-        c[1] = iy;
-        c[2] = ix;
-    } else {
-        c[0] = iy;
-        c[1] = ix;
-        c[2] = 0;
-    }
-    if (c[ND - 2] >= d.n[ND - 2] || c[ND - 1] >= d.n[ND - 1])
-        return;
-    const long long p = ND == 3 ? (long long)c[0] * d.st[0] + (long long)c[1] * d.st[1] + c[2]
-                                : (long long)c[0] * d.st[0] + c[1];
+    constexpr int ay = ND - 2, ax = ND - 1;
+    constexpr int TW = kTileX + 2 * R, TH = kMadjRows + 2 * R;
+    __shared__ float Yt[TH][TW];
+    __shared__ float Zy[TH][kTileX];
+    __shared__ float Zx[kMadjRows][TW];
+    const int tid = (int)threadIdx.x;
+    const int x0 = (int)blockIdx.x * kTileX, y0 = (int)blockIdx.y * kMadjRows;
+    const int z = ND == 3 ? (int)blockIdx.z : 0;
+    const int ny = d.n[ay], nx = d.n[ax];
+    const long long base = ND == 3 ? (long long)z * d.st[0] : 0;
+    const long long sty = d.st[ay];
     auto yv = [&](long long q) {
         if constexpr (Y2)
             return fmaf(mp.att[q], mp.w1[q] - mp.w2[q], mp.w1[q]);
         else
             return mp.w1[q];
     };
-    const float w1 = mp.w1[p];
-    float lap_y = cf.c0 * yv(p);
-    float dens = 0.f;
-#pragma unroll
-    for (int a = 0; a < ND; ++a) {
-        const long long st = d.st[a];
-        float sy = 0.f, sz = 0.f;
-#pragma unroll
-        for (int jj = 1; jj <= R; ++jj) {
-            const bool in_p = c[a] + jj < d.n[a], in_m = c[a] - jj >= 0;
-            const long long qp = p + jj * st, qm = p - jj * st;
-            const float yp = in_p ? yv(qp) : 0.f, ym = in_m ? yv(qm) : 0.f;
-            const float zp = in_p ? mp.gam[a][qp] * mp.w1[qp] : 0.f;
-            const float zm = in_m ? mp.gam[a][qm] * mp.w1[qm] : 0.f;
-            sy = fmaf(cf.c[a][jj], yp + ym, sy);
-            sz = fmaf(cf.d[a][jj], zp - zm, sz);
-        }
-        lap_y += sy;
-        dens += sz;
+    for (int e = tid; e < TH * TW; e += 256) {
+        const int ly = e / TW, lx = e - ly * TW;
+        const int gy = y0 + ly - R, gx = x0 + lx - R;
+        float v = 0.f;
+        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+            v = yv(base + gy * sty + gx);
+        Yt[ly][lx] = v;
     }
-    float eta = sponge_eta(d, sp, c);
-    if (mp.att && mp.att_power == 0)
-        eta += mp.att[p];
-    mp.w0[p] = leapfrog(w1, mp.w2[p], mp.k[p], lap_y - dens, eta, sp.half_dt);
-    if (mp.H)
-        mp.G[p] = fmaf(w1, mp.H[p], mp.G[p]);
+    for (int e = tid; e < TH * kTileX; e += 256) {
+        const int ly = e / kTileX, lx = e - ly * kTileX;
+        const int gy = y0 + ly - R, gx = x0 + lx;
+        float v = 0.f;
+        if (gy >= 0 && gy < ny && gx < nx) {
+            const long long q = base + gy * sty + gx;
+            v = mp.gam[ay][q] * mp.w1[q];
+        }
+        Zy[ly][lx] = v;
+    }
+    for (int e = tid; e < kMadjRows * TW; e += 256) {
+        const int ly = e / TW, lx = e - ly * TW;
+        const int gy = y0 + ly, gx = x0 + lx - R;
+        float v = 0.f;
+        if (gy < ny && gx >= 0 && gx < nx) {
+            const long long q = base + gy * sty + gx;
+            v = mp.gam[ax][q] * mp.w1[q];
+        }
+        Zx[ly][lx] = v;
+    }
+    __syncthreads();
+    const int lx = tid & 63;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int ly = (tid >> 6) * 2 + r;
+        const int gy = y0 + ly, gx = x0 + lx;
+        if (gy >= ny || gx >= nx)
+            continue;
+        int c[3];
+        if constexpr (ND == 3) {
+            c[0] = z;
+            c[1] = gy;
+            c[2] = gx;
+        } else {
+            c[0] = gy;
+            c[1] = gx;
+            c[2] = 0;
+        }
+        const long long p = base + gy * sty + gx;
+        const float w1 = mp.w1[p];
+        float lap_y = cf.c0 * Yt[ly + R][lx + R];
+        float dens = 0.f;
+#pragma unroll
+        for (int a = 0; a < ND; ++a) {
+            float sy = 0.f, sz = 0.f;
+#pragma unroll
+            for (int jj = 1; jj <= R; ++jj) {
+                float yp, ym, zp, zm;
+                if (a == ay) {
+                    yp = Yt[ly + R + jj][lx + R];
+                    ym = Yt[ly + R - jj][lx + R];
+                    zp = Zy[ly + R + jj][lx];
+                    zm = Zy[ly + R - jj][lx];
+                } else if (a == ax) {
+                    yp = Yt[ly + R][lx + R + jj];
+                    ym = Yt[ly + R][lx + R - jj];
+                    zp = Zx[ly][lx + R + jj];
+                    zm = Zx[ly][lx + R - jj];
+                } else {
+                    // axis 0 of a 3D grid: the neighbouring planes
+                    const long long st = d.st[0];
+                    const bool in_p = c[0] + jj < d.n[0], in_m = c[0] - jj >= 0;
+                    const long long qp = p + jj * st, qm = p - jj * st;
+                    yp = in_p ? yv(qp) : 0.f;
+                    ym = in_m ? yv(qm) : 0.f;
+                    zp = in_p ? mp.gam[0][qp] * mp.w1[qp] : 0.f;
+                    zm = in_m ? mp.gam[0][qm] * mp.w1[qm] : 0.f;
+                }
+                sy = fmaf(cf.c[a][jj], yp + ym, sy);
+                sz = fmaf(cf.d[a][jj], zp - zm, sz);
+            }
+            lap_y += sy;
+            dens += sz;
+        }
+        float eta = sponge_eta(d, sp, c);
+        if (mp.att && mp.att_power == 0)
+            eta += mp.att[p];
+        mp.w0[p] = leapfrog(w1, mp.w2[p], mp.k[p], lap_y - dens, eta, sp.half_dt);
+        if (mp.H)
+            mp.G[p] = fmaf(w1, mp.H[p], mp.G[p]);
+    }
 }
 
 template <int R, int ND>
 void launch_medium_adjoint_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                              const MediumAdjParams& mp, hipStream_t s)
 {
-    const dim3 g((unsigned)((d.n[ND - 1] + 63) / 64), (unsigned)((d.n[ND - 2] + 3) / 4),
-                 ND == 3 ? (unsigned)d.n[0] : 1u);
+    const dim3 g((unsigned)((d.n[ND - 1] + kTileX - 1) / kTileX),
+                 (unsigned)((d.n[ND - 2] + kMadjRows - 1) / kMadjRows), ND == 3 ? (unsigned)d.n[0] : 1u);
     if (mp.att && mp.att_power == 2)
         hipLaunchKernelGGL((medium_adjoint_kernel<R, ND, true>), g, dim3(256), 0, s, d, cf, sp, mp);
     else
