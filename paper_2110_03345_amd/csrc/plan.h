@@ -112,6 +112,27 @@ GradPath grad_path(const stride_plan& P, long long fields, int snaps);
 // steps in `fields` pool fields; false when no segmentation fits.
 bool make_segments(long long nt, long long fields, std::vector<int>& starts, int& vbuf);
 
+// Segmented history, first sweep: the field that receives u^t from the step
+// reading u^{t-1} (fc) and u^{t-2} (fp).  The start states x_{j_k} (k = 1 ..
+// K-2) land in their pool pair (pool[vbuf + 2k] = u^{j_k}, pool[vbuf + 2k + 1]
+// = u^{j_k - 1}) straight from the steps that produce them, so nothing is
+// copied; any other step writes in place of u^{t-2} when that is one of the two
+// working fields, else into the working field that does not hold u^{t-1}.
+inline float* seg_sweep_out(const GradPath& g, const std::vector<float*>& pool,
+                            float* const work[2], const float* fc, const float* fp, int t)
+{
+    const std::vector<int>& j = g.starts;
+    for (int k = 1; k + 1 < (int)j.size(); ++k) {
+        if (t == j[k])
+            return pool[g.vbuf + 2 * k];
+        if (t == j[k] - 1)
+            return pool[g.vbuf + 2 * k + 1];
+    }
+    if (fp == work[0] || fp == work[1])
+        return const_cast<float*>(fp);
+    return fc == work[0] ? work[1] : work[0];
+}
+
 // Views of a forward workspace: [scratch | k | u0 | u1 (| p, fourth order)
 // (| psi_a x 2, chi_a per axis, PML)].
 struct FwdWs {

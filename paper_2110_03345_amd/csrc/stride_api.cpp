@@ -858,13 +858,13 @@ struct Runner {
     float* seg_work(int i) const { return W.pool[path.vbuf + i]; }
     float* seg_state(int k, int i) const { return W.pool[path.vbuf + 2 * k + i]; }
 
-    // One forward step u[cur] = u^n, u[1-cur] = u^{n-1} -> u^{n+1} in place of
-    // u^{n-1}; with V it also keeps v^n there (kStepV), or with fourth-order
-    // time writes its p^n = k (L u^n + St^n) there instead of the scratch p.
-    void seg_step(float* const* u, int cur, int n, float* V, float* traces)
+    // One forward step A = u^n, B = u^{n-1} -> C = u^{n+1} (C may be B); with
+    // V it also keeps v^n there (kStepV), or with fourth-order time writes its
+    // p^n = k (L u^n + St^n) there instead of the scratch p.
+    void seg_step(const float* A, const float* B, float* C, int n, float* V, float* traces)
     {
         StepParams p = base_params(P);
-        p.A = u[cur];
+        p.A = A;
         p.K = W.k;
         p.step = n;
         p.inj_sig = wavelet;
@@ -877,17 +877,17 @@ struct Runner {
             launch_step_mode(P.dims, P.R, false, kPrep, P.cf, P.sp, P.ls_fwd, p, s);
             StepParams q = base_params(P);
             q.A = pp;
-            q.D = u[cur];
-            q.B = u[1 - cur];
-            q.C = u[1 - cur];
+            q.D = A;
+            q.B = B;
+            q.C = C;
             q.K = W.k;
             q.step = n;
             launch_step_mode(P.dims, P.R, false, kCorrect, P.cf, P.sp, P.ls_fwd, q, s);
             launches += 2;
             return;
         }
-        p.B = u[1 - cur];
-        p.C = u[1 - cur];
+        p.B = B;
+        p.C = C;
         if (V) {
             p.V = V;
             launch_step_mode(P.dims, P.R, false, kStepV, P.cf, P.sp, P.ls_fwd, p, s);
@@ -901,24 +901,19 @@ struct Runner {
     // returns the field of u^{nt-1}.
     const float* forward_seg(float* traces)
     {
-        const std::vector<int>& j = path.starts;
-        const int K = (int)j.size(), last = j[K - 1];
-        float* u[2] = {W.w[0], W.w[1]};
-        launch_fill(u[0], P.dims.total, 0.f, s);
-        launch_fill(u[1], P.dims.total, 0.f, s);
-        int cur = 0, next_state = 1;
+        const int last = path.starts.back();
+        launch_fill(W.w[0], P.dims.total, 0.f, s);
+        launch_fill(W.w[1], P.dims.total, 0.f, s);
+        float *fc = W.w[0], *fp = W.w[1];
         for (int n = 0; n < P.nt - 1; ++n) {
-            seg_step(u, cur, n, n >= last ? W.pool[n - last] : nullptr, traces);
-            cur = 1 - cur;
-            if (next_state <= K - 2 && n + 1 == j[next_state]) {
-                launch_copy(seg_state(next_state, 0), u[cur], P.dims.total, s);
-                launch_copy(seg_state(next_state, 1), u[1 - cur], P.dims.total, s);
-                ++next_state;
-            }
+            float* C = seg_sweep_out(path, W.pool, W.w, fc, fp, n + 1);
+            seg_step(fc, fp, C, n, n >= last ? W.pool[n - last] : nullptr, traces);
+            fp = fc;
+            fc = C;
         }
         // v^{nt-1} is held at zero, as on the full-history path
         launch_fill(W.pool[P.nt - 1 - last], P.dims.total, 0.f, s);
-        return u[cur];
+        return fc;
     }
 
     // Adjoint steps e-1 .. j with v^m in V[m - j] (imaging in pairs as in
@@ -965,18 +960,17 @@ struct Runner {
             const int e = k + 1 < K ? j[k + 1] : P.nt;
             if (k < K - 1) {
                 // recompute v^n, n in [j_k, e), from the segment's start state
-                float* u[2] = {k >= 1 ? seg_state(k, 0) : seg_work(0),
-                               k >= 1 ? seg_state(k, 1) : seg_work(1)};
+                float* fc = k >= 1 ? seg_state(k, 0) : seg_work(0);
+                float* fp = k >= 1 ? seg_state(k, 1) : seg_work(1);
                 if (k == 0) {
-                    launch_fill(u[0], P.dims.total, 0.f, s);
-                    launch_fill(u[1], P.dims.total, 0.f, s);
+                    launch_fill(fc, P.dims.total, 0.f, s);
+                    launch_fill(fp, P.dims.total, 0.f, s);
                 }
                 const int seg = g_timer.begin(s);
                 const long long s0 = steps, l0 = launches;
-                int cur = 0;
                 for (int n = j[k]; n < e; ++n) {
-                    seg_step(u, cur, n, W.pool[n - j[k]], nullptr);
-                    cur = 1 - cur;
+                    seg_step(fc, fp, fp, n, W.pool[n - j[k]], nullptr);
+                    std::swap(fc, fp);
                 }
                 g_timer.end(seg, s, 2, steps - s0, launches - l0);
             }

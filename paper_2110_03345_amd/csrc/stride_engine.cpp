@@ -198,25 +198,6 @@ void adjoint_v_row(const stride_plan& P, TickRows& R, SlotJob& J, int m, int j, 
     J.wa = 1 - J.wa;
 }
 
-// Segmented history, forward sweep: the field that receives u^t.  The start
-// states x_{j_k} (k = 1 .. K-2) land in their pool pair directly (u^{j_k - 1}
-// then u^{j_k}), so no copies are needed; every other step writes in place of
-// u^{n-1} when that is a working field (the adjoint fields, free until the
-// adjoint starts) and into the other working field otherwise.
-float* seg_sweep_target(const SlotJob& J, int t)
-{
-    const std::vector<int>& j = J.path.starts;
-    for (int k = 1; k + 1 < (int)j.size(); ++k) {
-        if (t == j[k])
-            return J.W.pool[J.path.vbuf + 2 * k];
-        if (t == j[k] - 1)
-            return J.W.pool[J.path.vbuf + 2 * k + 1];
-    }
-    if (J.fp == J.W.w[0] || J.fp == J.W.w[1])
-        return J.fp;
-    return J.fc == J.W.w[0] ? J.W.w[1] : J.W.w[0];
-}
-
 int fill_seg(SlotJob& J, TickRows& R)
 {
     const stride_plan& P = *J.P;
@@ -224,7 +205,7 @@ int fill_seg(SlotJob& J, TickRows& R)
     const int K = (int)st.size(), last = st[K - 1];
     if (J.phase == 0) {
         const int n = J.n;
-        float* C = seg_sweep_target(J, n + 1);
+        float* C = seg_sweep_out(J.path, J.W.pool, J.W.w, J.fc, J.fp, n + 1);
         forward_rows(P, R, J.fc, J.fp, C, J.W.k, n, J.wavelet, rec_samples(P, J.W.traces), nullptr,
                      n >= last ? J.W.pool[n - last] : nullptr);
         J.fp = J.fc;
