@@ -299,7 +299,7 @@ int stride_workspace_query(const stride_grid_t* grid, int32_t nsrc, int32_t nrec
  *   path 1 (STRIDE_PATH_SEGMENTED): the forward keeps the states at the
  *     starts of `segments` segments and v^n (p^n) over the last one; each
  *     other segment's v^n (p^n) is recomputed once, just before its adjoint
- *     steps (the batching engine runs fourth-order such slots by path 2);
+ *     steps;
  *   path 2 (STRIDE_PATH_BINOMIAL): binomial checkpointing (revolve) with the
  *     adjoint recomputing L u^m itself.
  * The library takes path 1 over path 2 when its cost model of the step

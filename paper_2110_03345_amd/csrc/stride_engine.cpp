@@ -198,6 +198,39 @@ void adjoint_v_row(const stride_plan& P, TickRows& R, SlotJob& J, int m, int j, 
     J.wa = 1 - J.wa;
 }
 
+// Adjoint step m of a gradient whose imaging operand is kept in
+// pool[m - j] (m in [j, e)): v^m (second order, above) or p^m (fourth order:
+// q = k L w^{m+1}, then the correction with p^m, two rows).
+void adjoint_hist_row(const stride_plan& P, TickRows& R, SlotJob& J, int m, int j, int e)
+{
+    if (P.torder == 2) {
+        adjoint_v_row(P, R, J, m, j, e);
+        return;
+    }
+    StepParams q = base_params(P);
+    q.A = J.W.w[J.wa];
+    q.C = J.W.q;
+    q.K = J.W.k;
+    q.step = m;
+    q.inj = P.no_inj;
+    R.add(kGPrep, make_row(P, q));
+    StepParams c = base_params(P);
+    c.A = J.W.q;
+    c.U = J.W.pool[m - j];
+    c.D = J.W.w[J.wa];
+    c.B = J.W.w[1 - J.wa];
+    c.C = J.W.w[1 - J.wa];
+    c.K = J.W.k;
+    c.G = J.W.G;
+    c.step = m;
+    c.inj = P.rec_inj;
+    c.inj_sig = J.W.residual;
+    c.inj_stride = P.nt;
+    c.img = P.no_inj;
+    R.add(kGAdjCorrect, make_row(P, c));
+    J.wa = 1 - J.wa;
+}
+
 int fill_seg(SlotJob& J, TickRows& R)
 {
     const stride_plan& P = *J.P;
@@ -206,7 +239,7 @@ int fill_seg(SlotJob& J, TickRows& R)
     if (J.phase == 0) {
         const int n = J.n;
         float* C = seg_sweep_out(J.path, J.W.pool, J.W.w, J.fc, J.fp, n + 1);
-        forward_rows(P, R, J.fc, J.fp, C, J.W.k, n, J.wavelet, rec_samples(P, J.W.traces), nullptr,
+        forward_rows(P, R, J.fc, J.fp, C, J.W.k, n, J.wavelet, rec_samples(P, J.W.traces), J.W.p,
                      n >= last ? J.W.pool[n - last] : nullptr);
         J.fp = J.fc;
         J.fc = C;
@@ -215,9 +248,9 @@ int fill_seg(SlotJob& J, TickRows& R)
     }
     const int j = st[J.sk], e = J.sk + 1 < K ? st[J.sk + 1] : P.nt;
     if (J.recompute) {
-        // v^n of segment sk from its start state, u in place
+        // v^n (p^n) of segment sk from its start state, u in place
         const int n = J.rn++;
-        forward_rows(P, R, J.fc, J.fp, J.fp, J.W.k, n, J.wavelet, SampleSet{}, nullptr,
+        forward_rows(P, R, J.fc, J.fp, J.fp, J.W.k, n, J.wavelet, SampleSet{}, J.W.p,
                      J.W.pool[n - j]);
         std::swap(J.fc, J.fp);
         if (J.rn == e) {
@@ -227,7 +260,7 @@ int fill_seg(SlotJob& J, TickRows& R)
         return STRIDE_OK;
     }
     const int m = J.m--;
-    adjoint_v_row(P, R, J, m, j, e);
+    adjoint_hist_row(P, R, J, m, j, e);
     if (m == j && J.sk > 0) {
         // next: segment sk - 1, recomputed from its start state (x_0 = 0 in
         // the zeroed working pair for the first segment)
@@ -262,35 +295,9 @@ int fill_tick(SlotJob& J, TickRows& R)
             ++J.n;
             return STRIDE_OK;
         }
-        const int m = J.m--;
-        if (P.torder == 2) {
-            // imaging terms in pairs: odd m leaves G alone, even m adds both
-            adjoint_v_row(P, R, J, m, 0, P.nt);
-            return STRIDE_OK;
-        }
-        StepParams c = base_params(P);
-        c.B = J.W.w[1 - J.wa];
-        c.C = J.W.w[1 - J.wa];
-        c.K = J.W.k;
-        c.G = J.W.G;
-        c.step = m;
-        c.inj = P.rec_inj;
-        c.inj_sig = J.W.residual;
-        c.inj_stride = P.nt;
-        c.img = P.no_inj;
-        // fourth order: q = k L w^{m+1}, then the correction with p^m from the history
-        StepParams q = base_params(P);
-        q.A = J.W.w[J.wa];
-        q.C = J.W.q;
-        q.K = J.W.k;
-        q.step = m;
-        q.inj = P.no_inj;
-        R.add(kGPrep, make_row(P, q));
-        c.A = J.W.q;
-        c.U = J.W.pool[m];
-        c.D = J.W.w[J.wa];
-        R.add(kGAdjCorrect, make_row(P, c));
-        J.wa = 1 - J.wa;
+        // imaging terms in pairs (second order), or q and the correction
+        // with p^m kept (fourth order)
+        adjoint_hist_row(P, R, J, J.m--, 0, P.nt);
         return STRIDE_OK;
     }
     StepOp op;
@@ -581,13 +588,10 @@ int stride_engine_attach(stride_engine_t* E, const stride_plan_t* plan, int32_t 
         launch_prep_k(plan->dims, vp, plan->g.dt, J.W.k, s);
         // the single-shot path for this workspace (the same bits): every
         // state fits, the forward keeps v^n (p^n) and the adjoint images from
-        // it; segmented history (second order); or the binomial schedule's
-        // own step cursor
+        // it; segmented history; or the binomial schedule's own step cursor
         J.path = grad_path(*plan, (long long)J.W.pool.size(), J.W.snaps);
         J.history = J.path.kind == GradPath::kFull;
-        // fourth-order segmented history stays a single-shot path: such slots
-        // take the binomial schedule (the same bits)
-        J.seg = J.path.kind == GradPath::kSegmented && plan->torder == 2;
+        J.seg = J.path.kind == GradPath::kSegmented;
         if (J.history || J.seg) {
             for (float* f : {J.W.G, J.W.w[0], J.W.w[1]})
                 launch_fill(f, plan->dims.total, 0.f, s);
