@@ -220,6 +220,38 @@ def test_server_results_equal_solo_solves(realtime):
     assert out["p99_s"] >= out["p50_s"] > 0
 
 
+def test_server_checkpointed_gradients_equal_solo_solves():
+    """Gradient requests under a 3 MiB per-shot cap, so that no shot keeps
+    every state: the 2D shots take the segmented history and the 3D ones
+    (whose minimum is above the cap) binomial checkpointing, in the server's
+    engine as in the one-at-a-time solves; every result is the same bits."""
+    from paper_2110_03345_amd.serving import _ws_bytes
+    specs = request_stream(8, 11, 200.0, nt_range=(80, 160), shots_range=(1, 3),
+                           classes_2d=(48, 64), classes_3d=(24,), frac_gradient=1.0)
+    specs = [materialise(s, nrec_2d=24, nrec_3d=32) for s in specs]
+    cap = 3 << 20
+    srv = Server(max_slots=6, max_chunk=16, use_graphs=True, grad_cap=cap)
+    try:
+        out = srv.run(specs, realtime=False)
+    finally:
+        srv.close()
+    paths = set()
+    for r in out["requests"]:
+        g = S.make_grid(r.spec.shape, r.spec.spacing, r.spec.space_order, r.spec.nb, r.spec.vref,
+                        r.spec.dt, r.spec.nt)
+        nrec = r.spec.rec_xyz.shape[0]
+        path = S.stride_gradient_path(g, nrec, _ws_bytes(g, nrec, "gradient", cap))
+        paths.add(path[0])
+        print(f"request {r.spec.rid} shape {r.spec.shape} nt={r.spec.nt} shots={r.spec.nshots} "
+              f"path {path}", flush=True)
+        solo = solve_one(r.spec, grad_cap=cap)
+        for a, b in zip(r.result["traces"], solo["traces"]):
+            assert torch.equal(a, b)
+        assert torch.equal(r.result["dvp"], solo["dvp"])
+        assert r.result["misfit"] == solo["misfit"]
+    assert {S.STRIDE_PATH_SEGMENTED, S.STRIDE_PATH_BINOMIAL} <= paths
+
+
 def test_server_io_limit_overrun_path():
     """An I/O limit too small for any shot: a shot is admitted only when no
     shot runs anywhere (one beyond the limit at a time), every request still
