@@ -444,6 +444,20 @@ def _timed(fn, steps, label=None):
     return t1 - t0, S.stride_timing_read()
 
 
+def gradient_budget(args):
+    """The gradient workspace budget: --budget-gb, but never more than 90 % of
+    the device memory free when the bench starts (so a box with less free
+    memory still runs; the line reports the workspace actually used)."""
+    import torch
+    global _FREE_AT_START
+    if _FREE_AT_START is None:
+        _FREE_AT_START = torch.cuda.mem_get_info()[0]
+    return min(int(args.budget_gb * 2**30), int(0.9 * _FREE_AT_START))
+
+
+_FREE_AT_START = None
+
+
 def measure(name, args, dev, headline, built=None, checkpointing=0, forward=True):
     """Shot gradient and forward solve of one workload: timing of the whole
     step, and per-kernel figures from the library's HIP events.  built: the
@@ -464,7 +478,7 @@ def measure(name, args, dev, headline, built=None, checkpointing=0, forward=True
     obs = plan.forward(vp_t, wav)        # observed data: forward on the phantom
     torch.cuda.synchronize()
 
-    budget = int(args.budget_gb * 2**30)
+    budget = gradient_budget(args)
     full = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT)
     ws_bytes = plan.workspace_bytes(S.STRIDE_MODE_GRADIENT, min(full, budget))
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
@@ -570,7 +584,7 @@ def variants(m, args, dev):
     traces = torch.empty((plan.nrec, plan.nt), dtype=torch.float32, device=dev)
     misfit = torch.zeros(1, dtype=torch.float64, device=dev)
     dvp = torch.empty_like(vp_m)
-    budget = int(args.budget_gb * 2**30)
+    budget = gradient_budget(args)
     steps = args.steps
     out = {}
 
