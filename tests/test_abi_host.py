@@ -224,6 +224,24 @@ def test_gradient_path_choice():
     assert e.value.code == _abi.STRIDE_E_INVALID_ARG
 
 
+def test_segmented_history_recomputes_only_steps_outside_the_buffer():
+    """2D, 300 steps, pools of F fields: the segmented path recomputes each
+    step before its last segment once, so the extra forward steps are an even
+    count (segment ends are even) no smaller than nt - F (the buffer holds at
+    most F states' worth of v) and at most that plus the fields the start
+    states and the working pair take (2 per segment)."""
+    nt = 300
+    g = _grid(nt=nt)
+    field = -(-(52 * 64 * 4) // 256) * 256
+    traces = -(-(3 * nt * 4) // 256) * 256
+    fixed = 256 + 256 * 8 + 4 * field + 2 * traces
+    for F in (80, 120, 200, 290):
+        path, fsteps, nseg = S.stride_gradient_path(g, 3, fixed + F * field)
+        assert path == S.STRIDE_PATH_SEGMENTED, F
+        extra = fsteps - (nt - 1)
+        assert extra % 2 == 0 and nt - F <= extra <= nt - F + 2 * nseg + 2, (F, extra, nseg)
+
+
 @lru_cache(None)
 def _dp(l, s):
     """Brute-force minimal forward steps to reverse l steps with s free slots."""
