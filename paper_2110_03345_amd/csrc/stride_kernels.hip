@@ -873,10 +873,144 @@ __global__ __launch_bounds__(256) void medium_adjoint_kernel(Dims d, StencilCoef
     }
 }
 
+// 3D form of the kernel above with one row per thread (512 threads, the same
+// 64 x 8 tile): the axis-0 taps of a thread's point are loaded first, into
+// registers, so that their loads are in flight together with the tile loads
+// instead of starting after the block's barrier.
+template <int R, bool Y2>
+__global__ __launch_bounds__(512) void medium_adjoint_kernel3(Dims d, StencilCoef cf, SpongeCoef sp,
+                                                              MediumAdjParams mp)
+{
+    constexpr int TW = kTileX + 2 * R, TH = kMadjRows + 2 * R;
+    __shared__ float Yt[TH][TW];
+    __shared__ float Zy[TH][kTileX];
+    __shared__ float Zx[kMadjRows][TW];
+    const int tid = (int)threadIdx.x;
+    const int x0 = (int)blockIdx.x * kTileX, y0 = (int)blockIdx.y * kMadjRows;
+    const int z = (int)blockIdx.z;
+    const int n0 = d.n[0], ny = d.n[1], nx = d.n[2];
+    const long long st0 = d.st[0], sty = d.st[1];
+    const long long base = (long long)z * st0;
+    const int lx = tid & 63, ly = tid >> 6;
+    const int gy = y0 + ly, gx = x0 + lx;
+    const bool inside = gy < ny && gx < nx;
+    const long long p = base + gy * sty + gx;
+    // axis-0 taps: raw values (the operand is formed after the barrier)
+    float w1p[R], w1m[R], gp[R], gm[R], w2p[R], w2m[R], ap[R], am[R];
+#pragma unroll
+    for (int jj = 1; jj <= R; ++jj) {
+        const bool in_p = inside && z + jj < n0, in_m = inside && z - jj >= 0;
+        const long long qp = p + jj * st0, qm = p - jj * st0;
+        w1p[jj - 1] = in_p ? mp.w1[qp] : 0.f;
+        w1m[jj - 1] = in_m ? mp.w1[qm] : 0.f;
+        gp[jj - 1] = in_p ? mp.gam[0][qp] : 0.f;
+        gm[jj - 1] = in_m ? mp.gam[0][qm] : 0.f;
+        if constexpr (Y2) {
+            w2p[jj - 1] = in_p ? mp.w2[qp] : 0.f;
+            w2m[jj - 1] = in_m ? mp.w2[qm] : 0.f;
+            ap[jj - 1] = in_p ? mp.att[qp] : 0.f;
+            am[jj - 1] = in_m ? mp.att[qm] : 0.f;
+        }
+    }
+    auto yv = [&](long long q) {
+        if constexpr (Y2)
+            return fmaf(mp.att[q], mp.w1[q] - mp.w2[q], mp.w1[q]);
+        else
+            return mp.w1[q];
+    };
+    for (int e = tid; e < TH * TW; e += 512) {
+        const int ty = e / TW, tx = e - ty * TW;
+        const int yy = y0 + ty - R, xx = x0 + tx - R;
+        float v = 0.f;
+        if (yy >= 0 && yy < ny && xx >= 0 && xx < nx)
+            v = yv(base + yy * sty + xx);
+        Yt[ty][tx] = v;
+    }
+    for (int e = tid; e < TH * kTileX; e += 512) {
+        const int ty = e / kTileX, tx = e - ty * kTileX;
+        const int yy = y0 + ty - R, xx = x0 + tx;
+        float v = 0.f;
+        if (yy >= 0 && yy < ny && xx < nx) {
+            const long long q = base + yy * sty + xx;
+            v = mp.gam[1][q] * mp.w1[q];
+        }
+        Zy[ty][tx] = v;
+    }
+    for (int e = tid; e < kMadjRows * TW; e += 512) {
+        const int ty = e / TW, tx = e - ty * TW;
+        const int yy = y0 + ty, xx = x0 + tx - R;
+        float v = 0.f;
+        if (yy < ny && xx >= 0 && xx < nx) {
+            const long long q = base + yy * sty + xx;
+            v = mp.gam[2][q] * mp.w1[q];
+        }
+        Zx[ty][tx] = v;
+    }
+    __syncthreads();
+    if (!inside)
+        return;
+    const int c[3] = {z, gy, gx};
+    const float w1 = mp.w1[p];
+    float lap_y = cf.c0 * Yt[ly + R][lx + R];
+    float dens = 0.f;
+    {
+        float sy = 0.f, sz = 0.f;
+#pragma unroll
+        for (int jj = 1; jj <= R; ++jj) {
+            float yp = w1p[jj - 1], ym = w1m[jj - 1];
+            if constexpr (Y2) {
+                // a point outside the grid loaded 0 for w1, w2 and att: 0 here too
+                yp = fmaf(ap[jj - 1], w1p[jj - 1] - w2p[jj - 1], w1p[jj - 1]);
+                ym = fmaf(am[jj - 1], w1m[jj - 1] - w2m[jj - 1], w1m[jj - 1]);
+            }
+            const float zp = gp[jj - 1] * w1p[jj - 1], zm = gm[jj - 1] * w1m[jj - 1];
+            sy = fmaf(cf.c[0][jj], yp + ym, sy);
+            sz = fmaf(cf.d[0][jj], zp - zm, sz);
+        }
+        lap_y += sy;
+        dens += sz;
+    }
+    {
+        float sy = 0.f, sz = 0.f;
+#pragma unroll
+        for (int jj = 1; jj <= R; ++jj) {
+            sy = fmaf(cf.c[1][jj], Yt[ly + R + jj][lx + R] + Yt[ly + R - jj][lx + R], sy);
+            sz = fmaf(cf.d[1][jj], Zy[ly + R + jj][lx] - Zy[ly + R - jj][lx], sz);
+        }
+        lap_y += sy;
+        dens += sz;
+    }
+    {
+        float sy = 0.f, sz = 0.f;
+#pragma unroll
+        for (int jj = 1; jj <= R; ++jj) {
+            sy = fmaf(cf.c[2][jj], Yt[ly + R][lx + R + jj] + Yt[ly + R][lx + R - jj], sy);
+            sz = fmaf(cf.d[2][jj], Zx[ly][lx + R + jj] - Zx[ly][lx + R - jj], sz);
+        }
+        lap_y += sy;
+        dens += sz;
+    }
+    float eta = sponge_eta(d, sp, c);
+    if (mp.att && mp.att_power == 0)
+        eta += mp.att[p];
+    mp.w0[p] = leapfrog(w1, mp.w2[p], mp.k[p], lap_y - dens, eta, sp.half_dt);
+    if (mp.H)
+        mp.G[p] = fmaf(w1, mp.H[p], mp.G[p]);
+}
+
 template <int R, int ND>
 void launch_medium_adjoint_t(const Dims& d, const StencilCoef& cf, const SpongeCoef& sp,
                              const MediumAdjParams& mp, hipStream_t s)
 {
+    if constexpr (ND == 3) {
+        const dim3 g((unsigned)((d.n[2] + kTileX - 1) / kTileX),
+                     (unsigned)((d.n[1] + kMadjRows - 1) / kMadjRows), (unsigned)d.n[0]);
+        if (mp.att && mp.att_power == 2)
+            hipLaunchKernelGGL((medium_adjoint_kernel3<R, true>), g, dim3(512), 0, s, d, cf, sp, mp);
+        else
+            hipLaunchKernelGGL((medium_adjoint_kernel3<R, false>), g, dim3(512), 0, s, d, cf, sp, mp);
+        return;
+    }
     const dim3 g((unsigned)((d.n[ND - 1] + kTileX - 1) / kTileX),
                  (unsigned)((d.n[ND - 2] + kMadjRows - 1) / kMadjRows), ND == 3 ? (unsigned)d.n[0] : 1u);
     if (mp.att && mp.att_power == 2)
